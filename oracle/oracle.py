@@ -1,0 +1,226 @@
+"""ctypes wrapper of the FP64 CPU oracle (rc_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the
+benchmark's CPU-baseline leg, never by the product package.  It compiles
+``rc_oracle.c`` with gcc (no FP contraction, no fast-math) into
+``liboracle.so`` next to this file.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "rc_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+P = ctypes.c_void_p
+I64 = ctypes.c_int64
+I32 = ctypes.c_int
+D = ctypes.c_double
+
+
+def build(force: bool = False) -> str:
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+                               "-fopenmp", "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_LIB)
+        L.or_prune.restype = I64
+        L.or_prune.argtypes = [I64, P, P, P, P, I32, P, P]
+        L.or_node_rect.restype = I32
+        L.or_node_rect.argtypes = [I32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, P, P]
+        L.or_pairs.restype = I64
+        L.or_pairs.argtypes = [I64, P, P, P, P, P, P, P, P, I64]
+        L.or_render.restype = I32
+        L.or_render.argtypes = [I64, P, P, P, P, I32, P, P, I32, I32, P, I64, P, P, P, P, P, P]
+        L.or_grad.restype = I32
+        L.or_grad.argtypes = [I64, P, P, P, P, I32, P, P, I32, I32, P, I64, P, P, P, P]
+        L.or_segment.restype = I32
+        L.or_segment.argtypes = [I32, P, P, ctypes.c_uint8, ctypes.c_uint32, ctypes.c_uint32,
+                                 ctypes.c_uint32, P, P, D, D, I32, I32, P, P]
+        L.or_march.restype = I32
+        L.or_march.argtypes = [I64, P, P, P, P, I32, P, P, P, I32, P, P, P]
+        for nm in ("or_combine", "or_average"):
+            getattr(L, nm).argtypes = [P, P, P]
+        L.or_inverse.argtypes = [P, P]
+        L.or_split.argtypes = [P, D, P, P]
+        L.or_physical.argtypes = [P, D, P]
+        L.or_rk4_step.argtypes = [P, P, D, P]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+def _c(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+def _forest_args(forest):
+    lv = _c(forest.level, np.uint8)
+    x = _c(forest.x, np.uint32)
+    y = _c(forest.y, np.uint32)
+    z = _c(forest.z, np.uint32)
+    return lv, x, y, z
+
+
+def _field_args(fields, kappa=None, eps=None):
+    k = _c(fields.kappa if kappa is None else kappa, np.float64)
+    e = _c(fields.eps if eps is None else eps, np.float64)
+    kind = 1 if k.shape[0] == 8 else 0
+    return kind, k, e
+
+
+# ---------------------------------------------------------------- group ops
+
+
+def combine(near, far):
+    a, b, o = _c(near, np.float64), _c(far, np.float64), np.zeros(2)
+    lib().or_combine(_p(a), _p(b), _p(o))
+    return o
+
+
+def inverse(s):
+    a, o = _c(s, np.float64), np.zeros(2)
+    lib().or_inverse(_p(a), _p(o))
+    return o
+
+
+def split(s, frac1):
+    a, o1, o2 = _c(s, np.float64), np.zeros(2), np.zeros(2)
+    lib().or_split(_p(a), float(frac1), _p(o1), _p(o2))
+    return o1, o2
+
+
+def average(s1, s2):
+    a, b, o = _c(s1, np.float64), _c(s2, np.float64), np.zeros(2)
+    lib().or_average(_p(a), _p(b), _p(o))
+    return o
+
+
+def physical(s, dx):
+    a, o = _c(s, np.float64), np.zeros(2)
+    lib().or_physical(_p(a), float(dx), _p(o))
+    return o
+
+
+def rk4_step(beta4, gamma4, h):
+    b, g, o = _c(beta4, np.float64), _c(gamma4, np.float64), np.zeros(2)
+    lib().or_rk4_step(_p(b), _p(g), float(h), _p(o))
+    return o
+
+
+def segment(kind, kap, eps, level, x, y, z, rho, r, s_in, s_out, method, substeps=4):
+    """(A, B) and d(A, B)/d(kappa corners, eps corners) of one segment."""
+    nc = 8 if kind else 1
+    k, e = _c(kap, np.float64), _c(eps, np.float64)
+    rh, rr = _c(rho, np.float64), _c(r, np.float64)
+    ab, dab = np.zeros(2), np.zeros((2, 2 * nc))
+    lib().or_segment(int(kind), _p(k), _p(e), int(level), int(x), int(y), int(z), _p(rh), _p(rr),
+                     float(s_in), float(s_out), int(method), int(substeps), _p(ab), _p(dab))
+    return ab, dab
+
+
+# ---------------------------------------------------------------- geometry
+
+
+def prune(forest, cams_raw):
+    """rect[cam][leaf] = (i0, i1, j0, j1); empty rectangles are (1, 0, 1, 0)."""
+    cams = _c(np.atleast_2d(cams_raw), np.float64)
+    lv, x, y, z = _forest_args(forest)
+    rect = np.zeros((cams.shape[0], forest.nleaves, 4), np.int32)
+    nvis = lib().or_prune(forest.nleaves, _p(lv), _p(x), _p(y), _p(z), cams.shape[0], _p(cams), _p(rect))
+    return rect, int(nvis)
+
+
+def node_rect(level, x, y, z, cam_raw):
+    cam = _c(cam_raw, np.float64)
+    rect = np.zeros(4, np.int32)
+    vis = lib().or_node_rect(int(level), int(x), int(y), int(z), _p(cam), _p(rect))
+    return rect, bool(vis)
+
+
+def pairs(forest, cam_raw, leaves=None):
+    """Candidate pairing in (leaf, row-major pixel) order for the listed leaves."""
+    lv, x, y, z = _forest_args(forest)
+    lst = np.arange(forest.nleaves, dtype=np.int64) if leaves is None else _c(leaves, np.int64)
+    cam = _c(cam_raw, np.float64)
+    L = lib()
+    ncand = L.or_pairs(lst.shape[0], _p(lst), _p(lv), _p(x), _p(y), _p(z), _p(cam), None, None, 0)
+    hit = np.zeros(max(ncand, 1), np.uint8)
+    sio = np.zeros((max(ncand, 1), 2), np.float64)
+    L.or_pairs(lst.shape[0], _p(lst), _p(lv), _p(x), _p(y), _p(z), _p(cam), _p(hit), _p(sio), ncand)
+    return hit[:ncand], sio[:ncand]
+
+
+# ---------------------------------------------------------------- render / grad
+
+METHODS = {"analytic": 0, "rk4": 1}
+
+
+def render(forest, fields, cam, method="rk4", substeps=4, pixels=None, kappa=None, eps=None,
+           background=None):
+    """FP64 oracle image of one camera.  Returns dict with A, B, I, nseg (flat, row j=0 first)."""
+    raw = cam.raw() if hasattr(cam, "raw") else np.asarray(cam, np.float64).copy()
+    if background is not None:
+        raw = raw.copy()
+        raw[17] = background
+    lv, x, y, z = _forest_args(forest)
+    kind, k, e = _field_args(fields, kappa, eps)
+    W, H = int(raw[14]), int(raw[15])
+    if pixels is None:
+        npo, pix = W * H, None
+        nsel = -1
+    else:
+        pix = _c(pixels, np.int64)
+        npo = nsel = pix.shape[0]
+    A, B, I = np.zeros(npo), np.zeros(npo), np.zeros(npo)
+    nseg = np.zeros(npo, np.int32)
+    stats = np.zeros(4, np.int64)
+    lib().or_render(forest.nleaves, _p(lv), _p(x), _p(y), _p(z), kind, _p(k), _p(e), METHODS[method],
+                    int(substeps), _p(raw), nsel, _p(pix), _p(A), _p(B), _p(I), _p(nseg), _p(stats))
+    return {"A": A, "B": B, "I": I, "nseg": nseg, "segments": int(stats[0]), "overlaps": int(stats[1])}
+
+
+def grad(forest, fields, cam, g, method="rk4", substeps=4, pixels=None, kappa=None, eps=None):
+    """dL/dkappa, dL/deps ([nc][N]) for per-pixel dL/dI = g."""
+    raw = cam.raw() if hasattr(cam, "raw") else np.asarray(cam, np.float64)
+    lv, x, y, z = _forest_args(forest)
+    kind, k, e = _field_args(fields, kappa, eps)
+    gg = _c(g, np.float64)
+    if pixels is None:
+        nsel, pix = -1, None
+    else:
+        pix = _c(pixels, np.int64)
+        nsel = pix.shape[0]
+    gk, ge = np.zeros_like(k), np.zeros_like(e)
+    lib().or_grad(forest.nleaves, _p(lv), _p(x), _p(y), _p(z), kind, _p(k), _p(e), METHODS[method],
+                  int(substeps), _p(_c(raw, np.float64)), nsel, _p(pix), _p(gg), _p(gk), _p(ge))
+    return gk, ge
+
+
+def march(forest, fields, cam, M=1024):
+    raw = cam.raw() if hasattr(cam, "raw") else np.asarray(cam, np.float64)
+    lv, x, y, z = _forest_args(forest)
+    kind, k, e = _field_args(fields)
+    P_ = int(raw[14]) * int(raw[15])
+    A, B, I = np.zeros(P_), np.zeros(P_), np.zeros(P_)
+    lib().or_march(forest.nleaves, _p(lv), _p(x), _p(y), _p(z), kind, _p(k), _p(e),
+                   _p(_c(raw, np.float64)), int(M), _p(A), _p(B), _p(I))
+    return {"A": A, "B": B, "I": I}

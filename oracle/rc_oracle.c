@@ -1,0 +1,854 @@
+/*
+ * rc_oracle.c -- plain FP64 CPU reference of the forest-of-octrees raycasting
+ * hot path (Burstedde, "Distributed-Memory Forest-of-Octrees Raycasting").
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the
+ * benchmark's CPU-baseline leg may load or call this file.  It shares no code,
+ * header, table or helper with the HIP library, and it computes everything in
+ * double precision with straightforward loops.
+ *
+ * What it computes, per pixel p of a camera (the classic back-to-front result
+ * written with the segment group operation of Sec. 2.4):
+ *   1. every leaf whose projected pixel rectangle (Sec. 2.2, camera-aligned
+ *      AABB projected to the image) contains p is intersected with p's ray;
+ *   2. every hit gives a segment [s_in, s_out] and its (A, B) from the ODE
+ *      I' = gamma - beta I (eq. Iode .. ABgeneral), either in closed form for
+ *      constant coefficients (eq. ABconstant) or by explicit RK4 stages
+ *      (eq. RKresultAB) over equal substeps combined with (+) (Sec. 2.4);
+ *   3. the segments of p are SORTED by entry depth (allowed here: this is the
+ *      definition the sort-free GPU fold must reproduce) and folded front to
+ *      back with (A2,B2) (+) (A1,B1) = (A2 A1, B2 + A2 B1) (eq. aggregate);
+ *   4. I = A * I_b + B (Sec. 2.4, final intensity).
+ * Gradients use forward-mode dual numbers through step 2 and the product
+ * structure of the fold in step 3.
+ *
+ * Readings of the paper that the text leaves open are fixed identically on
+ * both implementations: the canonical rectangle and slab predicates below,
+ * the orthographic ray, the corner numbering and the RK4 point placement.
+ *
+ * Parity: every function here is pinned by CPU tests against closed forms,
+ * group identities, brute-force marching and finite differences.
+ *
+ * Build: gcc -O2 -std=c11 -ffp-contract=off -fno-fast-math -fopenmp -shared -fPIC
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_QMAX 19
+#define OR_NPMAX 16
+
+/* ------------------------------------------------------------------------ */
+/* group operations on segments (Sec. 2.4 - 2.6)                            */
+/* ------------------------------------------------------------------------ */
+
+/* (A2,B2) (+) (A1,B1): segment 2 is the one nearer to the camera (eq. aggregate). */
+void or_combine(const double *near2, const double *far1, double *out)
+{
+    double A = near2[0] * far1[0];
+    double B = near2[1] + near2[0] * far1[1];
+    out[0] = A;
+    out[1] = B;
+}
+
+/* (-)(A,B) = (1/A, -B/A) (eq. identityinverse). */
+void or_inverse(const double *s, double *out)
+{
+    out[0] = 1.0 / s[0];
+    out[1] = -s[1] / s[0];
+}
+
+/* Split (A,B) of length dx into pieces of length dx1 and dx - dx1 (eq. segsplit).
+ * out1 is the piece of length dx1. */
+void or_split(const double *s, double frac1, double *out1, double *out2)
+{
+    double A = s[0], B = s[1];
+    double fr[2] = {frac1, 1.0 - frac1};
+    double *o[2] = {out1, out2};
+    for (int i = 0; i < 2; i++) {
+        double Ai = pow(A, fr[i]);
+        double Bi = (A == 1.0) ? B * fr[i] : B * (1.0 - Ai) / (1.0 - A);
+        o[i][0] = Ai;
+        o[i][1] = Bi;
+    }
+}
+
+/* Average of two segments over the same interval (eq. segaverage). */
+void or_average(const double *s1, const double *s2, double *out)
+{
+    out[0] = sqrt(s1[0] * s2[0]);
+    out[1] = 0.5 * (s1[1] + s2[1]);
+}
+
+/* Constant coefficients equivalent to (A,B) over length dx (eq. betagammafromAB). */
+void or_physical(const double *s, double dx, double *beta_gamma)
+{
+    double beta = -log(s[0]) / dx;
+    double gamma = (s[0] == 1.0) ? s[1] / dx : beta * s[1] / (1.0 - s[0]);
+    beta_gamma[0] = beta;
+    beta_gamma[1] = gamma;
+}
+
+/* ------------------------------------------------------------------------ */
+/* dual numbers: value plus np partial derivatives                          */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    double v;
+    double d[OR_NPMAX];
+} dn;
+
+static dn dn_c(double v, int np)
+{
+    dn r;
+    r.v = v;
+    for (int k = 0; k < np; k++) r.d[k] = 0.0;
+    return r;
+}
+static dn dn_add(dn a, dn b, int np)
+{
+    dn r;
+    r.v = a.v + b.v;
+    for (int k = 0; k < np; k++) r.d[k] = a.d[k] + b.d[k];
+    return r;
+}
+static dn dn_sub(dn a, dn b, int np)
+{
+    dn r;
+    r.v = a.v - b.v;
+    for (int k = 0; k < np; k++) r.d[k] = a.d[k] - b.d[k];
+    return r;
+}
+static dn dn_mul(dn a, dn b, int np)
+{
+    dn r;
+    r.v = a.v * b.v;
+    for (int k = 0; k < np; k++) r.d[k] = a.d[k] * b.v + a.v * b.d[k];
+    return r;
+}
+static dn dn_scale(dn a, double s, int np)
+{
+    dn r;
+    r.v = a.v * s;
+    for (int k = 0; k < np; k++) r.d[k] = a.d[k] * s;
+    return r;
+}
+static dn dn_exp(dn a, int np)
+{
+    dn r;
+    r.v = exp(a.v);
+    for (int k = 0; k < np; k++) r.d[k] = r.v * a.d[k];
+    return r;
+}
+/* phi(x) = (1 - e^{-x}) / x with phi(0) = 1, and its derivative. */
+static dn dn_phi(dn x, int np)
+{
+    dn r;
+    double v = x.v, f, df;
+    if (fabs(v) < 1e-4) {
+        /* Taylor: 1 - x/2 + x^2/6 - x^3/24 + x^4/120 */
+        f = 1.0 - v / 2.0 + v * v / 6.0 - v * v * v / 24.0 + v * v * v * v / 120.0;
+        df = -0.5 + v / 3.0 - v * v / 8.0 + v * v * v / 30.0;
+    } else {
+        double em = -expm1(-v); /* 1 - e^{-x} */
+        f = em / v;
+        df = (exp(-v) * v - em) / (v * v);
+    }
+    r.v = f;
+    for (int k = 0; k < np; k++) r.d[k] = df * x.d[k];
+    return r;
+}
+
+/* ------------------------------------------------------------------------ */
+/* segment evaluation (Sec. 2.3 and 2.7)                                    */
+/* ------------------------------------------------------------------------ */
+
+/* Constant coefficients (eq. ABconstant): A = exp(-beta dx), B = gamma dx phi(beta dx). */
+static void seg_const_dn(dn beta, dn gamma, double dx, int np, dn *A, dn *B)
+{
+    dn x = dn_scale(beta, dx, np);
+    *A = dn_exp(dn_scale(x, -1.0, np), np);
+    *B = dn_mul(dn_scale(gamma, dx, np), dn_phi(x, np), np);
+}
+
+/* One explicit RK step for the two ODEs of eq. ODEsAB from (A,B) = (1,0), with
+ * the stage values of eq. RKresultAB for the classical RK4 tableau:
+ * c = (0, 1/2, 1/2, 1), a10 = a21 = 1/2, a32 = 1, b = (1/6, 1/3, 1/3, 1/6).
+ * beta[i], gamma[i] are the coefficients at xi_i = x1 + c_i h (x1 = far end). */
+static void rk4_step_dn(const dn *beta, const dn *gamma, double h, int np, dn *Aout, dn *Bout)
+{
+    static const double a[5][4] = {
+        {0.0, 0.0, 0.0, 0.0},
+        {0.5, 0.0, 0.0, 0.0},
+        {0.0, 0.5, 0.0, 0.0},
+        {0.0, 0.0, 1.0, 0.0},
+        {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0}, /* final row a_Mj = b_j */
+    };
+    dn Ab[5], Bb[5];
+    for (int i = 0; i <= 4; i++) {
+        dn sa = dn_c(0.0, np), sb = dn_c(0.0, np);
+        for (int j = 0; j < i; j++) {
+            if (a[i][j] == 0.0) continue;
+            dn fa = dn_scale(dn_mul(beta[j], Ab[j], np), -1.0, np);       /* -beta A */
+            dn fb = dn_sub(gamma[j], dn_mul(beta[j], Bb[j], np), np);     /* gamma - beta B */
+            sa = dn_add(sa, dn_scale(fa, a[i][j], np), np);
+            sb = dn_add(sb, dn_scale(fb, a[i][j], np), np);
+        }
+        Ab[i] = dn_add(dn_c(1.0, np), dn_scale(sa, h, np), np);
+        Bb[i] = dn_scale(sb, h, np);
+    }
+    *Aout = Ab[4];
+    *Bout = Bb[4];
+}
+
+void or_rk4_step(const double *beta4, const double *gamma4, double h, double *AB)
+{
+    dn b[4], g[4], A, B;
+    for (int i = 0; i < 4; i++) {
+        b[i] = dn_c(beta4[i], 0);
+        g[i] = dn_c(gamma4[i], 0);
+    }
+    rk4_step_dn(b, g, h, 0, &A, &B);
+    AB[0] = A.v;
+    AB[1] = B.v;
+}
+
+/* Trilinear interpolation of 8 corner values (corner c = bx + 2 by + 4 bz) at
+ * reference coordinates xi in [0,1]^3; the corner values are the parameters
+ * p0 .. p0+7 of the dual numbers when np > 0. */
+static dn trilin_dn(const double *cv, const double *xi, int np, int p0)
+{
+    dn r = dn_c(0.0, np);
+    for (int c = 0; c < 8; c++) {
+        double w = 1.0;
+        for (int k = 0; k < 3; k++) w *= ((c >> k) & 1) ? xi[k] : 1.0 - xi[k];
+        r.v += cv[c] * w;
+        if (np > 0) r.d[p0 + c] += w;
+    }
+    return r;
+}
+
+/* Leaf geometry in the unit cube. */
+typedef struct {
+    double lo[3], hi[3], hlen;
+} leafbox;
+
+static leafbox leaf_box(uint8_t level, uint32_t x, uint32_t y, uint32_t z)
+{
+    leafbox b;
+    double q = ldexp(1.0, -OR_QMAX);
+    uint32_t len = (uint32_t)1 << (OR_QMAX - level);
+    uint32_t a[3] = {x, y, z};
+    for (int k = 0; k < 3; k++) {
+        b.lo[k] = (double)a[k] * q;
+        b.hi[k] = (double)(a[k] + len) * q;
+    }
+    b.hlen = ldexp(1.0, -(int)level);
+    return b;
+}
+
+/* Field evaluation context for one leaf. */
+typedef struct {
+    int kind;          /* 0: constant per leaf, 1: trilinear corners */
+    double kap[8], eps[8];
+} leaffield;
+
+/* Segment [s_in, s_out] of ray x(s) = rho + s r inside a leaf, integrated from
+ * the far end s_out toward the camera.  Returns (A,B) as dual numbers over the
+ * leaf's parameters: kappa corners 0..nc-1 then eps corners nc..2nc-1. */
+static void segment_dn(const leaffield *F, const leafbox *bx, const double *rho, const double *r,
+                       double rnorm, double s_in, double s_out, int method, int substeps, int np,
+                       dn *Aout, dn *Bout)
+{
+    int nc = F->kind ? 8 : 1;
+    if (method == 0) {
+        /* analytic: constant coefficients, eq. ABconstant */
+        dn beta = dn_c(F->kap[0], np), gamma = dn_c(F->eps[0], np);
+        if (np > 0) {
+            beta.d[0] = 1.0;
+            gamma.d[nc] = 1.0;
+        }
+        seg_const_dn(beta, gamma, (s_out - s_in) * rnorm, np, Aout, Bout);
+        return;
+    }
+    /* RK4 over `substeps` equal substeps, farthest first, combined with (+). */
+    double ds = (s_out - s_in) / substeps;
+    double h = ds * rnorm;
+    dn A = dn_c(1.0, np), B = dn_c(0.0, np);
+    for (int q = 0; q < substeps; q++) {
+        double s_far = s_out - q * ds;
+        double sp[4] = {s_far, s_far - 0.5 * ds, s_far - 0.5 * ds, s_far - ds};
+        dn beta[4], gamma[4];
+        for (int i = 0; i < 4; i++) {
+            double xi[3];
+            for (int k = 0; k < 3; k++) xi[k] = (rho[k] + sp[i] * r[k] - bx->lo[k]) / bx->hlen;
+            if (F->kind) {
+                beta[i] = trilin_dn(F->kap, xi, np, 0);
+                gamma[i] = trilin_dn(F->eps, xi, np, nc);
+            } else {
+                beta[i] = dn_c(F->kap[0], np);
+                gamma[i] = dn_c(F->eps[0], np);
+                if (np > 0) {
+                    beta[i].d[0] = 1.0;
+                    gamma[i].d[nc] = 1.0;
+                }
+            }
+        }
+        dn a, b;
+        rk4_step_dn(beta, gamma, h, np, &a, &b);
+        /* (A,B) <- (a,b) (+) (A,B): the new substep is nearer to the camera */
+        dn nA = dn_mul(a, A, np);
+        dn nB = dn_add(b, dn_mul(a, B, np), np);
+        A = nA;
+        B = nB;
+    }
+    *Aout = A;
+    *Bout = B;
+}
+
+/* ------------------------------------------------------------------------ */
+/* camera (Sec. 2.2) and the canonical visibility / pairing predicates      */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    double o[3], v[3], t[3], u[3], ell, zfar, bg;
+    int w, h, ortho;
+    /* derived */
+    double n, vh[3], sc, cx, cy, smin, smax;
+} orcam;
+
+static void cam_parse(const double *raw, orcam *c)
+{
+    for (int k = 0; k < 3; k++) {
+        c->o[k] = raw[k];
+        c->v[k] = raw[3 + k];
+        c->t[k] = raw[6 + k];
+        c->u[k] = raw[9 + k];
+    }
+    c->ell = raw[12];
+    c->zfar = raw[13];
+    c->w = (int)raw[14];
+    c->h = (int)raw[15];
+    c->ortho = raw[16] != 0.0;
+    c->bg = raw[17];
+    c->n = sqrt((c->v[0] * c->v[0] + c->v[1] * c->v[1]) + c->v[2] * c->v[2]);
+    for (int k = 0; k < 3; k++) c->vh[k] = c->v[k] / c->n;
+    c->sc = c->n / c->ell;
+    c->cx = (c->w - 1) / 2.0;
+    c->cy = (c->h - 1) / 2.0;
+    c->smin = c->ortho ? c->n : 1.0;
+    c->smax = c->ortho ? c->zfar : c->zfar / c->n;
+}
+
+/* extremes of a . (x - o) over the box [lo, hi] */
+static double box_dot_min(const double *a, const double *lo, const double *hi, const double *o)
+{
+    double s0 = a[0] * ((a[0] >= 0.0 ? lo[0] : hi[0]) - o[0]);
+    double s1 = a[1] * ((a[1] >= 0.0 ? lo[1] : hi[1]) - o[1]);
+    double s2 = a[2] * ((a[2] >= 0.0 ? lo[2] : hi[2]) - o[2]);
+    return (s0 + s1) + s2;
+}
+static double box_dot_max(const double *a, const double *lo, const double *hi, const double *o)
+{
+    double s0 = a[0] * ((a[0] >= 0.0 ? hi[0] : lo[0]) - o[0]);
+    double s1 = a[1] * ((a[1] >= 0.0 ? hi[1] : lo[1]) - o[1]);
+    double s2 = a[2] * ((a[2] >= 0.0 ? hi[2] : lo[2]) - o[2]);
+    return (s0 + s1) + s2;
+}
+
+/* Pixel interval [k0, k1] covered by camera-space extent [X0, X1] at clipped
+ * depths [Z0, Z1] (perspective) or directly (orthographic). */
+static void pixel_range(const orcam *c, double X0, double X1, double Z0, double Z1, double center,
+                        int npx, int *k0, int *k1)
+{
+    double p0, p1;
+    if (c->ortho) {
+        p0 = X0 / c->ell + center;
+        p1 = X1 / c->ell + center;
+    } else {
+        double q0 = (X0 >= 0.0) ? X0 / Z1 : X0 / Z0;
+        double q1 = (X1 >= 0.0) ? X1 / Z0 : X1 / Z1;
+        p0 = q0 * c->sc + center;
+        p1 = q1 * c->sc + center;
+    }
+    double a = ceil(p0), b = floor(p1);
+    if (a < 0.0) a = 0.0;
+    if (b > (double)(npx - 1)) b = (double)(npx - 1);
+    if (a > b) {
+        *k0 = 1;
+        *k1 = 0;
+    } else {
+        *k0 = (int)a;
+        *k1 = (int)b;
+    }
+}
+
+/* Pixel rectangle of a box: camera-aligned AABB (eq. camerageometry applied to
+ * the box), clipped to depth [n, f], projected to the image.  Returns 1 if the
+ * rectangle holds at least one pixel centre. */
+static int box_rect(const orcam *c, const double *lo, const double *hi, int *rect)
+{
+    double Z0 = box_dot_min(c->vh, lo, hi, c->o), Z1 = box_dot_max(c->vh, lo, hi, c->o);
+    rect[0] = 1;
+    rect[1] = 0;
+    rect[2] = 1;
+    rect[3] = 0;
+    if (Z1 < c->n || Z0 > c->zfar) return 0;
+    double Zc0 = Z0 < c->n ? c->n : Z0;
+    double Zc1 = Z1 > c->zfar ? c->zfar : Z1;
+    double X0 = box_dot_min(c->t, lo, hi, c->o), X1 = box_dot_max(c->t, lo, hi, c->o);
+    double Y0 = box_dot_min(c->u, lo, hi, c->o), Y1 = box_dot_max(c->u, lo, hi, c->o);
+    int i0, i1, j0, j1;
+    pixel_range(c, X0, X1, Zc0, Zc1, c->cx, c->w, &i0, &i1);
+    pixel_range(c, Y0, Y1, Zc0, Zc1, c->cy, c->h, &j0, &j1);
+    if (i0 > i1 || j0 > j1) return 0;
+    rect[0] = i0;
+    rect[1] = i1;
+    rect[2] = j0;
+    rect[3] = j1;
+    return 1;
+}
+
+/* Ray of pixel (i, j): x(s) = rho + s r (eq. ray; orthographic variant shifts the origin). */
+static void pixel_ray(const orcam *c, int i, int j, double *rho, double *r)
+{
+    double a = c->ell * ((double)i - c->cx);
+    double b = c->ell * ((double)j - c->cy);
+    for (int k = 0; k < 3; k++) {
+        double off = a * c->t[k] + b * c->u[k];
+        if (c->ortho) {
+            rho[k] = c->o[k] + off;
+            r[k] = c->vh[k];
+        } else {
+            rho[k] = c->o[k];
+            r[k] = c->v[k] + off;
+        }
+    }
+}
+
+/* Slab test of a ray against a box, clipped to [smin, smax].  Returns 1 on a
+ * hit of positive length.  Each face value enters through (face - rho) * inv,
+ * so boxes sharing a face share the crossing parameter bit for bit. */
+static int slab(const orcam *c, const double *rho, const double *r, const double *lo, const double *hi,
+                double *s_in, double *s_out)
+{
+    double a = c->smin, b = c->smax;
+    for (int k = 0; k < 3; k++) {
+        if (r[k] != 0.0) {
+            double inv = 1.0 / r[k];
+            double t0 = (lo[k] - rho[k]) * inv;
+            double t1 = (hi[k] - rho[k]) * inv;
+            double tmin = t0 < t1 ? t0 : t1, tmax = t0 < t1 ? t1 : t0;
+            if (tmin > a) a = tmin;
+            if (tmax < b) b = tmax;
+        } else if (!(rho[k] >= lo[k] && rho[k] < hi[k])) {
+            return 0;
+        }
+    }
+    *s_in = a;
+    *s_out = b;
+    return b > a;
+}
+
+static double ray_norm(const double *r)
+{
+    return sqrt((r[0] * r[0] + r[1] * r[1]) + r[2] * r[2]);
+}
+
+/* ------------------------------------------------------------------------ */
+/* exported: visibility                                                     */
+/* ------------------------------------------------------------------------ */
+
+/* Pixel rectangle of every leaf for every camera: rect[cam][leaf][4] =
+ * (i0, i1, j0, j1), empty as (1, 0, 1, 0).  Returns the number of visible pairs. */
+int64_t or_prune(int64_t n, const uint8_t *level, const uint32_t *x, const uint32_t *y, const uint32_t *z,
+                 int ncams, const double *cams, int32_t *rect)
+{
+    int64_t nvis = 0;
+    for (int ci = 0; ci < ncams; ci++) {
+        orcam c;
+        cam_parse(cams + 20 * ci, &c);
+        for (int64_t l = 0; l < n; l++) {
+            leafbox b = leaf_box(level[l], x[l], y[l], z[l]);
+            int rr[4];
+            nvis += box_rect(&c, b.lo, b.hi, rr);
+            for (int k = 0; k < 4; k++) rect[((int64_t)ci * n + l) * 4 + k] = rr[k];
+        }
+    }
+    return nvis;
+}
+
+/* Rectangle of an arbitrary node (level, anchor): used to pin nesting. */
+int or_node_rect(int level, uint32_t x, uint32_t y, uint32_t z, const double *cam, int32_t *rect)
+{
+    orcam c;
+    cam_parse(cam, &c);
+    leafbox b = leaf_box((uint8_t)level, x, y, z);
+    int rr[4];
+    int vis = box_rect(&c, b.lo, b.hi, rr);
+    for (int k = 0; k < 4; k++) rect[k] = rr[k];
+    return vis;
+}
+
+/* Pairing of the candidates of the listed leaves: for leaf list[m] and each
+ * pixel of its rectangle in row-major order, hit[q] in {0,1} and the interval
+ * (sio[2q], sio[2q+1]) (zeros on a miss).  Returns the number of candidates. */
+int64_t or_pairs(int64_t nlist, const int64_t *list, const uint8_t *level, const uint32_t *x,
+                 const uint32_t *y, const uint32_t *z, const double *cam, uint8_t *hit, double *sio,
+                 int64_t cap)
+{
+    orcam c;
+    cam_parse(cam, &c);
+    int64_t q = 0;
+    for (int64_t m = 0; m < nlist; m++) {
+        int64_t l = list[m];
+        leafbox b = leaf_box(level[l], x[l], y[l], z[l]);
+        int rr[4];
+        if (!box_rect(&c, b.lo, b.hi, rr)) continue;
+        for (int j = rr[2]; j <= rr[3]; j++)
+            for (int i = rr[0]; i <= rr[1]; i++) {
+                if (q < cap) {
+                    double rho[3], r[3], a = 0, bb = 0;
+                    pixel_ray(&c, i, j, rho, r);
+                    int h = slab(&c, rho, r, b.lo, b.hi, &a, &bb);
+                    hit[q] = (uint8_t)h;
+                    sio[2 * q] = h ? a : 0.0;
+                    sio[2 * q + 1] = h ? bb : 0.0;
+                }
+                q++;
+            }
+    }
+    return q;
+}
+
+/* ------------------------------------------------------------------------ */
+/* exported: rendering and gradients                                        */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int64_t pix;   /* selected-pixel index */
+    double s_in, s_out;
+    int64_t leaf;
+    double A, B;
+} orseg;
+
+static int seg_cmp(const void *pa, const void *pb)
+{
+    const orseg *a = (const orseg *)pa, *b = (const orseg *)pb;
+    if (a->pix != b->pix) return a->pix < b->pix ? -1 : 1;
+    if (a->s_in != b->s_in) return a->s_in < b->s_in ? -1 : 1;
+    if (a->s_out != b->s_out) return a->s_out < b->s_out ? -1 : 1;
+    return 0;
+}
+
+static void leaf_field(int kind, int64_t n, int64_t l, const double *kap, const double *eps, leaffield *F)
+{
+    F->kind = kind;
+    int nc = kind ? 8 : 1;
+    for (int c = 0; c < nc; c++) {
+        F->kap[c] = kap[(int64_t)c * n + l];
+        F->eps[c] = eps[(int64_t)c * n + l];
+    }
+}
+
+/* Gather all segments of the selected pixels (all pixels when npix_sel < 0). */
+static orseg *gather(const orcam *c, int64_t n, const uint8_t *level, const uint32_t *x, const uint32_t *y,
+                     const uint32_t *z, int64_t npix_sel, const int64_t *pix_sel, int64_t *nseg_out)
+{
+    int64_t W = c->w, H = c->h, P = W * H;
+    int64_t *selmap = NULL;
+    if (npix_sel >= 0) {
+        selmap = (int64_t *)malloc(sizeof(int64_t) * (size_t)P);
+        for (int64_t p = 0; p < P; p++) selmap[p] = -1;
+        for (int64_t q = 0; q < npix_sel; q++) selmap[pix_sel[q]] = q;
+    }
+    int64_t cap = 1 << 16, ns = 0;
+    orseg *segs = (orseg *)malloc(sizeof(orseg) * (size_t)cap);
+    for (int64_t l = 0; l < n; l++) {
+        leafbox b = leaf_box(level[l], x[l], y[l], z[l]);
+        int rr[4];
+        if (!box_rect(c, b.lo, b.hi, rr)) continue;
+        for (int j = rr[2]; j <= rr[3]; j++)
+            for (int i = rr[0]; i <= rr[1]; i++) {
+                int64_t p = (int64_t)j * W + i, ps = p;
+                if (selmap) {
+                    ps = selmap[p];
+                    if (ps < 0) continue;
+                }
+                double rho[3], r[3], a, bb;
+                pixel_ray(c, i, j, rho, r);
+                if (!slab(c, rho, r, b.lo, b.hi, &a, &bb)) continue;
+                if (ns == cap) {
+                    cap *= 2;
+                    segs = (orseg *)realloc(segs, sizeof(orseg) * (size_t)cap);
+                }
+                segs[ns].pix = ps;
+                segs[ns].s_in = a;
+                segs[ns].s_out = bb;
+                segs[ns].leaf = l;
+                ns++;
+            }
+    }
+    free(selmap);
+    qsort(segs, (size_t)ns, sizeof(orseg), seg_cmp);
+    *nseg_out = ns;
+    return segs;
+}
+
+static void selected_ij(const orcam *c, int64_t npix_sel, const int64_t *pix_sel, int64_t q, int *i, int *j)
+{
+    int64_t p = (npix_sel >= 0) ? pix_sel[q] : q;
+    *i = (int)(p % c->w);
+    *j = (int)(p / c->w);
+}
+
+/*
+ * Render one camera.  kap/eps: [nc][n] doubles (nc = 1 for kind 0, 8 for kind 1).
+ * method 0 = analytic (constant), 1 = RK4 over `substeps` substeps.
+ * Pixels: all (npix_sel < 0, outputs have w*h entries, row j = 0 at the bottom)
+ * or the listed pixel indices p = j*w + i (outputs have npix_sel entries).
+ * stats[0] = segments, stats[1] = overlaps beyond 1e-12 relative,
+ * stats[2] = candidates tested.  Returns 0.
+ */
+int or_render(int64_t n, const uint8_t *level, const uint32_t *x, const uint32_t *y, const uint32_t *z,
+              int kind, const double *kap, const double *eps, int method, int substeps, const double *cam,
+              int64_t npix_sel, const int64_t *pix_sel, double *Aout, double *Bout, double *Iout,
+              int32_t *nseg_pix, int64_t *stats)
+{
+    orcam c;
+    cam_parse(cam, &c);
+    int64_t npo = (npix_sel >= 0) ? npix_sel : (int64_t)c.w * c.h;
+    int64_t ns = 0;
+    orseg *segs = gather(&c, n, level, x, y, z, npix_sel, pix_sel, &ns);
+
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t k = 0; k < ns; k++) {
+        orseg *s = &segs[k];
+        int i, j;
+        selected_ij(&c, npix_sel, pix_sel, s->pix, &i, &j);
+        double rho[3], r[3];
+        pixel_ray(&c, i, j, rho, r);
+        leafbox b = leaf_box(level[s->leaf], x[s->leaf], y[s->leaf], z[s->leaf]);
+        leaffield F;
+        leaf_field(kind, n, s->leaf, kap, eps, &F);
+        dn A, B;
+        segment_dn(&F, &b, rho, r, ray_norm(r), s->s_in, s->s_out, method, substeps, 0, &A, &B);
+        s->A = A.v;
+        s->B = B.v;
+    }
+
+    int64_t overlaps = 0;
+    for (int64_t q = 0; q < npo; q++) {
+        Aout[q] = 1.0;
+        Bout[q] = 0.0;
+        if (nseg_pix) nseg_pix[q] = 0;
+    }
+    int64_t k = 0;
+    while (k < ns) {
+        int64_t q = segs[k].pix;
+        double acc[2] = {1.0, 0.0};
+        double prev_out = -INFINITY;
+        int cnt = 0;
+        for (; k < ns && segs[k].pix == q; k++) {
+            if (segs[k].s_in < prev_out - 1e-12 * fabs(prev_out)) overlaps++;
+            prev_out = segs[k].s_out;
+            double sg[2] = {segs[k].A, segs[k].B}, t[2];
+            or_combine(acc, sg, t); /* acc is nearer: acc (+) next */
+            acc[0] = t[0];
+            acc[1] = t[1];
+            cnt++;
+        }
+        Aout[q] = acc[0];
+        Bout[q] = acc[1];
+        if (nseg_pix) nseg_pix[q] = cnt;
+    }
+    for (int64_t q = 0; q < npo; q++) Iout[q] = Aout[q] * c.bg + Bout[q];
+    if (stats) {
+        stats[0] = ns;
+        stats[1] = overlaps;
+    }
+    free(segs);
+    return 0;
+}
+
+/*
+ * Gradient of a pixel loss: given g[p] = dL/dI_p for the selected pixels,
+ * accumulate dL/dkappa and dL/deps ([nc][n], overwritten) through
+ *   I = sum_k T_k B_k + T_{m+1} I_b,   T_k = prod_{j<k} A_j (front to back),
+ * so dI/dB_k = T_k and dI/dA_k = T_k J_k with J_k the intensity entering
+ * segment k from behind; segment derivatives come from dual numbers.
+ */
+int or_grad(int64_t n, const uint8_t *level, const uint32_t *x, const uint32_t *y, const uint32_t *z,
+            int kind, const double *kap, const double *eps, int method, int substeps, const double *cam,
+            int64_t npix_sel, const int64_t *pix_sel, const double *g, double *gk, double *ge)
+{
+    orcam c;
+    cam_parse(cam, &c);
+    int nc = kind ? 8 : 1, np = 2 * nc;
+    int64_t ns = 0;
+    orseg *segs = gather(&c, n, level, x, y, z, npix_sel, pix_sel, &ns);
+    for (int64_t q = 0; q < (int64_t)nc * n; q++) {
+        gk[q] = 0.0;
+        ge[q] = 0.0;
+    }
+    /* values */
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t k = 0; k < ns; k++) {
+        orseg *s = &segs[k];
+        int i, j;
+        selected_ij(&c, npix_sel, pix_sel, s->pix, &i, &j);
+        double rho[3], r[3];
+        pixel_ray(&c, i, j, rho, r);
+        leafbox b = leaf_box(level[s->leaf], x[s->leaf], y[s->leaf], z[s->leaf]);
+        leaffield F;
+        leaf_field(kind, n, s->leaf, kap, eps, &F);
+        dn A, B;
+        segment_dn(&F, &b, rho, r, ray_norm(r), s->s_in, s->s_out, method, substeps, 0, &A, &B);
+        s->A = A.v;
+        s->B = B.v;
+    }
+    /* per pixel: T (front product) and J (intensity from behind) per segment */
+    double *dIdA = (double *)malloc(sizeof(double) * (size_t)(ns > 0 ? ns : 1));
+    double *dIdB = (double *)malloc(sizeof(double) * (size_t)(ns > 0 ? ns : 1));
+    int64_t k = 0;
+    while (k < ns) {
+        int64_t k0 = k, q = segs[k].pix;
+        while (k < ns && segs[k].pix == q) k++;
+        double J = c.bg;
+        for (int64_t m = k - 1; m >= k0; m--) { /* back to front: J_m */
+            dIdA[m] = J;                        /* temporarily J_m */
+            J = segs[m].B + segs[m].A * J;
+        }
+        double T = 1.0;
+        for (int64_t m = k0; m < k; m++) {
+            double gp = g[q];
+            dIdA[m] = gp * T * dIdA[m];
+            dIdB[m] = gp * T;
+            T *= segs[m].A;
+        }
+    }
+    /* chain rule through each segment's dual numbers (serial accumulation) */
+    for (int64_t m = 0; m < ns; m++) {
+        orseg *s = &segs[m];
+        int i, j;
+        selected_ij(&c, npix_sel, pix_sel, s->pix, &i, &j);
+        double rho[3], r[3];
+        pixel_ray(&c, i, j, rho, r);
+        leafbox b = leaf_box(level[s->leaf], x[s->leaf], y[s->leaf], z[s->leaf]);
+        leaffield F;
+        leaf_field(kind, n, s->leaf, kap, eps, &F);
+        dn A, B;
+        segment_dn(&F, &b, rho, r, ray_norm(r), s->s_in, s->s_out, method, substeps, np, &A, &B);
+        for (int p = 0; p < nc; p++) {
+            gk[(int64_t)p * n + s->leaf] += dIdA[m] * A.d[p] + dIdB[m] * B.d[p];
+            ge[(int64_t)p * n + s->leaf] += dIdA[m] * A.d[nc + p] + dIdB[m] * B.d[nc + p];
+        }
+    }
+    free(dIdA);
+    free(dIdB);
+    free(segs);
+    return 0;
+}
+
+/* Value and gradient of one segment for a single leaf (exposed for pins):
+ * AB[2] and dAB[2][np] with np = 2 * nc. */
+int or_segment(int kind, const double *kap, const double *eps, uint8_t level, uint32_t x, uint32_t y,
+               uint32_t z, const double *rho, const double *r, double s_in, double s_out, int method,
+               int substeps, double *AB, double *dAB)
+{
+    leafbox b = leaf_box(level, x, y, z);
+    leaffield F;
+    F.kind = kind;
+    int nc = kind ? 8 : 1, np = 2 * nc;
+    for (int cc = 0; cc < nc; cc++) {
+        F.kap[cc] = kap[cc];
+        F.eps[cc] = eps[cc];
+    }
+    dn A, B;
+    segment_dn(&F, &b, rho, r, ray_norm(r), s_in, s_out, method, substeps, np, &A, &B);
+    AB[0] = A.v;
+    AB[1] = B.v;
+    if (dAB)
+        for (int p = 0; p < np; p++) {
+            dAB[p] = A.d[p];
+            dAB[np + p] = B.d[p];
+        }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* exported: brute-force marcher (independent of pairing and the fold)      */
+/* ------------------------------------------------------------------------ */
+
+/* Point location by scanning every leaf (tiny meshes only). */
+static int64_t locate(int64_t n, const uint8_t *level, const uint32_t *x, const uint32_t *y, const uint32_t *z,
+                      const double *p, leafbox *out)
+{
+    for (int64_t l = 0; l < n; l++) {
+        leafbox b = leaf_box(level[l], x[l], y[l], z[l]);
+        if (p[0] >= b.lo[0] && p[0] < b.hi[0] && p[1] >= b.lo[1] && p[1] < b.hi[1] && p[2] >= b.lo[2] &&
+            p[2] < b.hi[2]) {
+            *out = b;
+            return l;
+        }
+    }
+    return -1;
+}
+
+/*
+ * March every pixel's ray through the unit cube in M equal steps (midpoint
+ * rule): each step takes the coefficients at its midpoint as constant, uses
+ * eq. ABconstant, and is folded front to back.  Converges to the exact
+ * integral as M grows; shares neither pairing nor tree order with or_render.
+ */
+int or_march(int64_t n, const uint8_t *level, const uint32_t *x, const uint32_t *y, const uint32_t *z, int kind,
+             const double *kap, const double *eps, const double *cam, int M, double *Aout, double *Bout,
+             double *Iout)
+{
+    orcam c;
+    cam_parse(cam, &c);
+    double lo[3] = {0, 0, 0}, hi[3] = {1, 1, 1};
+    int64_t P = (int64_t)c.w * c.h;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t p = 0; p < P; p++) {
+        int i = (int)(p % c.w), j = (int)(p / c.w);
+        double rho[3], r[3], a, b;
+        pixel_ray(&c, i, j, rho, r);
+        double acc[2] = {1.0, 0.0};
+        if (slab(&c, rho, r, lo, hi, &a, &b)) {
+            double rn = ray_norm(r), ds = (b - a) / M;
+            for (int m = 0; m < M; m++) {
+                double sm = a + (m + 0.5) * ds, pt[3];
+                for (int k = 0; k < 3; k++) pt[k] = rho[k] + sm * r[k];
+                leafbox bx;
+                int64_t l = locate(n, level, x, y, z, pt, &bx);
+                if (l < 0) continue;
+                double kv, ev;
+                if (kind) {
+                    double xi[3], kc[8], ec[8];
+                    for (int k = 0; k < 3; k++) xi[k] = (pt[k] - bx.lo[k]) / bx.hlen;
+                    for (int cc = 0; cc < 8; cc++) {
+                        kc[cc] = kap[(int64_t)cc * n + l];
+                        ec[cc] = eps[(int64_t)cc * n + l];
+                    }
+                    kv = trilin_dn(kc, xi, 0, 0).v;
+                    ev = trilin_dn(ec, xi, 0, 0).v;
+                } else {
+                    kv = kap[l];
+                    ev = eps[l];
+                }
+                dn A, B;
+                seg_const_dn(dn_c(kv, 0), dn_c(ev, 0), ds * rn, 0, &A, &B);
+                double sg[2] = {A.v, B.v}, t[2];
+                or_combine(acc, sg, t);
+                acc[0] = t[0];
+                acc[1] = t[1];
+            }
+        }
+        Aout[p] = acc[0];
+        Bout[p] = acc[1];
+        Iout[p] = acc[0] * c.bg + acc[1];
+    }
+    return 0;
+}

@@ -1,0 +1,27 @@
+"""Seeded synthetic inputs for the forest-of-octrees raycaster.
+
+This package builds forests (leaves in space-filling-curve order), per-leaf
+coefficient fields and cameras.  It holds none of the rendering arithmetic:
+no ray intersection, no segment evaluation and no compositing.  Both the HIP
+path and the CPU oracle consume what it produces.
+"""
+
+from .scene import (  # noqa: F401
+    QMAX,
+    Camera,
+    Fields,
+    Forest,
+    Scene,
+    config_scene,
+    morton_keys,
+    orthographic_axis_camera,
+    perspective_camera,
+    random_perspective_camera,
+    small_scene,
+    uniform_forest,
+    adaptive_forest,
+    gaussian_sum,
+    perturb_fields,
+    trilinear_fields_from_gaussians,
+    constant_fields,
+)

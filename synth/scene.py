@@ -1,0 +1,369 @@
+"""Seeded generators for forests, fields and cameras.
+
+Conventions shared by every consumer (they are data formats, not method
+arithmetic):
+
+* Leaf anchors are integers in units of ``2**-QMAX`` of the tree's reference
+  cube; a leaf at level ``l`` spans ``2**(QMAX-l)`` units per axis.
+* Leaves are sorted tree-major, then by the Morton (z-order) key of the anchor,
+  with the x bit least significant in every bit triple.  Child and corner ids
+  follow the same convention: ``c = bx + 2*by + 4*bz``.
+* Fields are stored structure-of-arrays: ``kappa[corner][leaf]`` with one
+  corner for per-leaf constants and eight corners for trilinear data.
+* A camera is the paper's (o, v, t, u, ell, w, h) plus the far distance, an
+  orthographic flag and the background intensity.  ``raw()`` packs it into
+  the 20 doubles every interface takes.
+
+Seeds follow ``numpy.random.default_rng([1809, 1334, k])`` for workload k.
+"""
+
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional
+
+import numpy as np
+
+QMAX = 19  # deepest representable level; anchors fit in 19 bits per axis
+
+
+# ----------------------------------------------------------------------------
+# data holders
+# ----------------------------------------------------------------------------
+
+
+@dataclasses.dataclass
+class Forest:
+    level: np.ndarray  # uint8 [N]
+    x: np.ndarray  # uint32 [N]
+    y: np.ndarray  # uint32 [N]
+    z: np.ndarray  # uint32 [N]
+    tree_begin: np.ndarray  # int64 [ntrees + 1]
+    geom: str = "unit_cube"  # or "shell6"
+    geom_params: Optional[np.ndarray] = None  # float64, geometry-specific
+
+    @property
+    def nleaves(self) -> int:
+        return int(self.level.shape[0])
+
+    @property
+    def ntrees(self) -> int:
+        return int(self.tree_begin.shape[0] - 1)
+
+    def tree_of_leaf(self) -> np.ndarray:
+        t = np.zeros(self.nleaves, np.int32)
+        for k in range(self.ntrees):
+            t[self.tree_begin[k]:self.tree_begin[k + 1]] = k
+        return t
+
+
+@dataclasses.dataclass
+class Fields:
+    kind: str  # "const" or "trilinear"
+    kappa: np.ndarray  # float32 [ncorner][N]
+    eps: np.ndarray  # float32 [ncorner][N]
+
+    @property
+    def ncorner(self) -> int:
+        return int(self.kappa.shape[0])
+
+
+@dataclasses.dataclass
+class Camera:
+    o: np.ndarray
+    v: np.ndarray
+    t: np.ndarray
+    u: np.ndarray
+    ell: float
+    zfar: float
+    w: int
+    h: int
+    ortho: bool = False
+    background: float = 0.0
+
+    def raw(self) -> np.ndarray:
+        """The 20-double camera record: o, v, t, u, ell, zfar, w, h, ortho, I_b, 0, 0."""
+        r = np.zeros(20, np.float64)
+        r[0:3] = self.o
+        r[3:6] = self.v
+        r[6:9] = self.t
+        r[9:12] = self.u
+        r[12] = self.ell
+        r[13] = self.zfar
+        r[14] = self.w
+        r[15] = self.h
+        r[16] = 1.0 if self.ortho else 0.0
+        r[17] = self.background
+        return r
+
+    @property
+    def npix(self) -> int:
+        return int(self.w) * int(self.h)
+
+
+@dataclasses.dataclass
+class Scene:
+    name: str
+    forest: Forest
+    fields: Fields
+    cameras: List[Camera]
+    method: str  # "analytic" or "rk4"
+    substeps: int = 4
+    extra: dict = dataclasses.field(default_factory=dict)
+
+    def cams_raw(self) -> np.ndarray:
+        return np.stack([c.raw() for c in self.cameras]).astype(np.float64)
+
+
+# ----------------------------------------------------------------------------
+# forests
+# ----------------------------------------------------------------------------
+
+
+def morton_keys(x: np.ndarray, y: np.ndarray, z: np.ndarray) -> np.ndarray:
+    """Interleave anchor bits (x least significant) into a 57-bit key."""
+    x = x.astype(np.uint64)
+    y = y.astype(np.uint64)
+    z = z.astype(np.uint64)
+    key = np.zeros(x.shape, np.uint64)
+    one = np.uint64(1)
+    for b in range(QMAX):
+        bb = np.uint64(b)
+        key |= ((x >> bb) & one) << np.uint64(3 * b)
+        key |= ((y >> bb) & one) << np.uint64(3 * b + 1)
+        key |= ((z >> bb) & one) << np.uint64(3 * b + 2)
+    return key
+
+
+def _sorted_forest(level, x, y, z, tree=None, geom="unit_cube", geom_params=None, ntrees=1):
+    level = np.asarray(level, np.uint8)
+    x = np.asarray(x, np.uint32)
+    y = np.asarray(y, np.uint32)
+    z = np.asarray(z, np.uint32)
+    if tree is None:
+        tree = np.zeros(level.shape, np.int64)
+    key = morton_keys(x, y, z)
+    order = np.lexsort((key, tree))
+    tree = tree[order]
+    tb = np.searchsorted(tree, np.arange(ntrees + 1), side="left").astype(np.int64)
+    return Forest(level[order], x[order], y[order], z[order], tb, geom, geom_params)
+
+
+def uniform_forest(level: int) -> Forest:
+    n = 1 << level
+    g = np.arange(n, dtype=np.uint32) << np.uint32(QMAX - level)
+    zz, yy, xx = np.meshgrid(g, g, g, indexing="ij")
+    return _sorted_forest(np.full(n ** 3, level, np.uint8), xx.ravel(), yy.ravel(), zz.ravel())
+
+
+def gaussian_sum(p: np.ndarray, centers: np.ndarray, sigmas: np.ndarray) -> np.ndarray:
+    """Sum of unit-amplitude isotropic Gaussians at points p[..., 3]."""
+    s = np.zeros(p.shape[:-1], np.float64)
+    for c, sg in zip(centers, sigmas):
+        d2 = ((p - c) ** 2).sum(-1)
+        s += np.exp(-d2 / (2.0 * sg * sg))
+    return s
+
+
+def _lattice_offsets(m: int) -> np.ndarray:
+    g = np.linspace(0.0, 1.0, m)
+    zz, yy, xx = np.meshgrid(g, g, g, indexing="ij")
+    return np.stack([xx.ravel(), yy.ravel(), zz.ravel()], -1)  # [m^3, 3]
+
+
+def adaptive_forest(refine_fn, lmin: int, lmax: int, chunk: int = 1 << 15) -> Forest:
+    """Refine uniformly to ``lmin``, then split a leaf while ``refine_fn`` says so.
+
+    ``refine_fn(lo[n,3], h)`` receives leaf lower corners and the edge length
+    (in the unit cube) and returns a bool mask of leaves to split.
+    """
+    n0 = 1 << lmin
+    g = np.arange(n0, dtype=np.int64) << (QMAX - lmin)
+    zz, yy, xx = np.meshgrid(g, g, g, indexing="ij")
+    cur = np.stack([xx.ravel(), yy.ravel(), zz.ravel()], -1)
+    out_lv, out_xyz = [], []
+    scale = 1.0 / (1 << QMAX)
+    for lv in range(lmin, lmax + 1):
+        if lv == lmax or cur.shape[0] == 0:
+            out_lv.append(np.full(cur.shape[0], lv, np.uint8))
+            out_xyz.append(cur)
+            break
+        h = 1.0 / (1 << lv)
+        split = np.zeros(cur.shape[0], bool)
+        for a in range(0, cur.shape[0], chunk):
+            lo = cur[a:a + chunk].astype(np.float64) * scale
+            split[a:a + chunk] = refine_fn(lo, h)
+        out_lv.append(np.full(int((~split).sum()), lv, np.uint8))
+        out_xyz.append(cur[~split])
+        par = cur[split]
+        half = 1 << (QMAX - lv - 1)
+        kids = []
+        for c in range(8):
+            off = np.array([(c & 1) * half, ((c >> 1) & 1) * half, ((c >> 2) & 1) * half], np.int64)
+            kids.append(par + off)
+        cur = np.concatenate(kids, 0) if kids else np.zeros((0, 3), np.int64)
+    lv = np.concatenate(out_lv)
+    xyz = np.concatenate(out_xyz, 0)
+    return _sorted_forest(lv, xyz[:, 0], xyz[:, 1], xyz[:, 2])
+
+
+def straddle_refiner(centers, sigmas, thresh=0.2, lattice=3):
+    offs = _lattice_offsets(lattice)
+
+    def fn(lo, h):
+        pts = lo[:, None, :] + h * offs[None, :, :]
+        s = gaussian_sum(pts, centers, sigmas)
+        return (s.min(1) < thresh) & (s.max(1) > thresh)
+
+    return fn
+
+
+# ----------------------------------------------------------------------------
+# fields
+# ----------------------------------------------------------------------------
+
+
+def corner_points(forest: Forest) -> np.ndarray:
+    """Unit-cube positions of the 8 corners of every leaf: [8, N, 3]."""
+    scale = 1.0 / (1 << QMAX)
+    lo = np.stack([forest.x, forest.y, forest.z], -1).astype(np.float64) * scale
+    h = np.ldexp(1.0, -forest.level.astype(np.int64))
+    pts = np.empty((8, forest.nleaves, 3))
+    for c in range(8):
+        pts[c] = lo + h[:, None] * np.array([c & 1, (c >> 1) & 1, (c >> 2) & 1], np.float64)
+    return pts
+
+
+def constant_fields(kappa: np.ndarray, eps: np.ndarray) -> Fields:
+    return Fields("const", np.asarray(kappa, np.float32)[None, :].copy(),
+                  np.asarray(eps, np.float32)[None, :].copy())
+
+
+def trilinear_fields_from_gaussians(forest: Forest, centers, sigmas,
+                                    k0=0.2, k1=2.0, e0=0.1, e1=1.0) -> Fields:
+    """Linear transfer of the Gaussian sum at each leaf corner to (kappa, eps)."""
+    pts = corner_points(forest)
+    s = np.empty((8, forest.nleaves))
+    for c in range(8):
+        s[c] = gaussian_sum(pts[c], centers, sigmas)
+    return Fields("trilinear", (k0 + k1 * s).astype(np.float32), (e0 + e1 * s).astype(np.float32))
+
+
+def perturb_fields(fields: Fields, rng, sigma=0.05) -> Fields:
+    dk = rng.normal(0.0, sigma, fields.kappa.shape)
+    de = rng.normal(0.0, sigma, fields.eps.shape)
+    return Fields(fields.kind, (fields.kappa.astype(np.float64) + dk).astype(np.float32),
+                  (fields.eps.astype(np.float64) + de).astype(np.float32))
+
+
+# ----------------------------------------------------------------------------
+# cameras
+# ----------------------------------------------------------------------------
+
+
+def _unit(a):
+    a = np.asarray(a, np.float64)
+    return a / np.linalg.norm(a)
+
+
+def perspective_camera(eye, target, up, n, fov_deg, w, h, zfar, background=0.0) -> Camera:
+    """Camera at ``eye`` looking at ``target``; ell from the horizontal field of view."""
+    vh = _unit(np.asarray(target, np.float64) - np.asarray(eye, np.float64))
+    up = np.asarray(up, np.float64)
+    u = _unit(up - np.dot(up, vh) * vh)
+    t = np.cross(vh, u)  # left-handed frame: t x u = -vh
+    ell = 2.0 * n * math.tan(math.radians(fov_deg) / 2.0) / w
+    return Camera(np.asarray(eye, np.float64), n * vh, t, u, ell, float(zfar), int(w), int(h), False,
+                  float(background))
+
+
+def random_perspective_camera(rng, w, h, dist=2.5, center=(0.5, 0.5, 0.5), n=1.0, fov_deg=42.0,
+                              zfar=5.0, background=0.0) -> Camera:
+    d = _unit(rng.normal(size=3))
+    up = _unit(rng.normal(size=3))
+    if abs(np.dot(up, d)) > 0.99:
+        up = _unit(np.cross(d, [1.0, 0.0, 0.0]) + 0.1)
+    c = np.asarray(center, np.float64)
+    return perspective_camera(c + dist * d, c, up, n, fov_deg, w, h, zfar, background)
+
+
+def orthographic_axis_camera(axis: int, sign: int, w=64, h=64, ell=1.0 / 64, n=1.0, zfar=3.0,
+                             center=(0.5, 0.5, 0.5), background=0.0) -> Camera:
+    vh = np.zeros(3)
+    vh[axis] = float(sign)
+    u = np.zeros(3)
+    u[(axis + 1) % 3] = 1.0
+    t = np.cross(vh, u)
+    c = np.asarray(center, np.float64)
+    return Camera(c - 2.0 * vh, n * vh, t, u, float(ell), float(zfar), int(w), int(h), True,
+                  float(background))
+
+
+# ----------------------------------------------------------------------------
+# workloads
+# ----------------------------------------------------------------------------
+
+
+def _gaussians(rng, k, smin, smax):
+    centers = rng.uniform(0.0, 1.0, (k, 3))
+    sigmas = rng.uniform(smin, smax, k)
+    return centers, sigmas
+
+
+def small_scene(seed=0, lmin=2, lmax=5, ngauss=4, w=96, h=72, method="rk4", ncams=1,
+                background=0.0, sigma=(0.06, 0.2), ortho=False) -> Scene:
+    """A few-thousand-leaf adaptive scene the oracle renders in well under a second."""
+    rng = np.random.default_rng([1809, 1334, 1000 + seed])
+    centers, sigmas = _gaussians(rng, ngauss, *sigma)
+    forest = adaptive_forest(straddle_refiner(centers, sigmas), lmin, lmax)
+    if method == "analytic":
+        fields = constant_fields(rng.uniform(0.1, 2.0, forest.nleaves),
+                                 rng.uniform(0.0, 1.0, forest.nleaves))
+    else:
+        fields = trilinear_fields_from_gaussians(forest, centers, sigmas)
+    cams = []
+    for _ in range(ncams):
+        if ortho:
+            cams.append(orthographic_axis_camera(int(rng.integers(3)), int(rng.choice([-1, 1])),
+                                                 w=w, h=h, ell=1.4 / w, background=background))
+        else:
+            cams.append(random_perspective_camera(rng, w, h, background=background))
+    return Scene(f"small{seed}", forest, fields, cams, method, 4,
+                 {"centers": centers, "sigmas": sigmas})
+
+
+def config_scene(k: int, w: Optional[int] = None) -> Scene:
+    """The five seeded workloads.
+
+    1: uniform level-3 unit cube, per-leaf constants, 64x64 orthographic, analytic.
+    2: adaptive levels 4-9 (~1M leaves), trilinear, 1024^2 perspective, RK4 x 4.
+    3: six-tree spherical shell (not built by this generator yet).
+    4: the workload-2 forest seen by 64 cameras of uneven resolution.
+    5: a workload-2-shaped forest, 512^2, background 0.5, perturbed target fields.
+    """
+    rng = np.random.default_rng([1809, 1334, k])
+    if k == 1:
+        forest = uniform_forest(3)
+        kappa = rng.uniform(0.1, 2.0, forest.nleaves)
+        eps = rng.uniform(0.0, 1.0, forest.nleaves)
+        axis = int(rng.integers(3))
+        sign = int(rng.choice([-1, 1]))
+        cam = orthographic_axis_camera(axis, sign)
+        return Scene("config1", forest, constant_fields(kappa, eps), [cam], "analytic", 1,
+                     {"axis": axis, "sign": sign})
+    if k in (2, 4, 5):
+        centers, sigmas = _gaussians(rng, 8, 0.03, 0.1)
+        forest = adaptive_forest(straddle_refiner(centers, sigmas), 4, 9)
+        fields = trilinear_fields_from_gaussians(forest, centers, sigmas)
+        extra = {"centers": centers, "sigmas": sigmas}
+        if k == 2:
+            cams = [random_perspective_camera(rng, w or 1024, w or 1024)]
+        elif k == 4:
+            res = rng.choice([256, 512, 1024, 2048], size=64)
+            cams = [random_perspective_camera(rng, int(r), int(r)) for r in res]
+        else:
+            cams = [random_perspective_camera(rng, w or 512, w or 512, background=0.5)]
+            extra["target_fields"] = perturb_fields(fields, rng, 0.05)
+        return Scene(f"config{k}", forest, fields, cams, "rk4", 4, extra)
+    raise ValueError(f"workload {k} is not generated here")
