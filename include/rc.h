@@ -1,0 +1,233 @@
+/*
+ * rc.h -- C ABI of the MI355X forest-of-octrees raycasting library (librc.so).
+ *
+ * The library implements the per-view hot path of Burstedde's distributed
+ * forest-of-octrees raycaster for one process's share of the forest:
+ *   visibility (Sec. 3.1), ray segments per leaf (Sec. 2.3, 2.7, 3.2),
+ *   sort-free compositing by octree coarsening (Sec. 2.4, 3.3, 3.4) and the
+ *   adjoint of the rendered image with respect to the per-leaf coefficients.
+ *
+ * Conventions (every entry point):
+ *  - Pointers marked [device] are HIP device pointers owned by the caller;
+ *    [host] pointers are ordinary host memory.  The library never allocates
+ *    persistent device memory, never frees caller memory and keeps no pointer
+ *    after a call returns.
+ *  - `stream` is a hipStream_t passed as void*; NULL is the default stream.
+ *    Every call only enqueues work on `stream` and returns without waiting,
+ *    except rc_forest_index and rc_camera_prepare, which are set-up calls and
+ *    block until their work is done.
+ *  - Return value: RC_OK (0) or a negative rc_status; rc_strerror names it.
+ *    On an error return nothing has been enqueued.  Capacity overflows that
+ *    can only be detected on the device are reported through the device
+ *    status word counts[3] of the rc_vforest (see rc_prune_visible).
+ *  - Results are deterministic: no floating-point atomics are used, so
+ *    repeated calls on identical inputs give bitwise identical outputs.
+ *
+ * Geometry and ordering (Sec. 2.1, 3): a forest is a set of trees; each tree
+ * is the unit reference cube subdivided into leaves.  Leaves are given in
+ * space-filling-curve order: tree-major, then by the Morton key of the anchor
+ * (x bit least significant).  A leaf at level l with integer anchor (x, y, z)
+ * covers [x, x + 2^(19-l)) * 2^-19 per axis.  Child and corner ids are
+ * c = bx + 2 by + 4 bz.
+ *
+ * Camera (Sec. 2.2, eq. ray): 20 doubles
+ *   o[3] position, v[3] view vector (n = |v| is the projection-plane
+ *   distance), t[3] right, u[3] up (t, u, v/n orthonormal, t x u = -v/n),
+ *   ell pixel edge length on the projection plane, zfar far distance (> n),
+ *   w, h pixel counts, ortho flag (0 = perspective, 1 = orthographic along
+ *   v/n with the ray of pixel (i, j) starting at
+ *   o + ell((i-(w-1)/2) t + (j-(h-1)/2) u)), background intensity I_b, 0, 0.
+ *   The ray of pixel (i, j) is o + alpha r, r = v + ell((i-(w-1)/2) t +
+ *   (j-(h-1)/2) u), clipped to depths [n, zfar] (alpha in [1, zfar/n]).
+ *   Images are row-major [j][i] with j = 0 the bottom row.
+ */
+#ifndef RC_H
+#define RC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t rc_status;
+
+#define RC_OK 0
+#define RC_EINVAL (-1)        /* bad argument: null pointer, bad size, bad camera */
+#define RC_EUNSUPPORTED (-2)  /* unsupported geometry / field / integrator combination */
+#define RC_EWORKSPACE (-3)    /* workspace smaller than rc_workspace_bytes() */
+#define RC_ECAPACITY (-4)     /* a caller buffer is too small (host-detectable case) */
+#define RC_EFOREST (-5)       /* leaves not in SFC order or overlapping */
+#define RC_EHIP (-6)          /* a HIP runtime call failed */
+
+#define RC_QMAXLEVEL 19
+#define RC_CAMERA_DOUBLES 20
+#define RC_ABSENT (-1)        /* child slot without a node in this share */
+
+enum { RC_GEOM_UNIT_CUBE = 0 };
+enum { RC_FIELD_CONST = 0, RC_FIELD_TRILINEAR = 1 };
+enum { RC_INT_ANALYTIC = 0, RC_INT_RK4 = 1 };
+
+/* One process's share of a forest (Sec. 2.1): leaves in SFC order. */
+typedef struct rc_forest {
+    int32_t ntrees;             /* trees in the share (RC_GEOM_UNIT_CUBE: 1) */
+    int32_t geom;               /* RC_GEOM_UNIT_CUBE: identity map of the unit cube */
+    int64_t nleaves;            /* N >= 1 */
+    const int64_t *tree_begin;  /* [host] ntrees + 1 leaf offsets per tree */
+    const uint8_t *level;       /* [device] N leaf levels, 0 .. RC_QMAXLEVEL */
+    const uint32_t *x, *y, *z;  /* [device] N anchors in units of 2^-19 */
+} rc_forest;
+
+/* Per-leaf coefficient data (Sec. 2.3): absorption kappa (beta in the paper)
+ * and emission eps (gamma), single channel, structure of arrays
+ * [corner][leaf]: one corner for per-leaf constants, eight for trilinear data
+ * interpolated in leaf reference coordinates. */
+typedef struct rc_fields {
+    int32_t kind;               /* RC_FIELD_CONST or RC_FIELD_TRILINEAR */
+    int32_t nch;                /* channels; 1 */
+    const float *kappa;         /* [device] ncorner * N */
+    const float *eps;           /* [device] ncorner * N */
+} rc_fields;
+
+/* Segment integrator (Sec. 2.3, 2.7): closed form for constant coefficients,
+ * or `substeps` equal classical RK4 steps combined with the group operation. */
+typedef struct rc_integrator {
+    int32_t method;             /* RC_INT_ANALYTIC (needs RC_FIELD_CONST) or RC_INT_RK4 */
+    int32_t substeps;           /* RK4 substeps per segment, 1 .. 64 */
+} rc_integrator;
+
+/* Static node table of a forest share: the internal nodes above the leaves,
+ * level-major and in SFC order within a level.  Built by rc_forest_index.
+ * A child slot holds an internal node index (>= 0), RC_ABSENT, or a leaf
+ * l encoded as -2 - l. */
+typedef struct rc_index {
+    int32_t maxlevel;                       /* [out] deepest leaf level */
+    int32_t pad;
+    int64_t ninternal;                      /* [out] internal nodes (required capacity on RC_ECAPACITY) */
+    int64_t cap_internal;                   /* [in] capacity of the arrays below */
+    int64_t level_begin[RC_QMAXLEVEL + 2];  /* [out] internal nodes of level l: [level_begin[l], level_begin[l+1]) */
+    int32_t root;                           /* [out] root node of tree 0 (same encoding as a child slot) */
+    int32_t pad2;
+    int32_t *child;                         /* [device] cap_internal * 8 */
+    uint8_t *level;                         /* [device] cap_internal */
+    uint32_t *x, *y, *z;                    /* [device] cap_internal anchors */
+} rc_index;
+
+/* The visible forest ("vforest", Sec. 3.1) of a set of cameras, written by
+ * rc_prune_visible and read by the other calls.  Capacities are inputs. */
+typedef struct rc_vforest {
+    int64_t cap_vis;       /* capacity of the visible (camera, leaf) list */
+    int64_t cap_cand;      /* capacity of leaf candidate records (camera, leaf, pixel) */
+    int64_t cap_rec;       /* capacity of internal-node records (camera, node, pixel) */
+    int32_t *vis_leaf;     /* [device] cap_vis: leaf of visible pair v (camera-major, SFC order) */
+    int16_t *vis_cam;      /* [device] cap_vis: camera of pair v */
+    int16_t *vis_rect;     /* [device] cap_vis * 4: pixel rectangle i0, i1, j0, j1 (inclusive) */
+    int64_t *cand_offset;  /* [device] cap_vis + 1: first candidate of pair v; [nvis] = ncand */
+    int32_t *leaf_vis;     /* [device] ncams * N: pair index of (camera, leaf), -1 if invisible */
+    int16_t *node_rect;    /* [device] rc_node_slots() * 4: rectangle per (level >= 1, camera, node) */
+    int64_t *node_offset;  /* [device] rc_node_slots() + 1: first record per slot */
+    int64_t *counts;       /* [device] 4: nvis, ncand, nrec, status (nonzero = capacity exceeded) */
+} rc_vforest;
+
+/* Name of a status code. */
+const char *rc_strerror(rc_status s);
+
+/* Bytes of device workspace the calls need for this forest, index, camera
+ * count and (for rc_segments_backward) vforest capacities; index and vf may be
+ * NULL before they exist (rc_forest_index needs neither). */
+size_t rc_workspace_bytes(const rc_forest *forest, const rc_index *index, int32_t ncams, const rc_vforest *vf);
+
+/* Bytes of the device camera block for ncams cameras. */
+size_t rc_camera_bytes(int32_t ncams);
+
+/* Number of (level >= 1, camera, internal node) slots: sizes node_rect/node_offset. */
+int64_t rc_node_slots(const rc_index *index, int32_t ncams);
+
+/*
+ * Validate cams[ncams][20] [host] (Sec. 2.2: orthonormal left-handed frame,
+ * n > 0, zfar > n, ell > 0, w, h in 1 .. 32767) and upload them to dcams
+ * [device, rc_camera_bytes(ncams)] with the derived quantities (n, v/n, image
+ * offsets: camera k's pixels start at the sum of the earlier w*h).  Blocks.
+ * Returns RC_EINVAL on a bad camera.  *total_pixels receives the image size.
+ */
+rc_status rc_camera_prepare(const double *cams, int32_t ncams, void *dcams, int64_t *total_pixels,
+                            void *stream);
+
+/*
+ * Build the static node table of a forest share (the trees above the leaves,
+ * Sec. 2.1).  Validates that the leaves are in strict SFC order without
+ * overlap (RC_EFOREST otherwise).  If index->cap_internal is too small,
+ * returns RC_ECAPACITY with index->ninternal set to the required capacity.
+ * Blocks until done.
+ */
+rc_status rc_forest_index(const rc_forest *forest, rc_index *index, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Visibility and work partition (Sec. 3.1, Sec. 2.2 "our (2D) AABB"): for
+ * every (camera, leaf) and (camera, internal node) compute the pixel
+ * rectangle of the node's camera-aligned bounding box, clipped to [n, zfar]
+ * and projected to the image; a node is visible iff the rectangle holds a
+ * pixel centre.  Writes the compacted visible list in SFC order per camera
+ * (vis_*), the exclusive scan of rectangle areas (cand_offset, the visible
+ * pixel weight of the paper's repartition), leaf_vis, the internal-node
+ * rectangles and record offsets, and counts = {nvis, ncand, nrec, status}.
+ * If a count exceeds its capacity, status becomes nonzero and the later
+ * calls do nothing; the caller reads counts and retries with more room.
+ */
+rc_status rc_prune_visible(const rc_forest *forest, const rc_index *index, const void *dcams, int32_t ncams,
+                           rc_vforest *vf, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Ray segments of every candidate (Sec. 3.2): for each visible pair and each
+ * pixel of its rectangle, intersect the pixel's ray with the leaf (a slab test
+ * whose shared faces give bitwise equal crossing depths) and integrate
+ * I' = eps - kappa I over the hit interval from the far end toward the camera
+ * (eq. ABconstant, or RK4 per eq. RKresultAB over equal substeps combined by
+ * eq. aggregate).  rec_leaf[device, cap_cand * 2] receives (A, B) per
+ * candidate, the identity (1, 0) on a miss.  Optional debug outputs (NULL to
+ * skip): hit[device, cap_cand] 1/0 and sio[device, cap_cand * 2] the hit
+ * interval in the ray parameter (alpha for perspective, depth for
+ * orthographic), zeros on a miss.
+ */
+rc_status rc_segments(const rc_forest *forest, const rc_fields *fields, const void *dcams, int32_t ncams,
+                      const rc_vforest *vf, const rc_integrator *integ, float *rec_leaf, uint8_t *hit,
+                      double *sio, void *stream);
+
+/*
+ * Sort-free compositing (Sec. 2.4, 3.3): coarsen the octree level by level;
+ * the record of an internal node at a pixel is the group product of its
+ * children's records taken in the camera's view order (the Morton child id
+ * with every bit flipped where the camera lies on the high side of the
+ * node's midplane), absent or invisible children acting as the identity.
+ * The roots are folded straight into the images: A, B and I = A I_b + B
+ * [device, total_pixels floats each].  rec_node [device, cap_rec * 2] holds
+ * the internal-node records (kept for the adjoint).
+ */
+rc_status rc_composite(const rc_forest *forest, const rc_index *index, const void *dcams, int32_t ncams,
+                       const rc_vforest *vf, const float *rec_leaf, float *rec_node, int64_t total_pixels,
+                       float *A, float *B, float *I, void *stream);
+
+/*
+ * Adjoint of the images with respect to the coefficients.  Given
+ * dL_dI [device, total_pixels], pass (g T_front, J_behind) down the same
+ * hierarchy (T_front: transmittance in front of a node, J_behind: intensity
+ * entering it from behind; no division), so that a segment receives
+ * dL/dA = g T J and dL/dB = g T; then differentiate each segment's
+ * evaluation (recomputed from the coefficients) and reduce per leaf in a
+ * fixed order.  dL_dkappa, dL_deps [device, layout of rc_fields] are
+ * overwritten, or added to when accumulate != 0.  adj_leaf [device,
+ * cap_cand * 2] and adj_node [device, cap_rec * 2] are scratch.
+ */
+rc_status rc_segments_backward(const rc_forest *forest, const rc_index *index, const rc_fields *fields,
+                               const void *dcams, int32_t ncams, const rc_vforest *vf,
+                               const rc_integrator *integ, const float *rec_leaf, const float *rec_node,
+                               int64_t total_pixels, const float *dL_dI, float *adj_leaf, float *adj_node,
+                               float *dL_dkappa,
+                               float *dL_deps, int32_t accumulate, void *ws, size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RC_H */

@@ -1,0 +1,21 @@
+"""MI355X forest-of-octrees raycasting: visibility, ray segments, sort-free
+compositing and the adjoint, as hand-written HIP kernels behind the C ABI of
+include/rc.h (librc.so).  This package is the Python binding."""
+
+from ._lib import EXPORTS, LIB_PATH, RcError, lib  # noqa: F401
+from .render import (  # noqa: F401
+    DeviceCameras,
+    DeviceFields,
+    DeviceForest,
+    DeviceIndex,
+    RenderFn,
+    Renderer,
+    VForest,
+    rc_camera_prepare,
+    rc_composite,
+    rc_forest_index,
+    rc_prune_visible,
+    rc_segments,
+    rc_segments_backward,
+    render,
+)

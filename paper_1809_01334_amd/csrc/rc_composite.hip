@@ -1,0 +1,81 @@
+// rc_composite.hip -- sort-free compositing by octree coarsening (Sec. 3.3,
+// Sec. 2.4).  Level by level from the deepest, the record of an internal
+// node at a pixel is the group product of its children's records taken in
+// the camera's view order; children that are absent, invisible or whose
+// rectangle misses the pixel act as the identity (segments separated by
+// empty space may be combined, Sec. 2.4).  The tree roots are folded straight
+// into the images, where I = A I_b + B (Sec. 2.4, final intensity).
+#include "rc_composite.h"
+
+using namespace rc;
+
+namespace rc {
+namespace {
+
+__global__ __launch_bounds__(256) void k_fold_level(FoldCtx C, int l, float2* out) {
+    if (C.counts[3]) return;
+    int64_t s0 = C.L.slot_begin[l], s1 = C.L.slot_begin[l + 1];
+    int64_t R0 = C.node_offset[s0], R1 = C.node_offset[s1];
+    int64_t M = C.L.level_begin[l + 1] - C.L.level_begin[l];
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t g = R0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < R1; g += stride) {
+        int64_t slot = upper_index(C.node_offset, s0, s1, g);
+        int64_t loc = slot - s0;
+        int cam = (int)(loc / M);
+        int64_t m = C.L.level_begin[l] + (loc - (int64_t)cam * M);
+        Rect r = load_rect(C.node_rect + 4 * slot);
+        int k = (int)(g - C.node_offset[slot]);
+        int wr = r.width();
+        int j = r.j0 + k / wr;
+        int i = r.i0 + (k - (k / wr) * wr);
+        out[g] = fold_children(C, cam, m, l, i, j);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_fold_root(FoldCtx C, int32_t root, int64_t npix, float* A, float* B,
+                                                   float* I) {
+    if (C.counts[3]) return;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < npix; p += stride) {
+        int cam = camera_of_pixel(C.cams, C.ncams, p);
+        const Cam& c = C.cams[cam];
+        int64_t loc = p - c.img_off;
+        int j = (int)(loc / c.w);
+        int i = (int)(loc - (int64_t)j * c.w);
+        float2 acc = make_float2(1.0f, 0.0f);
+        if (root >= 0) {
+            acc = fold_children(C, cam, root, 0, i, j);
+        } else if (root <= -2) {
+            acc = child_record(C, cam, root, 0, i, j);
+        }
+        A[p] = acc.x;
+        B[p] = acc.y;
+        I[p] = fmaf(acc.x, (float)c.bg, acc.y);
+    }
+}
+
+}  // namespace
+}  // namespace rc
+
+extern "C" rc_status rc_composite(const rc_forest* f, const rc_index* ix, const void* dcams, int32_t ncams,
+                                  const rc_vforest* vf, const float* rec_leaf, float* rec_node, int64_t npix,
+                                  float* A, float* B, float* I, void* stream) {
+    rc_status s = check_forest(f);
+    if (s != RC_OK) return s;
+    if ((s = check_index(ix)) != RC_OK) return s;
+    if ((s = check_vforest(vf, ix->maxlevel >= 1)) != RC_OK) return s;
+    if (!dcams || ncams <= 0 || npix <= 0 || !rec_leaf || !A || !B || !I) return RC_EINVAL;
+    if (rc_node_slots(ix, ncams) > 0 && !rec_node) return RC_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    FoldCtx C = make_fold_ctx(f, ix, dcams, ncams, vf, rec_leaf, rec_node);
+    unsigned grid = stride_grid(vf->cap_rec, 256, 256 * 16);
+    for (int l = ix->maxlevel - 1; l >= 1; l--) {
+        if (ix->level_begin[l + 1] == ix->level_begin[l]) continue;
+        hipLaunchKernelGGL(k_fold_level, dim3(grid), dim3(256), 0, st, C, l, (float2*)rec_node);
+        RC_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_fold_root, dim3(stride_grid(npix, 256, 256 * 16)), dim3(256), 0, st, C, ix->root, npix, A,
+                       B, I);
+    RC_HIP(hipGetLastError());
+    return RC_OK;
+}

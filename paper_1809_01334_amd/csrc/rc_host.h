@@ -1,0 +1,93 @@
+// rc_host.h -- host-side helpers shared by the entry points of librc.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rc.h"
+
+namespace rc {
+
+constexpr int WAVE = 64;
+constexpr int GRAD_MAX = 16;  // 8 kappa + 8 eps corners per leaf
+
+inline size_t align_up(size_t b, size_t a = 256) { return (b + a - 1) / a * a; }
+
+// Workspace of rc_segments_backward: per-(wave chunk, visible pair) gradient
+// partials and per-visible-pair gradients.
+inline size_t backward_ws_bytes(int64_t cap_cand, int64_t cap_vis, int64_t ncams, int64_t N) {
+    (void)ncams;
+    (void)N;
+    int64_t nchunks = (cap_cand + WAVE - 1) / WAVE;
+    size_t partial = align_up((size_t)(nchunks + cap_vis + 1) * GRAD_MAX * sizeof(float));
+    size_t gvis = align_up((size_t)(cap_vis + 1) * GRAD_MAX * sizeof(float));
+    return partial + gvis;
+}
+
+#define RC_HIP(call)                                 \
+    do {                                             \
+        if ((call) != hipSuccess) return RC_EHIP;    \
+    } while (0)
+
+inline rc_status check_forest(const rc_forest* f) {
+    if (!f || f->nleaves < 1 || !f->level || !f->x || !f->y || !f->z) return RC_EINVAL;
+    if (f->geom != RC_GEOM_UNIT_CUBE) return RC_EUNSUPPORTED;
+    if (f->ntrees != 1) return RC_EUNSUPPORTED;
+    if (f->tree_begin && (f->tree_begin[0] != 0 || f->tree_begin[1] != f->nleaves)) return RC_EINVAL;
+    if (f->nleaves > (int64_t)0x7ffffffe) return RC_EUNSUPPORTED;
+    return RC_OK;
+}
+
+inline rc_status check_index(const rc_index* ix) {
+    if (!ix || !ix->child || !ix->level || !ix->x || !ix->y || !ix->z) return RC_EINVAL;
+    if (ix->maxlevel < 0 || ix->maxlevel > RC_QMAXLEVEL) return RC_EINVAL;
+    if (ix->ninternal > ix->cap_internal) return RC_ECAPACITY;
+    return RC_OK;
+}
+
+inline rc_status check_vforest(const rc_vforest* vf, bool need_nodes) {
+    if (!vf || !vf->vis_leaf || !vf->vis_cam || !vf->vis_rect || !vf->cand_offset || !vf->leaf_vis || !vf->counts)
+        return RC_EINVAL;
+    if (need_nodes && (!vf->node_rect || !vf->node_offset)) return RC_EINVAL;
+    if (vf->cap_vis < 0 || vf->cap_cand < 0 || vf->cap_rec < 0) return RC_EINVAL;
+    return RC_OK;
+}
+
+inline rc_status check_fields(const rc_fields* fl, const rc_integrator* in) {
+    if (!fl || !fl->kappa || !fl->eps || !in) return RC_EINVAL;
+    if (fl->nch != 1) return RC_EUNSUPPORTED;
+    if (fl->kind != RC_FIELD_CONST && fl->kind != RC_FIELD_TRILINEAR) return RC_EUNSUPPORTED;
+    if (in->method == RC_INT_ANALYTIC) {
+        if (fl->kind != RC_FIELD_CONST) return RC_EUNSUPPORTED;
+    } else if (in->method == RC_INT_RK4) {
+        if (in->substeps < 1 || in->substeps > 64) return RC_EINVAL;
+    } else {
+        return RC_EUNSUPPORTED;
+    }
+    return RC_OK;
+}
+
+// Slot layout of internal nodes of level >= 1: (level, camera, node).
+struct SlotLayout {
+    int64_t level_begin[RC_QMAXLEVEL + 2];
+    int64_t slot_begin[RC_QMAXLEVEL + 2];
+    int32_t maxlevel;
+    int32_t ncams;
+};
+
+inline SlotLayout make_layout(const rc_index* ix, int32_t ncams) {
+    SlotLayout L;
+    L.maxlevel = ix->maxlevel;
+    L.ncams = ncams;
+    for (int l = 0; l < RC_QMAXLEVEL + 2; l++) {
+        int ll = l <= ix->maxlevel ? l : ix->maxlevel;
+        L.level_begin[l] = ix->level_begin[ll];
+    }
+    for (int l = 0; l < RC_QMAXLEVEL + 2; l++) {
+        int ll = l < 1 ? 1 : l;
+        L.slot_begin[l] = (int64_t)ncams * (L.level_begin[ll] - L.level_begin[1]);
+    }
+    return L;
+}
+
+}  // namespace rc

@@ -1,0 +1,424 @@
+// rc_internal.h -- device-side building blocks of librc (gfx950).
+//
+// Geometry predicates here decide integers (visibility rectangles, hit or
+// miss), so they run in FP64 with floating-point contraction switched off and
+// with correctly rounded division: the same sequence of IEEE operations
+// always gives the same bits.  Segment values run in FP32.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rc.h"
+
+namespace rc {
+
+constexpr int QMAX = RC_QMAXLEVEL;
+constexpr double QSCALE = 1.0 / 524288.0;  // 2^-19, exact
+
+// Derived camera (Sec. 2.2), prepared on the host by rc_camera_prepare.
+struct Cam {
+    double o[3], v[3], t[3], u[3], vh[3];
+    double ell, n, zfar;
+    double sc;          // n / ell: projection-plane to pixel scale
+    double cx, cy;      // (w - 1) / 2, (h - 1) / 2
+    double smin, smax;  // ray-parameter clip range: [1, zfar / n] or [n, zfar]
+    double bg;          // background intensity I_b
+    int32_t w, h, ortho, pad;
+    int64_t img_off;    // first pixel of this camera in the concatenated images
+};
+
+struct Rect {
+    int i0, i1, j0, j1;
+    __device__ __host__ bool empty() const { return i0 > i1 || j0 > j1; }
+    __device__ __host__ int width() const { return i1 - i0 + 1; }
+    __device__ __host__ int64_t area() const { return empty() ? 0 : (int64_t)(i1 - i0 + 1) * (j1 - j0 + 1); }
+    __device__ __host__ bool contains(int i, int j) const { return i >= i0 && i <= i1 && j >= j0 && j <= j1; }
+};
+
+__device__ inline Rect load_rect(const int16_t* r4) {
+    // one 64-bit load of four int16
+    uint64_t bits = *reinterpret_cast<const uint64_t*>(r4);
+    Rect r;
+    r.i0 = (int16_t)(bits & 0xffff);
+    r.i1 = (int16_t)((bits >> 16) & 0xffff);
+    r.j0 = (int16_t)((bits >> 32) & 0xffff);
+    r.j1 = (int16_t)((bits >> 48) & 0xffff);
+    return r;
+}
+
+__device__ inline void store_rect(int16_t* r4, const Rect& r) {
+    uint64_t bits = (uint64_t)(uint16_t)r.i0 | ((uint64_t)(uint16_t)r.i1 << 16) |
+                    ((uint64_t)(uint16_t)r.j0 << 32) | ((uint64_t)(uint16_t)r.j1 << 48);
+    *reinterpret_cast<uint64_t*>(r4) = bits;
+}
+
+// Box of a node in the unit cube: exact dyadic values.
+__device__ inline void node_box(int level, uint32_t x, uint32_t y, uint32_t z, double lo[3], double hi[3]) {
+    uint32_t len = 1u << (QMAX - level);
+    lo[0] = (double)x * QSCALE;
+    lo[1] = (double)y * QSCALE;
+    lo[2] = (double)z * QSCALE;
+    hi[0] = (double)(x + len) * QSCALE;
+    hi[1] = (double)(y + len) * QSCALE;
+    hi[2] = (double)(z + len) * QSCALE;
+}
+
+// ---------------------------------------------------------------------------
+// canonical visibility rectangle (Sec. 2.2: camera-aligned AABB of the box,
+// projected to the image).  Every operation is monotone, so a child's
+// rectangle lies inside its parent's bit for bit.
+// ---------------------------------------------------------------------------
+
+__device__ inline double extent_lo(const double a[3], const double lo[3], const double hi[3], const double o[3]) {
+#pragma clang fp contract(off)
+    double p0 = a[0] * ((a[0] >= 0.0 ? lo[0] : hi[0]) - o[0]);
+    double p1 = a[1] * ((a[1] >= 0.0 ? lo[1] : hi[1]) - o[1]);
+    double p2 = a[2] * ((a[2] >= 0.0 ? lo[2] : hi[2]) - o[2]);
+    return (p0 + p1) + p2;
+}
+
+__device__ inline double extent_hi(const double a[3], const double lo[3], const double hi[3], const double o[3]) {
+#pragma clang fp contract(off)
+    double p0 = a[0] * ((a[0] >= 0.0 ? hi[0] : lo[0]) - o[0]);
+    double p1 = a[1] * ((a[1] >= 0.0 ? hi[1] : lo[1]) - o[1]);
+    double p2 = a[2] * ((a[2] >= 0.0 ? hi[2] : lo[2]) - o[2]);
+    return (p0 + p1) + p2;
+}
+
+__device__ inline void axis_pixels(const Cam& c, double e0, double e1, double z0, double z1, double ctr, int npx,
+                                   int& k0, int& k1) {
+#pragma clang fp contract(off)
+    double p0, p1;
+    if (c.ortho) {
+        p0 = e0 / c.ell + ctr;
+        p1 = e1 / c.ell + ctr;
+    } else {
+        double q0 = (e0 >= 0.0) ? e0 / z1 : e0 / z0;
+        double q1 = (e1 >= 0.0) ? e1 / z0 : e1 / z1;
+        p0 = q0 * c.sc + ctr;
+        p1 = q1 * c.sc + ctr;
+    }
+    double a = ceil(p0);
+    double b = floor(p1);
+    if (a < 0.0) a = 0.0;
+    if (b > (double)(npx - 1)) b = (double)(npx - 1);
+    if (a > b) {
+        k0 = 1;
+        k1 = 0;
+    } else {
+        k0 = (int)a;
+        k1 = (int)b;
+    }
+}
+
+__device__ inline Rect box_rect(const Cam& c, const double lo[3], const double hi[3]) {
+    Rect r{1, 0, 1, 0};
+    double z0 = extent_lo(c.vh, lo, hi, c.o);
+    double z1 = extent_hi(c.vh, lo, hi, c.o);
+    if (z1 < c.n || z0 > c.zfar) return r;
+    double zc0 = z0 < c.n ? c.n : z0;
+    double zc1 = z1 > c.zfar ? c.zfar : z1;
+    double x0 = extent_lo(c.t, lo, hi, c.o), x1 = extent_hi(c.t, lo, hi, c.o);
+    double y0 = extent_lo(c.u, lo, hi, c.o), y1 = extent_hi(c.u, lo, hi, c.o);
+    Rect q;
+    axis_pixels(c, x0, x1, zc0, zc1, c.cx, c.w, q.i0, q.i1);
+    axis_pixels(c, y0, y1, zc0, zc1, c.cy, c.h, q.j0, q.j1);
+    if (q.empty()) return r;
+    return q;
+}
+
+// ---------------------------------------------------------------------------
+// pixel ray (eq. ray) and the slab test against a box
+// ---------------------------------------------------------------------------
+
+__device__ inline void pixel_ray(const Cam& c, int i, int j, double rho[3], double r[3]) {
+#pragma clang fp contract(off)
+    double a = c.ell * ((double)i - c.cx);
+    double b = c.ell * ((double)j - c.cy);
+    for (int k = 0; k < 3; k++) {
+        double off = a * c.t[k] + b * c.u[k];
+        if (c.ortho) {
+            rho[k] = c.o[k] + off;
+            r[k] = c.vh[k];
+        } else {
+            rho[k] = c.o[k];
+            r[k] = c.v[k] + off;
+        }
+    }
+}
+
+// Hit interval of the ray in the box, clipped to [smin, smax].  A face enters
+// as (face - rho) * (1 / r_k), so two boxes sharing a face produce the same
+// crossing parameter; a ray parallel to a slab is inside iff lo <= rho < hi.
+__device__ inline bool slab_hit(const Cam& c, const double rho[3], const double r[3], const double lo[3],
+                                const double hi[3], double& s_in, double& s_out) {
+#pragma clang fp contract(off)
+    double a = c.smin, b = c.smax;
+    bool ok = true;
+    for (int k = 0; k < 3; k++) {
+        if (r[k] != 0.0) {
+            double inv = 1.0 / r[k];
+            double t0 = (lo[k] - rho[k]) * inv;
+            double t1 = (hi[k] - rho[k]) * inv;
+            double tmin = t0 < t1 ? t0 : t1;
+            double tmax = t0 < t1 ? t1 : t0;
+            if (tmin > a) a = tmin;
+            if (tmax < b) b = tmax;
+        } else if (!(rho[k] >= lo[k] && rho[k] < hi[k])) {
+            ok = false;
+        }
+    }
+    s_in = a;
+    s_out = b;
+    return ok && (b > a);
+}
+
+// View order of a node's children: child c is visited at position c ^ bits,
+// bit k set when the camera lies on the high side of the node's k-midplane
+// (orthographic: when the view direction points toward decreasing k).
+__device__ inline int view_bits(const Cam& c, int level, uint32_t x, uint32_t y, uint32_t z) {
+    if (c.ortho) return (c.vh[0] < 0.0 ? 1 : 0) | (c.vh[1] < 0.0 ? 2 : 0) | (c.vh[2] < 0.0 ? 4 : 0);
+    uint32_t half = 1u << (QMAX - level - 1);
+    double m0 = (double)(x + half) * QSCALE;
+    double m1 = (double)(y + half) * QSCALE;
+    double m2 = (double)(z + half) * QSCALE;
+    return (c.o[0] >= m0 ? 1 : 0) | (c.o[1] >= m1 ? 2 : 0) | (c.o[2] >= m2 ? 4 : 0);
+}
+
+// ---------------------------------------------------------------------------
+// segment group (eq. aggregate): near (+) far
+// ---------------------------------------------------------------------------
+
+__device__ inline float2 seg_combine(float2 near2, float2 far1) {
+    return make_float2(near2.x * far1.x, fmaf(near2.x, far1.y, near2.y));
+}
+
+// ---------------------------------------------------------------------------
+// segment evaluation in FP32
+// ---------------------------------------------------------------------------
+
+// Geometry of one hit: reference coordinates at the far end, their change to
+// the near end, and the real length dx (Sec. 2.3: x runs far -> near).
+struct SegGeom {
+    float xf[3];
+    float dxi[3];
+    float dx;
+};
+
+__device__ inline SegGeom seg_geom(const double rho[3], const double r[3], double s_in, double s_out,
+                                   const double lo[3], int level) {
+    SegGeom g;
+    double scale = (double)(1u << level);
+    for (int k = 0; k < 3; k++) {
+        double pf = rho[k] + s_out * r[k];
+        g.xf[k] = (float)((pf - lo[k]) * scale);
+        g.dxi[k] = (float)((s_in - s_out) * r[k] * scale);
+    }
+    double rn = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    g.dx = (float)((s_out - s_in) * rn);
+    return g;
+}
+
+// Trilinear interpolation, corner c = bx + 2 by + 4 bz.
+__device__ inline float trilin(const float v[8], float x, float y, float z) {
+    float c00 = fmaf(x, v[1] - v[0], v[0]);
+    float c10 = fmaf(x, v[3] - v[2], v[2]);
+    float c01 = fmaf(x, v[5] - v[4], v[4]);
+    float c11 = fmaf(x, v[7] - v[6], v[6]);
+    float c0 = fmaf(y, c10 - c00, c00);
+    float c1 = fmaf(y, c11 - c01, c01);
+    return fmaf(z, c1 - c0, c0);
+}
+
+// One classical RK4 step of eq. ODEsAB from (A, B) = (1, 0) over length h with
+// the stage values of eq. RKresultAB; b0/g0 at the far end, bm/gm at the
+// midpoint (stages 1 and 2), b1/g1 at the near end.
+__device__ inline float2 rk4_step(float b0, float bm, float b1, float g0, float gm, float g1, float h) {
+    float hh = 0.5f * h;
+    float A1 = fmaf(-hh, b0, 1.0f);
+    float A2 = fmaf(-hh * bm, A1, 1.0f);
+    float A3 = fmaf(-h * bm, A2, 1.0f);
+    float sa = fmaf(b1, A3, fmaf(2.0f * bm, A1 + A2, b0));
+    float A = fmaf(-h * (1.0f / 6.0f), sa, 1.0f);
+    float B1 = hh * g0;
+    float f1 = fmaf(-bm, B1, gm);
+    float B2 = hh * f1;
+    float f2 = fmaf(-bm, B2, gm);
+    float B3 = h * f2;
+    float f3 = fmaf(-b1, B3, g1);
+    float sb = fmaf(2.0f, f1 + f2, g0 + f3);
+    float B = h * (1.0f / 6.0f) * sb;
+    return make_float2(A, B);
+}
+
+// RK4 over `nsub` equal substeps, farthest first, combined with (+).
+__device__ inline float2 seg_rk4(const float kc[8], const float ec[8], const SegGeom& g, int nsub) {
+    float inv = 1.0f / (float)nsub;
+    float h = g.dx * inv;
+    float xa = g.xf[0], ya = g.xf[1], za = g.xf[2];
+    float kf = trilin(kc, xa, ya, za), ef = trilin(ec, xa, ya, za);
+    float2 acc = make_float2(1.0f, 0.0f);
+    for (int q = 0; q < nsub; q++) {
+        float tm = ((float)q + 0.5f) * inv, tn = (float)(q + 1) * inv;
+        float xm = fmaf(tm, g.dxi[0], xa), ym = fmaf(tm, g.dxi[1], ya), zm = fmaf(tm, g.dxi[2], za);
+        float xn = fmaf(tn, g.dxi[0], xa), yn = fmaf(tn, g.dxi[1], ya), zn = fmaf(tn, g.dxi[2], za);
+        float km = trilin(kc, xm, ym, zm), em = trilin(ec, xm, ym, zm);
+        float kn = trilin(kc, xn, yn, zn), en = trilin(ec, xn, yn, zn);
+        float2 s = rk4_step(kf, km, kn, ef, em, en, h);
+        acc = seg_combine(s, acc);
+        kf = kn;
+        ef = en;
+    }
+    return acc;
+}
+
+// Constant coefficients (eq. ABconstant): A = e^{-k dx}, B = e dx (1 - A)/(k dx).
+__device__ inline float2 seg_const(float k, float e, float dx) {
+    float x = k * dx;
+    float A = expf(-x);
+    float phi = (fabsf(x) < 1e-4f) ? fmaf(x, fmaf(x, 1.0f / 6.0f, -0.5f), 1.0f) : -expm1f(-x) / x;
+    return make_float2(A, e * dx * phi);
+}
+
+// ---------------------------------------------------------------------------
+// searches
+// ---------------------------------------------------------------------------
+
+// Largest s in [lo, hi) with off[s] <= g, for nondecreasing off and off[lo] <= g.
+__device__ inline int64_t upper_index(const int64_t* off, int64_t lo, int64_t hi, int64_t g) {
+    while (hi - lo > 1) {
+        int64_t mid = (lo + hi) >> 1;
+        if (off[mid] <= g)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// Camera of a pixel in the concatenated images.
+__device__ inline int camera_of_pixel(const Cam* cams, int ncams, int64_t p) {
+    int lo = 0, hi = ncams;
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (cams[mid].img_off <= p)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------------------
+// device-wide exclusive scan (reduce, scan of block sums, re-scan and apply);
+// deterministic and independent of timing.
+// ---------------------------------------------------------------------------
+
+constexpr int SCAN_NT = 256;
+constexpr int SCAN_ITEMS = 16;
+constexpr int64_t SCAN_CHUNK = (int64_t)SCAN_NT * SCAN_ITEMS;
+
+struct I64x2 {
+    int64_t a, b;
+    __device__ __host__ I64x2 operator+(const I64x2& o) const { return I64x2{a + o.a, b + o.b}; }
+};
+
+template <typename T, int NT>
+__device__ inline T block_exclusive_scan(T v, T* sh, T& total) {
+    int tid = threadIdx.x;
+    sh[tid] = v;
+    __syncthreads();
+    for (int off = 1; off < NT; off <<= 1) {
+        T t = (tid >= off) ? sh[tid - off] : T();
+        __syncthreads();
+        if (tid >= off) sh[tid] = sh[tid] + t;
+        __syncthreads();
+    }
+    total = sh[NT - 1];
+    T ex = (tid > 0) ? sh[tid - 1] : T();
+    __syncthreads();
+    return ex;
+}
+
+// Src: __device__ Item operator()(int64_t i) with member `T val`.
+template <typename T, typename Src>
+__global__ __launch_bounds__(SCAN_NT) void k_scan_reduce(int64_t n, Src src, T* partial) {
+    __shared__ T sh[SCAN_NT];
+    int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK + (int64_t)threadIdx.x * SCAN_ITEMS;
+    T acc = T();
+    for (int k = 0; k < SCAN_ITEMS; k++) {
+        int64_t i = base + k;
+        if (i < n) acc = acc + src(i).val;
+    }
+    T total;
+    block_exclusive_scan<T, SCAN_NT>(acc, sh, total);
+    if (threadIdx.x == 0) partial[blockIdx.x] = total;
+}
+
+// Single block: partial[0..nb) -> exclusive prefix, partial[nb] = total.
+template <typename T>
+__global__ __launch_bounds__(SCAN_NT) void k_scan_partials(int64_t nb, T* partial) {
+    __shared__ T sh[SCAN_NT];
+    T carry = T();
+    for (int64_t base = 0; base < nb; base += SCAN_NT) {
+        int64_t i = base + threadIdx.x;
+        T v = (i < nb) ? partial[i] : T();
+        T total;
+        T ex = block_exclusive_scan<T, SCAN_NT>(v, sh, total);
+        if (i < nb) partial[i] = carry + ex;
+        carry = carry + total;
+    }
+    if (threadIdx.x == 0) partial[nb] = carry;
+}
+
+// Dst: __device__ void operator()(int64_t i, T prefix, const Item& item) and
+//      __device__ void total(T tot)  (called once, by the last block).
+template <typename T, typename Src, typename Dst>
+__global__ __launch_bounds__(SCAN_NT) void k_scan_apply(int64_t n, int64_t nb, Src src, Dst dst, const T* partial) {
+    __shared__ T sh[SCAN_NT];
+    int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK + (int64_t)threadIdx.x * SCAN_ITEMS;
+    T acc = T();
+    for (int k = 0; k < SCAN_ITEMS; k++) {
+        int64_t i = base + k;
+        if (i < n) acc = acc + src(i).val;
+    }
+    T total;
+    T run = partial[blockIdx.x] + block_exclusive_scan<T, SCAN_NT>(acc, sh, total);
+    for (int k = 0; k < SCAN_ITEMS; k++) {
+        int64_t i = base + k;
+        if (i < n) {
+            auto item = src(i);
+            dst(i, run, item);
+            run = run + item.val;
+        }
+    }
+    if (blockIdx.x == nb - 1 && threadIdx.x == 0) dst.total(partial[nb]);
+}
+
+template <typename T, typename Src, typename Dst>
+inline hipError_t launch_scan(int64_t n, Src src, Dst dst, T* partial, hipStream_t st) {
+    int64_t nb = (n + SCAN_CHUNK - 1) / SCAN_CHUNK;
+    if (nb < 1) nb = 1;
+    hipLaunchKernelGGL((k_scan_reduce<T, Src>), dim3((unsigned)nb), dim3(SCAN_NT), 0, st, n, src, partial);
+    hipLaunchKernelGGL((k_scan_partials<T>), dim3(1), dim3(SCAN_NT), 0, st, nb, partial);
+    hipLaunchKernelGGL((k_scan_apply<T, Src, Dst>), dim3((unsigned)nb), dim3(SCAN_NT), 0, st, n, nb, src, dst,
+                       (const T*)partial);
+    return hipGetLastError();
+}
+
+inline size_t scan_partial_bytes(int64_t n, size_t elem) {
+    int64_t nb = (n + SCAN_CHUNK - 1) / SCAN_CHUNK;
+    if (nb < 1) nb = 1;
+    return (size_t)(nb + 1) * elem;
+}
+
+// Grid for a grid-stride kernel over at most `n` items.
+inline unsigned stride_grid(int64_t n, int nt, unsigned maxblocks = 256 * 16) {
+    int64_t b = (n + nt - 1) / nt;
+    if (b < 1) b = 1;
+    if (b > (int64_t)maxblocks) b = maxblocks;
+    return (unsigned)b;
+}
+
+}  // namespace rc

@@ -1,0 +1,330 @@
+"""Python binding of librc: device buffers (torch) plus calls under the C
+names of include/rc.h, and a Renderer that sequences them for one forest and
+a set of cameras.  torch supplies device memory and streams only; every step
+of the path runs in librc's kernels."""
+
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def _stream(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _empty(n, dtype, device):
+    return torch.empty(max(int(n), 1), dtype=dtype, device=device)
+
+
+# ---------------------------------------------------------------------------- device data
+
+
+class DeviceForest:
+    """Leaves of one forest share on the device (SFC order, unit-cube geometry)."""
+
+    def __init__(self, level, x, y, z, device, tree_begin=None):
+        self.device = torch.device(device)
+        self.nleaves = int(len(level))
+        self.level = torch.from_numpy(np.ascontiguousarray(level, np.uint8)).to(self.device)
+        self.x = torch.from_numpy(np.ascontiguousarray(x, np.uint32).view(np.int32)).to(self.device)
+        self.y = torch.from_numpy(np.ascontiguousarray(y, np.uint32).view(np.int32)).to(self.device)
+        self.z = torch.from_numpy(np.ascontiguousarray(z, np.uint32).view(np.int32)).to(self.device)
+        tb = np.array([0, self.nleaves], np.int64) if tree_begin is None else np.asarray(tree_begin, np.int64)
+        self.tree_begin = np.ascontiguousarray(tb)
+        self.struct = L.RcForest(int(len(tb) - 1), L.RC_GEOM_UNIT_CUBE, self.nleaves,
+                                 self.tree_begin.ctypes.data_as(ctypes.c_void_p), _ptr(self.level), _ptr(self.x),
+                                 _ptr(self.y), _ptr(self.z))
+
+    @classmethod
+    def from_synth(cls, forest, device):
+        return cls(forest.level, forest.x, forest.y, forest.z, device, forest.tree_begin)
+
+
+class DeviceFields:
+    def __init__(self, kappa: torch.Tensor, eps: torch.Tensor):
+        assert kappa.shape == eps.shape and kappa.dim() == 2 and kappa.shape[0] in (1, 8)
+        self.kappa = kappa.contiguous()
+        self.eps = eps.contiguous()
+        self.kind = L.RC_FIELD_TRILINEAR if kappa.shape[0] == 8 else L.RC_FIELD_CONST
+        self.struct = L.RcFields(self.kind, 1, _ptr(self.kappa), _ptr(self.eps))
+
+    @classmethod
+    def from_synth(cls, fields, device):
+        return cls(torch.from_numpy(np.ascontiguousarray(fields.kappa, np.float32)).to(device),
+                   torch.from_numpy(np.ascontiguousarray(fields.eps, np.float32)).to(device))
+
+
+class DeviceCameras:
+    def __init__(self, cams_raw: np.ndarray, device):
+        self.device = torch.device(device)
+        self.raw = np.ascontiguousarray(np.atleast_2d(cams_raw), np.float64)
+        self.ncams = int(self.raw.shape[0])
+        self.buf = torch.empty(int(L.lib().rc_camera_bytes(self.ncams)), dtype=torch.uint8, device=self.device)
+        self.npix = 0
+        self.wh = [(int(r[14]), int(r[15])) for r in self.raw]
+        off = np.cumsum([0] + [w * h for w, h in self.wh])
+        self.img_off = off.astype(np.int64)
+
+    def image(self, t: torch.Tensor, k: int) -> torch.Tensor:
+        w, h = self.wh[k]
+        return t[self.img_off[k]:self.img_off[k + 1]].view(h, w)
+
+
+class DeviceIndex:
+    def __init__(self, device):
+        self.device = torch.device(device)
+        self.struct = L.RcIndex()
+        self.tensors = []
+
+    def alloc(self, cap):
+        d = self.device
+        self.child = _empty(cap * 8, torch.int32, d)
+        self.level = _empty(cap, torch.uint8, d)
+        self.x = _empty(cap, torch.int32, d)
+        self.y = _empty(cap, torch.int32, d)
+        self.z = _empty(cap, torch.int32, d)
+        s = self.struct
+        s.cap_internal = max(int(cap), 1)
+        s.child, s.level, s.x, s.y, s.z = (_ptr(self.child), _ptr(self.level), _ptr(self.x), _ptr(self.y),
+                                           _ptr(self.z))
+
+    @property
+    def maxlevel(self):
+        return int(self.struct.maxlevel)
+
+    @property
+    def ninternal(self):
+        return int(self.struct.ninternal)
+
+    def level_begin(self):
+        return np.array(list(self.struct.level_begin), np.int64)
+
+
+class VForest:
+    """Buffers of rc_vforest with their capacities."""
+
+    def __init__(self, device, nleaves, ncams, nslots, cap_vis, cap_cand, cap_rec):
+        d = torch.device(device)
+        self.device = d
+        self.cap_vis, self.cap_cand, self.cap_rec = int(cap_vis), int(cap_cand), int(cap_rec)
+        self.vis_leaf = _empty(cap_vis, torch.int32, d)
+        self.vis_cam = _empty(cap_vis, torch.int16, d)
+        self.vis_rect = _empty(4 * cap_vis, torch.int16, d)
+        self.cand_offset = _empty(cap_vis + 1, torch.int64, d)
+        self.leaf_vis = _empty(ncams * nleaves, torch.int32, d)
+        self.node_rect = _empty(4 * nslots, torch.int16, d)
+        self.node_offset = _empty(nslots + 1, torch.int64, d)
+        self.counts = torch.zeros(4, dtype=torch.int64, device=d)
+        self.struct = L.RcVforest(self.cap_vis, self.cap_cand, self.cap_rec, _ptr(self.vis_leaf), _ptr(self.vis_cam),
+                                  _ptr(self.vis_rect), _ptr(self.cand_offset), _ptr(self.leaf_vis),
+                                  _ptr(self.node_rect), _ptr(self.node_offset), _ptr(self.counts))
+
+    def read_counts(self):
+        c = self.counts.cpu().numpy()
+        return {"nvis": int(c[0]), "ncand": int(c[1]), "nrec": int(c[2]), "status": int(c[3])}
+
+
+# ---------------------------------------------------------------------------- entry points
+
+
+def rc_camera_prepare(cams_raw, device) -> DeviceCameras:
+    cams = DeviceCameras(cams_raw, device)
+    npix = ctypes.c_int64(0)
+    L.call("rc_camera_prepare", cams.raw.ctypes.data_as(ctypes.c_void_p), cams.ncams, _ptr(cams.buf),
+           ctypes.byref(npix), _stream(cams.device))
+    cams.npix = int(npix.value)
+    return cams
+
+
+def workspace_bytes(forest: DeviceForest, index: Optional[DeviceIndex], ncams: int, vf: Optional[VForest]) -> int:
+    return int(L.lib().rc_workspace_bytes(ctypes.byref(forest.struct),
+                                          ctypes.byref(index.struct) if index is not None else None, int(ncams),
+                                          ctypes.byref(vf.struct) if vf is not None else None))
+
+
+def rc_forest_index(forest: DeviceForest) -> DeviceIndex:
+    d = forest.device
+    ix = DeviceIndex(d)
+    ws = _empty(workspace_bytes(forest, None, 1, None), torch.uint8, d)
+    st = L.call("rc_forest_index", ctypes.byref(forest.struct), ctypes.byref(ix.struct), _ptr(ws), ws.numel(),
+                _stream(d), ok=(L.RC_OK, L.RC_ECAPACITY))
+    if st == L.RC_ECAPACITY or ix.struct.ninternal > 0:
+        ix.alloc(max(int(ix.struct.ninternal), 1))
+        L.call("rc_forest_index", ctypes.byref(forest.struct), ctypes.byref(ix.struct), _ptr(ws), ws.numel(),
+               _stream(d))
+    else:
+        ix.alloc(1)
+        L.call("rc_forest_index", ctypes.byref(forest.struct), ctypes.byref(ix.struct), _ptr(ws), ws.numel(),
+               _stream(d))
+    return ix
+
+
+def node_slots(index: DeviceIndex, ncams: int) -> int:
+    return int(L.lib().rc_node_slots(ctypes.byref(index.struct), int(ncams)))
+
+
+def rc_prune_visible(forest: DeviceForest, index: DeviceIndex, cams: DeviceCameras, vf: VForest, ws: torch.Tensor):
+    L.call("rc_prune_visible", ctypes.byref(forest.struct), ctypes.byref(index.struct), _ptr(cams.buf), cams.ncams,
+           ctypes.byref(vf.struct), _ptr(ws), ws.numel(), _stream(forest.device))
+
+
+def rc_segments(forest: DeviceForest, fields: DeviceFields, cams: DeviceCameras, vf: VForest, method: int,
+                substeps: int, rec_leaf: torch.Tensor, hit: Optional[torch.Tensor] = None,
+                sio: Optional[torch.Tensor] = None):
+    integ = L.RcIntegrator(int(method), int(substeps))
+    L.call("rc_segments", ctypes.byref(forest.struct), ctypes.byref(fields.struct), _ptr(cams.buf), cams.ncams,
+           ctypes.byref(vf.struct), ctypes.byref(integ), _ptr(rec_leaf), _ptr(hit), _ptr(sio),
+           _stream(forest.device))
+
+
+def rc_composite(forest: DeviceForest, index: DeviceIndex, cams: DeviceCameras, vf: VForest, rec_leaf, rec_node,
+                 A, B, I):
+    L.call("rc_composite", ctypes.byref(forest.struct), ctypes.byref(index.struct), _ptr(cams.buf), cams.ncams,
+           ctypes.byref(vf.struct), _ptr(rec_leaf), _ptr(rec_node), cams.npix, _ptr(A), _ptr(B), _ptr(I),
+           _stream(forest.device))
+
+
+def rc_segments_backward(forest: DeviceForest, index: DeviceIndex, fields: DeviceFields, cams: DeviceCameras,
+                         vf: VForest, method: int, substeps: int, rec_leaf, rec_node, dLdI, adj_leaf, adj_node, dk,
+                         de, accumulate: bool, ws):
+    integ = L.RcIntegrator(int(method), int(substeps))
+    L.call("rc_segments_backward", ctypes.byref(forest.struct), ctypes.byref(index.struct),
+           ctypes.byref(fields.struct), _ptr(cams.buf), cams.ncams, ctypes.byref(vf.struct), ctypes.byref(integ),
+           _ptr(rec_leaf), _ptr(rec_node), cams.npix, _ptr(dLdI), _ptr(adj_leaf), _ptr(adj_node), _ptr(dk), _ptr(de),
+           1 if accumulate else 0, _ptr(ws), ws.numel(), _stream(forest.device))
+
+
+# ---------------------------------------------------------------------------- renderer
+
+METHODS = {"analytic": L.RC_INT_ANALYTIC, "rk4": L.RC_INT_RK4}
+
+
+class Renderer:
+    """Prune, segments and composite for one forest share and a set of cameras.
+
+    ``plan()`` sizes every buffer once (one host read-back of the device
+    counts); after that ``forward()`` and ``backward()`` only enqueue work.
+    """
+
+    def __init__(self, forest, fields, cameras, method="rk4", substeps=4, device="cuda:0",
+                 keep_backward_buffers=False):
+        self.device = torch.device(device)
+        if not torch.cuda.is_available():
+            raise RuntimeError("the rc renderer needs a GPU")
+        L.lib()
+        self.forest = forest if isinstance(forest, DeviceForest) else DeviceForest.from_synth(forest, self.device)
+        self.fields = fields if isinstance(fields, DeviceFields) else DeviceFields.from_synth(fields, self.device)
+        raw = cameras if isinstance(cameras, np.ndarray) else np.stack([c.raw() for c in cameras])
+        self.cams = rc_camera_prepare(raw, self.device)
+        self.method = METHODS[method] if isinstance(method, str) else int(method)
+        self.substeps = int(substeps)
+        self.index = rc_forest_index(self.forest)
+        self.nslots = node_slots(self.index, self.cams.ncams)
+        self.vf = None
+        self.counts = None
+        self.bwd_ready = False
+        self.plan()
+
+    # -- sizing -----------------------------------------------------------
+    def plan(self, slack: float = 1.0):
+        N, nc = self.forest.nleaves, self.cams.ncams
+        vf = VForest(self.device, N, nc, self.nslots, 0, 0, 0)
+        ws = _empty(workspace_bytes(self.forest, self.index, nc, None), torch.uint8, self.device)
+        rc_prune_visible(self.forest, self.index, self.cams, vf, ws)
+        c = vf.read_counts()
+        cap_vis = int(c["nvis"] * slack) + 1
+        cap_cand = int(c["ncand"] * slack) + 1
+        cap_rec = int(c["nrec"] * slack) + 1
+        self.vf = VForest(self.device, N, nc, self.nslots, cap_vis, cap_cand, cap_rec)
+        self.ws = _empty(workspace_bytes(self.forest, self.index, nc, self.vf), torch.uint8, self.device)
+        self.rec_leaf = _empty(2 * cap_cand, torch.float32, self.device)
+        self.rec_node = _empty(2 * cap_rec, torch.float32, self.device)
+        P = self.cams.npix
+        self.A = _empty(P, torch.float32, self.device)
+        self.B = _empty(P, torch.float32, self.device)
+        self.I = _empty(P, torch.float32, self.device)
+        self.bwd_ready = False
+        self.prune()
+        self.counts = self.vf.read_counts()
+        if self.counts["status"] != 0:
+            raise RuntimeError(f"capacity plan failed: {self.counts}")
+        return self.counts
+
+    def _bwd_alloc(self):
+        if not self.bwd_ready:
+            self.adj_leaf = _empty(2 * self.vf.cap_cand, torch.float32, self.device)
+            self.adj_node = _empty(2 * self.vf.cap_rec, torch.float32, self.device)
+            self.bwd_ready = True
+
+    # -- steps -------------------------------------------------------------
+    def prune(self):
+        rc_prune_visible(self.forest, self.index, self.cams, self.vf, self.ws)
+
+    def segments(self, hit=None, sio=None):
+        rc_segments(self.forest, self.fields, self.cams, self.vf, self.method, self.substeps, self.rec_leaf, hit, sio)
+
+    def composite(self):
+        rc_composite(self.forest, self.index, self.cams, self.vf, self.rec_leaf, self.rec_node, self.A, self.B,
+                     self.I)
+
+    def forward(self):
+        self.prune()
+        self.segments()
+        self.composite()
+        return self.A, self.B, self.I
+
+    def backward(self, dLdI: torch.Tensor, dk: Optional[torch.Tensor] = None, de: Optional[torch.Tensor] = None,
+                 accumulate=False):
+        self._bwd_alloc()
+        if dk is None:
+            dk = torch.empty_like(self.fields.kappa)
+        if de is None:
+            de = torch.empty_like(self.fields.eps)
+        rc_segments_backward(self.forest, self.index, self.fields, self.cams, self.vf, self.method, self.substeps,
+                             self.rec_leaf, self.rec_node, dLdI.contiguous(), self.adj_leaf, self.adj_node, dk, de,
+                             accumulate, self.ws)
+        return dk, de
+
+    def set_fields(self, kappa: torch.Tensor, eps: torch.Tensor):
+        self.fields = DeviceFields(kappa, eps)
+
+    def debug_segments(self):
+        """Run rc_segments with the pairing outputs: (hit u8, (s_in, s_out) f64) per candidate."""
+        n = self.vf.cap_cand
+        hit = _empty(n, torch.uint8, self.device)
+        sio = _empty(2 * n, torch.float64, self.device)
+        self.segments(hit, sio)
+        return hit, sio
+
+    def image(self, t: torch.Tensor, k: int = 0) -> torch.Tensor:
+        return self.cams.image(t, k)
+
+
+class RenderFn(torch.autograd.Function):
+    """I = render(kappa, eps) with the hand-written adjoint of librc."""
+
+    @staticmethod
+    def forward(ctx, kappa, eps, renderer: Renderer):
+        renderer.set_fields(kappa.detach(), eps.detach())
+        _, _, I = renderer.forward()
+        ctx.renderer = renderer
+        return I.clone()
+
+    @staticmethod
+    def backward(ctx, gI):
+        dk, de = ctx.renderer.backward(gI.contiguous().float())
+        return dk, de, None
+
+
+def render(kappa: torch.Tensor, eps: torch.Tensor, renderer: Renderer) -> torch.Tensor:
+    return RenderFn.apply(kappa, eps, renderer)

@@ -1,0 +1,114 @@
+"""CPU checks of the C ABI: the library loads, exports every symbol the
+header declares, and rejects bad arguments before touching the GPU."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_1809_01334_amd import _lib as L
+
+    if not os.path.exists(L.LIB_PATH):
+        pytest.skip("librc.so not built")
+    return L
+
+
+def test_library_exports_every_declared_entry_point():
+    L = _lib()
+    header = open(os.path.join(ROOT, "include", "rc.h")).read()
+    declared = set(re.findall(r"^\s*(?:rc_status|size_t|int64_t|const char \*)\s*(rc_\w+)\(", header, re.M))
+    assert {"rc_prune_visible", "rc_segments", "rc_composite", "rc_segments_backward"} <= declared
+    lib = L.lib()
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert declared == set(L.EXPORTS)
+
+
+def test_status_names():
+    L = _lib()
+    assert L.strerror(0) == "ok"
+    for s in (-1, -2, -3, -4, -5, -6):
+        assert L.strerror(s) != "unknown status"
+
+
+def test_camera_validation_rejects_bad_cameras():
+    L = _lib()
+    lib = L.lib()
+    good = synth.random_perspective_camera(np.random.default_rng(1), 64, 48).raw()
+    npix = ctypes.c_int64(0)
+
+    def prep(raw):
+        raw = np.ascontiguousarray(raw, np.float64)
+        # a non-null device pointer is never dereferenced when validation fails
+        return lib.rc_camera_prepare(raw.ctypes.data_as(ctypes.c_void_p), 1, ctypes.c_void_p(16),
+                                     ctypes.byref(npix), None)
+
+    bad = []
+    r = good.copy(); r[13] = 0.5; bad.append(r)            # zfar <= n
+    r = good.copy(); r[14] = 0; bad.append(r)              # w = 0
+    r = good.copy(); r[15] = 40000; bad.append(r)          # h too large
+    r = good.copy(); r[12] = -1.0; bad.append(r)           # ell <= 0
+    r = good.copy(); r[6:9] *= 2.0; bad.append(r)          # t not unit
+    r = good.copy(); r[6:9] = -r[6:9]; bad.append(r)       # right-handed frame
+    r = good.copy(); r[3:6] = 0.0; bad.append(r)           # n = 0
+    r = good.copy(); r[0] = np.nan; bad.append(r)
+    for raw in bad:
+        assert prep(raw) == L.RC_EINVAL
+    assert lib.rc_camera_prepare(None, 1, ctypes.c_void_p(16), ctypes.byref(npix), None) == L.RC_EINVAL
+
+
+def test_null_and_unsupported_arguments():
+    L = _lib()
+    lib = L.lib()
+    assert lib.rc_forest_index(None, None, None, 0, None) == L.RC_EINVAL
+    f = L.RcForest(1, 0, 0, None, None, None, None, None)  # no leaves
+    ix = L.RcIndex()
+    assert lib.rc_forest_index(ctypes.byref(f), ctypes.byref(ix), None, 0, None) == L.RC_EINVAL
+    f = L.RcForest(2, 0, 8, None, ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(16))
+    assert lib.rc_forest_index(ctypes.byref(f), ctypes.byref(ix), None, 0, None) == L.RC_EUNSUPPORTED
+    f = L.RcForest(1, 0, 8, None, ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(16))
+    assert lib.rc_forest_index(ctypes.byref(f), ctypes.byref(ix), None, 0, None) == L.RC_EWORKSPACE
+    # analytic integration needs constant fields; more than 64 substeps is rejected
+    fl = L.RcFields(L.RC_FIELD_TRILINEAR, 1, ctypes.c_void_p(16), ctypes.c_void_p(16))
+    vf = L.RcVforest()
+    integ = L.RcIntegrator(L.RC_INT_ANALYTIC, 1)
+    assert lib.rc_segments(ctypes.byref(f), ctypes.byref(fl), ctypes.c_void_p(16), 1, ctypes.byref(vf),
+                           ctypes.byref(integ), ctypes.c_void_p(16), None, None, None) == L.RC_EUNSUPPORTED
+    integ = L.RcIntegrator(L.RC_INT_RK4, 65)
+    assert lib.rc_segments(ctypes.byref(f), ctypes.byref(fl), ctypes.c_void_p(16), 1, ctypes.byref(vf),
+                           ctypes.byref(integ), ctypes.c_void_p(16), None, None, None) == L.RC_EINVAL
+    fl = L.RcFields(L.RC_FIELD_CONST, 2, ctypes.c_void_p(16), ctypes.c_void_p(16))
+    assert lib.rc_segments(ctypes.byref(f), ctypes.byref(fl), ctypes.c_void_p(16), 1, ctypes.byref(vf),
+                           ctypes.byref(integ), ctypes.c_void_p(16), None, None, None) == L.RC_EUNSUPPORTED
+
+
+def test_sizes_are_consistent():
+    L = _lib()
+    lib = L.lib()
+    assert lib.rc_camera_bytes(3) == 3 * lib.rc_camera_bytes(1) > 0
+    ix = L.RcIndex()
+    ix.maxlevel = 3
+    for l, b in enumerate([0, 1, 9, 73, 73]):
+        ix.level_begin[l] = b
+    assert lib.rc_node_slots(ctypes.byref(ix), 2) == 2 * (73 - 1)
+    f = L.RcForest(1, 0, 1000, None, None, None, None, None)
+    b1 = lib.rc_workspace_bytes(ctypes.byref(f), None, 1, None)
+    b4 = lib.rc_workspace_bytes(ctypes.byref(f), ctypes.byref(ix), 64, None)
+    assert b4 >= b1 > 0
+
+
+def test_product_path_has_no_cpu_fallback():
+    """The package never imports the oracle and fails loudly without librc."""
+    pkg = os.path.join(ROOT, "paper_1809_01334_amd")
+    for fn in os.listdir(pkg):
+        if fn.endswith(".py"):
+            src = open(os.path.join(pkg, fn)).read()
+            assert "oracle" not in src, fn
