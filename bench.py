@@ -90,8 +90,13 @@ def main():
     for _ in range(args.warmup):
         r.forward()
     torch.cuda.synchronize()
-    ms = time_region(torch, r.forward, args.steps)
-    log(f"[bench] forward {ms:.3f} ms")
+    ms_eager = time_region(torch, r.forward, args.steps)
+    log(f"[bench] forward (eager launches) {ms_eager:.3f} ms")
+    r.capture()
+    for _ in range(args.warmup):
+        r.replay()
+    ms = time_region(torch, r.replay, args.steps)
+    log(f"[bench] forward (one HIP graph) {ms:.3f} ms")
 
     # per-phase times (same stream, HIP events)
     t_prune = time_region(torch, r.prune, args.steps)
@@ -123,6 +128,7 @@ def main():
             "pixels": r.cams.npix,
         },
         "images_per_s": 1e3 / ms,
+        "forward_eager_ms": ms_eager,
         "phase_ms": {"prune": t_prune, "segments": t_seg, "composite": t_comp},
     }
     # dominant kernel: segment generation (one launch of k_segments per call)
@@ -146,10 +152,15 @@ def main():
             r.forward()
             r.backward(g)
 
-        ms_fb = time_region(torch, fb, max(args.steps // 2, 5))
+        ms_fb_eager = time_region(torch, fb, max(args.steps // 2, 5))
+        r.capture(backward=True, dLdI=g)
+        for _ in range(2):
+            r.replay()
+        ms_fb = time_region(torch, r.replay, max(args.steps // 2, 5))
         out["fwd_bwd_ms"] = ms_fb
+        out["fwd_bwd_eager_ms"] = ms_fb_eager
         out["fwd_bwd_over_fwd"] = ms_fb / ms
-        log(f"[bench] forward+backward {ms_fb:.3f} ms")
+        log(f"[bench] forward+backward {ms_fb:.3f} ms (graph), {ms_fb_eager:.3f} ms (eager)")
 
     if not args.no_cpu:
         log("[bench] timing the CPU oracle")

@@ -80,14 +80,15 @@ typedef struct rc_forest {
 } rc_forest;
 
 /* Per-leaf coefficient data (Sec. 2.3): absorption kappa (beta in the paper)
- * and emission eps (gamma), single channel, structure of arrays
- * [corner][leaf]: one corner for per-leaf constants, eight for trilinear data
- * interpolated in leaf reference coordinates. */
+ * and emission eps (gamma), single channel, leaf-major [leaf][corner] in SFC
+ * order: one value per leaf for per-leaf constants, eight consecutive corner
+ * values (corner c = bx + 2 by + 4 bz, 32-byte aligned rows) for trilinear
+ * data interpolated in leaf reference coordinates. */
 typedef struct rc_fields {
     int32_t kind;               /* RC_FIELD_CONST or RC_FIELD_TRILINEAR */
     int32_t nch;                /* channels; 1 */
-    const float *kappa;         /* [device] ncorner * N */
-    const float *eps;           /* [device] ncorner * N */
+    const float *kappa;         /* [device] N * ncorner, 16-byte aligned */
+    const float *eps;           /* [device] N * ncorner, 16-byte aligned */
 } rc_fields;
 
 /* Segment integrator (Sec. 2.3, 2.7): closed form for constant coefficients,
@@ -128,6 +129,10 @@ typedef struct rc_vforest {
     int16_t *node_rect;    /* [device] rc_node_slots() * 4: rectangle per (level >= 1, camera, node) */
     int64_t *node_offset;  /* [device] rc_node_slots() + 1: first record per slot */
     int64_t *counts;       /* [device] 4: nvis, ncand, nrec, status (nonzero = capacity exceeded) */
+    int32_t *cand_chunk;   /* [device] cap_cand / 64 + 2: visible pair holding candidate 64 w */
+    int32_t *rec_chunk;    /* [device] cap_rec / 64 + 2: slot holding internal-node record 64 w */
+    void *child_desc;      /* [device] ncams * ninternal * 8 * 16 bytes: children of every internal node in
+                              view order, each with its rectangle and record offset */
 } rc_vforest;
 
 /* Name of a status code. */

@@ -49,7 +49,8 @@ class RcIndex(ctypes.Structure):
 class RcVforest(ctypes.Structure):
     _fields_ = [("cap_vis", c_i64), ("cap_cand", c_i64), ("cap_rec", c_i64), ("vis_leaf", c_vp), ("vis_cam", c_vp),
                 ("vis_rect", c_vp), ("cand_offset", c_vp), ("leaf_vis", c_vp), ("node_rect", c_vp),
-                ("node_offset", c_vp), ("counts", c_vp)]
+                ("node_offset", c_vp), ("counts", c_vp), ("cand_chunk", c_vp), ("rec_chunk", c_vp),
+                ("child_desc", c_vp)]
 
 
 P = ctypes.POINTER

@@ -102,12 +102,8 @@ extern "C" size_t rc_workspace_bytes(const rc_forest* f, const rc_index* ix, int
     // rc_forest_index: status words, per-leaf current node, scan partials
     size_t bi = 256 + rc::align_up((size_t)N * 4) + rc::scan_partial_bytes(N, 8);
     b = bi > b ? bi : b;
-    // rc_prune_visible: scan partials of the leaf and node scans (reused)
-    size_t bp = rc::scan_partial_bytes(N * nc, sizeof(rc::I64x2));
-    if (ix) {
-        size_t bn = rc::scan_partial_bytes(rc_node_slots(ix, ncams), 8);
-        bp = bp > bn ? bp : bn;
-    }
+    // rc_prune_visible: partials of the joint scan over leaves and node slots
+    size_t bp = rc::scan_partial_bytes(N * nc + (ix ? rc_node_slots(ix, ncams) : 0), sizeof(rc::I64x3));
     b = bp > b ? bp : b;
     // rc_segments_backward: gradient partials per (wave chunk, visible pair)
     if (vf) {

@@ -16,37 +16,55 @@ using namespace rc;
 namespace rc {
 namespace {
 
-constexpr int MAXSUB_BWD = 16;
-
-// Hand the adjoint (gT, J) of node m (level l) at pixel (i, j) to its children.
-__device__ inline void push_children(const FoldCtx& C, int cam, int64_t m, int l, int i, int j, float gT, float J,
+// Hand the adjoint (gT, J) of descriptor slot `dslot` at pixel (i, j) to the
+// node's children: the nearer siblings' transmittances multiply gT, the
+// farther siblings' fold applied to J gives the intensity from behind.
+template <bool UNIFORM>
+__device__ inline void push_children(const FoldCtx& C, int64_t dslot, int i, int j, float gT, float J,
                                      float2* adj_leaf, float2* adj_node) {
-    int sb = view_bits(C.cams[cam], l, C.nx[m], C.ny[m], C.nz[m]);
-    const int32_t* ch = C.child + m * 8;
+    ChildDesc d[8];
     float2 rv[8];
-    int kind[8];
-    int64_t idx[8];
+    bool has[8];
+#pragma unroll
     for (int q = 0; q < 8; q++) {
-        idx[q] = 0;
-        kind[q] = child_slot(C, cam, ch[q ^ sb], l, i, j, idx[q]);
-        rv[q] = kind[q] == 1 ? C.rec_leaf[idx[q]] : kind[q] == 2 ? C.rec_node[idx[q]] : make_float2(1.0f, 0.0f);
+        d[q] = UNIFORM ? load_desc_scalar(C.desc, dslot * 8 + q) : load_desc(C.desc + dslot * 8 + q);
+        has[q] = desc_has(d[q], i, j);
+        rv[q] = has[q] ? desc_record(C, d[q], i, j) : make_float2(1.0f, 0.0f);
     }
     float Jq[8];
     float Jc = J;
+#pragma unroll
     for (int q = 7; q >= 0; q--) {
         Jq[q] = Jc;
         Jc = fmaf(rv[q].x, Jc, rv[q].y);
     }
     float T = gT;
+#pragma unroll
     for (int q = 0; q < 8; q++) {
-        if (kind[q] == 1) adj_leaf[idx[q]] = make_float2(T, Jq[q]);
-        if (kind[q] == 2) adj_node[idx[q]] = make_float2(T, Jq[q]);
+        if (has[q]) {
+            int64_t k = desc_index(d[q], i, j);
+            if (d[q].off >= 0)
+                adj_node[d[q].off + k] = make_float2(T, Jq[q]);
+            else
+                adj_leaf[-1 - d[q].off + k] = make_float2(T, Jq[q]);
+        }
         T *= rv[q].x;
     }
 }
 
+__device__ inline void push_children_auto(const FoldCtx& C, int64_t dslot, bool active, int i, int j, float gT,
+                                          float J, float2* adj_leaf, float2* adj_node) {
+    int64_t d0 = uniform64(dslot);
+    if (__all(!active || dslot == d0)) {
+        if (active) push_children<true>(C, d0, i, j, gT, J, adj_leaf, adj_node);
+    } else if (active) {
+        push_children<false>(C, dslot, i, j, gT, J, adj_leaf, adj_node);
+    }
+}
+
 __global__ __launch_bounds__(256) void k_adj_root(FoldCtx C, int32_t root, int64_t npix, const float* dLdI,
-                                                  float2* adj_leaf, float2* adj_node) {
+                                                  float2* adj_leaf, float2* adj_node, const int32_t* leaf_vis,
+                                                  const int16_t* vis_rect, const int64_t* cand_offset) {
     if (C.counts[3]) return;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < npix; p += stride) {
@@ -58,10 +76,14 @@ __global__ __launch_bounds__(256) void k_adj_root(FoldCtx C, int32_t root, int64
         float g = dLdI[p];
         float bg = (float)c.bg;
         if (root >= 0) {
-            push_children(C, cam, root, 0, i, j, g, bg, adj_leaf, adj_node);
+            push_children_auto(C, (int64_t)cam * C.ninternal + root, true, i, j, g, bg, adj_leaf, adj_node);
         } else if (root <= -2) {
-            int64_t idx = 0;
-            if (child_slot(C, cam, root, 0, i, j, idx) == 1) adj_leaf[idx] = make_float2(g, bg);
+            int32_t v = leaf_vis[(int64_t)cam * C.N + (-2 - (int64_t)root)];
+            if (v >= 0) {
+                Rect r = load_rect(vis_rect + 4 * (int64_t)v);
+                if (r.contains(i, j))
+                    adj_leaf[cand_offset[v] + (int64_t)(j - r.j0) * r.width() + (i - r.i0)] = make_float2(g, bg);
+            }
         }
     }
 }
@@ -69,21 +91,26 @@ __global__ __launch_bounds__(256) void k_adj_root(FoldCtx C, int32_t root, int64
 __global__ __launch_bounds__(256) void k_adj_level(FoldCtx C, int l, float2* adj_leaf, float2* adj_node) {
     if (C.counts[3]) return;
     int64_t s0 = C.L.slot_begin[l], s1 = C.L.slot_begin[l + 1];
-    int64_t R0 = C.node_offset[s0], R1 = C.node_offset[s1];
+    int64_t R0 = C.node_offset[s0], R1 = C.node_offset[s1], Rtot = C.node_offset[C.nslots];
     int64_t M = C.L.level_begin[l + 1] - C.L.level_begin[l];
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t g = R0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < R1; g += stride) {
-        int64_t slot = upper_index(C.node_offset, s0, s1, g);
+    int lane = threadIdx.x & (WAVE - 1);
+    int64_t wave = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    int64_t nw = (int64_t)gridDim.x * (blockDim.x / WAVE);
+    for (int64_t w = R0 / WAVE + wave; w * WAVE < R1; w += nw) {
+        int64_t g = w * WAVE + lane;
+        bool act = g >= R0 && g < R1;
+        int64_t gg = act ? g : (g < R0 ? R0 : R1 - 1);
+        int64_t slot = record_slot(C, gg, w, s0, s1, Rtot);
         int64_t loc = slot - s0;
-        int cam = (int)(loc / M);
-        int64_t m = C.L.level_begin[l] + (loc - (int64_t)cam * M);
+        int64_t cam = divu(loc, M);
+        int64_t m = C.L.level_begin[l] + (loc - cam * M);
         Rect r = load_rect(C.node_rect + 4 * slot);
-        int k = (int)(g - C.node_offset[slot]);
+        int k = (int)(gg - C.node_offset[slot]);
         int wr = r.width();
         int j = r.j0 + k / wr;
         int i = r.i0 + (k - (k / wr) * wr);
-        float2 a = adj_node[g];
-        push_children(C, cam, m, l, i, j, a.x, a.y, adj_leaf, adj_node);
+        float2 a = adj_node[gg];
+        push_children_auto(C, cam * C.ninternal + m, act, i, j, a.x, a.y, adj_leaf, adj_node);
     }
 }
 
@@ -138,23 +165,36 @@ __device__ inline void rk4_step_bwd(float b0, float bm, float b1, float g0, floa
     db0 -= hh * A1b;
 }
 
-__device__ inline void trilin_weights(float x, float y, float z, float w[8]) {
-    float x0 = 1.0f - x, y0 = 1.0f - y, z0 = 1.0f - z;
-    w[0] = x0 * y0 * z0;
-    w[1] = x * y0 * z0;
-    w[2] = x0 * y * z0;
-    w[3] = x * y * z0;
-    w[4] = x0 * y0 * z;
-    w[5] = x * y0 * z;
-    w[6] = x0 * y * z;
-    w[7] = x * y * z;
+// Reverse of field_cubic: corner adjoints vb[8] from the adjoints pb[4] of
+// the cubic's coefficients.
+__device__ inline void field_cubic_bwd(const float a[3], const float d[3], const float pb[4], float vb[8]) {
+    float G0b = fmaf(a[2], pb[0], d[2] * pb[1]);
+    float G1b = fmaf(a[2], pb[1], d[2] * pb[2]);
+    float G2b = fmaf(a[2], pb[2], d[2] * pb[3]);
+    float fb[2][3] = {{pb[0] - G0b, pb[1] - G1b, pb[2] - G2b}, {G0b, G1b, G2b}};
+    float e0b[4], e1b[4];
+#pragma unroll
+    for (int z = 0; z < 2; z++) {
+        float D0b = fmaf(a[1], fb[z][0], d[1] * fb[z][1]);
+        float D1b = fmaf(a[1], fb[z][1], d[1] * fb[z][2]);
+        e0b[2 * z] = fb[z][0] - D0b;
+        e0b[2 * z + 1] = D0b;
+        e1b[2 * z] = fb[z][1] - D1b;
+        e1b[2 * z + 1] = D1b;
+    }
+#pragma unroll
+    for (int m = 0; m < 4; m++) {
+        float dvb = fmaf(a[0], e0b[m], d[0] * e1b[m]);
+        vb[2 * m] = e0b[m] - dvb;
+        vb[2 * m + 1] = dvb;
+    }
 }
 
 // Gradient of one segment's (A, B) contribution: grad[0..nc) kappa corners,
 // grad[nc..2nc) eps corners.  gT = g T_front, J = intensity from behind.
-template <int KIND>
-__device__ inline void segment_grad(const float kc[8], const float ec[8], const SegGeom& sg, int nsub, float gT,
-                                    float J, float grad[GRAD_MAX]) {
+template <int KIND, int NSUB>
+__device__ inline void segment_grad(const float kc[8], const float ec[8], const SegGeom& sg, float gT, float J,
+                                    float grad[GRAD_MAX]) {
     if (KIND == 0) {
         float k = kc[0], e = ec[0], dx = sg.dx;
         float x = k * dx;
@@ -180,44 +220,54 @@ __device__ inline void segment_grad(const float kc[8], const float ec[8], const 
         grad[1] = gT * dBde;
         return;
     }
-    // forward: substep values and the intensity entering each substep
-    float inv = 1.0f / (float)nsub;
+    // forward: field values at the 2 NSUB + 1 stage points, substep values and
+    // the intensity entering each substep
+    constexpr int NP = 2 * NSUB + 1;
+    const float inv = 1.0f / (float)NSUB;
     float h = sg.dx * inv;
-    float bs[2 * MAXSUB_BWD + 1], gs[2 * MAXSUB_BWD + 1];
-    float px[2 * MAXSUB_BWD + 1], py[2 * MAXSUB_BWD + 1], pz[2 * MAXSUB_BWD + 1];
-    int np = 2 * nsub + 1;
-    for (int p = 0; p < np; p++) {
-        float t = (float)p * (0.5f * inv);
-        if (p % 2 == 0) t = (float)(p / 2) * inv;
-        px[p] = fmaf(t, sg.dxi[0], sg.xf[0]);
-        py[p] = fmaf(t, sg.dxi[1], sg.xf[1]);
-        pz[p] = fmaf(t, sg.dxi[2], sg.xf[2]);
-        bs[p] = trilin(kc, px[p], py[p], pz[p]);
-        gs[p] = trilin(ec, px[p], py[p], pz[p]);
+    float pk[4], pe[4];
+    if (KIND == 2) {
+        field_cubic(kc, sg.xf, sg.dxi, pk);
+        field_cubic(ec, sg.xf, sg.dxi, pe);
+    } else {
+        pk[0] = kc[0];
+        pe[0] = ec[0];
+        pk[1] = pk[2] = pk[3] = pe[1] = pe[2] = pe[3] = 0.0f;
     }
-    float Iin[MAXSUB_BWD], av[MAXSUB_BWD];
+    float bs[NP], gs[NP];
+#pragma unroll
+    for (int p = 0; p < NP; p++) {
+        float t = (float)p * (0.5f * inv);
+        bs[p] = horner3(pk, t);
+        gs[p] = horner3(pe, t);
+    }
+    float Iin[NSUB], av[NSUB];
     float Ic = J;
-    for (int q = 0; q < nsub; q++) {
-        float2 s = rk4_step(bs[2 * q], bs[2 * q + 1], bs[2 * q + 2], gs[2 * q], gs[2 * q + 1], gs[2 * q + 2], h);
+#pragma unroll
+    for (int q = 0; q < NSUB; q++) {
+        float2 st = rk4_step(bs[2 * q], bs[2 * q + 1], bs[2 * q + 2], gs[2 * q], gs[2 * q + 1], gs[2 * q + 2], h);
         Iin[q] = Ic;
-        av[q] = s.x;
-        Ic = fmaf(s.x, Ic, s.y);
+        av[q] = st.x;
+        Ic = fmaf(st.x, Ic, st.y);
     }
     // reverse: G = dL/d(intensity leaving substep q), nearest first
-    float dbs[2 * MAXSUB_BWD + 1], dgs[2 * MAXSUB_BWD + 1];
-    for (int p = 0; p < np; p++) {
+    float dbs[NP], dgs[NP];
+#pragma unroll
+    for (int p = 0; p < NP; p++) {
         dbs[p] = 0.0f;
         dgs[p] = 0.0f;
     }
     float G = gT;
-    for (int q = nsub - 1; q >= 0; q--) {
+#pragma unroll
+    for (int q = NSUB - 1; q >= 0; q--) {
         rk4_step_bwd(bs[2 * q], bs[2 * q + 1], bs[2 * q + 2], gs[2 * q], gs[2 * q + 1], h, G * Iin[q], G,
                      dbs[2 * q], dbs[2 * q + 1], dbs[2 * q + 2], dgs[2 * q], dgs[2 * q + 1], dgs[2 * q + 2]);
         G *= av[q];
     }
     if (KIND == 1) {
         float sk = 0.0f, se = 0.0f;
-        for (int p = 0; p < np; p++) {
+#pragma unroll
+        for (int p = 0; p < NP; p++) {
             sk += dbs[p];
             se += dgs[p];
         }
@@ -225,15 +275,21 @@ __device__ inline void segment_grad(const float kc[8], const float ec[8], const 
         grad[1] = se;
         return;
     }
-    for (int c = 0; c < 16; c++) grad[c] = 0.0f;
-    for (int p = 0; p < np; p++) {
-        float w[8];
-        trilin_weights(px[p], py[p], pz[p], w);
-        for (int c = 0; c < 8; c++) {
-            grad[c] = fmaf(dbs[p], w[c], grad[c]);
-            grad[8 + c] = fmaf(dgs[p], w[c], grad[8 + c]);
+    // adjoints of the cubic coefficients: moments of the point adjoints
+    float pkb[4] = {0.0f, 0.0f, 0.0f, 0.0f}, peb[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int p = 0; p < NP; p++) {
+        float t = (float)p * (0.5f * inv);
+        float tn = 1.0f;
+#pragma unroll
+        for (int n = 0; n < 4; n++) {
+            pkb[n] = fmaf(dbs[p], tn, pkb[n]);
+            peb[n] = fmaf(dgs[p], tn, peb[n]);
+            tn *= t;
         }
     }
+    field_cubic_bwd(sg.xf, sg.dxi, pkb, grad);
+    field_cubic_bwd(sg.xf, sg.dxi, peb, grad + 8);
 }
 
 struct LeafAdjArgs {
@@ -248,6 +304,7 @@ struct LeafAdjArgs {
     const int16_t* vis_rect;
     const int64_t* cand_offset;
     const int64_t* counts;
+    const int32_t* cand_chunk;
     int64_t cap_cand;
     const float2* adj_leaf;
     float* partial;  // [(nchunks + nvis)][GRAD_MAX], entry (chunk w, pair v) at w + v
@@ -255,7 +312,7 @@ struct LeafAdjArgs {
 
 // One wavefront per 64 consecutive candidates; per-pair sums by a segmented
 // shuffle scan in a fixed order.
-template <int KIND>
+template <int KIND, int NSUB>
 __global__ __launch_bounds__(256) void k_adj_leaf(LeafAdjArgs a) {
     if (a.counts[3]) return;
     constexpr int NPAR = KIND == 2 ? 16 : 2;
@@ -271,7 +328,7 @@ __global__ __launch_bounds__(256) void k_adj_leaf(LeafAdjArgs a) {
         for (int c = 0; c < GRAD_MAX; c++) grad[c] = 0.0f;
         int64_t key = -1;
         if (g < ncand) {
-            int64_t v = upper_index(a.cand_offset, 0, nvis, g);
+            int64_t v = cand_pair(a.cand_offset, a.cand_chunk, g, w, nvis, ncand);
             key = v;
             int32_t leaf = a.vis_leaf[v];
             const Cam& c = a.cams[a.vis_cam[v]];
@@ -289,17 +346,20 @@ __global__ __launch_bounds__(256) void k_adj_leaf(LeafAdjArgs a) {
                 float2 ad = a.adj_leaf[g];
                 float kc[8], ec[8];
                 if (KIND == 2) {
-                    for (int q = 0; q < 8; q++) {
-                        kc[q] = a.kappa[(int64_t)q * a.N + leaf];
-                        ec[q] = a.eps[(int64_t)q * a.N + leaf];
-                    }
+                    const float4* kp = reinterpret_cast<const float4*>(a.kappa + (int64_t)leaf * 8);
+                    const float4* ep = reinterpret_cast<const float4*>(a.eps + (int64_t)leaf * 8);
+                    float4 k0 = kp[0], k1 = kp[1], e0 = ep[0], e1 = ep[1];
+                    kc[0] = k0.x; kc[1] = k0.y; kc[2] = k0.z; kc[3] = k0.w;
+                    kc[4] = k1.x; kc[5] = k1.y; kc[6] = k1.z; kc[7] = k1.w;
+                    ec[0] = e0.x; ec[1] = e0.y; ec[2] = e0.z; ec[3] = e0.w;
+                    ec[4] = e1.x; ec[5] = e1.y; ec[6] = e1.z; ec[7] = e1.w;
                 } else {
                     for (int q = 0; q < 8; q++) {
                         kc[q] = a.kappa[leaf];
                         ec[q] = a.eps[leaf];
                     }
                 }
-                segment_grad<KIND>(kc, ec, sg, a.nsub, ad.x, ad.y, grad);
+                segment_grad<KIND, NSUB>(kc, ec, sg, ad.x, ad.y, grad);
             }
         }
         // segmented inclusive scan over lanes with equal (sorted) keys
@@ -320,25 +380,24 @@ __global__ __launch_bounds__(256) void k_adj_leaf(LeafAdjArgs a) {
     }
 }
 
-// Per visible pair: add its chunk partials in chunk order.
+// Per (visible pair, parameter): add the pair's chunk partials in chunk order.
 __global__ __launch_bounds__(256) void k_grad_pairs(const int64_t* counts, int64_t cap_cand, const int64_t* cand_offset,
                                                     const float* partial, float* gvis, int npar) {
     if (counts[3]) return;
     int64_t nvis = counts[0];
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nvis; v += stride) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nvis * GRAD_MAX; t += stride) {
+        int64_t v = t >> 4;  // GRAD_MAX = 16
+        int c = (int)(t - v * GRAD_MAX);
+        if (c >= npar) continue;
         int64_t c0 = cand_offset[v], c1 = cand_offset[v + 1];
         if (c1 > cap_cand) c1 = cap_cand;
-        float acc[GRAD_MAX];
-        for (int c = 0; c < GRAD_MAX; c++) acc[c] = 0.0f;
+        float acc = 0.0f;
         if (c1 > c0) {
             int64_t w0 = c0 / WAVE, w1 = (c1 - 1) / WAVE;
-            for (int64_t w = w0; w <= w1; w++) {
-                const float* src = partial + (w + v) * GRAD_MAX;
-                for (int c = 0; c < npar; c++) acc[c] += src[c];
-            }
+            for (int64_t w = w0; w <= w1; w++) acc += partial[(w + v) * GRAD_MAX + c];
         }
-        for (int c = 0; c < npar; c++) gvis[v * GRAD_MAX + c] = acc[c];
+        gvis[v * GRAD_MAX + c] = acc;
     }
 }
 
@@ -356,7 +415,7 @@ __global__ __launch_bounds__(256) void k_grad_leaves(const int64_t* counts, int6
             for (int c = 0; c < 2 * nc; c++) acc[c] += gvis[(int64_t)v * GRAD_MAX + c];
         }
         for (int c = 0; c < nc; c++) {
-            int64_t o = (int64_t)c * N + l;
+            int64_t o = l * nc + c;
             dk[o] = accumulate ? dk[o] + acc[c] : acc[c];
             de[o] = accumulate ? de[o] + acc[nc + c] : acc[nc + c];
         }
@@ -380,13 +439,15 @@ extern "C" rc_status rc_segments_backward(const rc_forest* f, const rc_index* ix
     if (!dcams || ncams <= 0 || npix <= 0 || !rec_leaf || !dLdI || !adj_leaf || !dk || !de) return RC_EINVAL;
     bool nodes = rc_node_slots(ix, ncams) > 0;
     if (nodes && (!rec_node || !adj_node)) return RC_EINVAL;
-    if (in->method == RC_INT_RK4 && in->substeps > MAXSUB_BWD) return RC_EUNSUPPORTED;
+    if (in->method == RC_INT_RK4 && in->substeps != 1 && in->substeps != 2 && in->substeps != 4 && in->substeps != 8)
+        return RC_EUNSUPPORTED;
+    if ((s = check_tables(vf, ix, ncams)) != RC_OK) return s;
     if (!ws || ws_bytes < rc_workspace_bytes(f, ix, ncams, vf)) return RC_EWORKSPACE;
     hipStream_t st = (hipStream_t)stream;
 
     FoldCtx C = make_fold_ctx(f, ix, dcams, ncams, vf, rec_leaf, rec_node);
     hipLaunchKernelGGL(k_adj_root, dim3(stride_grid(npix, 256, 256 * 16)), dim3(256), 0, st, C, ix->root, npix, dLdI,
-                       (float2*)adj_leaf, (float2*)adj_node);
+                       (float2*)adj_leaf, (float2*)adj_node, vf->leaf_vis, vf->vis_rect, vf->cand_offset);
     RC_HIP(hipGetLastError());
     unsigned grid = stride_grid(vf->cap_rec, 256, 256 * 16);
     for (int l = 1; l < ix->maxlevel; l++) {
@@ -400,18 +461,33 @@ extern "C" rc_status rc_segments_backward(const rc_forest* f, const rc_index* ix
     float* gvis = (float*)((char*)ws + align_up((size_t)(nchunks + vf->cap_vis + 1) * GRAD_MAX * sizeof(float)));
     LeafAdjArgs la{(const Cam*)dcams, f->level,       f->x,          f->y,         f->z,
                    f->nleaves,        fl->kappa,      fl->eps,       in->substeps, vf->vis_leaf,
-                   vf->vis_cam,       vf->vis_rect,   vf->cand_offset, vf->counts, vf->cap_cand,
-                   (const float2*)adj_leaf, partial};
+                   vf->vis_cam,       vf->vis_rect,   vf->cand_offset, vf->counts, vf->cand_chunk,
+                   vf->cap_cand,      (const float2*)adj_leaf, partial};
     unsigned lg = stride_grid(nchunks * WAVE, 256, 256 * 8);
     int nc = fl->kind == RC_FIELD_TRILINEAR ? 8 : 1;
-    if (in->method == RC_INT_ANALYTIC)
-        hipLaunchKernelGGL(k_adj_leaf<0>, dim3(lg), dim3(256), 0, st, la);
-    else if (fl->kind == RC_FIELD_CONST)
-        hipLaunchKernelGGL(k_adj_leaf<1>, dim3(lg), dim3(256), 0, st, la);
-    else
-        hipLaunchKernelGGL(k_adj_leaf<2>, dim3(lg), dim3(256), 0, st, la);
+    dim3 G(lg), B(256);
+    if (in->method == RC_INT_ANALYTIC) {
+        hipLaunchKernelGGL((k_adj_leaf<0, 1>), G, B, 0, st, la);
+    } else if (fl->kind == RC_FIELD_CONST) {
+        switch (in->substeps) {
+            case 1: hipLaunchKernelGGL((k_adj_leaf<1, 1>), G, B, 0, st, la); break;
+            case 2: hipLaunchKernelGGL((k_adj_leaf<1, 2>), G, B, 0, st, la); break;
+            case 4: hipLaunchKernelGGL((k_adj_leaf<1, 4>), G, B, 0, st, la); break;
+            case 8: hipLaunchKernelGGL((k_adj_leaf<1, 8>), G, B, 0, st, la); break;
+            default: return RC_EUNSUPPORTED;
+        }
+    } else {
+        switch (in->substeps) {
+            case 1: hipLaunchKernelGGL((k_adj_leaf<2, 1>), G, B, 0, st, la); break;
+            case 2: hipLaunchKernelGGL((k_adj_leaf<2, 2>), G, B, 0, st, la); break;
+            case 4: hipLaunchKernelGGL((k_adj_leaf<2, 4>), G, B, 0, st, la); break;
+            case 8: hipLaunchKernelGGL((k_adj_leaf<2, 8>), G, B, 0, st, la); break;
+            default: return RC_EUNSUPPORTED;
+        }
+    }
     RC_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_grad_pairs, dim3(stride_grid(vf->cap_vis, 256, 256 * 16)), dim3(256), 0, st, vf->counts,
+    hipLaunchKernelGGL(k_grad_pairs, dim3(stride_grid(vf->cap_vis * GRAD_MAX, 256, 256 * 32)), dim3(256), 0, st,
+                       vf->counts,
                        vf->cap_cand, vf->cand_offset, partial, gvis, 2 * nc);
     RC_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_grad_leaves, dim3(stride_grid(f->nleaves, 256, 256 * 16)), dim3(256), 0, st, vf->counts,

@@ -1,6 +1,6 @@
 // rc_composite.h -- the coarsening hierarchy as seen by compositing and its
-// adjoint: where a child's record of a pixel lives, and the ordered fold of
-// a node's children.
+// adjoint: the ordered fold of a node's children through the per-node child
+// descriptors written by rc_prune_visible.
 #pragma once
 
 #include "rc_host.h"
@@ -11,18 +11,15 @@ namespace rc {
 struct FoldCtx {
     const Cam* cams;
     int ncams;
-    int64_t N;
-    const int32_t* child;
-    const uint8_t* nlevel;
-    const uint32_t *nx, *ny, *nz;
-    const int32_t* leaf_vis;
-    const int16_t* vis_rect;
-    const int64_t* cand_offset;
-    const float2* rec_leaf;
+    int64_t N, ninternal;
+    const ChildDesc* desc;
     const int16_t* node_rect;
     const int64_t* node_offset;
+    const int32_t* rec_chunk;
+    const float2* rec_leaf;
     const float2* rec_node;
     const int64_t* counts;
+    int64_t nslots;
     SlotLayout L;
 };
 
@@ -32,69 +29,69 @@ inline FoldCtx make_fold_ctx(const rc_forest* f, const rc_index* ix, const void*
     C.cams = (const Cam*)dcams;
     C.ncams = ncams;
     C.N = f->nleaves;
-    C.child = ix->child;
-    C.nlevel = ix->level;
-    C.nx = ix->x;
-    C.ny = ix->y;
-    C.nz = ix->z;
-    C.leaf_vis = vf->leaf_vis;
-    C.vis_rect = vf->vis_rect;
-    C.cand_offset = vf->cand_offset;
-    C.rec_leaf = (const float2*)rec_leaf;
+    C.ninternal = ix->ninternal;
+    C.desc = (const ChildDesc*)vf->child_desc;
     C.node_rect = vf->node_rect;
     C.node_offset = vf->node_offset;
+    C.rec_chunk = vf->rec_chunk;
+    C.rec_leaf = (const float2*)rec_leaf;
     C.rec_node = (const float2*)rec_node;
     C.counts = vf->counts;
     C.L = make_layout(ix, ncams);
+    C.nslots = C.L.slot_begin[ix->maxlevel > 0 ? ix->maxlevel : 0];
     return C;
 }
 
-// Location of the record of child `ref` (a slot value of a level-l node) for
-// pixel (i, j) of camera `cam`: index into rec_leaf (leaf, returns 1) or
-// rec_node (internal, returns 2); 0 when the child contributes nothing.
-__device__ inline int child_slot(const FoldCtx& C, int cam, int32_t ref, int l, int i, int j, int64_t& idx) {
-    if (ref == RC_ABSENT) return 0;
-    if (ref >= 0) {
-        int lc = l + 1;
-        int64_t M = C.L.level_begin[lc + 1] - C.L.level_begin[lc];
-        int64_t slot = C.L.slot_begin[lc] + (int64_t)cam * M + (ref - C.L.level_begin[lc]);
-        Rect r = load_rect(C.node_rect + 4 * slot);
-        if (!r.contains(i, j)) return 0;
-        idx = C.node_offset[slot] + (int64_t)(j - r.j0) * r.width() + (i - r.i0);
-        return 2;
+__device__ inline bool desc_has(const ChildDesc& d, int i, int j) {
+    return i >= d.i0 && i <= d.i1 && j >= d.j0 && j <= d.j1;
+}
+
+__device__ inline int64_t desc_index(const ChildDesc& d, int i, int j) {
+    return (int64_t)(j - d.j0) * (d.i1 - d.i0 + 1) + (i - d.i0);
+}
+
+__device__ inline float2 desc_record(const FoldCtx& C, const ChildDesc& d, int i, int j) {
+    int64_t k = desc_index(d, i, j);
+    return d.off >= 0 ? C.rec_node[d.off + k] : C.rec_leaf[-1 - d.off + k];
+}
+
+// Group product of the children of descriptor slot `dslot` at pixel (i, j),
+// nearest child first (descriptors are stored in view order).  UNIFORM: dslot
+// is the same in every lane, so the descriptors come through the scalar cache.
+template <bool UNIFORM>
+__device__ inline float2 fold_desc(const FoldCtx& C, int64_t dslot, int i, int j) {
+    ChildDesc d[8];
+    if (UNIFORM) {
+#pragma unroll
+        for (int q = 0; q < 8; q++) d[q] = load_desc_scalar(C.desc, dslot * 8 + q);
+    } else {
+        const ChildDesc* dp = C.desc + dslot * 8;
+#pragma unroll
+        for (int q = 0; q < 8; q++) d[q] = load_desc(dp + q);
     }
-    int64_t leaf = -2 - (int64_t)ref;
-    int32_t v = C.leaf_vis[(int64_t)cam * C.N + leaf];
-    if (v < 0) return 0;
-    Rect r = load_rect(C.vis_rect + 4 * (int64_t)v);
-    if (!r.contains(i, j)) return 0;
-    idx = C.cand_offset[v] + (int64_t)(j - r.j0) * r.width() + (i - r.i0);
-    return 1;
-}
-
-__device__ inline float2 child_record(const FoldCtx& C, int cam, int32_t ref, int l, int i, int j) {
-    int64_t idx = 0;
-    int kind = child_slot(C, cam, ref, l, i, j, idx);
-    if (kind == 1) return C.rec_leaf[idx];
-    if (kind == 2) return C.rec_node[idx];
-    return make_float2(1.0f, 0.0f);
-}
-
-// Group product of the children of internal node m (level l) at pixel (i, j),
-// nearest child first.
-__device__ inline float2 fold_children(const FoldCtx& C, int cam, int64_t m, int l, int i, int j) {
-    int sb = view_bits(C.cams[cam], l, C.nx[m], C.ny[m], C.nz[m]);
     float2 acc = make_float2(1.0f, 0.0f);
-    const int32_t* ch = C.child + m * 8;
-    for (int q = 0; q < 8; q++) {
-        int32_t ref = ch[q ^ sb];
-        int64_t idx = 0;
-        int kind = child_slot(C, cam, ref, l, i, j, idx);
-        if (kind == 0) continue;
-        float2 rv = (kind == 1) ? C.rec_leaf[idx] : C.rec_node[idx];
-        acc = seg_combine(acc, rv);
-    }
+#pragma unroll
+    for (int q = 0; q < 8; q++)
+        if (desc_has(d[q], i, j)) acc = seg_combine(acc, desc_record(C, d[q], i, j));
     return acc;
+}
+
+// fold_desc, switching to scalar descriptor loads when the wave agrees on dslot
+// (inactive lanes pass active = false and take part in the vote only).
+__device__ inline float2 fold_desc_auto(const FoldCtx& C, int64_t dslot, bool active, int i, int j) {
+    int64_t d0 = uniform64(dslot);
+    if (__all(!active || dslot == d0)) return fold_desc<true>(C, d0, i, j);
+    return fold_desc<false>(C, dslot, i, j);
+}
+
+// Slot of internal-node record g of level l, searched between the slots of
+// its wave chunk's first and next records.
+__device__ inline int64_t record_slot(const FoldCtx& C, int64_t g, int64_t w, int64_t s0, int64_t s1, int64_t Rtot) {
+    int64_t lo = C.rec_chunk[w];
+    if (lo < s0) lo = s0;
+    int64_t hi = ((w + 1) * WAVE < Rtot) ? (int64_t)C.rec_chunk[w + 1] + 1 : s1;
+    if (hi > s1) hi = s1;
+    return upper_index(C.node_offset, lo, hi, g);
 }
 
 }  // namespace rc

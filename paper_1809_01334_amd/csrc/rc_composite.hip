@@ -15,25 +15,32 @@ namespace {
 __global__ __launch_bounds__(256) void k_fold_level(FoldCtx C, int l, float2* out) {
     if (C.counts[3]) return;
     int64_t s0 = C.L.slot_begin[l], s1 = C.L.slot_begin[l + 1];
-    int64_t R0 = C.node_offset[s0], R1 = C.node_offset[s1];
+    int64_t R0 = C.node_offset[s0], R1 = C.node_offset[s1], Rtot = C.node_offset[C.nslots];
     int64_t M = C.L.level_begin[l + 1] - C.L.level_begin[l];
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t g = R0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < R1; g += stride) {
-        int64_t slot = upper_index(C.node_offset, s0, s1, g);
+    int lane = threadIdx.x & (WAVE - 1);
+    int64_t wave = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    int64_t nw = (int64_t)gridDim.x * (blockDim.x / WAVE);
+    for (int64_t w = R0 / WAVE + wave; w * WAVE < R1; w += nw) {
+        int64_t g = w * WAVE + lane;
+        bool act = g >= R0 && g < R1;
+        int64_t gg = act ? g : (g < R0 ? R0 : R1 - 1);
+        int64_t slot = record_slot(C, gg, w, s0, s1, Rtot);
         int64_t loc = slot - s0;
-        int cam = (int)(loc / M);
-        int64_t m = C.L.level_begin[l] + (loc - (int64_t)cam * M);
+        int64_t cam = divu(loc, M);
+        int64_t m = C.L.level_begin[l] + (loc - cam * M);
         Rect r = load_rect(C.node_rect + 4 * slot);
-        int k = (int)(g - C.node_offset[slot]);
+        int k = (int)(gg - C.node_offset[slot]);
         int wr = r.width();
         int j = r.j0 + k / wr;
         int i = r.i0 + (k - (k / wr) * wr);
-        out[g] = fold_children(C, cam, m, l, i, j);
+        float2 v = fold_desc_auto(C, cam * C.ninternal + m, act, i, j);
+        if (act) out[g] = v;
     }
 }
 
 __global__ __launch_bounds__(256) void k_fold_root(FoldCtx C, int32_t root, int64_t npix, float* A, float* B,
-                                                   float* I) {
+                                                   float* I, const int32_t* leaf_vis, const int16_t* vis_rect,
+                                                   const int64_t* cand_offset) {
     if (C.counts[3]) return;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < npix; p += stride) {
@@ -44,9 +51,14 @@ __global__ __launch_bounds__(256) void k_fold_root(FoldCtx C, int32_t root, int6
         int i = (int)(loc - (int64_t)j * c.w);
         float2 acc = make_float2(1.0f, 0.0f);
         if (root >= 0) {
-            acc = fold_children(C, cam, root, 0, i, j);
+            acc = fold_desc_auto(C, (int64_t)cam * C.ninternal + root, true, i, j);
         } else if (root <= -2) {
-            acc = child_record(C, cam, root, 0, i, j);
+            // a forest of one leaf
+            int32_t v = leaf_vis[(int64_t)cam * C.N + (-2 - (int64_t)root)];
+            if (v >= 0) {
+                Rect r = load_rect(vis_rect + 4 * (int64_t)v);
+                if (r.contains(i, j)) acc = C.rec_leaf[cand_offset[v] + (int64_t)(j - r.j0) * r.width() + (i - r.i0)];
+            }
         }
         A[p] = acc.x;
         B[p] = acc.y;
@@ -66,6 +78,7 @@ extern "C" rc_status rc_composite(const rc_forest* f, const rc_index* ix, const 
     if ((s = check_vforest(vf, ix->maxlevel >= 1)) != RC_OK) return s;
     if (!dcams || ncams <= 0 || npix <= 0 || !rec_leaf || !A || !B || !I) return RC_EINVAL;
     if (rc_node_slots(ix, ncams) > 0 && !rec_node) return RC_EINVAL;
+    if ((s = check_tables(vf, ix, ncams)) != RC_OK) return s;
     hipStream_t st = (hipStream_t)stream;
     FoldCtx C = make_fold_ctx(f, ix, dcams, ncams, vf, rec_leaf, rec_node);
     unsigned grid = stride_grid(vf->cap_rec, 256, 256 * 16);
@@ -75,7 +88,7 @@ extern "C" rc_status rc_composite(const rc_forest* f, const rc_index* ix, const 
         RC_HIP(hipGetLastError());
     }
     hipLaunchKernelGGL(k_fold_root, dim3(stride_grid(npix, 256, 256 * 16)), dim3(256), 0, st, C, ix->root, npix, A,
-                       B, I);
+                       B, I, vf->leaf_vis, vf->vis_rect, vf->cand_offset);
     RC_HIP(hipGetLastError());
     return RC_OK;
 }

@@ -67,6 +67,16 @@ inline rc_status check_fields(const rc_fields* fl, const rc_integrator* in) {
     return RC_OK;
 }
 
+// The per-call tables written by rc_prune_visible and read by later calls.
+inline rc_status check_tables(const rc_vforest* vf, const rc_index* ix, int32_t ncams) {
+    if (!vf->cand_chunk) return RC_EINVAL;
+    if (ix->maxlevel >= 1 && ncams > 0 && (int64_t)ncams * (ix->level_begin[ix->maxlevel] - ix->level_begin[1]) > 0 &&
+        !vf->rec_chunk)
+        return RC_EINVAL;
+    if (ix->ninternal > 0 && !vf->child_desc) return RC_EINVAL;
+    return RC_OK;
+}
+
 // Slot layout of internal nodes of level >= 1: (level, camera, node).
 struct SlotLayout {
     int64_t level_begin[RC_QMAXLEVEL + 2];

@@ -186,6 +186,47 @@ __device__ inline int view_bits(const Cam& c, int level, uint32_t x, uint32_t y,
     return (c.o[0] >= m0 ? 1 : 0) | (c.o[1] >= m1 ? 2 : 0) | (c.o[2] >= m2 ? 4 : 0);
 }
 
+// Child of an internal node as seen by one camera: pixel rectangle and the
+// record index of its (0,0) corner pixel; off >= 0 indexes internal-node
+// records, off < 0 leaf records at -1 - off.  An empty rectangle marks a child
+// that is absent or invisible.  16 bytes, loaded as one 128-bit word.
+struct ChildDesc {
+    int16_t i0, i1, j0, j1;
+    int64_t off;
+};
+
+__device__ inline ChildDesc load_desc(const ChildDesc* p) {
+    uint4 u = *reinterpret_cast<const uint4*>(p);
+    ChildDesc d;
+    d.i0 = (int16_t)(u.x & 0xffff);
+    d.i1 = (int16_t)(u.x >> 16);
+    d.j0 = (int16_t)(u.y & 0xffff);
+    d.j1 = (int16_t)(u.y >> 16);
+    d.off = (int64_t)(((uint64_t)u.w << 32) | (uint64_t)u.z);
+    return d;
+}
+
+// Wave-uniform 64-bit value (first active lane's).
+__device__ inline int64_t uniform64(int64_t v) {
+    uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v & 0xffffffffu));
+    uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Descriptor load through the scalar cache: `idx` must be wave-uniform.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef const __attribute__((address_space(4))) u32x4* const_u32x4_ptr;
+__device__ inline ChildDesc load_desc_scalar(const ChildDesc* base, int64_t idx) {
+    u32x4 u = ((const_u32x4_ptr)base)[idx];
+    ChildDesc d;
+    d.i0 = (int16_t)(u.x & 0xffff);
+    d.i1 = (int16_t)(u.x >> 16);
+    d.j0 = (int16_t)(u.y & 0xffff);
+    d.j1 = (int16_t)(u.y >> 16);
+    d.off = (int64_t)(((uint64_t)u.w << 32) | (uint64_t)u.z);
+    return d;
+}
+
 // ---------------------------------------------------------------------------
 // segment group (eq. aggregate): near (+) far
 // ---------------------------------------------------------------------------
@@ -252,24 +293,73 @@ __device__ inline float2 rk4_step(float b0, float bm, float b1, float g0, float 
     return make_float2(A, B);
 }
 
-// RK4 over `nsub` equal substeps, farthest first, combined with (+).
+// Restriction of a trilinear field to the segment: with reference
+// coordinates xi(t) = a + d t (t = 0 far end, t = 1 near end) the
+// interpolant is exactly the cubic p0 + p1 t + p2 t^2 + p3 t^3, built by
+// interpolating along x, then y, then z on polynomial coefficients.
+__device__ inline void field_cubic(const float v[8], const float a[3], const float d[3], float p[4]) {
+    float e0[4], e1[4];  // linear in t per (y, z) corner pair m = y + 2 z
+#pragma unroll
+    for (int m = 0; m < 4; m++) {
+        float dv = v[2 * m + 1] - v[2 * m];
+        e0[m] = fmaf(a[0], dv, v[2 * m]);
+        e1[m] = d[0] * dv;
+    }
+    float f[2][3];  // quadratic in t per z
+#pragma unroll
+    for (int z = 0; z < 2; z++) {
+        float D0 = e0[2 * z + 1] - e0[2 * z], D1 = e1[2 * z + 1] - e1[2 * z];
+        f[z][0] = fmaf(a[1], D0, e0[2 * z]);
+        f[z][1] = fmaf(d[1], D0, fmaf(a[1], D1, e1[2 * z]));
+        f[z][2] = d[1] * D1;
+    }
+    float G0 = f[1][0] - f[0][0], G1 = f[1][1] - f[0][1], G2 = f[1][2] - f[0][2];
+    p[0] = fmaf(a[2], G0, f[0][0]);
+    p[1] = fmaf(d[2], G0, fmaf(a[2], G1, f[0][1]));
+    p[2] = fmaf(d[2], G1, fmaf(a[2], G2, f[0][2]));
+    p[3] = d[2] * G2;
+}
+
+__device__ inline float horner3(const float p[4], float t) { return fmaf(t, fmaf(t, fmaf(t, p[3], p[2]), p[1]), p[0]); }
+
+// RK4 over NSUB equal substeps (NSUB = 0: `nsub` at run time), farthest
+// first, combined with (+).  Field values come from the cubic restriction.
+template <int NSUB>
 __device__ inline float2 seg_rk4(const float kc[8], const float ec[8], const SegGeom& g, int nsub) {
-    float inv = 1.0f / (float)nsub;
+    const int ns = NSUB > 0 ? NSUB : nsub;
+    float inv = 1.0f / (float)ns;
     float h = g.dx * inv;
-    float xa = g.xf[0], ya = g.xf[1], za = g.xf[2];
-    float kf = trilin(kc, xa, ya, za), ef = trilin(ec, xa, ya, za);
+    float pk[4], pe[4];
+    field_cubic(kc, g.xf, g.dxi, pk);
+    field_cubic(ec, g.xf, g.dxi, pe);
+    float kf = pk[0], ef = pe[0];
     float2 acc = make_float2(1.0f, 0.0f);
-    for (int q = 0; q < nsub; q++) {
+    auto substep = [&](int q) {
         float tm = ((float)q + 0.5f) * inv, tn = (float)(q + 1) * inv;
-        float xm = fmaf(tm, g.dxi[0], xa), ym = fmaf(tm, g.dxi[1], ya), zm = fmaf(tm, g.dxi[2], za);
-        float xn = fmaf(tn, g.dxi[0], xa), yn = fmaf(tn, g.dxi[1], ya), zn = fmaf(tn, g.dxi[2], za);
-        float km = trilin(kc, xm, ym, zm), em = trilin(ec, xm, ym, zm);
-        float kn = trilin(kc, xn, yn, zn), en = trilin(ec, xn, yn, zn);
+        float km = horner3(pk, tm), em = horner3(pe, tm);
+        float kn = horner3(pk, tn), en = horner3(pe, tn);
         float2 s = rk4_step(kf, km, kn, ef, em, en, h);
         acc = seg_combine(s, acc);
         kf = kn;
         ef = en;
+    };
+    if constexpr (NSUB > 0) {
+#pragma unroll
+        for (int q = 0; q < NSUB; q++) substep(q);
+    } else {
+        for (int q = 0; q < ns; q++) substep(q);
     }
+    return acc;
+}
+
+// Constant-per-leaf coefficients through the same RK4 stages.
+template <int NSUB>
+__device__ inline float2 seg_rk4_const(float k, float e, float dx, int nsub) {
+    const int ns = NSUB > 0 ? NSUB : nsub;
+    float h = dx / (float)ns;
+    float2 s = rk4_step(k, k, k, e, e, e, h);
+    float2 acc = s;
+    for (int q = 1; q < ns; q++) acc = seg_combine(s, acc);
     return acc;
 }
 
@@ -282,8 +372,15 @@ __device__ inline float2 seg_const(float k, float e, float dx) {
 }
 
 // ---------------------------------------------------------------------------
-// searches
+// searches and index arithmetic
 // ---------------------------------------------------------------------------
+
+// a / b for non-negative operands: 32-bit division whenever both fit.
+__device__ inline int64_t divu(int64_t a, int64_t b) {
+    if (a < b) return 0;
+    if ((uint64_t)a <= 0xffffffffull && (uint64_t)b <= 0xffffffffull) return (int64_t)((uint32_t)a / (uint32_t)b);
+    return a / b;
+}
 
 // Largest s in [lo, hi) with off[s] <= g, for nondecreasing off and off[lo] <= g.
 __device__ inline int64_t upper_index(const int64_t* off, int64_t lo, int64_t hi, int64_t g) {
@@ -295,6 +392,15 @@ __device__ inline int64_t upper_index(const int64_t* off, int64_t lo, int64_t hi
             hi = mid;
     }
     return lo;
+}
+
+// Visible pair holding candidate g of wave chunk w: between the pairs of the
+// chunk's first candidate and the next chunk's (at most 64 pairs apart).
+__device__ inline int64_t cand_pair(const int64_t* cand_offset, const int32_t* cand_chunk, int64_t g, int64_t w,
+                                    int64_t nvis, int64_t ncand) {
+    int64_t lo = cand_chunk[w];
+    int64_t hi = ((w + 1) * 64 < ncand) ? (int64_t)cand_chunk[w + 1] + 1 : nvis;
+    return upper_index(cand_offset, lo, hi, g);
 }
 
 // Camera of a pixel in the concatenated images.
@@ -312,42 +418,60 @@ __device__ inline int camera_of_pixel(const Cam* cams, int ncams, int64_t p) {
 
 // ---------------------------------------------------------------------------
 // device-wide exclusive scan (reduce, scan of block sums, re-scan and apply);
-// deterministic and independent of timing.
+// deterministic and independent of timing.  Each thread takes ITEMS
+// consecutive items; ITEMS grows with n so the block count stays moderate.
 // ---------------------------------------------------------------------------
 
 constexpr int SCAN_NT = 256;
-constexpr int SCAN_ITEMS = 16;
-constexpr int64_t SCAN_CHUNK = (int64_t)SCAN_NT * SCAN_ITEMS;
+constexpr int SCAN_MAX_ITEMS = 16;
 
 struct I64x2 {
     int64_t a, b;
     __device__ __host__ I64x2 operator+(const I64x2& o) const { return I64x2{a + o.a, b + o.b}; }
 };
 
+struct I64x3 {
+    int64_t a, b, c;
+    __device__ __host__ I64x3 operator+(const I64x3& o) const { return I64x3{a + o.a, b + o.b, c + o.c}; }
+};
+
+__device__ inline int64_t shfl_up_t(int64_t v, int d) { return __shfl_up(v, d); }
+__device__ inline I64x2 shfl_up_t(I64x2 v, int d) { return I64x2{__shfl_up(v.a, d), __shfl_up(v.b, d)}; }
+__device__ inline I64x3 shfl_up_t(I64x3 v, int d) {
+    return I64x3{__shfl_up(v.a, d), __shfl_up(v.b, d), __shfl_up(v.c, d)};
+}
+
+// Exclusive scan over the block; `sh` holds NT/64 wave totals.
 template <typename T, int NT>
 __device__ inline T block_exclusive_scan(T v, T* sh, T& total) {
-    int tid = threadIdx.x;
-    sh[tid] = v;
-    __syncthreads();
-    for (int off = 1; off < NT; off <<= 1) {
-        T t = (tid >= off) ? sh[tid - off] : T();
-        __syncthreads();
-        if (tid >= off) sh[tid] = sh[tid] + t;
-        __syncthreads();
+    int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    T x = v;
+    for (int d = 1; d < 64; d <<= 1) {
+        T y = shfl_up_t(x, d);
+        if (lane >= d) x = x + y;
     }
-    total = sh[NT - 1];
-    T ex = (tid > 0) ? sh[tid - 1] : T();
+    T ex = shfl_up_t(x, 1);
+    if (lane == 0) ex = T();
+    if (lane == 63) sh[wid] = x;
     __syncthreads();
-    return ex;
+    T wpre = T();
+    total = T();
+    for (int k = 0; k < NT / 64; k++) {
+        T t = sh[k];
+        if (k < wid) wpre = wpre + t;
+        total = total + t;
+    }
+    __syncthreads();
+    return wpre + ex;
 }
 
 // Src: __device__ Item operator()(int64_t i) with member `T val`.
-template <typename T, typename Src>
+template <typename T, int ITEMS, typename Src>
 __global__ __launch_bounds__(SCAN_NT) void k_scan_reduce(int64_t n, Src src, T* partial) {
-    __shared__ T sh[SCAN_NT];
-    int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK + (int64_t)threadIdx.x * SCAN_ITEMS;
+    __shared__ T sh[SCAN_NT / 64];
+    int64_t base = ((int64_t)blockIdx.x * SCAN_NT + threadIdx.x) * ITEMS;
     T acc = T();
-    for (int k = 0; k < SCAN_ITEMS; k++) {
+    for (int k = 0; k < ITEMS; k++) {
         int64_t i = base + k;
         if (i < n) acc = acc + src(i).val;
     }
@@ -359,14 +483,23 @@ __global__ __launch_bounds__(SCAN_NT) void k_scan_reduce(int64_t n, Src src, T* 
 // Single block: partial[0..nb) -> exclusive prefix, partial[nb] = total.
 template <typename T>
 __global__ __launch_bounds__(SCAN_NT) void k_scan_partials(int64_t nb, T* partial) {
-    __shared__ T sh[SCAN_NT];
+    __shared__ T sh[SCAN_NT / 64];
+    constexpr int PI = 4;
     T carry = T();
-    for (int64_t base = 0; base < nb; base += SCAN_NT) {
-        int64_t i = base + threadIdx.x;
-        T v = (i < nb) ? partial[i] : T();
+    for (int64_t base = 0; base < nb; base += SCAN_NT * PI) {
+        int64_t i0 = base + (int64_t)threadIdx.x * PI;
+        T v[PI];
+        T acc = T();
+        for (int k = 0; k < PI; k++) {
+            v[k] = (i0 + k < nb) ? partial[i0 + k] : T();
+            acc = acc + v[k];
+        }
         T total;
-        T ex = block_exclusive_scan<T, SCAN_NT>(v, sh, total);
-        if (i < nb) partial[i] = carry + ex;
+        T run = carry + block_exclusive_scan<T, SCAN_NT>(acc, sh, total);
+        for (int k = 0; k < PI; k++) {
+            if (i0 + k < nb) partial[i0 + k] = run;
+            run = run + v[k];
+        }
         carry = carry + total;
     }
     if (threadIdx.x == 0) partial[nb] = carry;
@@ -374,18 +507,18 @@ __global__ __launch_bounds__(SCAN_NT) void k_scan_partials(int64_t nb, T* partia
 
 // Dst: __device__ void operator()(int64_t i, T prefix, const Item& item) and
 //      __device__ void total(T tot)  (called once, by the last block).
-template <typename T, typename Src, typename Dst>
+template <typename T, int ITEMS, typename Src, typename Dst>
 __global__ __launch_bounds__(SCAN_NT) void k_scan_apply(int64_t n, int64_t nb, Src src, Dst dst, const T* partial) {
-    __shared__ T sh[SCAN_NT];
-    int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK + (int64_t)threadIdx.x * SCAN_ITEMS;
+    __shared__ T sh[SCAN_NT / 64];
+    int64_t base = ((int64_t)blockIdx.x * SCAN_NT + threadIdx.x) * ITEMS;
     T acc = T();
-    for (int k = 0; k < SCAN_ITEMS; k++) {
+    for (int k = 0; k < ITEMS; k++) {
         int64_t i = base + k;
         if (i < n) acc = acc + src(i).val;
     }
     T total;
     T run = partial[blockIdx.x] + block_exclusive_scan<T, SCAN_NT>(acc, sh, total);
-    for (int k = 0; k < SCAN_ITEMS; k++) {
+    for (int k = 0; k < ITEMS; k++) {
         int64_t i = base + k;
         if (i < n) {
             auto item = src(i);
@@ -396,22 +529,38 @@ __global__ __launch_bounds__(SCAN_NT) void k_scan_apply(int64_t n, int64_t nb, S
     if (blockIdx.x == nb - 1 && threadIdx.x == 0) dst.total(partial[nb]);
 }
 
-template <typename T, typename Src, typename Dst>
-inline hipError_t launch_scan(int64_t n, Src src, Dst dst, T* partial, hipStream_t st) {
-    int64_t nb = (n + SCAN_CHUNK - 1) / SCAN_CHUNK;
-    if (nb < 1) nb = 1;
-    hipLaunchKernelGGL((k_scan_reduce<T, Src>), dim3((unsigned)nb), dim3(SCAN_NT), 0, st, n, src, partial);
+inline int scan_items(int64_t n) {
+    if (n <= (int64_t)SCAN_NT * 1024) return 1;
+    if (n <= (int64_t)SCAN_NT * 4 * 2048) return 4;
+    return SCAN_MAX_ITEMS;
+}
+
+inline int64_t scan_blocks(int64_t n) {
+    int64_t chunk = (int64_t)SCAN_NT * scan_items(n);
+    int64_t nb = (n + chunk - 1) / chunk;
+    return nb < 1 ? 1 : nb;
+}
+
+template <typename T, int ITEMS, typename Src, typename Dst>
+inline hipError_t launch_scan_n(int64_t n, int64_t nb, Src src, Dst dst, T* partial, hipStream_t st) {
+    hipLaunchKernelGGL((k_scan_reduce<T, ITEMS, Src>), dim3((unsigned)nb), dim3(SCAN_NT), 0, st, n, src, partial);
     hipLaunchKernelGGL((k_scan_partials<T>), dim3(1), dim3(SCAN_NT), 0, st, nb, partial);
-    hipLaunchKernelGGL((k_scan_apply<T, Src, Dst>), dim3((unsigned)nb), dim3(SCAN_NT), 0, st, n, nb, src, dst,
-                       (const T*)partial);
+    hipLaunchKernelGGL((k_scan_apply<T, ITEMS, Src, Dst>), dim3((unsigned)nb), dim3(SCAN_NT), 0, st, n, nb, src,
+                       dst, (const T*)partial);
     return hipGetLastError();
 }
 
-inline size_t scan_partial_bytes(int64_t n, size_t elem) {
-    int64_t nb = (n + SCAN_CHUNK - 1) / SCAN_CHUNK;
-    if (nb < 1) nb = 1;
-    return (size_t)(nb + 1) * elem;
+template <typename T, typename Src, typename Dst>
+inline hipError_t launch_scan(int64_t n, Src src, Dst dst, T* partial, hipStream_t st) {
+    int64_t nb = scan_blocks(n);
+    switch (scan_items(n)) {
+        case 1: return launch_scan_n<T, 1>(n, nb, src, dst, partial, st);
+        case 4: return launch_scan_n<T, 4>(n, nb, src, dst, partial, st);
+        default: return launch_scan_n<T, SCAN_MAX_ITEMS>(n, nb, src, dst, partial, st);
+    }
 }
+
+inline size_t scan_partial_bytes(int64_t n, size_t elem) { return (size_t)(scan_blocks(n) + 1) * elem; }
 
 // Grid for a grid-stride kernel over at most `n` items.
 inline unsigned stride_grid(int64_t n, int nt, unsigned maxblocks = 256 * 16) {

@@ -10,100 +10,157 @@
 namespace rc {
 namespace {
 
-struct LeafItem {
-    I64x2 val;  // (visible, rectangle area)
+// One scan over (camera, leaf) items followed by (level >= 1, camera, node)
+// slots; the value counts (visible pairs, candidate records, node records).
+struct Item {
+    I64x3 val;
     Rect r;
 };
 
-struct LeafSrc {
+struct PruneSrc {
     const Cam* cams;
     const uint8_t* level;
     const uint32_t *x, *y, *z;
-    int64_t N;
-    __device__ LeafItem operator()(int64_t i) const {
-        int64_t cam = i / N, l = i - cam * N;
+    const uint8_t* nlevel;
+    const uint32_t *nx, *ny, *nz;
+    int64_t N, nleafitems;
+    SlotLayout L;
+    __device__ Item operator()(int64_t i) const {
+        Item it;
         double lo[3], hi[3];
-        node_box(level[l], x[l], y[l], z[l], lo, hi);
-        LeafItem it;
-        it.r = box_rect(cams[cam], lo, hi);
-        it.val = it.r.empty() ? I64x2{0, 0} : I64x2{1, it.r.area()};
+        if (i < nleafitems) {
+            int64_t cam = divu(i, N), l = i - cam * N;
+            node_box(level[l], x[l], y[l], z[l], lo, hi);
+            it.r = box_rect(cams[cam], lo, hi);
+            it.val = it.r.empty() ? I64x3{0, 0, 0} : I64x3{1, it.r.area(), 0};
+        } else {
+            int64_t s = i - nleafitems;
+            int lv = 1;
+            while (lv < L.maxlevel && s >= L.slot_begin[lv + 1]) lv++;
+            int64_t M = L.level_begin[lv + 1] - L.level_begin[lv];
+            int64_t loc = s - L.slot_begin[lv];
+            int64_t cam = divu(loc, M);
+            int64_t m = L.level_begin[lv] + (loc - cam * M);
+            node_box(nlevel[m], nx[m], ny[m], nz[m], lo, hi);
+            it.r = box_rect(cams[cam], lo, hi);
+            it.val = I64x3{0, 0, it.r.area()};
+        }
         return it;
     }
 };
 
-struct LeafDst {
-    int64_t N, cap_vis, cap_cand;
+struct PruneDst {
+    int64_t N, nleafitems, nslots, cap_vis, cap_cand, cap_rec;
     int32_t* vis_leaf;
     int16_t* vis_cam;
     int16_t* vis_rect;
     int64_t* cand_offset;
     int32_t* leaf_vis;
-    int64_t* counts;
-    __device__ void operator()(int64_t i, I64x2 pre, const LeafItem& it) const {
-        int32_t v = -1;
-        if (it.val.a && pre.a < cap_vis && pre.b + it.val.b <= cap_cand) {
-            int64_t cam = i / N;
-            v = (int32_t)pre.a;
-            vis_leaf[v] = (int32_t)(i - cam * N);
-            vis_cam[v] = (int16_t)cam;
-            store_rect(vis_rect + 4 * (int64_t)v, it.r);
-            cand_offset[v] = pre.b;
-        }
-        leaf_vis[i] = v;
-    }
-    __device__ void total(I64x2 t) const {
-        counts[0] = t.a;
-        counts[1] = t.b;
-        if (t.a <= cap_vis) cand_offset[t.a] = t.b;
-        counts[3] = (t.a > cap_vis || t.b > cap_cand) ? 1 : 0;
-    }
-};
-
-struct NodeItem {
-    int64_t val;  // rectangle area
-    Rect r;
-};
-
-struct NodeSrc {
-    const Cam* cams;
-    const uint8_t* level;
-    const uint32_t *x, *y, *z;
-    SlotLayout L;
-    __device__ NodeItem operator()(int64_t s) const {
-        int l = 1;
-        while (l < L.maxlevel && s >= L.slot_begin[l + 1]) l++;
-        int64_t M = L.level_begin[l + 1] - L.level_begin[l];
-        int64_t loc = s - L.slot_begin[l];
-        int64_t cam = loc / M;
-        int64_t m = L.level_begin[l] + (loc - cam * M);
-        double lo[3], hi[3];
-        node_box(level[m], x[m], y[m], z[m], lo, hi);
-        NodeItem it;
-        it.r = box_rect(cams[cam], lo, hi);
-        it.val = it.r.area();
-        return it;
-    }
-};
-
-struct NodeDst {
-    int64_t nslots, cap_rec;
     int16_t* node_rect;
     int64_t* node_offset;
     int64_t* counts;
-    __device__ void operator()(int64_t s, int64_t pre, const NodeItem& it) const {
-        store_rect(node_rect + 4 * s, it.r);
-        node_offset[s] = pre;
+    __device__ void operator()(int64_t i, I64x3 pre, const Item& it) const {
+        if (i < nleafitems) {
+            int32_t v = -1;
+            if (it.val.a && pre.a < cap_vis && pre.b + it.val.b <= cap_cand) {
+                int64_t cam = divu(i, N);
+                v = (int32_t)pre.a;
+                vis_leaf[v] = (int32_t)(i - cam * N);
+                vis_cam[v] = (int16_t)cam;
+                store_rect(vis_rect + 4 * (int64_t)v, it.r);
+                cand_offset[v] = pre.b;
+            }
+            leaf_vis[i] = v;
+        } else {
+            int64_t s = i - nleafitems;
+            store_rect(node_rect + 4 * s, it.r);
+            node_offset[s] = pre.c;
+        }
     }
-    __device__ void total(int64_t t) const {
-        node_offset[nslots] = t;
-        counts[2] = t;
-        if (t > cap_rec) counts[3] |= 2;
+    __device__ void total(I64x3 t) const {
+        counts[0] = t.a;
+        counts[1] = t.b;
+        counts[2] = t.c;
+        if (t.a <= cap_vis) cand_offset[t.a] = t.b;
+        if (node_offset) node_offset[nslots] = t.c;
+        counts[3] = ((t.a > cap_vis || t.b > cap_cand) ? 1 : 0) | (t.c > cap_rec ? 2 : 0);
     }
 };
 
-__global__ void k_empty_nodes(int64_t* node_offset, int64_t* counts) {
-    if (node_offset) node_offset[0] = 0;
-    counts[2] = 0;
+// table[w] = the item k whose range [off[k], off[k+1]) holds index 64 w.
+__device__ inline void chunk_entry(const int64_t* off, int64_t n, int64_t w, int32_t* table) {
+    table[w] = (int32_t)upper_index(off, 0, n, w * WAVE);
+}
+
+// Children of every (camera, internal node) in view order with their
+// rectangles and record offsets.
+struct DescArgs {
+    const Cam* cams;
+    int64_t N, ninternal, total;
+    const int32_t* child;
+    const uint8_t* nlevel;
+    const uint32_t *nx, *ny, *nz;
+    const int32_t* leaf_vis;
+    const int16_t* vis_rect;
+    const int64_t* cand_offset;
+    const int16_t* node_rect;
+    const int64_t* node_offset;
+    const int64_t* counts;
+    ChildDesc* desc;
+    SlotLayout L;
+};
+
+__device__ inline void child_desc_entry(const DescArgs& a, int64_t t) {
+    int q = (int)(t & 7);
+    int64_t dslot = t >> 3;
+    int64_t cam = divu(dslot, a.ninternal);
+    int64_t m = dslot - cam * a.ninternal;
+    int l = a.nlevel[m];
+    int sb = view_bits(a.cams[cam], l, a.nx[m], a.ny[m], a.nz[m]);
+    int32_t ref = a.child[m * 8 + (q ^ sb)];
+    Rect r{1, 0, 1, 0};
+    int64_t off = 0;
+    if (ref <= -2) {
+        int64_t leaf = -2 - (int64_t)ref;
+        int32_t v = a.leaf_vis[cam * a.N + leaf];
+        if (v >= 0) {
+            r = load_rect(a.vis_rect + 4 * (int64_t)v);
+            off = -1 - a.cand_offset[v];
+        }
+    } else if (ref >= 0) {
+        int lc = l + 1;
+        int64_t M = a.L.level_begin[lc + 1] - a.L.level_begin[lc];
+        int64_t slot = a.L.slot_begin[lc] + cam * M + (ref - a.L.level_begin[lc]);
+        r = load_rect(a.node_rect + 4 * slot);
+        off = a.node_offset[slot];
+    }
+    uint4 u;
+    u.x = (uint32_t)(uint16_t)r.i0 | ((uint32_t)(uint16_t)r.i1 << 16);
+    u.y = (uint32_t)(uint16_t)r.j0 | ((uint32_t)(uint16_t)r.j1 << 16);
+    u.z = (uint32_t)((uint64_t)off & 0xffffffffu);
+    u.w = (uint32_t)((uint64_t)off >> 32);
+    *reinterpret_cast<uint4*>(a.desc + t) = u;
+}
+
+// Chunk tables of candidates and node records, then the child descriptors,
+// in one grid: index ranges [0, nc1), [nc1, nc1 + nc2), [nc1 + nc2, end).
+__global__ __launch_bounds__(256) void k_tables(DescArgs a, int64_t nslots, int64_t nc1, int64_t nc2,
+                                                int32_t* cand_chunk, int32_t* rec_chunk) {
+    if (a.counts[3]) return;
+    int64_t nvis = a.counts[0];
+    int64_t w1 = (a.counts[1] + WAVE - 1) / WAVE, w2 = (a.counts[2] + WAVE - 1) / WAVE;
+    int64_t end = nc1 + nc2 + a.total;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < end; t += stride) {
+        if (t < nc1) {
+            if (t < w1) chunk_entry(a.cand_offset, nvis, t, cand_chunk);
+        } else if (t < nc1 + nc2) {
+            int64_t w = t - nc1;
+            if (w < w2) chunk_entry(a.node_offset, nslots, w, rec_chunk);
+        } else {
+            child_desc_entry(a, t - nc1 - nc2);
+        }
+    }
 }
 
 }  // namespace
@@ -118,26 +175,29 @@ extern "C" rc_status rc_prune_visible(const rc_forest* f, const rc_index* ix, co
     if ((s = check_index(ix)) != RC_OK) return s;
     if ((s = check_vforest(vf, ix->maxlevel >= 1)) != RC_OK) return s;
     if (!dcams || ncams <= 0 || ncams > 32767) return RC_EINVAL;
+    if ((s = check_tables(vf, ix, ncams)) != RC_OK) return s;
     if (!ws || ws_bytes < rc_workspace_bytes(f, ix, ncams, nullptr)) return RC_EWORKSPACE;
     hipStream_t st = (hipStream_t)stream;
     const Cam* cams = (const Cam*)dcams;
     int64_t N = f->nleaves;
 
-    LeafSrc ls{cams, f->level, f->x, f->y, f->z, N};
-    LeafDst ld{N, vf->cap_vis, vf->cap_cand, vf->vis_leaf, vf->vis_cam, vf->vis_rect, vf->cand_offset, vf->leaf_vis,
-               vf->counts};
-    RC_HIP(launch_scan<I64x2>(N * (int64_t)ncams, ls, ld, (I64x2*)ws, st));
-
     SlotLayout L = make_layout(ix, ncams);
     int64_t nslots = rc_node_slots(ix, ncams);
-    NodeSrc ns{cams, ix->level, ix->x, ix->y, ix->z, L};
-    NodeDst nd{nslots, vf->cap_rec, vf->node_rect, vf->node_offset, vf->counts};
-    if (nslots > 0) {
-        RC_HIP(launch_scan<int64_t>(nslots, ns, nd, (int64_t*)ws, st));
-    } else {
-        // no internal node below the roots: the record space is empty
-        hipLaunchKernelGGL(k_empty_nodes, dim3(1), dim3(1), 0, st, vf->node_offset, vf->counts);
-        RC_HIP(hipGetLastError());
-    }
+    int64_t nleafitems = N * (int64_t)ncams;
+    PruneSrc src{cams, f->level, f->x, f->y, f->z, ix->level, ix->x, ix->y, ix->z, N, nleafitems, L};
+    PruneDst dst{N,           nleafitems,      nslots,      vf->cap_vis,   vf->cap_cand,
+                 vf->cap_rec, vf->vis_leaf,    vf->vis_cam, vf->vis_rect,  vf->cand_offset,
+                 vf->leaf_vis, vf->node_rect,  nslots > 0 ? vf->node_offset : vf->node_offset, vf->counts};
+    RC_HIP(launch_scan<I64x3>(nleafitems + nslots, src, dst, (I64x3*)ws, st));
+
+    DescArgs da{cams,          N,            ix->ninternal,   ix->ninternal * ncams * 8,
+                ix->child,     ix->level,    ix->x,           ix->y,
+                ix->z,         vf->leaf_vis, vf->vis_rect,    vf->cand_offset,
+                vf->node_rect, vf->node_offset, vf->counts,   (ChildDesc*)vf->child_desc,
+                L};
+    int64_t nc1 = vf->cap_cand / WAVE + 1, nc2 = nslots > 0 ? vf->cap_rec / WAVE + 1 : 0;
+    hipLaunchKernelGGL(k_tables, dim3(stride_grid(nc1 + nc2 + da.total, 256, 256 * 32)), dim3(256), 0, st, da, nslots,
+                       nc1, nc2, vf->cand_chunk, vf->rec_chunk);
+    RC_HIP(hipGetLastError());
     return RC_OK;
 }

@@ -22,59 +22,155 @@ struct SegArgs {
     const int16_t* vis_rect;
     const int64_t* cand_offset;
     const int64_t* counts;
+    const int32_t* cand_chunk;
     int64_t cap_cand;
     float2* rec;
     uint8_t* hit;
     double2* sio;
 };
 
-// KIND: 0 = constant analytic, 1 = constant RK4, 2 = trilinear RK4
-template <int KIND>
-__global__ __launch_bounds__(256) void k_segments(SegArgs a) {
+// Pairing of candidate g: leaf, ray, hit interval (Sec. 2.1, 2.2).
+struct Pairing {
+    int32_t leaf;
+    int lv;
+    bool hit;
+    double lo[3], rho[3], rr[3], s_in, s_out;
+};
+
+__device__ inline Pairing pair_candidate(const SegArgs& a, int64_t g, int64_t w, int64_t nvis, int64_t ncand) {
+    Pairing p;
+    int64_t v = cand_pair(a.cand_offset, a.cand_chunk, g, w, nvis, ncand);
+    p.leaf = a.vis_leaf[v];
+    const Cam& c = a.cams[a.vis_cam[v]];
+    Rect r = load_rect(a.vis_rect + 4 * v);
+    int k = (int)(g - a.cand_offset[v]);
+    int wr = r.width();
+    int j = r.j0 + k / wr;
+    int i = r.i0 + (k - (k / wr) * wr);
+    p.lv = a.level[p.leaf];
+    double hi[3];
+    node_box(p.lv, a.x[p.leaf], a.y[p.leaf], a.z[p.leaf], p.lo, hi);
+    pixel_ray(c, i, j, p.rho, p.rr);
+    p.hit = slab_hit(c, p.rho, p.rr, p.lo, hi, p.s_in, p.s_out);
+    return p;
+}
+
+template <int KIND, int NSUB>
+__device__ inline float2 integrate(const SegArgs& a, int64_t leaf, const SegGeom& sg) {
+    if (KIND == 1) return seg_rk4_const<NSUB>(a.kappa[leaf], a.eps[leaf], sg.dx, a.nsub);
+    float kc[8], ec[8];
+    const float4* kp = reinterpret_cast<const float4*>(a.kappa + leaf * 8);
+    const float4* ep = reinterpret_cast<const float4*>(a.eps + leaf * 8);
+    float4 k0 = kp[0], k1 = kp[1], e0 = ep[0], e1 = ep[1];
+    kc[0] = k0.x; kc[1] = k0.y; kc[2] = k0.z; kc[3] = k0.w;
+    kc[4] = k1.x; kc[5] = k1.y; kc[6] = k1.z; kc[7] = k1.w;
+    ec[0] = e0.x; ec[1] = e0.y; ec[2] = e0.z; ec[3] = e0.w;
+    ec[4] = e1.x; ec[5] = e1.y; ec[6] = e1.z; ec[7] = e1.w;
+    return seg_rk4<NSUB>(kc, ec, sg, a.nsub);
+}
+
+// Closed-form constant coefficients: one candidate per lane.
+__global__ __launch_bounds__(256) void k_segments_analytic(SegArgs a) {
     if (a.counts[3]) return;
     int64_t nvis = a.counts[0];
     int64_t ncand = a.counts[1] < a.cap_cand ? a.counts[1] : a.cap_cand;
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < ncand; g += stride) {
-        int64_t v = upper_index(a.cand_offset, 0, nvis, g);
-        int32_t leaf = a.vis_leaf[v];
-        const Cam& c = a.cams[a.vis_cam[v]];
-        Rect r = load_rect(a.vis_rect + 4 * v);
-        int k = (int)(g - a.cand_offset[v]);
-        int wr = r.width();
-        int j = r.j0 + k / wr;
-        int i = r.i0 + (k - (k / wr) * wr);
-        int lv = a.level[leaf];
-        double lo[3], hi[3], rho[3], rr[3], s_in, s_out;
-        node_box(lv, a.x[leaf], a.y[leaf], a.z[leaf], lo, hi);
-        pixel_ray(c, i, j, rho, rr);
-        bool h = slab_hit(c, rho, rr, lo, hi, s_in, s_out);
+    int lane = threadIdx.x & (WAVE - 1);
+    int64_t wave = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    int64_t nw = (int64_t)gridDim.x * (blockDim.x / WAVE);
+    for (int64_t w = wave; w * WAVE < ncand; w += nw) {
+        int64_t g = w * WAVE + lane;
+        if (g >= ncand) continue;
+        Pairing p = pair_candidate(a, g, w, nvis, ncand);
         float2 ab = make_float2(1.0f, 0.0f);
-        if (h) {
-            SegGeom sg = seg_geom(rho, rr, s_in, s_out, lo, lv);
-            if (KIND == 0) {
-                ab = seg_const(a.kappa[leaf], a.eps[leaf], sg.dx);
-            } else if (KIND == 1) {
-                float kc[8], ec[8];
-                float kv = a.kappa[leaf], ev = a.eps[leaf];
-                for (int q = 0; q < 8; q++) {
-                    kc[q] = kv;
-                    ec[q] = ev;
-                }
-                ab = seg_rk4(kc, ec, sg, a.nsub);
-            } else {
-                float kc[8], ec[8];
-                for (int q = 0; q < 8; q++) {
-                    kc[q] = a.kappa[(int64_t)q * a.N + leaf];
-                    ec[q] = a.eps[(int64_t)q * a.N + leaf];
-                }
-                ab = seg_rk4(kc, ec, sg, a.nsub);
-            }
+        if (p.hit) {
+            SegGeom sg = seg_geom(p.rho, p.rr, p.s_in, p.s_out, p.lo, p.lv);
+            ab = seg_const(a.kappa[p.leaf], a.eps[p.leaf], sg.dx);
         }
         a.rec[g] = ab;
-        if (a.hit) a.hit[g] = h ? 1 : 0;
-        if (a.sio) a.sio[g] = h ? make_double2(s_in, s_out) : make_double2(0.0, 0.0);
+        if (a.hit) a.hit[g] = p.hit ? 1 : 0;
+        if (a.sio) a.sio[g] = p.hit ? make_double2(p.s_in, p.s_out) : make_double2(0.0, 0.0);
     }
+}
+
+// RK4 segments.  Pairing runs one candidate per lane; hits go to a per-wave
+// LDS queue and are integrated 64 at a time, so the RK4 stages run with every
+// lane busy whatever the hit rate of the candidates.
+constexpr int QCAP = 128;
+struct HitQueue {
+    int64_t g[QCAP];
+    int32_t leaf[QCAP];
+    float xf0[QCAP], xf1[QCAP], xf2[QCAP], d0[QCAP], d1[QCAP], d2[QCAP], dx[QCAP];
+};
+
+template <int KIND, int NSUB>
+__device__ inline void drain(const SegArgs& a, HitQueue& q, int e) {
+    SegGeom sg;
+    sg.xf[0] = q.xf0[e];
+    sg.xf[1] = q.xf1[e];
+    sg.xf[2] = q.xf2[e];
+    sg.dxi[0] = q.d0[e];
+    sg.dxi[1] = q.d1[e];
+    sg.dxi[2] = q.d2[e];
+    sg.dx = q.dx[e];
+    int64_t g = q.g[e];
+    int64_t leaf = q.leaf[e];
+    a.rec[g] = integrate<KIND, NSUB>(a, leaf, sg);
+}
+
+template <int KIND, int NSUB>
+__global__ __launch_bounds__(256) void k_segments_rk4(SegArgs a) {
+    __shared__ HitQueue Q[256 / WAVE];
+    if (a.counts[3]) return;
+    int64_t nvis = a.counts[0];
+    int64_t ncand = a.counts[1] < a.cap_cand ? a.counts[1] : a.cap_cand;
+    int lane = threadIdx.x & (WAVE - 1);
+    HitQueue& q = Q[threadIdx.x / WAVE];
+    int64_t wave = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    int64_t nw = (int64_t)gridDim.x * (blockDim.x / WAVE);
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int qn = 0;  // queued hits, the same in every lane
+    for (int64_t w = wave; w * WAVE < ncand; w += nw) {
+        int64_t g = w * WAVE + lane;
+        bool h = false;
+        SegGeom sg;
+        int32_t leaf = 0;
+        if (g < ncand) {
+            Pairing p = pair_candidate(a, g, w, nvis, ncand);
+            h = p.hit;
+            leaf = p.leaf;
+            if (h)
+                sg = seg_geom(p.rho, p.rr, p.s_in, p.s_out, p.lo, p.lv);
+            else
+                a.rec[g] = make_float2(1.0f, 0.0f);
+            if (a.hit) a.hit[g] = h ? 1 : 0;
+            if (a.sio) a.sio[g] = h ? make_double2(p.s_in, p.s_out) : make_double2(0.0, 0.0);
+        }
+        uint64_t mask = __ballot(h);
+        if (h) {
+            int pos = qn + __popcll(mask & below);
+            q.g[pos] = g;
+            q.leaf[pos] = leaf;
+            q.xf0[pos] = sg.xf[0];
+            q.xf1[pos] = sg.xf[1];
+            q.xf2[pos] = sg.xf[2];
+            q.d0[pos] = sg.dxi[0];
+            q.d1[pos] = sg.dxi[1];
+            q.d2[pos] = sg.dxi[2];
+            q.dx[pos] = sg.dx;
+        }
+        qn += __popcll(mask);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (qn >= WAVE) {
+            drain<KIND, NSUB>(a, q, qn - WAVE + lane);
+            qn -= WAVE;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+    }
+    if (lane < qn) drain<KIND, NSUB>(a, q, lane);
 }
 
 }  // namespace
@@ -89,18 +185,33 @@ extern "C" rc_status rc_segments(const rc_forest* f, const rc_fields* fl, const 
     if (s != RC_OK) return s;
     if ((s = check_fields(fl, in)) != RC_OK) return s;
     if ((s = check_vforest(vf, false)) != RC_OK) return s;
-    if (!dcams || ncams <= 0 || !rec_leaf) return RC_EINVAL;
+    if (!dcams || ncams <= 0 || !rec_leaf || !vf->cand_chunk) return RC_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     SegArgs a{(const Cam*)dcams, f->level,       f->x,           f->y,         f->z,        f->nleaves,
               fl->kappa,        fl->eps,        in->substeps,   vf->vis_leaf, vf->vis_cam, vf->vis_rect,
-              vf->cand_offset,  vf->counts,     vf->cap_cand,   (float2*)rec_leaf, hit,    (double2*)sio};
+              vf->cand_offset,  vf->counts,     vf->cand_chunk, vf->cap_cand, (float2*)rec_leaf, hit,
+              (double2*)sio};
     unsigned grid = stride_grid(vf->cap_cand, 256, 256 * 8);
-    if (in->method == RC_INT_ANALYTIC)
-        hipLaunchKernelGGL(k_segments<0>, dim3(grid), dim3(256), 0, st, a);
-    else if (fl->kind == RC_FIELD_CONST)
-        hipLaunchKernelGGL(k_segments<1>, dim3(grid), dim3(256), 0, st, a);
-    else
-        hipLaunchKernelGGL(k_segments<2>, dim3(grid), dim3(256), 0, st, a);
+    dim3 G(grid), B(256);
+    if (in->method == RC_INT_ANALYTIC) {
+        hipLaunchKernelGGL(k_segments_analytic, G, B, 0, st, a);
+    } else if (fl->kind == RC_FIELD_CONST) {
+        switch (in->substeps) {
+            case 1: hipLaunchKernelGGL((k_segments_rk4<1, 1>), G, B, 0, st, a); break;
+            case 2: hipLaunchKernelGGL((k_segments_rk4<1, 2>), G, B, 0, st, a); break;
+            case 4: hipLaunchKernelGGL((k_segments_rk4<1, 4>), G, B, 0, st, a); break;
+            case 8: hipLaunchKernelGGL((k_segments_rk4<1, 8>), G, B, 0, st, a); break;
+            default: hipLaunchKernelGGL((k_segments_rk4<1, 0>), G, B, 0, st, a); break;
+        }
+    } else {
+        switch (in->substeps) {
+            case 1: hipLaunchKernelGGL((k_segments_rk4<2, 1>), G, B, 0, st, a); break;
+            case 2: hipLaunchKernelGGL((k_segments_rk4<2, 2>), G, B, 0, st, a); break;
+            case 4: hipLaunchKernelGGL((k_segments_rk4<2, 4>), G, B, 0, st, a); break;
+            case 8: hipLaunchKernelGGL((k_segments_rk4<2, 8>), G, B, 0, st, a); break;
+            default: hipLaunchKernelGGL((k_segments_rk4<2, 0>), G, B, 0, st, a); break;
+        }
+    }
     RC_HIP(hipGetLastError());
     return RC_OK;
 }

@@ -51,17 +51,25 @@ class DeviceForest:
 
 
 class DeviceFields:
+    """Coefficients leaf-major: kappa, eps of shape [N, ncorner] (ncorner 1 or 8)."""
+
     def __init__(self, kappa: torch.Tensor, eps: torch.Tensor):
-        assert kappa.shape == eps.shape and kappa.dim() == 2 and kappa.shape[0] in (1, 8)
+        assert kappa.shape == eps.shape and kappa.dim() == 2 and kappa.shape[1] in (1, 8)
+        assert kappa.dtype == torch.float32 and eps.dtype == torch.float32
         self.kappa = kappa.contiguous()
         self.eps = eps.contiguous()
-        self.kind = L.RC_FIELD_TRILINEAR if kappa.shape[0] == 8 else L.RC_FIELD_CONST
+        self.kind = L.RC_FIELD_TRILINEAR if kappa.shape[1] == 8 else L.RC_FIELD_CONST
         self.struct = L.RcFields(self.kind, 1, _ptr(self.kappa), _ptr(self.eps))
+
+    @staticmethod
+    def leaf_major(a) -> np.ndarray:
+        """[ncorner][N] (the generators' layout) to [N][ncorner]."""
+        return np.ascontiguousarray(np.asarray(a, np.float32).T)
 
     @classmethod
     def from_synth(cls, fields, device):
-        return cls(torch.from_numpy(np.ascontiguousarray(fields.kappa, np.float32)).to(device),
-                   torch.from_numpy(np.ascontiguousarray(fields.eps, np.float32)).to(device))
+        return cls(torch.from_numpy(cls.leaf_major(fields.kappa)).to(device),
+                   torch.from_numpy(cls.leaf_major(fields.eps)).to(device))
 
 
 class DeviceCameras:
@@ -113,7 +121,7 @@ class DeviceIndex:
 class VForest:
     """Buffers of rc_vforest with their capacities."""
 
-    def __init__(self, device, nleaves, ncams, nslots, cap_vis, cap_cand, cap_rec):
+    def __init__(self, device, nleaves, ncams, nslots, cap_vis, cap_cand, cap_rec, ninternal=0):
         d = torch.device(device)
         self.device = d
         self.cap_vis, self.cap_cand, self.cap_rec = int(cap_vis), int(cap_cand), int(cap_rec)
@@ -125,9 +133,13 @@ class VForest:
         self.node_rect = _empty(4 * nslots, torch.int16, d)
         self.node_offset = _empty(nslots + 1, torch.int64, d)
         self.counts = torch.zeros(4, dtype=torch.int64, device=d)
+        self.cand_chunk = _empty(self.cap_cand // 64 + 2, torch.int32, d)
+        self.rec_chunk = _empty(self.cap_rec // 64 + 2, torch.int32, d)
+        self.child_desc = _empty(ncams * max(int(ninternal), 1) * 8 * 4, torch.int32, d)  # 16 bytes per child
         self.struct = L.RcVforest(self.cap_vis, self.cap_cand, self.cap_rec, _ptr(self.vis_leaf), _ptr(self.vis_cam),
                                   _ptr(self.vis_rect), _ptr(self.cand_offset), _ptr(self.leaf_vis),
-                                  _ptr(self.node_rect), _ptr(self.node_offset), _ptr(self.counts))
+                                  _ptr(self.node_rect), _ptr(self.node_offset), _ptr(self.counts),
+                                  _ptr(self.cand_chunk), _ptr(self.rec_chunk), _ptr(self.child_desc))
 
     def read_counts(self):
         c = self.counts.cpu().numpy()
@@ -238,14 +250,14 @@ class Renderer:
     # -- sizing -----------------------------------------------------------
     def plan(self, slack: float = 1.0):
         N, nc = self.forest.nleaves, self.cams.ncams
-        vf = VForest(self.device, N, nc, self.nslots, 0, 0, 0)
+        vf = VForest(self.device, N, nc, self.nslots, 0, 0, 0, self.index.ninternal)
         ws = _empty(workspace_bytes(self.forest, self.index, nc, None), torch.uint8, self.device)
         rc_prune_visible(self.forest, self.index, self.cams, vf, ws)
         c = vf.read_counts()
         cap_vis = int(c["nvis"] * slack) + 1
         cap_cand = int(c["ncand"] * slack) + 1
         cap_rec = int(c["nrec"] * slack) + 1
-        self.vf = VForest(self.device, N, nc, self.nslots, cap_vis, cap_cand, cap_rec)
+        self.vf = VForest(self.device, N, nc, self.nslots, cap_vis, cap_cand, cap_rec, self.index.ninternal)
         self.ws = _empty(workspace_bytes(self.forest, self.index, nc, self.vf), torch.uint8, self.device)
         self.rec_leaf = _empty(2 * cap_cand, torch.float32, self.device)
         self.rec_node = _empty(2 * cap_rec, torch.float32, self.device)
@@ -294,6 +306,35 @@ class Renderer:
                              self.rec_leaf, self.rec_node, dLdI.contiguous(), self.adj_leaf, self.adj_node, dk, de,
                              accumulate, self.ws)
         return dk, de
+
+    # -- graph capture -----------------------------------------------------
+    def capture(self, backward: bool = False, dLdI: Optional[torch.Tensor] = None):
+        """Capture forward (and optionally backward with the gradient buffer dLdI)
+        into a HIP graph; ``replay()`` then re-runs it with one launch."""
+        if backward:
+            self._bwd_alloc()
+            self.g_dk = torch.empty_like(self.fields.kappa)
+            self.g_de = torch.empty_like(self.fields.eps)
+            self.g_dLdI = dLdI
+        s = torch.cuda.Stream(self.device)
+        s.wait_stream(torch.cuda.current_stream(self.device))
+        with torch.cuda.stream(s):
+            for _ in range(2):
+                self._graph_body(backward)
+        torch.cuda.current_stream(self.device).wait_stream(s)
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self._graph_body(backward)
+        return self.graph
+
+    def _graph_body(self, backward):
+        self.forward()
+        if backward:
+            self.backward(self.g_dLdI, self.g_dk, self.g_de)
+
+    def replay(self):
+        self.graph.replay()
+        return self.A, self.B, self.I
 
     def set_fields(self, kappa: torch.Tensor, eps: torch.Tensor):
         self.fields = DeviceFields(kappa, eps)
