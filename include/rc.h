@@ -206,8 +206,10 @@ rc_status rc_segments(const rc_forest *forest, const rc_fields *fields, const vo
  * with every bit flipped where the camera lies on the high side of the
  * node's midplane), absent or invisible children acting as the identity.
  * The roots are folded straight into the images: A, B and I = A I_b + B
- * [device, total_pixels floats each].  rec_node [device, cap_rec * 2] holds
- * the internal-node records (kept for the adjoint).
+ * [device, total_pixels floats each; total_pixels as returned by
+ * rc_camera_prepare].  rec_node [device, cap_rec * 2] holds the
+ * internal-node records (kept for the adjoint).  vf->cap_cand must be at
+ * least 1: rec_leaf always holds at least one record.
  */
 rc_status rc_composite(const rc_forest *forest, const rc_index *index, const void *dcams, int32_t ncams,
                        const rc_vforest *vf, const float *rec_leaf, float *rec_node, int64_t total_pixels,

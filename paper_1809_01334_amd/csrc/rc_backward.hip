@@ -29,8 +29,11 @@ __device__ inline void push_children(const FoldCtx& C, int64_t dslot, int i, int
     for (int q = 0; q < 8; q++) {
         d[q] = UNIFORM ? load_desc_scalar(C.desc, dslot * 8 + q) : load_desc(C.desc + dslot * 8 + q);
         has[q] = desc_has(d[q], i, j);
-        rv[q] = has[q] ? desc_record(C, d[q], i, j) : make_float2(1.0f, 0.0f);
+        rv[q] = *desc_ptr(C, d[q], has[q], i, j);
     }
+#pragma unroll
+    for (int q = 0; q < 8; q++)
+        if (!has[q]) rv[q] = make_float2(1.0f, 0.0f);
     float Jq[8];
     float Jc = J;
 #pragma unroll
@@ -310,74 +313,163 @@ struct LeafAdjArgs {
     float* partial;  // [(nchunks + nvis)][GRAD_MAX], entry (chunk w, pair v) at w + v
 };
 
-// One wavefront per 64 consecutive candidates; per-pair sums by a segmented
-// shuffle scan in a fixed order.
+// Zero the (chunk, pair) partial slots that the leaf adjoint may leave unwritten.
+__global__ __launch_bounds__(256) void k_fill_partials(const int64_t* counts, int64_t cap_cand, float* partial) {
+    if (counts[3]) return;
+    int64_t ncand = counts[1] < cap_cand ? counts[1] : cap_cand;
+    int64_t n = ((ncand + WAVE - 1) / WAVE + counts[0] + 1) * GRAD_MAX;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) partial[t] = 0.0f;
+}
+
+// Leaf adjoint.  Pairing runs one candidate per lane; hits go through a
+// per-wave FIFO in LDS and are differentiated 64 at a time.  Each batch sums
+// its lanes per (chunk w, pair v) key with a segmented shuffle scan (keys are
+// non-decreasing in FIFO order); a key that continues into the next batch is
+// carried, so every (w, v) slot at index w + v is written once, in a fixed
+// order.
+constexpr int BQCAP = 128;
+struct AdjQueue {
+    int64_t key[BQCAP];
+    int32_t leaf[BQCAP];
+    float xf0[BQCAP], xf1[BQCAP], xf2[BQCAP], d0[BQCAP], d1[BQCAP], d2[BQCAP], dx[BQCAP], gT[BQCAP], J[BQCAP];
+};
+
 template <int KIND, int NSUB>
-__global__ __launch_bounds__(256) void k_adj_leaf(LeafAdjArgs a) {
-    if (a.counts[3]) return;
+__device__ inline void adj_drain(const LeafAdjArgs& a, AdjQueue& q, int head, int tail, int n, int lane,
+                                 float* carry, int64_t& carry_key) {
     constexpr int NPAR = KIND == 2 ? 16 : 2;
-    int64_t nvis = a.counts[0];
-    int64_t ncand = a.counts[1] < a.cap_cand ? a.counts[1] : a.cap_cand;
-    int64_t nchunks = (ncand + WAVE - 1) / WAVE;
-    int lane = threadIdx.x & (WAVE - 1);
-    int64_t wave = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
-    int64_t wstride = (int64_t)gridDim.x * (blockDim.x / WAVE);
-    for (int64_t w = wave; w < nchunks; w += wstride) {
-        int64_t g = w * WAVE + lane;
-        float grad[GRAD_MAX];
-        for (int c = 0; c < GRAD_MAX; c++) grad[c] = 0.0f;
-        int64_t key = -1;
-        if (g < ncand) {
-            int64_t v = cand_pair(a.cand_offset, a.cand_chunk, g, w, nvis, ncand);
-            key = v;
-            int32_t leaf = a.vis_leaf[v];
-            const Cam& c = a.cams[a.vis_cam[v]];
-            Rect r = load_rect(a.vis_rect + 4 * v);
-            int k = (int)(g - a.cand_offset[v]);
-            int wr = r.width();
-            int j = r.j0 + k / wr;
-            int i = r.i0 + (k - (k / wr) * wr);
-            int lv = a.level[leaf];
-            double lo[3], hi[3], rho[3], rr[3], s_in, s_out;
-            node_box(lv, a.x[leaf], a.y[leaf], a.z[leaf], lo, hi);
-            pixel_ray(c, i, j, rho, rr);
-            if (slab_hit(c, rho, rr, lo, hi, s_in, s_out)) {
-                SegGeom sg = seg_geom(rho, rr, s_in, s_out, lo, lv);
-                float2 ad = a.adj_leaf[g];
-                float kc[8], ec[8];
-                if (KIND == 2) {
-                    const float4* kp = reinterpret_cast<const float4*>(a.kappa + (int64_t)leaf * 8);
-                    const float4* ep = reinterpret_cast<const float4*>(a.eps + (int64_t)leaf * 8);
-                    float4 k0 = kp[0], k1 = kp[1], e0 = ep[0], e1 = ep[1];
-                    kc[0] = k0.x; kc[1] = k0.y; kc[2] = k0.z; kc[3] = k0.w;
-                    kc[4] = k1.x; kc[5] = k1.y; kc[6] = k1.z; kc[7] = k1.w;
-                    ec[0] = e0.x; ec[1] = e0.y; ec[2] = e0.z; ec[3] = e0.w;
-                    ec[4] = e1.x; ec[5] = e1.y; ec[6] = e1.z; ec[7] = e1.w;
-                } else {
-                    for (int q = 0; q < 8; q++) {
-                        kc[q] = a.kappa[leaf];
-                        ec[q] = a.eps[leaf];
-                    }
-                }
-                segment_grad<KIND, NSUB>(kc, ec, sg, ad.x, ad.y, grad);
+    const int mask = BQCAP - 1;
+    int e = (head + lane) & mask;
+    bool act = lane < n;
+    int64_t key = act ? q.key[e] : INT64_MAX;
+    float grad[GRAD_MAX];
+#pragma unroll
+    for (int c = 0; c < GRAD_MAX; c++) grad[c] = 0.0f;
+    if (act) {
+        SegGeom sg;
+        sg.xf[0] = q.xf0[e];
+        sg.xf[1] = q.xf1[e];
+        sg.xf[2] = q.xf2[e];
+        sg.dxi[0] = q.d0[e];
+        sg.dxi[1] = q.d1[e];
+        sg.dxi[2] = q.d2[e];
+        sg.dx = q.dx[e];
+        int64_t leaf = q.leaf[e];
+        float kc[8], ec[8];
+        if (KIND == 2) {
+            const float4* kp = reinterpret_cast<const float4*>(a.kappa + leaf * 8);
+            const float4* ep = reinterpret_cast<const float4*>(a.eps + leaf * 8);
+            float4 k0 = kp[0], k1 = kp[1], e0 = ep[0], e1 = ep[1];
+            kc[0] = k0.x; kc[1] = k0.y; kc[2] = k0.z; kc[3] = k0.w;
+            kc[4] = k1.x; kc[5] = k1.y; kc[6] = k1.z; kc[7] = k1.w;
+            ec[0] = e0.x; ec[1] = e0.y; ec[2] = e0.z; ec[3] = e0.w;
+            ec[4] = e1.x; ec[5] = e1.y; ec[6] = e1.z; ec[7] = e1.w;
+        } else {
+#pragma unroll
+            for (int c = 0; c < 8; c++) {
+                kc[c] = a.kappa[leaf];
+                ec[c] = a.eps[leaf];
             }
         }
-        // segmented inclusive scan over lanes with equal (sorted) keys
-        for (int d = 1; d < WAVE; d <<= 1) {
-            int64_t kd = __shfl_up(key, d);
-            bool same = lane >= d && kd == key;
-            for (int c = 0; c < NPAR; c++) {
-                float y = __shfl_up(grad[c], d);
-                if (same) grad[c] += y;
-            }
-        }
-        int64_t knext = __shfl_down(key, 1);
-        bool last = (lane == WAVE - 1) || knext != key;
-        if (key >= 0 && last) {
-            float* dst = a.partial + (w + key) * GRAD_MAX;
-            for (int c = 0; c < NPAR; c++) dst[c] = grad[c];
+        segment_grad<KIND, NSUB>(kc, ec, sg, q.gT[e], q.J[e], grad);
+    }
+    // segmented inclusive scan over lanes with equal keys
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        int64_t kd = __shfl_up(key, d);
+        bool same = lane >= d && kd == key;
+#pragma unroll
+        for (int c = 0; c < NPAR; c++) {
+            float y = __shfl_up(grad[c], d);
+            if (same) grad[c] += y;
         }
     }
+    int64_t knext = __shfl_down(key, 1);
+    bool last = act && ((lane == WAVE - 1) || knext != key);
+    int64_t key0 = __shfl(key, 0);
+    int64_t next_key = (tail - head > n) ? q.key[(head + n) & mask] : -2;
+    int64_t key_end = __shfl(key, n - 1);
+    bool cont = key_end == next_key;  // the batch's last key goes on in the queue
+    float val[NPAR];
+#pragma unroll
+    for (int c = 0; c < NPAR; c++) val[c] = grad[c] + ((key == key0 && key == carry_key) ? carry[c] : 0.0f);
+    if (last && !(cont && lane == n - 1)) {
+        float* dst = a.partial + key * GRAD_MAX;
+#pragma unroll
+        for (int c = 0; c < NPAR; c++) dst[c] = val[c];
+    }
+    if (cont) {
+#pragma unroll
+        for (int c = 0; c < NPAR; c++) carry[c] = __shfl(val[c], n - 1);
+        carry_key = key_end;
+    } else {
+        carry_key = -1;
+    }
+}
+
+template <int KIND, int NSUB>
+__global__ __launch_bounds__(256) void k_adj_leaf(LeafAdjArgs a) {
+    __shared__ AdjQueue Q[256 / WAVE];
+    if (a.counts[3]) return;
+    int64_t nvis = a.counts[0];
+    int64_t ncand = a.counts[1] < a.cap_cand ? a.counts[1] : a.cap_cand;
+    int lane = threadIdx.x & (WAVE - 1);
+    AdjQueue& q = Q[threadIdx.x / WAVE];
+    int64_t wave = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    int64_t nw = (int64_t)gridDim.x * (blockDim.x / WAVE);
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int head = 0, tail = 0;  // FIFO positions (mod BQCAP), the same in every lane
+    float carry[GRAD_MAX];
+#pragma unroll
+    for (int c = 0; c < GRAD_MAX; c++) carry[c] = 0.0f;
+    int64_t carry_key = -1;
+    for (int64_t w = wave; w * WAVE < ncand; w += nw) {
+        int64_t g = w * WAVE + lane;
+        bool h = false;
+        SegGeom sg;
+        int32_t leaf = 0;
+        int64_t key = 0;
+        float2 ad = make_float2(0.0f, 0.0f);
+        if (g < ncand) {
+            int64_t v = 0;
+            Pairing p = pair_candidate(a, g, w, nvis, ncand, &v);
+            key = w + v;
+            h = p.hit;
+            leaf = p.leaf;
+            if (h) {
+                sg = seg_geom(p.rho, p.rr, p.s_in, p.s_out, p.lo, p.lv);
+                ad = a.adj_leaf[g];
+            }
+        }
+        uint64_t m = __ballot(h);
+        if (h) {
+            int e = (tail + __popcll(m & below)) & (BQCAP - 1);
+            q.key[e] = key;
+            q.leaf[e] = leaf;
+            q.xf0[e] = sg.xf[0];
+            q.xf1[e] = sg.xf[1];
+            q.xf2[e] = sg.xf[2];
+            q.d0[e] = sg.dxi[0];
+            q.d1[e] = sg.dxi[1];
+            q.d2[e] = sg.dxi[2];
+            q.dx[e] = sg.dx;
+            q.gT[e] = ad.x;
+            q.J[e] = ad.y;
+        }
+        tail += __popcll(m);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (tail - head >= WAVE) {
+            adj_drain<KIND, NSUB>(a, q, head, tail, WAVE, lane, carry, carry_key);
+            head += WAVE;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+    }
+    if (tail - head > 0) adj_drain<KIND, NSUB>(a, q, head, tail, tail - head, lane, carry, carry_key);
 }
 
 // Per (visible pair, parameter): add the pair's chunk partials in chunk order.
@@ -401,24 +493,23 @@ __global__ __launch_bounds__(256) void k_grad_pairs(const int64_t* counts, int64
     }
 }
 
-// Per leaf: sum over cameras in camera order into the coefficient layout.
+// Per (leaf, parameter): sum over cameras in camera order into the
+// leaf-major coefficient layout.
 __global__ __launch_bounds__(256) void k_grad_leaves(const int64_t* counts, int64_t N, int ncams, const int32_t* leaf_vis,
                                                      const float* gvis, int nc, float* dk, float* de, int accumulate) {
     if (counts[3]) return;
+    int64_t npar = 2 * nc;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; l < N; l += stride) {
-        float acc[GRAD_MAX];
-        for (int c = 0; c < GRAD_MAX; c++) acc[c] = 0.0f;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < N * npar; t += stride) {
+        int64_t l = divu(t, npar);
+        int c = (int)(t - l * npar);
+        float acc = 0.0f;
         for (int cam = 0; cam < ncams; cam++) {
             int32_t v = leaf_vis[(int64_t)cam * N + l];
-            if (v < 0) continue;
-            for (int c = 0; c < 2 * nc; c++) acc[c] += gvis[(int64_t)v * GRAD_MAX + c];
+            if (v >= 0) acc += gvis[(int64_t)v * GRAD_MAX + c];
         }
-        for (int c = 0; c < nc; c++) {
-            int64_t o = l * nc + c;
-            dk[o] = accumulate ? dk[o] + acc[c] : acc[c];
-            de[o] = accumulate ? de[o] + acc[nc + c] : acc[nc + c];
-        }
+        float* dst = c < nc ? dk + l * nc + c : de + l * nc + (c - nc);
+        *dst = accumulate ? *dst + acc : acc;
     }
 }
 
@@ -436,7 +527,8 @@ extern "C" rc_status rc_segments_backward(const rc_forest* f, const rc_index* ix
     if ((s = check_index(ix)) != RC_OK) return s;
     if ((s = check_fields(fl, in)) != RC_OK) return s;
     if ((s = check_vforest(vf, ix->maxlevel >= 1)) != RC_OK) return s;
-    if (!dcams || ncams <= 0 || npix <= 0 || !rec_leaf || !dLdI || !adj_leaf || !dk || !de) return RC_EINVAL;
+    if (!dcams || ncams <= 0 || npix <= 0 || !rec_leaf || !dLdI || !adj_leaf || !dk || !de || vf->cap_cand < 1)
+        return RC_EINVAL;
     bool nodes = rc_node_slots(ix, ncams) > 0;
     if (nodes && (!rec_node || !adj_node)) return RC_EINVAL;
     if (in->method == RC_INT_RK4 && in->substeps != 1 && in->substeps != 2 && in->substeps != 4 && in->substeps != 8)
@@ -463,6 +555,9 @@ extern "C" rc_status rc_segments_backward(const rc_forest* f, const rc_index* ix
                    f->nleaves,        fl->kappa,      fl->eps,       in->substeps, vf->vis_leaf,
                    vf->vis_cam,       vf->vis_rect,   vf->cand_offset, vf->counts, vf->cand_chunk,
                    vf->cap_cand,      (const float2*)adj_leaf, partial};
+    hipLaunchKernelGGL(k_fill_partials, dim3(stride_grid((nchunks + vf->cap_vis + 1) * GRAD_MAX, 256, 256 * 16)),
+                       dim3(256), 0, st, vf->counts, vf->cap_cand, partial);
+    RC_HIP(hipGetLastError());
     unsigned lg = stride_grid(nchunks * WAVE, 256, 256 * 8);
     int nc = fl->kind == RC_FIELD_TRILINEAR ? 8 : 1;
     dim3 G(lg), B(256);
@@ -490,7 +585,8 @@ extern "C" rc_status rc_segments_backward(const rc_forest* f, const rc_index* ix
                        vf->counts,
                        vf->cap_cand, vf->cand_offset, partial, gvis, 2 * nc);
     RC_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_grad_leaves, dim3(stride_grid(f->nleaves, 256, 256 * 16)), dim3(256), 0, st, vf->counts,
+    hipLaunchKernelGGL(k_grad_leaves, dim3(stride_grid(f->nleaves * 2 * nc, 256, 256 * 32)), dim3(256), 0, st,
+                       vf->counts,
                        f->nleaves, ncams, vf->leaf_vis, gvis, nc, dk, de, accumulate);
     RC_HIP(hipGetLastError());
     return RC_OK;

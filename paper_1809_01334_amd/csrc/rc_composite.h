@@ -55,6 +55,15 @@ __device__ inline float2 desc_record(const FoldCtx& C, const ChildDesc& d, int i
     return d.off >= 0 ? C.rec_node[d.off + k] : C.rec_leaf[-1 - d.off + k];
 }
 
+// Address of the record of child d at (i, j), or of the first leaf record
+// (always present) when the child does not hold the pixel: every lane can
+// issue all eight loads at once and select afterwards.
+__device__ inline const float2* desc_ptr(const FoldCtx& C, const ChildDesc& d, bool has, int i, int j) {
+    if (!has) return C.rec_leaf;
+    int64_t k = desc_index(d, i, j);
+    return d.off >= 0 ? C.rec_node + (d.off + k) : C.rec_leaf + (-1 - d.off + k);
+}
+
 // Group product of the children of descriptor slot `dslot` at pixel (i, j),
 // nearest child first (descriptors are stored in view order).  UNIFORM: dslot
 // is the same in every lane, so the descriptors come through the scalar cache.
@@ -69,10 +78,17 @@ __device__ inline float2 fold_desc(const FoldCtx& C, int64_t dslot, int i, int j
 #pragma unroll
         for (int q = 0; q < 8; q++) d[q] = load_desc(dp + q);
     }
+    bool has[8];
+    float2 rv[8];
+#pragma unroll
+    for (int q = 0; q < 8; q++) {
+        has[q] = desc_has(d[q], i, j);
+        rv[q] = *desc_ptr(C, d[q], has[q], i, j);
+    }
     float2 acc = make_float2(1.0f, 0.0f);
 #pragma unroll
     for (int q = 0; q < 8; q++)
-        if (desc_has(d[q], i, j)) acc = seg_combine(acc, desc_record(C, d[q], i, j));
+        if (has[q]) acc = seg_combine(acc, rv[q]);
     return acc;
 }
 

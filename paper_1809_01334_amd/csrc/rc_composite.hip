@@ -76,7 +76,7 @@ extern "C" rc_status rc_composite(const rc_forest* f, const rc_index* ix, const 
     if (s != RC_OK) return s;
     if ((s = check_index(ix)) != RC_OK) return s;
     if ((s = check_vforest(vf, ix->maxlevel >= 1)) != RC_OK) return s;
-    if (!dcams || ncams <= 0 || npix <= 0 || !rec_leaf || !A || !B || !I) return RC_EINVAL;
+    if (!dcams || ncams <= 0 || npix <= 0 || !rec_leaf || !A || !B || !I || vf->cap_cand < 1) return RC_EINVAL;
     if (rc_node_slots(ix, ncams) > 0 && !rec_node) return RC_EINVAL;
     if ((s = check_tables(vf, ix, ncams)) != RC_OK) return s;
     hipStream_t st = (hipStream_t)stream;

@@ -403,6 +403,36 @@ __device__ inline int64_t cand_pair(const int64_t* cand_offset, const int32_t* c
     return upper_index(cand_offset, lo, hi, g);
 }
 
+// Pairing of candidate g (Sec. 2.1, 2.2): its leaf, the pixel's ray and the
+// hit interval.  Args provides the vforest and leaf arrays.
+struct Pairing {
+    int32_t leaf;
+    int lv;
+    bool hit;
+    double lo[3], rho[3], rr[3], s_in, s_out;
+};
+
+template <typename Args>
+__device__ inline Pairing pair_candidate(const Args& a, int64_t g, int64_t w, int64_t nvis, int64_t ncand,
+                                         int64_t* vout = nullptr) {
+    Pairing p;
+    int64_t v = cand_pair(a.cand_offset, a.cand_chunk, g, w, nvis, ncand);
+    if (vout) *vout = v;
+    p.leaf = a.vis_leaf[v];
+    const Cam& c = a.cams[a.vis_cam[v]];
+    Rect r = load_rect(a.vis_rect + 4 * v);
+    int k = (int)(g - a.cand_offset[v]);
+    int wr = r.width();
+    int j = r.j0 + k / wr;
+    int i = r.i0 + (k - (k / wr) * wr);
+    p.lv = a.level[p.leaf];
+    double hi[3];
+    node_box(p.lv, a.x[p.leaf], a.y[p.leaf], a.z[p.leaf], p.lo, hi);
+    pixel_ray(c, i, j, p.rho, p.rr);
+    p.hit = slab_hit(c, p.rho, p.rr, p.lo, hi, p.s_in, p.s_out);
+    return p;
+}
+
 // Camera of a pixel in the concatenated images.
 __device__ inline int camera_of_pixel(const Cam* cams, int ncams, int64_t p) {
     int lo = 0, hi = ncams;

@@ -29,32 +29,6 @@ struct SegArgs {
     double2* sio;
 };
 
-// Pairing of candidate g: leaf, ray, hit interval (Sec. 2.1, 2.2).
-struct Pairing {
-    int32_t leaf;
-    int lv;
-    bool hit;
-    double lo[3], rho[3], rr[3], s_in, s_out;
-};
-
-__device__ inline Pairing pair_candidate(const SegArgs& a, int64_t g, int64_t w, int64_t nvis, int64_t ncand) {
-    Pairing p;
-    int64_t v = cand_pair(a.cand_offset, a.cand_chunk, g, w, nvis, ncand);
-    p.leaf = a.vis_leaf[v];
-    const Cam& c = a.cams[a.vis_cam[v]];
-    Rect r = load_rect(a.vis_rect + 4 * v);
-    int k = (int)(g - a.cand_offset[v]);
-    int wr = r.width();
-    int j = r.j0 + k / wr;
-    int i = r.i0 + (k - (k / wr) * wr);
-    p.lv = a.level[p.leaf];
-    double hi[3];
-    node_box(p.lv, a.x[p.leaf], a.y[p.leaf], a.z[p.leaf], p.lo, hi);
-    pixel_ray(c, i, j, p.rho, p.rr);
-    p.hit = slab_hit(c, p.rho, p.rr, p.lo, hi, p.s_in, p.s_out);
-    return p;
-}
-
 template <int KIND, int NSUB>
 __device__ inline float2 integrate(const SegArgs& a, int64_t leaf, const SegGeom& sg) {
     if (KIND == 1) return seg_rk4_const<NSUB>(a.kappa[leaf], a.eps[leaf], sg.dx, a.nsub);
