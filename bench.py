@@ -66,6 +66,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-bwd", action="store_true")
     ap.add_argument("--res", type=int, default=1024)
+    ap.add_argument("--no-batch", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the forest share of one "
@@ -82,8 +83,7 @@ def main():
     log(f"[bench] {scene.forest.nleaves} leaves; building renderer")
     r = P.Renderer(scene.forest, scene.fields, scene.cameras, "rk4", 4, device="cuda:0")
     counts = r.counts
-    hit, _ = r.debug_segments()
-    S = int(hit[:counts["ncand"]].sum().item())
+    S = r.count_segments()
     C = counts["ncand"]
     log(f"[bench] visible {counts['nvis']}, candidates {C}, segments {S}, node records {counts['nrec']}")
 
@@ -162,10 +162,78 @@ def main():
         out["fwd_bwd_over_fwd"] = ms_fb / ms
         log(f"[bench] forward+backward {ms_fb:.3f} ms (graph), {ms_fb_eager:.3f} ms (eager)")
 
+    if not args.no_bwd:
+        out["adjoint_workload"] = bench_adjoint(torch, P, synth, max(args.steps // 2, 5))
+    if not args.no_batch:
+        out["batched_workload"] = bench_batched(torch, P, synth, r, max(args.steps // 10, 3))
+
     if not args.no_cpu:
         log("[bench] timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(scene)
     print(json.dumps(out), flush=True)
+
+
+def bench_adjoint(torch, P, synth, steps):
+    """512^2 view, background 0.5: forward vs forward + adjoint of L = sum (I - I*)^2."""
+    log("[bench] adjoint workload: generating")
+    sc = synth.config_scene(5)
+    r = P.Renderer(sc.forest, sc.fields, sc.cameras, "rk4", 4, device="cuda:0")
+    tgt = P.Renderer(r.forest, P.DeviceFields.from_synth(sc.extra["target_fields"], r.device), sc.cameras, "rk4", 4,
+                     device="cuda:0", index=r.index)
+    _, _, It = tgt.forward()
+    It = It.clone()
+    g = torch.empty_like(It)
+
+    def fwd():
+        r.forward()
+
+    def fwd_bwd():
+        _, _, I = r.forward()
+        torch.mul(torch.sub(I, It), 2.0, out=g)
+        r.backward(g, r.g_dk, r.g_de)
+
+    r.g_dk = torch.empty_like(r.fields.kappa)
+    r.g_de = torch.empty_like(r.fields.eps)
+    for _ in range(3):
+        fwd_bwd()
+    t_f = time_region(torch, fwd, steps)
+    t_fb = time_region(torch, fwd_bwd, steps)
+    S = r.count_segments()
+    log(f"[bench] adjoint workload: {sc.forest.nleaves} leaves, {S} segments, fwd {t_f:.3f} ms, fwd+bwd {t_fb:.3f} ms")
+    return {"workload": f"{sc.forest.nleaves}-leaf adaptive forest, 512x512, background 0.5, "
+                        f"loss sum (I - I_target)^2 with perturbed target fields",
+            "segments": S, "fwd_ms": t_f, "fwd_bwd_ms": t_fb, "fwd_bwd_over_fwd": t_fb / t_f}
+
+
+def bench_batched(torch, P, synth, r, steps):
+    """The forest of the main workload seen by 64 cameras of uneven resolution: one
+    graph launch for all views (autotuned) versus 64 plain per-view forwards."""
+    cams = synth.config4_cameras()
+    log(f"[bench] batched workload: {len(cams)} cameras, {sum(c.npix for c in cams)} pixels")
+    rb = P.Renderer(r.forest, r.fields, cams, "rk4", 4, device="cuda:0", index=r.index)
+    from paper_1809_01334_amd.tune import autotune
+
+    tune = autotune(rb, reps=2)
+    log(f"[bench] autotuned launch shapes {tune['tuning']}")
+    rb.capture()
+    rb.replay()
+    t_batch = time_region(torch, rb.replay, steps)
+    S = rb.count_segments()
+    singles = [P.Renderer(r.forest, r.fields, [c], "rk4", 4, device="cuda:0", index=r.index) for c in cams]
+
+    def plain():
+        for x in singles:
+            x.forward()
+
+    plain()
+    t_plain = time_region(torch, plain, steps)
+    log(f"[bench] batched: one graph {t_batch:.2f} ms, 64 plain forwards {t_plain:.2f} ms, segments {S}")
+    del singles
+    return {"workload": "64 cameras, resolutions from {256,512,1024,2048}^2, same forest",
+            "views": len(cams), "pixels": int(sum(c.npix for c in cams)), "candidates": rb.counts["ncand"],
+            "segments": S, "batched_ms": t_batch, "plain_sum_ms": t_plain, "plain_over_batched": t_plain / t_batch,
+            "ray_segments_per_s": S / (t_batch * 1e-3), "images_per_s": len(cams) / (t_batch * 1e-3),
+            "tuning": tune["tuning"]}
 
 
 if __name__ == "__main__":

@@ -98,6 +98,16 @@ typedef struct rc_integrator {
     int32_t substeps;           /* RK4 substeps per segment, 1 .. 64 */
 } rc_integrator;
 
+/* Launch shapes of the grid-stride kernels, in 256-thread workgroups; 0 (or a
+ * NULL rc_tuning pointer) selects the default.  Forward results do not depend
+ * on these values; adjoint sums are deterministic for a given value. */
+typedef struct rc_tuning {
+    int32_t seg_blocks;   /* rc_segments (default 2048) */
+    int32_t fold_blocks;  /* rc_composite and adjoint level passes (default 4096) */
+    int32_t root_blocks;  /* root passes over the image pixels (default 4096) */
+    int32_t adj_blocks;   /* rc_segments_backward leaf adjoint (default 2048) */
+} rc_tuning;
+
 /* Static node table of a forest share: the internal nodes above the leaves,
  * level-major and in SFC order within a level.  Built by rc_forest_index.
  * A child slot holds an internal node index (>= 0), RC_ABSENT, or a leaf
@@ -197,7 +207,7 @@ rc_status rc_prune_visible(const rc_forest *forest, const rc_index *index, const
  */
 rc_status rc_segments(const rc_forest *forest, const rc_fields *fields, const void *dcams, int32_t ncams,
                       const rc_vforest *vf, const rc_integrator *integ, float *rec_leaf, uint8_t *hit,
-                      double *sio, void *stream);
+                      double *sio, const rc_tuning *tune, void *stream);
 
 /*
  * Sort-free compositing (Sec. 2.4, 3.3): coarsen the octree level by level;
@@ -213,7 +223,7 @@ rc_status rc_segments(const rc_forest *forest, const rc_fields *fields, const vo
  */
 rc_status rc_composite(const rc_forest *forest, const rc_index *index, const void *dcams, int32_t ncams,
                        const rc_vforest *vf, const float *rec_leaf, float *rec_node, int64_t total_pixels,
-                       float *A, float *B, float *I, void *stream);
+                       float *A, float *B, float *I, const rc_tuning *tune, void *stream);
 
 /*
  * Adjoint of the images with respect to the coefficients.  Given
@@ -231,7 +241,8 @@ rc_status rc_segments_backward(const rc_forest *forest, const rc_index *index, c
                                const rc_integrator *integ, const float *rec_leaf, const float *rec_node,
                                int64_t total_pixels, const float *dL_dI, float *adj_leaf, float *adj_node,
                                float *dL_dkappa,
-                               float *dL_deps, int32_t accumulate, void *ws, size_t ws_bytes, void *stream);
+                               float *dL_deps, int32_t accumulate, void *ws, size_t ws_bytes,
+                               const rc_tuning *tune, void *stream);
 
 #ifdef __cplusplus
 }

@@ -40,6 +40,10 @@ class RcIntegrator(ctypes.Structure):
     _fields_ = [("method", c_i32), ("substeps", c_i32)]
 
 
+class RcTuning(ctypes.Structure):
+    _fields_ = [("seg_blocks", c_i32), ("fold_blocks", c_i32), ("root_blocks", c_i32), ("adj_blocks", c_i32)]
+
+
 class RcIndex(ctypes.Structure):
     _fields_ = [("maxlevel", c_i32), ("pad", c_i32), ("ninternal", c_i64), ("cap_internal", c_i64),
                 ("level_begin", c_i64 * (RC_QMAXLEVEL + 2)), ("root", c_i32), ("pad2", c_i32), ("child", c_vp),
@@ -63,12 +67,12 @@ _SIGS = {
     "rc_forest_index": (c_i32, [P(RcForest), P(RcIndex), c_vp, c_sz, c_vp]),
     "rc_prune_visible": (c_i32, [P(RcForest), P(RcIndex), c_vp, c_i32, P(RcVforest), c_vp, c_sz, c_vp]),
     "rc_segments": (c_i32, [P(RcForest), P(RcFields), c_vp, c_i32, P(RcVforest), P(RcIntegrator), c_vp, c_vp, c_vp,
-                            c_vp]),
+                            P(RcTuning), c_vp]),
     "rc_composite": (c_i32, [P(RcForest), P(RcIndex), c_vp, c_i32, P(RcVforest), c_vp, c_vp, c_i64, c_vp, c_vp, c_vp,
-                             c_vp]),
+                             P(RcTuning), c_vp]),
     "rc_segments_backward": (c_i32, [P(RcForest), P(RcIndex), P(RcFields), c_vp, c_i32, P(RcVforest),
                                      P(RcIntegrator), c_vp, c_vp, c_i64, c_vp, c_vp, c_vp, c_vp, c_vp, c_i32, c_vp,
-                                     c_sz, c_vp]),
+                                     c_sz, P(RcTuning), c_vp]),
 }
 
 EXPORTS = tuple(_SIGS)

@@ -521,7 +521,7 @@ extern "C" rc_status rc_segments_backward(const rc_forest* f, const rc_index* ix
                                           const rc_integrator* in, const float* rec_leaf, const float* rec_node,
                                           int64_t npix, const float* dLdI, float* adj_leaf, float* adj_node,
                                           float* dk, float* de, int32_t accumulate, void* ws, size_t ws_bytes,
-                                          void* stream) {
+                                          const rc_tuning* tune, void* stream) {
     rc_status s = check_forest(f);
     if (s != RC_OK) return s;
     if ((s = check_index(ix)) != RC_OK) return s;
@@ -538,10 +538,11 @@ extern "C" rc_status rc_segments_backward(const rc_forest* f, const rc_index* ix
     hipStream_t st = (hipStream_t)stream;
 
     FoldCtx C = make_fold_ctx(f, ix, dcams, ncams, vf, rec_leaf, rec_node);
-    hipLaunchKernelGGL(k_adj_root, dim3(stride_grid(npix, 256, 256 * 16)), dim3(256), 0, st, C, ix->root, npix, dLdI,
+    hipLaunchKernelGGL(k_adj_root, dim3(stride_grid(npix, 256, tuned(tune, 2, 256 * 16))), dim3(256), 0, st, C,
+                       ix->root, npix, dLdI,
                        (float2*)adj_leaf, (float2*)adj_node, vf->leaf_vis, vf->vis_rect, vf->cand_offset);
     RC_HIP(hipGetLastError());
-    unsigned grid = stride_grid(vf->cap_rec, 256, 256 * 16);
+    unsigned grid = stride_grid(vf->cap_rec, 256, tuned(tune, 1, 256 * 16));
     for (int l = 1; l < ix->maxlevel; l++) {
         if (ix->level_begin[l + 1] == ix->level_begin[l]) continue;
         hipLaunchKernelGGL(k_adj_level, dim3(grid), dim3(256), 0, st, C, l, (float2*)adj_leaf, (float2*)adj_node);
@@ -558,7 +559,7 @@ extern "C" rc_status rc_segments_backward(const rc_forest* f, const rc_index* ix
     hipLaunchKernelGGL(k_fill_partials, dim3(stride_grid((nchunks + vf->cap_vis + 1) * GRAD_MAX, 256, 256 * 16)),
                        dim3(256), 0, st, vf->counts, vf->cap_cand, partial);
     RC_HIP(hipGetLastError());
-    unsigned lg = stride_grid(nchunks * WAVE, 256, 256 * 8);
+    unsigned lg = stride_grid(nchunks * WAVE, 256, tuned(tune, 3, 256 * 8));
     int nc = fl->kind == RC_FIELD_TRILINEAR ? 8 : 1;
     dim3 G(lg), B(256);
     if (in->method == RC_INT_ANALYTIC) {

@@ -71,7 +71,7 @@ __global__ __launch_bounds__(256) void k_fold_root(FoldCtx C, int32_t root, int6
 
 extern "C" rc_status rc_composite(const rc_forest* f, const rc_index* ix, const void* dcams, int32_t ncams,
                                   const rc_vforest* vf, const float* rec_leaf, float* rec_node, int64_t npix,
-                                  float* A, float* B, float* I, void* stream) {
+                                  float* A, float* B, float* I, const rc_tuning* tune, void* stream) {
     rc_status s = check_forest(f);
     if (s != RC_OK) return s;
     if ((s = check_index(ix)) != RC_OK) return s;
@@ -81,13 +81,14 @@ extern "C" rc_status rc_composite(const rc_forest* f, const rc_index* ix, const 
     if ((s = check_tables(vf, ix, ncams)) != RC_OK) return s;
     hipStream_t st = (hipStream_t)stream;
     FoldCtx C = make_fold_ctx(f, ix, dcams, ncams, vf, rec_leaf, rec_node);
-    unsigned grid = stride_grid(vf->cap_rec, 256, 256 * 16);
+    unsigned grid = stride_grid(vf->cap_rec, 256, tuned(tune, 1, 256 * 16));
     for (int l = ix->maxlevel - 1; l >= 1; l--) {
         if (ix->level_begin[l + 1] == ix->level_begin[l]) continue;
         hipLaunchKernelGGL(k_fold_level, dim3(grid), dim3(256), 0, st, C, l, (float2*)rec_node);
         RC_HIP(hipGetLastError());
     }
-    hipLaunchKernelGGL(k_fold_root, dim3(stride_grid(npix, 256, 256 * 16)), dim3(256), 0, st, C, ix->root, npix, A,
+    hipLaunchKernelGGL(k_fold_root, dim3(stride_grid(npix, 256, tuned(tune, 2, 256 * 16))), dim3(256), 0, st, C,
+                       ix->root, npix, A,
                        B, I, vf->leaf_vis, vf->vis_rect, vf->cand_offset);
     RC_HIP(hipGetLastError());
     return RC_OK;

@@ -77,6 +77,12 @@ inline rc_status check_tables(const rc_vforest* vf, const rc_index* ix, int32_t 
     return RC_OK;
 }
 
+inline unsigned tuned(const rc_tuning* t, int which, unsigned dflt) {
+    if (!t) return dflt;
+    int32_t v = which == 0 ? t->seg_blocks : which == 1 ? t->fold_blocks : which == 2 ? t->root_blocks : t->adj_blocks;
+    return v > 0 ? (unsigned)v : dflt;
+}
+
 // Slot layout of internal nodes of level >= 1: (level, camera, node).
 struct SlotLayout {
     int64_t level_begin[RC_QMAXLEVEL + 2];

@@ -154,7 +154,7 @@ using namespace rc;
 
 extern "C" rc_status rc_segments(const rc_forest* f, const rc_fields* fl, const void* dcams, int32_t ncams,
                                  const rc_vforest* vf, const rc_integrator* in, float* rec_leaf, uint8_t* hit,
-                                 double* sio, void* stream) {
+                                 double* sio, const rc_tuning* tune, void* stream) {
     rc_status s = check_forest(f);
     if (s != RC_OK) return s;
     if ((s = check_fields(fl, in)) != RC_OK) return s;
@@ -165,7 +165,7 @@ extern "C" rc_status rc_segments(const rc_forest* f, const rc_fields* fl, const 
               fl->kappa,        fl->eps,        in->substeps,   vf->vis_leaf, vf->vis_cam, vf->vis_rect,
               vf->cand_offset,  vf->counts,     vf->cand_chunk, vf->cap_cand, (float2*)rec_leaf, hit,
               (double2*)sio};
-    unsigned grid = stride_grid(vf->cap_cand, 256, 256 * 8);
+    unsigned grid = stride_grid(vf->cap_cand, 256, tuned(tune, 0, 256 * 8));
     dim3 G(grid), B(256);
     if (in->method == RC_INT_ANALYTIC) {
         hipLaunchKernelGGL(k_segments_analytic, G, B, 0, st, a);

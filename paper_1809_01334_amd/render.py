@@ -190,30 +190,34 @@ def rc_prune_visible(forest: DeviceForest, index: DeviceIndex, cams: DeviceCamer
            ctypes.byref(vf.struct), _ptr(ws), ws.numel(), _stream(forest.device))
 
 
+def _tune(t: Optional[L.RcTuning]):
+    return ctypes.byref(t) if t is not None else None
+
+
 def rc_segments(forest: DeviceForest, fields: DeviceFields, cams: DeviceCameras, vf: VForest, method: int,
                 substeps: int, rec_leaf: torch.Tensor, hit: Optional[torch.Tensor] = None,
-                sio: Optional[torch.Tensor] = None):
+                sio: Optional[torch.Tensor] = None, tuning: Optional[L.RcTuning] = None):
     integ = L.RcIntegrator(int(method), int(substeps))
     L.call("rc_segments", ctypes.byref(forest.struct), ctypes.byref(fields.struct), _ptr(cams.buf), cams.ncams,
-           ctypes.byref(vf.struct), ctypes.byref(integ), _ptr(rec_leaf), _ptr(hit), _ptr(sio),
+           ctypes.byref(vf.struct), ctypes.byref(integ), _ptr(rec_leaf), _ptr(hit), _ptr(sio), _tune(tuning),
            _stream(forest.device))
 
 
 def rc_composite(forest: DeviceForest, index: DeviceIndex, cams: DeviceCameras, vf: VForest, rec_leaf, rec_node,
-                 A, B, I):
+                 A, B, I, tuning: Optional[L.RcTuning] = None):
     L.call("rc_composite", ctypes.byref(forest.struct), ctypes.byref(index.struct), _ptr(cams.buf), cams.ncams,
            ctypes.byref(vf.struct), _ptr(rec_leaf), _ptr(rec_node), cams.npix, _ptr(A), _ptr(B), _ptr(I),
-           _stream(forest.device))
+           _tune(tuning), _stream(forest.device))
 
 
 def rc_segments_backward(forest: DeviceForest, index: DeviceIndex, fields: DeviceFields, cams: DeviceCameras,
                          vf: VForest, method: int, substeps: int, rec_leaf, rec_node, dLdI, adj_leaf, adj_node, dk,
-                         de, accumulate: bool, ws):
+                         de, accumulate: bool, ws, tuning: Optional[L.RcTuning] = None):
     integ = L.RcIntegrator(int(method), int(substeps))
     L.call("rc_segments_backward", ctypes.byref(forest.struct), ctypes.byref(index.struct),
            ctypes.byref(fields.struct), _ptr(cams.buf), cams.ncams, ctypes.byref(vf.struct), ctypes.byref(integ),
            _ptr(rec_leaf), _ptr(rec_node), cams.npix, _ptr(dLdI), _ptr(adj_leaf), _ptr(adj_node), _ptr(dk), _ptr(de),
-           1 if accumulate else 0, _ptr(ws), ws.numel(), _stream(forest.device))
+           1 if accumulate else 0, _ptr(ws), ws.numel(), _tune(tuning), _stream(forest.device))
 
 
 # ---------------------------------------------------------------------------- renderer
@@ -228,8 +232,8 @@ class Renderer:
     counts); after that ``forward()`` and ``backward()`` only enqueue work.
     """
 
-    def __init__(self, forest, fields, cameras, method="rk4", substeps=4, device="cuda:0",
-                 keep_backward_buffers=False):
+    def __init__(self, forest, fields, cameras, method="rk4", substeps=4, device="cuda:0", index=None,
+                 tuning: Optional[dict] = None):
         self.device = torch.device(device)
         if not torch.cuda.is_available():
             raise RuntimeError("the rc renderer needs a GPU")
@@ -240,7 +244,8 @@ class Renderer:
         self.cams = rc_camera_prepare(raw, self.device)
         self.method = METHODS[method] if isinstance(method, str) else int(method)
         self.substeps = int(substeps)
-        self.index = rc_forest_index(self.forest)
+        self.index = index if index is not None else rc_forest_index(self.forest)
+        self.tuning = L.RcTuning(**(tuning or {}))
         self.nslots = node_slots(self.index, self.cams.ncams)
         self.vf = None
         self.counts = None
@@ -283,11 +288,12 @@ class Renderer:
         rc_prune_visible(self.forest, self.index, self.cams, self.vf, self.ws)
 
     def segments(self, hit=None, sio=None):
-        rc_segments(self.forest, self.fields, self.cams, self.vf, self.method, self.substeps, self.rec_leaf, hit, sio)
+        rc_segments(self.forest, self.fields, self.cams, self.vf, self.method, self.substeps, self.rec_leaf, hit, sio,
+                    self.tuning)
 
     def composite(self):
         rc_composite(self.forest, self.index, self.cams, self.vf, self.rec_leaf, self.rec_node, self.A, self.B,
-                     self.I)
+                     self.I, self.tuning)
 
     def forward(self):
         self.prune()
@@ -304,7 +310,7 @@ class Renderer:
             de = torch.empty_like(self.fields.eps)
         rc_segments_backward(self.forest, self.index, self.fields, self.cams, self.vf, self.method, self.substeps,
                              self.rec_leaf, self.rec_node, dLdI.contiguous(), self.adj_leaf, self.adj_node, dk, de,
-                             accumulate, self.ws)
+                             accumulate, self.ws, self.tuning)
         return dk, de
 
     # -- graph capture -----------------------------------------------------
@@ -339,13 +345,18 @@ class Renderer:
     def set_fields(self, kappa: torch.Tensor, eps: torch.Tensor):
         self.fields = DeviceFields(kappa, eps)
 
-    def debug_segments(self):
-        """Run rc_segments with the pairing outputs: (hit u8, (s_in, s_out) f64) per candidate."""
+    def debug_segments(self, intervals: bool = True):
+        """Run rc_segments with the pairing outputs: (hit u8, (s_in, s_out) f64 or None) per candidate."""
         n = self.vf.cap_cand
         hit = _empty(n, torch.uint8, self.device)
-        sio = _empty(2 * n, torch.float64, self.device)
+        sio = _empty(2 * n, torch.float64, self.device) if intervals else None
         self.segments(hit, sio)
         return hit, sio
+
+    def count_segments(self) -> int:
+        """Number of hit segments (one rc_segments pass with the hit flags)."""
+        hit, _ = self.debug_segments(intervals=False)
+        return int(hit[:self.counts["ncand"]].sum(dtype=torch.int64).item())
 
     def image(self, t: torch.Tensor, k: int = 0) -> torch.Tensor:
         return self.cams.image(t, k)

@@ -1,0 +1,80 @@
+"""Autotuner for the launch shapes of a Renderer (rc_tuning).
+
+For a fixed forest and camera set it times the forward with candidate
+workgroup counts for the segment kernel, the level folds and the root fold
+(coordinate descent, HIP events on the renderer's stream) and keeps the
+fastest.  Forward results are identical for every shape, so tuning changes
+time only.  Chosen shapes can be cached in a JSON file keyed by the
+workload's signature.
+"""
+
+from __future__ import annotations
+
+import json
+import os
+from typing import Dict, Optional
+
+import torch
+
+from . import _lib as L
+
+SEG_BLOCKS = (1024, 2048, 4096, 8192)
+FOLD_BLOCKS = (1024, 2048, 4096, 8192, 16384)
+ROOT_BLOCKS = (1024, 2048, 4096, 8192)
+
+
+def _time(renderer, fn, reps: int) -> float:
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fn()
+    torch.cuda.synchronize(renderer.device)
+    start.record()
+    for _ in range(reps):
+        fn()
+    end.record()
+    torch.cuda.synchronize(renderer.device)
+    return start.elapsed_time(end) / reps
+
+
+def signature(renderer) -> str:
+    c = renderer.counts
+    wh = ",".join(f"{w}x{h}" for w, h in renderer.cams.wh)
+    return f"N{renderer.forest.nleaves}-vis{c['nvis']}-cand{c['ncand']}-rec{c['nrec']}-m{renderer.method}-s{renderer.substeps}-{wh}"
+
+
+def autotune(renderer, reps: int = 5, cache: Optional[str] = None) -> Dict:
+    """Pick rc_tuning for `renderer` in place; returns the choice and the timings."""
+    sig = signature(renderer)
+    if cache and os.path.exists(cache):
+        try:
+            known = json.load(open(cache))
+        except (OSError, ValueError):
+            known = {}
+        if sig in known:
+            renderer.tuning = L.RcTuning(**known[sig]["tuning"])
+            return known[sig]
+    renderer.prune()
+    renderer.segments()
+    best = {"seg_blocks": 0, "fold_blocks": 0, "root_blocks": 0, "adj_blocks": 0}
+    log = {}
+    for key, opts, fn in (("seg_blocks", SEG_BLOCKS, renderer.segments),
+                          ("fold_blocks", FOLD_BLOCKS, renderer.composite),
+                          ("root_blocks", ROOT_BLOCKS, renderer.composite)):
+        times = {}
+        for v in opts:
+            renderer.tuning = L.RcTuning(**{**best, key: v})
+            times[v] = _time(renderer, fn, reps)
+        best[key] = min(times, key=times.get)
+        log[key] = {str(k): round(t, 4) for k, t in times.items()}
+    renderer.tuning = L.RcTuning(**best)
+    result = {"tuning": best, "ms": log, "signature": sig}
+    if cache:
+        known = {}
+        if os.path.exists(cache):
+            try:
+                known = json.load(open(cache))
+            except (OSError, ValueError):
+                known = {}
+        known[sig] = result
+        with open(cache, "w") as fh:
+            json.dump(known, fh, indent=1)
+    return result

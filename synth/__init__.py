@@ -13,6 +13,7 @@ from .scene import (  # noqa: F401
     Forest,
     Scene,
     config_scene,
+    config4_cameras,
     morton_keys,
     orthographic_axis_camera,
     perspective_camera,

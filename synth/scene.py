@@ -333,6 +333,13 @@ def small_scene(seed=0, lmin=2, lmax=5, ngauss=4, w=96, h=72, method="rk4", ncam
                  {"centers": centers, "sigmas": sigmas})
 
 
+def config4_cameras(ncams: int = 64, resolutions=(256, 512, 1024, 2048)) -> List[Camera]:
+    """The cameras of workload 4 (drawn from its own seed) without rebuilding the forest."""
+    rng = np.random.default_rng([1809, 1334, 4])
+    res = rng.choice(list(resolutions), size=ncams)
+    return [random_perspective_camera(rng, int(r), int(r)) for r in res]
+
+
 def config_scene(k: int, w: Optional[int] = None) -> Scene:
     """The five seeded workloads.
 
@@ -353,7 +360,9 @@ def config_scene(k: int, w: Optional[int] = None) -> Scene:
         return Scene("config1", forest, constant_fields(kappa, eps), [cam], "analytic", 1,
                      {"axis": axis, "sign": sign})
     if k in (2, 4, 5):
-        centers, sigmas = _gaussians(rng, 8, 0.03, 0.1)
+        # workload 4 renders the forest of workload 2 with cameras of its own seed
+        frng = np.random.default_rng([1809, 1334, 2]) if k == 4 else rng
+        centers, sigmas = _gaussians(frng, 8, 0.03, 0.1)
         forest = adaptive_forest(straddle_refiner(centers, sigmas), 4, 9)
         fields = trilinear_fields_from_gaussians(forest, centers, sigmas)
         extra = {"centers": centers, "sigmas": sigmas}

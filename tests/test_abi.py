@@ -81,13 +81,13 @@ def test_null_and_unsupported_arguments():
     vf = L.RcVforest()
     integ = L.RcIntegrator(L.RC_INT_ANALYTIC, 1)
     assert lib.rc_segments(ctypes.byref(f), ctypes.byref(fl), ctypes.c_void_p(16), 1, ctypes.byref(vf),
-                           ctypes.byref(integ), ctypes.c_void_p(16), None, None, None) == L.RC_EUNSUPPORTED
+                           ctypes.byref(integ), ctypes.c_void_p(16), None, None, None, None) == L.RC_EUNSUPPORTED
     integ = L.RcIntegrator(L.RC_INT_RK4, 65)
     assert lib.rc_segments(ctypes.byref(f), ctypes.byref(fl), ctypes.c_void_p(16), 1, ctypes.byref(vf),
-                           ctypes.byref(integ), ctypes.c_void_p(16), None, None, None) == L.RC_EINVAL
+                           ctypes.byref(integ), ctypes.c_void_p(16), None, None, None, None) == L.RC_EINVAL
     fl = L.RcFields(L.RC_FIELD_CONST, 2, ctypes.c_void_p(16), ctypes.c_void_p(16))
     assert lib.rc_segments(ctypes.byref(f), ctypes.byref(fl), ctypes.c_void_p(16), 1, ctypes.byref(vf),
-                           ctypes.byref(integ), ctypes.c_void_p(16), None, None, None) == L.RC_EUNSUPPORTED
+                           ctypes.byref(integ), ctypes.c_void_p(16), None, None, None, None) == L.RC_EUNSUPPORTED
 
 
 def test_sizes_are_consistent():

@@ -269,3 +269,37 @@ def test_graph_replay_matches_eager():
             assert torch.equal(x, y), k
         r.forward()  # eager work between replays
         torch.cuda.synchronize()
+
+
+def test_batched_views_equal_single_views_and_tuning_invariance():
+    """Views rendered together equal views rendered alone, bit for bit, for any launch shape."""
+    torch = _torch()
+    import paper_1809_01334_amd as P
+    from paper_1809_01334_amd.tune import autotune
+
+    scene = synth.small_scene(9, ncams=5, w=64, h=48)
+    rng = np.random.default_rng(90)
+    sizes = [(16, 16), (128, 64), (33, 97), (64, 48), (200, 150)]
+    scene.cameras = [synth.random_perspective_camera(rng, w, h, background=0.1 * k) for k, (w, h) in
+                     enumerate(sizes)]
+    rb = _renderer(scene)
+    Ab, Bb, Ib = (t.clone() for t in rb.forward())
+    for k, cam in enumerate(scene.cameras):
+        rs = P.Renderer(rb.forest, rb.fields, [cam], "rk4", 4, index=rb.index)
+        A, B, I = rs.forward()
+        sl = slice(rb.cams.img_off[k], rb.cams.img_off[k + 1])
+        assert torch.equal(A, Ab[sl]) and torch.equal(B, Bb[sl]) and torch.equal(I, Ib[sl]), k
+    for tun in ({"seg_blocks": 1, "fold_blocks": 3, "root_blocks": 7}, {"seg_blocks": 8192, "fold_blocks": 16384}):
+        rb.tuning = P._lib.RcTuning(**tun)
+        A, B, I = rb.forward()
+        assert torch.equal(A, Ab) and torch.equal(B, Bb) and torch.equal(I, Ib), tun
+    res = autotune(rb, reps=1)
+    A, B, I = rb.forward()
+    assert torch.equal(I, Ib) and set(res["tuning"]) >= {"seg_blocks", "fold_blocks"}
+    _check_images(rb, scene, _oracle())
+
+
+def _oracle():
+    from oracle import oracle as O
+
+    return O
