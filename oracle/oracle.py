@@ -54,6 +54,16 @@ def lib():
                                  ctypes.c_uint32, P, P, D, D, I32, I32, P, P]
         L.or_march.restype = I32
         L.or_march.argtypes = [I64, P, P, P, P, I32, P, P, P, I32, P, P, P]
+        L.or_shell_prune.restype = I64
+        L.or_shell_prune.argtypes = [I64, I32, P, P, P, P, P, P, P, P]
+        L.or_shell_pairs.restype = I64
+        L.or_shell_pairs.argtypes = [I64, P, I32, P, P, P, P, P, P, P, P, P, I64]
+        L.or_shell_render.restype = I32
+        L.or_shell_render.argtypes = [I64, I32, P, P, P, P, P, P, I32, P, P, I32, I32, P, I64, P, P, P, P, P, P]
+        L.or_shell_march.restype = I32
+        L.or_shell_march.argtypes = [I64, I32, P, P, P, P, P, P, I32, P, P, P, I32, P, P, P]
+        L.or_shell_map.argtypes = [P, I32, P, P]
+        L.or_shell_inverse.argtypes = [P, I32, P, P]
         for nm in ("or_combine", "or_average"):
             getattr(L, nm).argtypes = [P, P, P]
         L.or_inverse.argtypes = [P, P]
@@ -140,11 +150,28 @@ def segment(kind, kap, eps, level, x, y, z, rho, r, s_in, s_out, method, substep
 # ---------------------------------------------------------------- geometry
 
 
+def _shell(forest):
+    return getattr(forest, "geom", "unit_cube") == "shell6"
+
+
+def _shell_args(forest):
+    return (forest.ntrees, _c(forest.tree_begin, np.int64), _c(forest.geom_params, np.float64))
+
+
 def prune(forest, cams_raw):
     """rect[cam][leaf] = (i0, i1, j0, j1); empty rectangles are (1, 0, 1, 0)."""
     cams = _c(np.atleast_2d(cams_raw), np.float64)
     lv, x, y, z = _forest_args(forest)
     rect = np.zeros((cams.shape[0], forest.nleaves, 4), np.int32)
+    if _shell(forest):
+        nt, tb, gp = _shell_args(forest)
+        nvis = 0
+        for k in range(cams.shape[0]):
+            out = np.zeros((forest.nleaves, 4), np.int32)
+            nvis += lib().or_shell_prune(forest.nleaves, nt, _p(tb), _p(gp), _p(lv), _p(x), _p(y), _p(z),
+                                         _p(_c(cams[k], np.float64)), _p(out))
+            rect[k] = out
+        return rect, int(nvis)
     nvis = lib().or_prune(forest.nleaves, _p(lv), _p(x), _p(y), _p(z), cams.shape[0], _p(cams), _p(rect))
     return rect, int(nvis)
 
@@ -154,6 +181,21 @@ def node_rect(level, x, y, z, cam_raw):
     rect = np.zeros(4, np.int32)
     vis = lib().or_node_rect(int(level), int(x), int(y), int(z), _p(cam), _p(rect))
     return rect, bool(vis)
+
+
+def shell_pairs(forest, cam_raw, leaves=None):
+    """Shell pairing: per candidate the number of intervals (0..2) and [s_in0, s_out0, s_in1, s_out1]."""
+    lv, x, y, z = _forest_args(forest)
+    nt, tb, gp = _shell_args(forest)
+    lst = np.arange(forest.nleaves, dtype=np.int64) if leaves is None else _c(leaves, np.int64)
+    cam = _c(cam_raw, np.float64)
+    L = lib()
+    args = (lst.shape[0], _p(lst), nt, _p(tb), _p(gp), _p(lv), _p(x), _p(y), _p(z), _p(cam))
+    ncand = L.or_shell_pairs(*args, None, None, 0)
+    nseg = np.zeros(max(ncand, 1), np.uint8)
+    sio = np.zeros((max(ncand, 1), 4), np.float64)
+    L.or_shell_pairs(*args, _p(nseg), _p(sio), ncand)
+    return nseg[:ncand], sio[:ncand]
 
 
 def pairs(forest, cam_raw, leaves=None):
@@ -193,6 +235,12 @@ def render(forest, fields, cam, method="rk4", substeps=4, pixels=None, kappa=Non
     A, B, I = np.zeros(npo), np.zeros(npo), np.zeros(npo)
     nseg = np.zeros(npo, np.int32)
     stats = np.zeros(4, np.int64)
+    if _shell(forest):
+        nt, tb, gp = _shell_args(forest)
+        lib().or_shell_render(forest.nleaves, nt, _p(tb), _p(gp), _p(lv), _p(x), _p(y), _p(z), kind, _p(k), _p(e),
+                              METHODS[method], int(substeps), _p(raw), nsel, _p(pix), _p(A), _p(B), _p(I), _p(nseg),
+                              _p(stats))
+        return {"A": A, "B": B, "I": I, "nseg": nseg, "segments": int(stats[0]), "overlaps": int(stats[1])}
     lib().or_render(forest.nleaves, _p(lv), _p(x), _p(y), _p(z), kind, _p(k), _p(e), METHODS[method],
                     int(substeps), _p(raw), nsel, _p(pix), _p(A), _p(B), _p(I), _p(nseg), _p(stats))
     return {"A": A, "B": B, "I": I, "nseg": nseg, "segments": int(stats[0]), "overlaps": int(stats[1])}
@@ -221,6 +269,23 @@ def march(forest, fields, cam, M=1024):
     kind, k, e = _field_args(fields)
     P_ = int(raw[14]) * int(raw[15])
     A, B, I = np.zeros(P_), np.zeros(P_), np.zeros(P_)
+    if _shell(forest):
+        nt, tb, gp = _shell_args(forest)
+        lib().or_shell_march(forest.nleaves, nt, _p(tb), _p(gp), _p(lv), _p(x), _p(y), _p(z), kind, _p(k), _p(e),
+                             _p(_c(raw, np.float64)), int(M), _p(A), _p(B), _p(I))
+        return {"A": A, "B": B, "I": I}
     lib().or_march(forest.nleaves, _p(lv), _p(x), _p(y), _p(z), kind, _p(k), _p(e),
                    _p(_c(raw, np.float64)), int(M), _p(A), _p(B), _p(I))
     return {"A": A, "B": B, "I": I}
+
+
+def shell_map(geom, k, t):
+    x = np.zeros(3)
+    lib().or_shell_map(_p(_c(geom, np.float64)), int(k), _p(_c(t, np.float64)), _p(x))
+    return x
+
+
+def shell_inverse(geom, k, x):
+    t = np.zeros(3)
+    lib().or_shell_inverse(_p(_c(geom, np.float64)), int(k), _p(_c(x, np.float64)), _p(t))
+    return t

@@ -38,6 +38,7 @@
 
 #define OR_QMAX 19
 #define OR_NPMAX 16
+#define OR_PI 3.14159265358979323846
 
 /* ------------------------------------------------------------------------ */
 /* group operations on segments (Sec. 2.4 - 2.6)                            */
@@ -254,12 +255,32 @@ typedef struct {
     double kap[8], eps[8];
 } leaffield;
 
+/* Leaf reference coordinates of a real-space point. */
+typedef void (*ref_fn)(const void *ctx, const double *x, double *xi);
+
+static void cube_ref(const void *ctx, const double *x, double *xi)
+{
+    const leafbox *bx = (const leafbox *)ctx;
+    for (int k = 0; k < 3; k++) xi[k] = (x[k] - bx->lo[k]) / bx->hlen;
+}
+
 /* Segment [s_in, s_out] of ray x(s) = rho + s r inside a leaf, integrated from
  * the far end s_out toward the camera.  Returns (A,B) as dual numbers over the
  * leaf's parameters: kappa corners 0..nc-1 then eps corners nc..2nc-1. */
+static void segment_dn_ref(const leaffield *F, ref_fn ref, const void *ctx, const double *rho, const double *r,
+                           double rnorm, double s_in, double s_out, int method, int substeps, int np, dn *Aout,
+                           dn *Bout);
+
 static void segment_dn(const leaffield *F, const leafbox *bx, const double *rho, const double *r,
                        double rnorm, double s_in, double s_out, int method, int substeps, int np,
                        dn *Aout, dn *Bout)
+{
+    segment_dn_ref(F, cube_ref, bx, rho, r, rnorm, s_in, s_out, method, substeps, np, Aout, Bout);
+}
+
+static void segment_dn_ref(const leaffield *F, ref_fn ref, const void *ctx, const double *rho, const double *r,
+                           double rnorm, double s_in, double s_out, int method, int substeps, int np, dn *Aout,
+                           dn *Bout)
 {
     int nc = F->kind ? 8 : 1;
     if (method == 0) {
@@ -281,8 +302,9 @@ static void segment_dn(const leaffield *F, const leafbox *bx, const double *rho,
         double sp[4] = {s_far, s_far - 0.5 * ds, s_far - 0.5 * ds, s_far - ds};
         dn beta[4], gamma[4];
         for (int i = 0; i < 4; i++) {
-            double xi[3];
-            for (int k = 0; k < 3; k++) xi[k] = (rho[k] + sp[i] * r[k] - bx->lo[k]) / bx->hlen;
+            double xi[3], pt[3];
+            for (int k = 0; k < 3; k++) pt[k] = rho[k] + sp[i] * r[k];
+            ref(ctx, pt, xi);
             if (F->kind) {
                 beta[i] = trilin_dn(F->kap, xi, np, 0);
                 gamma[i] = trilin_dn(F->eps, xi, np, nc);
@@ -844,6 +866,458 @@ int or_march(int64_t n, const uint8_t *level, const uint32_t *x, const uint32_t 
                 or_combine(acc, sg, t);
                 acc[0] = t[0];
                 acc[1] = t[1];
+            }
+        }
+        Aout[p] = acc[0];
+        Bout[p] = acc[1];
+        Iout[p] = acc[0] * c.bg + acc[1];
+    }
+    return 0;
+}
+
+/* ======================================================================== */
+/* six-tree spherical shell (equiangular cubed sphere, Sec. 2.1 eq.          */
+/* geometrytrafo with a smooth per-tree map)                                 */
+/* ======================================================================== */
+/*
+ * Tree k: axis m = k / 2, sign sg = +1 (k even) or -1; frame e1 = unit(m+1),
+ * e2 = unit(m+2), e3 = sg unit(m).  Reference t in [0,1]^3 maps to
+ *   x = r (a e1 + b e2 + e3) / sqrt(1 + a^2 + b^2),
+ *   a = tan(pi/4 (2 t1 - 1)), b = tan(pi/4 (2 t2 - 1)), r = r0 + (r1 - r0) t3.
+ * geom = [r0, r1, L, tan(pi/4 (2 i / 2^L - 1)) for i = 0 .. 2^L]: the tan values
+ * at dyadic parameters are an input table, so no library call enters a
+ * predicate.  An element is bounded by four planes through the origin
+ * (constant t1, t2) and two spheres (constant t3); a ray meets it in at most
+ * two intervals.
+ */
+
+typedef struct {
+    int k, m, m1, m2;
+    double sg;
+    double alo, ahi, blo, bhi, rlo, rhi;
+    double tlo[3];
+    double hlen;
+    double r0, r1;
+} shellelem;
+
+static shellelem shell_elem(const double *geom, int k, uint8_t level, uint32_t x, uint32_t y, uint32_t z)
+{
+    shellelem e;
+    e.k = k;
+    e.m = k / 2;
+    e.sg = (k % 2 == 0) ? 1.0 : -1.0;
+    e.m1 = (e.m + 1) % 3;
+    e.m2 = (e.m + 2) % 3;
+    e.r0 = geom[0];
+    e.r1 = geom[1];
+    int L = (int)geom[2];
+    const double *tab = geom + 3;
+    uint32_t len = (uint32_t)1 << (OR_QMAX - level);
+    int sh = OR_QMAX - L;
+    e.alo = tab[x >> sh];
+    e.ahi = tab[(x + len) >> sh];
+    e.blo = tab[y >> sh];
+    e.bhi = tab[(y + len) >> sh];
+    double q = ldexp(1.0, -OR_QMAX);
+    double dr = e.r1 - e.r0;
+    e.rlo = e.r0 + dr * ((double)z * q);
+    e.rhi = e.r0 + dr * ((double)(z + len) * q);
+    e.tlo[0] = (double)x * q;
+    e.tlo[1] = (double)y * q;
+    e.tlo[2] = (double)z * q;
+    e.hlen = ldexp(1.0, -(int)level);
+    return e;
+}
+
+/* Reference coordinates of a point by the closed-form inverse of the map. */
+static void shell_ref(const void *ctx, const double *x, double *xi)
+{
+    const shellelem *e = (const shellelem *)ctx;
+    double w = e->sg * x[e->m];
+    double a = x[e->m1] / w, b = x[e->m2] / w;
+    double t[3];
+    t[0] = (atan(a) / (OR_PI / 4.0) + 1.0) / 2.0;
+    t[1] = (atan(b) / (OR_PI / 4.0) + 1.0) / 2.0;
+    double rr = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+    t[2] = (rr - e->r0) / (e->r1 - e->r0);
+    for (int c = 0; c < 3; c++) xi[c] = (t[c] - e->tlo[c]) / e->hlen;
+}
+
+/* Plane of constant a (tangent axis mt) through the origin: P(v) = v[mt] - a (sg v[m]).
+ * lower != 0: the element keeps P >= 0, else P < 0.  Clips [*sa, *sb]. */
+static int shell_plane(const shellelem *e, int mt, double a, int lower, const double *rho, const double *r,
+                       double *sa, double *sb)
+{
+    double Pr = r[mt] - a * (e->sg * r[e->m]);
+    double Pp = rho[mt] - a * (e->sg * rho[e->m]);
+    if (Pr != 0.0) {
+        double sx = -(Pp / Pr);
+        int ge = lower ? (Pr > 0.0) : (Pr < 0.0); /* keep s >= sx */
+        if (ge) {
+            if (sx > *sa) *sa = sx;
+        } else {
+            if (sx < *sb) *sb = sx;
+        }
+        return 1;
+    }
+    return lower ? (Pp >= 0.0) : (Pp < 0.0);
+}
+
+/* Parameters where |rho + s r| = R: |.|^2 = A s^2 + 2 B s + C. */
+static int shell_sphere(double A, double B, double C, double R, double *lo, double *hi)
+{
+    double c = C - R * R;
+    double D = B * B - A * c;
+    if (!(D > 0.0)) return 0;
+    double sq = sqrt(D);
+    double q = (B >= 0.0) ? -(B + sq) : (sq - B);
+    double s1 = q / A, s2 = c / q;
+    *lo = s1 < s2 ? s1 : s2;
+    *hi = s1 < s2 ? s2 : s1;
+    return 1;
+}
+
+/* Hit intervals of a ray with a shell element, clipped to [smin, smax]. */
+static int shell_pair(const orcam *c, const shellelem *e, const double *rho, const double *r, double *iv)
+{
+    double sa = c->smin, sb = c->smax;
+    if (!shell_plane(e, e->m1, e->alo, 1, rho, r, &sa, &sb)) return 0;
+    if (!shell_plane(e, e->m1, e->ahi, 0, rho, r, &sa, &sb)) return 0;
+    if (!shell_plane(e, e->m2, e->blo, 1, rho, r, &sa, &sb)) return 0;
+    if (!shell_plane(e, e->m2, e->bhi, 0, rho, r, &sa, &sb)) return 0;
+    if (!(sb > sa)) return 0;
+    double A = (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2];
+    double B = (rho[0] * r[0] + rho[1] * r[1]) + rho[2] * r[2];
+    double C = (rho[0] * rho[0] + rho[1] * rho[1]) + rho[2] * rho[2];
+    double o0, o1, i0, i1;
+    if (!shell_sphere(A, B, C, e->rhi, &o0, &o1)) return 0;
+    if (o0 > sa) sa = o0;
+    if (o1 < sb) sb = o1;
+    if (!(sb > sa)) return 0;
+    int n = 0;
+    if (!shell_sphere(A, B, C, e->rlo, &i0, &i1)) {
+        iv[0] = sa;
+        iv[1] = sb;
+        return 1;
+    }
+    double b0 = i0 < sb ? i0 : sb;
+    if (b0 > sa) {
+        iv[2 * n] = sa;
+        iv[2 * n + 1] = b0;
+        n++;
+    }
+    double a1 = i1 > sa ? i1 : sa;
+    if (sb > a1) {
+        iv[2 * n] = a1;
+        iv[2 * n + 1] = sb;
+        n++;
+    }
+    return n;
+}
+
+/* Lenient camera-space box of a shell element: the element lies in the convex
+ * hull of rlo c_i and (rhi / mu) c_i, c_i the unit corner directions and mu the
+ * smallest cosine between them and their normalized mean. */
+static int shell_rect(const orcam *c, const shellelem *e, int *rect)
+{
+    double cd[4][3];
+    double av[2] = {e->alo, e->ahi}, bv[2] = {e->blo, e->bhi};
+    for (int q = 0; q < 4; q++) {
+        double a = av[q & 1], b = bv[q >> 1];
+        double nrm = sqrt((1.0 + a * a) + b * b);
+        cd[q][e->m1] = a / nrm;
+        cd[q][e->m2] = b / nrm;
+        cd[q][e->m] = e->sg / nrm;
+    }
+    double mean[3];
+    for (int k = 0; k < 3; k++) mean[k] = ((cd[0][k] + cd[1][k]) + cd[2][k]) + cd[3][k];
+    double ml = sqrt((mean[0] * mean[0] + mean[1] * mean[1]) + mean[2] * mean[2]);
+    for (int k = 0; k < 3; k++) mean[k] = mean[k] / ml;
+    double mu = 1.0;
+    for (int q = 0; q < 4; q++) {
+        double d = (cd[q][0] * mean[0] + cd[q][1] * mean[1]) + cd[q][2] * mean[2];
+        if (d < mu) mu = d;
+    }
+    double sin_ = e->rlo * (1.0 - 1e-12), sout = e->rhi * (1.0 + 1e-12) / mu;
+    double ext[3][2];
+    const double *axes[3] = {c->t, c->u, c->vh};
+    for (int ax = 0; ax < 3; ax++) {
+        ext[ax][0] = INFINITY;
+        ext[ax][1] = -INFINITY;
+    }
+    for (int q = 0; q < 8; q++) {
+        double sc = (q < 4) ? sin_ : sout;
+        double p[3];
+        for (int k = 0; k < 3; k++) p[k] = sc * cd[q & 3][k] - c->o[k];
+        for (int ax = 0; ax < 3; ax++) {
+            const double *a = axes[ax];
+            double v = (a[0] * p[0] + a[1] * p[1]) + a[2] * p[2];
+            if (v < ext[ax][0]) ext[ax][0] = v;
+            if (v > ext[ax][1]) ext[ax][1] = v;
+        }
+    }
+    rect[0] = 1;
+    rect[1] = 0;
+    rect[2] = 1;
+    rect[3] = 0;
+    double Z0 = ext[2][0], Z1 = ext[2][1];
+    if (Z1 < c->n || Z0 > c->zfar) return 0;
+    double Zc0 = Z0 < c->n ? c->n : Z0;
+    double Zc1 = Z1 > c->zfar ? c->zfar : Z1;
+    int i0, i1, j0, j1;
+    pixel_range(c, ext[0][0], ext[0][1], Zc0, Zc1, c->cx, c->w, &i0, &i1);
+    pixel_range(c, ext[1][0], ext[1][1], Zc0, Zc1, c->cy, c->h, &j0, &j1);
+    if (i0 > i1 || j0 > j1) return 0;
+    rect[0] = i0;
+    rect[1] = i1;
+    rect[2] = j0;
+    rect[3] = j1;
+    return 1;
+}
+
+static int tree_of(int64_t l, int ntrees, const int64_t *tree_begin)
+{
+    int k = 0;
+    while (k + 1 < ntrees && l >= tree_begin[k + 1]) k++;
+    return k;
+}
+
+int64_t or_shell_prune(int64_t n, int ntrees, const int64_t *tree_begin, const double *geom, const uint8_t *level,
+                       const uint32_t *x, const uint32_t *y, const uint32_t *z, const double *cam, int32_t *rect)
+{
+    orcam c;
+    cam_parse(cam, &c);
+    int64_t nvis = 0;
+    for (int64_t l = 0; l < n; l++) {
+        shellelem e = shell_elem(geom, tree_of(l, ntrees, tree_begin), level[l], x[l], y[l], z[l]);
+        int rr[4];
+        nvis += shell_rect(&c, &e, rr);
+        for (int k = 0; k < 4; k++) rect[l * 4 + k] = rr[k];
+    }
+    return nvis;
+}
+
+/* Pairing of the listed leaves' candidates: nseg[q] in {0,1,2} and up to two
+ * intervals (sio[4q .. 4q+3], zeros where absent).  Returns the candidate count. */
+int64_t or_shell_pairs(int64_t nlist, const int64_t *list, int ntrees, const int64_t *tree_begin, const double *geom,
+                       const uint8_t *level, const uint32_t *x, const uint32_t *y, const uint32_t *z,
+                       const double *cam, uint8_t *nseg, double *sio, int64_t cap)
+{
+    orcam c;
+    cam_parse(cam, &c);
+    int64_t q = 0;
+    for (int64_t m = 0; m < nlist; m++) {
+        int64_t l = list[m];
+        shellelem e = shell_elem(geom, tree_of(l, ntrees, tree_begin), level[l], x[l], y[l], z[l]);
+        int rr[4];
+        if (!shell_rect(&c, &e, rr)) continue;
+        for (int j = rr[2]; j <= rr[3]; j++)
+            for (int i = rr[0]; i <= rr[1]; i++) {
+                if (q < cap) {
+                    double rho[3], r[3], iv[4] = {0, 0, 0, 0};
+                    pixel_ray(&c, i, j, rho, r);
+                    int ns = shell_pair(&c, &e, rho, r, iv);
+                    nseg[q] = (uint8_t)ns;
+                    for (int k = 0; k < 4; k++) sio[4 * q + k] = (k < 2 * ns) ? iv[k] : 0.0;
+                }
+                q++;
+            }
+    }
+    return q;
+}
+
+/* Render one camera of a shell forest (trilinear or constant fields in
+ * reference coordinates): same definition as or_render, with the closed-form
+ * inverse map for the field points.  Arguments as or_render plus the tree
+ * layout and the geometry table. */
+int or_shell_render(int64_t n, int ntrees, const int64_t *tree_begin, const double *geom, const uint8_t *level,
+                    const uint32_t *x, const uint32_t *y, const uint32_t *z, int kind, const double *kap,
+                    const double *eps, int method, int substeps, const double *cam, int64_t npix_sel,
+                    const int64_t *pix_sel, double *Aout, double *Bout, double *Iout, int32_t *nseg_pix,
+                    int64_t *stats)
+{
+    orcam c;
+    cam_parse(cam, &c);
+    int64_t W = c.w, H = c.h, P = W * H;
+    int64_t npo = (npix_sel >= 0) ? npix_sel : P;
+    int64_t *selmap = NULL;
+    if (npix_sel >= 0) {
+        selmap = (int64_t *)malloc(sizeof(int64_t) * (size_t)P);
+        for (int64_t p = 0; p < P; p++) selmap[p] = -1;
+        for (int64_t q = 0; q < npix_sel; q++) selmap[pix_sel[q]] = q;
+    }
+    int64_t cap = 1 << 16, ns = 0;
+    orseg *segs = (orseg *)malloc(sizeof(orseg) * (size_t)cap);
+    for (int64_t l = 0; l < n; l++) {
+        shellelem e = shell_elem(geom, tree_of(l, ntrees, tree_begin), level[l], x[l], y[l], z[l]);
+        int rr[4];
+        if (!shell_rect(&c, &e, rr)) continue;
+        for (int j = rr[2]; j <= rr[3]; j++)
+            for (int i = rr[0]; i <= rr[1]; i++) {
+                int64_t p = (int64_t)j * W + i, ps = p;
+                if (selmap) {
+                    ps = selmap[p];
+                    if (ps < 0) continue;
+                }
+                double rho[3], r[3], iv[4];
+                pixel_ray(&c, i, j, rho, r);
+                int nh = shell_pair(&c, &e, rho, r, iv);
+                for (int h = 0; h < nh; h++) {
+                    if (ns == cap) {
+                        cap *= 2;
+                        segs = (orseg *)realloc(segs, sizeof(orseg) * (size_t)cap);
+                    }
+                    segs[ns].pix = ps;
+                    segs[ns].s_in = iv[2 * h];
+                    segs[ns].s_out = iv[2 * h + 1];
+                    segs[ns].leaf = l;
+                    ns++;
+                }
+            }
+    }
+    free(selmap);
+    qsort(segs, (size_t)ns, sizeof(orseg), seg_cmp);
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t k = 0; k < ns; k++) {
+        orseg *s = &segs[k];
+        int64_t p = (npix_sel >= 0) ? pix_sel[s->pix] : s->pix;
+        int i = (int)(p % W), j = (int)(p / W);
+        double rho[3], r[3];
+        pixel_ray(&c, i, j, rho, r);
+        int64_t l = s->leaf;
+        shellelem e = shell_elem(geom, tree_of(l, ntrees, tree_begin), level[l], x[l], y[l], z[l]);
+        leaffield F;
+        leaf_field(kind, n, l, kap, eps, &F);
+        dn A, B;
+        segment_dn_ref(&F, shell_ref, &e, rho, r, ray_norm(r), s->s_in, s->s_out, method, substeps, 0, &A, &B);
+        s->A = A.v;
+        s->B = B.v;
+    }
+    int64_t overlaps = 0;
+    for (int64_t q = 0; q < npo; q++) {
+        Aout[q] = 1.0;
+        Bout[q] = 0.0;
+        if (nseg_pix) nseg_pix[q] = 0;
+    }
+    int64_t k = 0;
+    while (k < ns) {
+        int64_t q = segs[k].pix;
+        double acc[2] = {1.0, 0.0};
+        double prev_out = -INFINITY;
+        int cnt = 0;
+        for (; k < ns && segs[k].pix == q; k++) {
+            if (segs[k].s_in < prev_out - 1e-12 * fabs(prev_out)) overlaps++;
+            prev_out = segs[k].s_out;
+            double sg[2] = {segs[k].A, segs[k].B}, t[2];
+            or_combine(acc, sg, t);
+            acc[0] = t[0];
+            acc[1] = t[1];
+            cnt++;
+        }
+        Aout[q] = acc[0];
+        Bout[q] = acc[1];
+        if (nseg_pix) nseg_pix[q] = cnt;
+    }
+    for (int64_t q = 0; q < npo; q++) Iout[q] = Aout[q] * c.bg + Bout[q];
+    if (stats) {
+        stats[0] = ns;
+        stats[1] = overlaps;
+    }
+    free(segs);
+    return 0;
+}
+
+/* Forward map of tree k (for pins): reference t -> real x, using the library tan. */
+void or_shell_map(const double *geom, int k, const double *t, double *x)
+{
+    shellelem e = shell_elem(geom, k, 0, 0, 0, 0);
+    double a = tan(OR_PI / 4.0 * (2.0 * t[0] - 1.0)), b = tan(OR_PI / 4.0 * (2.0 * t[1] - 1.0));
+    double r = e.r0 + (e.r1 - e.r0) * t[2];
+    double nrm = sqrt(1.0 + a * a + b * b);
+    x[e.m1] = r * a / nrm;
+    x[e.m2] = r * b / nrm;
+    x[e.m] = r * e.sg / nrm;
+}
+
+/* Closed-form inverse of tree k's map (for pins). */
+void or_shell_inverse(const double *geom, int k, const double *x, double *t)
+{
+    shellelem e = shell_elem(geom, k, 0, 0, 0, 0);
+    shell_ref(&e, x, t);
+}
+
+/* Brute-force march through the shell: M equal steps over the ray's chord of
+ * the outer sphere; each step's midpoint is located by its dominant axis
+ * (tree), the closed-form inverse map and a scan of the tree's leaves; the
+ * step uses eq. ABconstant with the coefficients at the midpoint. */
+int or_shell_march(int64_t n, int ntrees, const int64_t *tree_begin, const double *geom, const uint8_t *level,
+                   const uint32_t *x, const uint32_t *y, const uint32_t *z, int kind, const double *kap,
+                   const double *eps, const double *cam, int M, double *Aout, double *Bout, double *Iout)
+{
+    orcam c;
+    cam_parse(cam, &c);
+    int64_t P = (int64_t)c.w * c.h;
+    double r0 = geom[0], r1 = geom[1];
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t p = 0; p < P; p++) {
+        int i = (int)(p % c.w), j = (int)(p / c.w);
+        double rho[3], r[3];
+        pixel_ray(&c, i, j, rho, r);
+        double acc[2] = {1.0, 0.0};
+        double A = (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2];
+        double B = (rho[0] * r[0] + rho[1] * r[1]) + rho[2] * r[2];
+        double C = (rho[0] * rho[0] + rho[1] * rho[1]) + rho[2] * rho[2];
+        double a, b;
+        if (shell_sphere(A, B, C, r1, &a, &b)) {
+            if (a < c.smin) a = c.smin;
+            if (b > c.smax) b = c.smax;
+            double rn = ray_norm(r), ds = (b - a) / M;
+            for (int m = 0; m < M && b > a; m++) {
+                double sm = a + (m + 0.5) * ds, pt[3];
+                for (int k = 0; k < 3; k++) pt[k] = rho[k] + sm * r[k];
+                double rad = sqrt(pt[0] * pt[0] + pt[1] * pt[1] + pt[2] * pt[2]);
+                if (rad < r0 || rad >= r1) continue;
+                int ax = 0;
+                for (int k = 1; k < 3; k++)
+                    if (fabs(pt[k]) > fabs(pt[ax])) ax = k;
+                int tree = 2 * ax + (pt[ax] < 0.0 ? 1 : 0);
+                if (tree >= ntrees) continue;
+                shellelem e0 = shell_elem(geom, tree, 0, 0, 0, 0);
+                double t[3];
+                shell_ref(&e0, pt, t);
+                int64_t found = -1;
+                for (int64_t l = tree_begin[tree]; l < tree_begin[tree + 1]; l++) {
+                    double q = ldexp(1.0, -OR_QMAX), hl = ldexp(1.0, -(int)level[l]);
+                    double lo[3] = {(double)x[l] * q, (double)y[l] * q, (double)z[l] * q};
+                    if (t[0] >= lo[0] && t[0] < lo[0] + hl && t[1] >= lo[1] && t[1] < lo[1] + hl && t[2] >= lo[2] &&
+                        t[2] < lo[2] + hl) {
+                        found = l;
+                        break;
+                    }
+                }
+                if (found < 0) continue;
+                shellelem e = shell_elem(geom, tree, level[found], x[found], y[found], z[found]);
+                double xi[3];
+                shell_ref(&e, pt, xi);
+                double kv, ev;
+                if (kind) {
+                    double kc[8], ec[8];
+                    for (int cc = 0; cc < 8; cc++) {
+                        kc[cc] = kap[(int64_t)cc * n + found];
+                        ec[cc] = eps[(int64_t)cc * n + found];
+                    }
+                    kv = trilin_dn(kc, xi, 0, 0).v;
+                    ev = trilin_dn(ec, xi, 0, 0).v;
+                } else {
+                    kv = kap[found];
+                    ev = eps[found];
+                }
+                dn Ad, Bd;
+                seg_const_dn(dn_c(kv, 0), dn_c(ev, 0), ds * rn, 0, &Ad, &Bd);
+                double sg[2] = {Ad.v, Bd.v}, tt[2];
+                or_combine(acc, sg, tt);
+                acc[0] = tt[0];
+                acc[1] = tt[1];
             }
         }
         Aout[p] = acc[0];

@@ -14,6 +14,12 @@ from .scene import (  # noqa: F401
     Scene,
     config_scene,
     config4_cameras,
+    shell_scene,
+    shell_map,
+    shell_frame,
+    shell_params,
+    SHELL_R0,
+    SHELL_R1,
     morton_keys,
     orthographic_axis_camera,
     perspective_camera,

@@ -220,6 +220,118 @@ def straddle_refiner(centers, sigmas, thresh=0.2, lattice=3):
 
 
 # ----------------------------------------------------------------------------
+# six-tree spherical shell (equiangular cubed sphere)
+# ----------------------------------------------------------------------------
+
+SHELL_R0, SHELL_R1 = 0.55, 1.0
+
+
+def shell_frame(k: int):
+    """(e1, e2, e3) of tree k: e3 = +-e_m (m = k // 2, sign + for even k), e1 = e_{m+1}, e2 = e_{m+2}."""
+    m, sgn = k // 2, (1.0 if k % 2 == 0 else -1.0)
+    e = np.eye(3)
+    return e[(m + 1) % 3], e[(m + 2) % 3], sgn * e[m]
+
+
+def shell_map(k: int, t: np.ndarray, r0=SHELL_R0, r1=SHELL_R1) -> np.ndarray:
+    """Equiangular map of tree k: reference t[..., 3] in [0,1]^3 to real space."""
+    e1, e2, e3 = shell_frame(k)
+    a = np.tan(np.pi / 4 * (2 * t[..., 0] - 1))
+    b = np.tan(np.pi / 4 * (2 * t[..., 1] - 1))
+    r = r0 + (r1 - r0) * t[..., 2]
+    d = a[..., None] * e1 + b[..., None] * e2 + e3
+    return (r / np.sqrt(1 + a * a + b * b))[..., None] * d
+
+
+def shell_params(level: int, r0=SHELL_R0, r1=SHELL_R1) -> np.ndarray:
+    """Geometry table: r0, r1, table level L, then tan(pi/4 (2 i / 2^L - 1)) for i = 0 .. 2^L."""
+    i = np.arange((1 << level) + 1, dtype=np.float64)
+    tab = np.tan(np.pi / 4 * (2 * i / (1 << level) - 1))
+    # exact values where they exist: tree boundaries must coincide between trees
+    tab[0], tab[-1], tab[(1 << level) // 2] = -1.0, 1.0, 0.0
+    return np.concatenate([[r0, r1, float(level)], tab])
+
+
+def shell_forest(refine_fn, lmin: int, lmax: int, chunk: int = 1 << 15) -> Forest:
+    """Six trees refined uniformly to lmin, then while refine_fn(points [n, P, 3]) says so."""
+    levels, xs, ys, zs, trees = [], [], [], [], []
+    offs = _lattice_offsets(3)
+    scale = 1.0 / (1 << QMAX)
+    for k in range(6):
+        n0 = 1 << lmin
+        g = np.arange(n0, dtype=np.int64) << (QMAX - lmin)
+        zz, yy, xx = np.meshgrid(g, g, g, indexing="ij")
+        cur = np.stack([xx.ravel(), yy.ravel(), zz.ravel()], -1)
+        for lv in range(lmin, lmax + 1):
+            if lv == lmax or cur.shape[0] == 0:
+                split = np.zeros(cur.shape[0], bool)
+            else:
+                h = 1.0 / (1 << lv)
+                split = np.zeros(cur.shape[0], bool)
+                for a in range(0, cur.shape[0], chunk):
+                    lo = cur[a:a + chunk].astype(np.float64) * scale
+                    pts = shell_map(k, lo[:, None, :] + h * offs[None, :, :])
+                    split[a:a + chunk] = refine_fn(pts)
+            keep = cur[~split]
+            levels.append(np.full(keep.shape[0], lv, np.uint8))
+            xs.append(keep[:, 0]); ys.append(keep[:, 1]); zs.append(keep[:, 2])
+            trees.append(np.full(keep.shape[0], k, np.int64))
+            if lv == lmax:
+                break
+            par = cur[split]
+            half = 1 << (QMAX - lv - 1)
+            kids = [par + np.array([(c & 1) * half, ((c >> 1) & 1) * half, ((c >> 2) & 1) * half], np.int64)
+                    for c in range(8)]
+            cur = np.concatenate(kids, 0)
+    return _sorted_forest(np.concatenate(levels), np.concatenate(xs), np.concatenate(ys), np.concatenate(zs),
+                          np.concatenate(trees), "shell6", shell_params(lmax), 6)
+
+
+def shell_corner_points(forest: Forest) -> np.ndarray:
+    """Real-space positions of the 8 reference corners of every leaf: [8, N, 3]."""
+    scale = 1.0 / (1 << QMAX)
+    lo = np.stack([forest.x, forest.y, forest.z], -1).astype(np.float64) * scale
+    h = np.ldexp(1.0, -forest.level.astype(np.int64))
+    tree = forest.tree_of_leaf()
+    r0, r1 = forest.geom_params[0], forest.geom_params[1]
+    pts = np.empty((8, forest.nleaves, 3))
+    for c in range(8):
+        t = lo + h[:, None] * np.array([c & 1, (c >> 1) & 1, (c >> 2) & 1], np.float64)
+        for k in range(6):
+            sel = tree == k
+            pts[c, sel] = shell_map(k, t[sel], r0, r1)
+    return pts
+
+
+def shell_centers(rng, k, r0=SHELL_R0, r1=SHELL_R1):
+    d = rng.normal(size=(k, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    r = (r0 ** 3 + rng.uniform(0, 1, k) * (r1 ** 3 - r0 ** 3)) ** (1.0 / 3.0)
+    return d * r[:, None]
+
+
+def shell_scene(seed=0, lmin=1, lmax=3, ngauss=4, w=96, h=72, sigma=(0.09, 0.3), dist=3.0, background=0.0,
+                rule="volume", name=None) -> "Scene":
+    """Six-tree shell with trilinear fields (in reference coordinates) from Gaussians in the shell."""
+    rng = np.random.default_rng([1809, 1334, 3] if seed is None else [1809, 1334, 3000 + seed])
+    centers = shell_centers(rng, ngauss)
+    sigmas = rng.uniform(sigma[0], sigma[1], ngauss)
+
+    def refine(pts):
+        s = gaussian_sum(pts, centers, sigmas)
+        if rule == "volume":
+            return s.max(1) > 0.2
+        return (s.min(1) < 0.2) & (s.max(1) > 0.2)
+
+    forest = shell_forest(refine, lmin, lmax)
+    pts = shell_corner_points(forest)
+    sc = np.stack([gaussian_sum(pts[c], centers, sigmas) for c in range(8)])
+    fields = Fields("trilinear", (0.2 + 2.0 * sc).astype(np.float32), (0.1 + 1.0 * sc).astype(np.float32))
+    cam = random_perspective_camera(rng, w, h, dist=dist, center=(0.0, 0.0, 0.0), background=background)
+    return Scene(name or f"shell{seed}", forest, fields, [cam], "rk4", 4, {"centers": centers, "sigmas": sigmas})
+
+
+# ----------------------------------------------------------------------------
 # fields
 # ----------------------------------------------------------------------------
 
@@ -345,7 +457,7 @@ def config_scene(k: int, w: Optional[int] = None) -> Scene:
 
     1: uniform level-3 unit cube, per-leaf constants, 64x64 orthographic, analytic.
     2: adaptive levels 4-9 (~1M leaves), trilinear, 1024^2 perspective, RK4 x 4.
-    3: six-tree spherical shell (not built by this generator yet).
+    3: six-tree equiangular shell r in [0.55, 1], levels 3-7, trilinear, 2048^2 perspective at distance 3.
     4: the workload-2 forest seen by 64 cameras of uneven resolution.
     5: a workload-2-shaped forest, 512^2, background 0.5, perturbed target fields.
     """
@@ -375,4 +487,6 @@ def config_scene(k: int, w: Optional[int] = None) -> Scene:
             cams = [random_perspective_camera(rng, w or 512, w or 512, background=0.5)]
             extra["target_fields"] = perturb_fields(fields, rng, 0.05)
         return Scene(f"config{k}", forest, fields, cams, "rk4", 4, extra)
+    if k == 3:
+        return shell_scene(None, 3, 7, 8, w or 2048, w or 2048, name="config3")
     raise ValueError(f"workload {k} is not generated here")
