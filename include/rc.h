@@ -65,18 +65,31 @@ typedef int32_t rc_status;
 #define RC_CAMERA_DOUBLES 20
 #define RC_ABSENT (-1)        /* child slot without a node in this share */
 
-enum { RC_GEOM_UNIT_CUBE = 0 };
+#define RC_MAXTREES 64
+
+enum { RC_GEOM_UNIT_CUBE = 0, RC_GEOM_SHELL6 = 1 };
 enum { RC_FIELD_CONST = 0, RC_FIELD_TRILINEAR = 1 };
 enum { RC_INT_ANALYTIC = 0, RC_INT_RK4 = 1 };
 
-/* One process's share of a forest (Sec. 2.1): leaves in SFC order. */
+/* One process's share of a forest (Sec. 2.1): leaves in SFC order.
+ *
+ * RC_GEOM_UNIT_CUBE: one tree, the identity map of the unit cube.
+ * RC_GEOM_SHELL6: six trees, the equiangular cubed-sphere shell (eq.
+ *   geometrytrafo with a smooth map per tree): tree k has axis m = k / 2, sign
+ *   sg = +1 for even k and -1 for odd k, frame e1 = unit(m+1), e2 = unit(m+2),
+ *   e3 = sg unit(m), and maps t in [0,1]^3 to
+ *   x = r (a e1 + b e2 + e3) / sqrt(1 + a^2 + b^2) with a = tan(pi/4 (2 t1 - 1)),
+ *   b = tan(pi/4 (2 t2 - 1)), r = r0 + (r1 - r0) t3.  geom_table holds
+ *   [r0, r1, L, tan(pi/4 (2 i / 2^L - 1)) for i = 0 .. 2^L] (entries 0, 2^(L-1),
+ *   2^L exactly -1, 0, 1); leaves may not be finer than level L. */
 typedef struct rc_forest {
-    int32_t ntrees;             /* trees in the share (RC_GEOM_UNIT_CUBE: 1) */
-    int32_t geom;               /* RC_GEOM_UNIT_CUBE: identity map of the unit cube */
+    int32_t ntrees;             /* trees in the share: 1 (unit cube) or 6 (shell) */
+    int32_t geom;               /* RC_GEOM_UNIT_CUBE or RC_GEOM_SHELL6 */
     int64_t nleaves;            /* N >= 1 */
     const int64_t *tree_begin;  /* [host] ntrees + 1 leaf offsets per tree */
     const uint8_t *level;       /* [device] N leaf levels, 0 .. RC_QMAXLEVEL */
     const uint32_t *x, *y, *z;  /* [device] N anchors in units of 2^-19 */
+    const double *geom_table;   /* [device] geometry table (RC_GEOM_SHELL6), else NULL */
 } rc_forest;
 
 /* Per-leaf coefficient data (Sec. 2.3): absorption kappa (beta in the paper)
@@ -119,10 +132,12 @@ typedef struct rc_index {
     int64_t cap_internal;                   /* [in] capacity of the arrays below */
     int64_t level_begin[RC_QMAXLEVEL + 2];  /* [out] internal nodes of level l: [level_begin[l], level_begin[l+1]) */
     int32_t root;                           /* [out] root node of tree 0 (same encoding as a child slot) */
-    int32_t pad2;
+    int32_t ntrees;                         /* [out] trees */
+    int32_t roots[RC_MAXTREES];             /* [out] root node of every tree (same encoding) */
     int32_t *child;                         /* [device] cap_internal * 8 */
     uint8_t *level;                         /* [device] cap_internal */
     uint32_t *x, *y, *z;                    /* [device] cap_internal anchors */
+    uint8_t *tree;                          /* [device] cap_internal: tree of each internal node */
 } rc_index;
 
 /* The visible forest ("vforest", Sec. 3.1) of a set of cameras, written by
@@ -189,6 +204,9 @@ rc_status rc_forest_index(const rc_forest *forest, rc_index *index, void *ws, si
  * rectangles and record offsets, and counts = {nvis, ncand, nrec, status}.
  * If a count exceeds its capacity, status becomes nonzero and the later
  * calls do nothing; the caller reads counts and retries with more room.
+ * RC_GEOM_SHELL6: node rectangles are unions of the children's (curved
+ * elements' boxes do not nest), so nrec is exact only once cap_vis and
+ * cap_cand suffice; a retry may then ask for more record room once more.
  */
 rc_status rc_prune_visible(const rc_forest *forest, const rc_index *index, const void *dcams, int32_t ncams,
                            rc_vforest *vf, void *ws, size_t ws_bytes, void *stream);
@@ -204,6 +222,15 @@ rc_status rc_prune_visible(const rc_forest *forest, const rc_index *index, const
  * skip): hit[device, cap_cand] 1/0 and sio[device, cap_cand * 2] the hit
  * interval in the ray parameter (alpha for perspective, depth for
  * orthographic), zeros on a miss.
+ *
+ * RC_GEOM_SHELL6 forests: a ray meets a curved element in up to two
+ * intervals (bounded by two planes through the centre per tangent axis and
+ * two spheres), so each candidate holds two records of four floats
+ * (s_in, s_out, A, B), nearer first, an unused one (0, 0, 1, 0):
+ * rec_leaf[device, cap_cand * 8], hit[] the number of intervals (0..2) and
+ * sio[device, cap_cand * 4] both intervals in FP64.  Field values at the RK4
+ * points use the reference coordinates obtained by inverting the tree map
+ * with Newton's method in FP64.
  */
 rc_status rc_segments(const rc_forest *forest, const rc_fields *fields, const void *dcams, int32_t ncams,
                       const rc_vforest *vf, const rc_integrator *integ, float *rec_leaf, uint8_t *hit,
@@ -220,6 +247,11 @@ rc_status rc_segments(const rc_forest *forest, const rc_fields *fields, const vo
  * rc_camera_prepare].  rec_node [device, cap_rec * 2] holds the
  * internal-node records (kept for the adjoint).  vf->cap_cand must be at
  * least 1: rec_leaf always holds at least one record.
+ *
+ * RC_GEOM_SHELL6 forests: records hold two intervals as in rc_segments
+ * (rec_node [device, cap_rec * 8]); a node's intervals are its children's
+ * merged by depth, touching ones combined, and the six roots' intervals are
+ * folded in depth order.
  */
 rc_status rc_composite(const rc_forest *forest, const rc_index *index, const void *dcams, int32_t ncams,
                        const rc_vforest *vf, const float *rec_leaf, float *rec_node, int64_t total_pixels,
@@ -235,6 +267,7 @@ rc_status rc_composite(const rc_forest *forest, const rc_index *index, const voi
  * fixed order.  dL_dkappa, dL_deps [device, layout of rc_fields] are
  * overwritten, or added to when accumulate != 0.  adj_leaf [device,
  * cap_cand * 2] and adj_node [device, cap_rec * 2] are scratch.
+ * RC_GEOM_SHELL6 forests return RC_EUNSUPPORTED.
  */
 rc_status rc_segments_backward(const rc_forest *forest, const rc_index *index, const rc_fields *fields,
                                const void *dcams, int32_t ncams, const rc_vforest *vf,

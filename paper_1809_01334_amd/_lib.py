@@ -22,14 +22,16 @@ RC_EFOREST = -5
 RC_EHIP = -6
 RC_QMAXLEVEL = 19
 RC_CAMERA_DOUBLES = 20
-RC_GEOM_UNIT_CUBE = 0
+RC_GEOM_UNIT_CUBE, RC_GEOM_SHELL6 = 0, 1
+RC_MAXTREES = 64
+RC_ABSENT = -1
 RC_FIELD_CONST, RC_FIELD_TRILINEAR = 0, 1
 RC_INT_ANALYTIC, RC_INT_RK4 = 0, 1
 
 
 class RcForest(ctypes.Structure):
     _fields_ = [("ntrees", c_i32), ("geom", c_i32), ("nleaves", c_i64), ("tree_begin", c_vp), ("level", c_vp),
-                ("x", c_vp), ("y", c_vp), ("z", c_vp)]
+                ("x", c_vp), ("y", c_vp), ("z", c_vp), ("geom_table", c_vp)]
 
 
 class RcFields(ctypes.Structure):
@@ -46,8 +48,9 @@ class RcTuning(ctypes.Structure):
 
 class RcIndex(ctypes.Structure):
     _fields_ = [("maxlevel", c_i32), ("pad", c_i32), ("ninternal", c_i64), ("cap_internal", c_i64),
-                ("level_begin", c_i64 * (RC_QMAXLEVEL + 2)), ("root", c_i32), ("pad2", c_i32), ("child", c_vp),
-                ("level", c_vp), ("x", c_vp), ("y", c_vp), ("z", c_vp)]
+                ("level_begin", c_i64 * (RC_QMAXLEVEL + 2)), ("root", c_i32), ("ntrees", c_i32),
+                ("roots", c_i32 * RC_MAXTREES), ("child", c_vp), ("level", c_vp), ("x", c_vp), ("y", c_vp),
+                ("z", c_vp), ("tree", c_vp)]
 
 
 class RcVforest(ctypes.Structure):

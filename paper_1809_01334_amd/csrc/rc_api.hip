@@ -100,7 +100,7 @@ extern "C" size_t rc_workspace_bytes(const rc_forest* f, const rc_index* ix, int
     int64_t nc = ncams > 0 ? ncams : 1;
     size_t b = 0;
     // rc_forest_index: status words, per-leaf current node, scan partials
-    size_t bi = 256 + rc::align_up((size_t)N * 4) + rc::scan_partial_bytes(N, 8);
+    size_t bi = rc::IX_CUR + rc::align_up((size_t)N * 4) + rc::scan_partial_bytes(N, 8);
     b = bi > b ? bi : b;
     // rc_prune_visible: partials of the joint scan over leaves and node slots
     size_t bp = rc::scan_partial_bytes(N * nc + (ix ? rc_node_slots(ix, ncams) : 0), sizeof(rc::I64x3));

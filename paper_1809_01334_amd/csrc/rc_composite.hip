@@ -80,6 +80,7 @@ extern "C" rc_status rc_composite(const rc_forest* f, const rc_index* ix, const 
     if (rc_node_slots(ix, ncams) > 0 && !rec_node) return RC_EINVAL;
     if ((s = check_tables(vf, ix, ncams)) != RC_OK) return s;
     hipStream_t st = (hipStream_t)stream;
+    if (is_shell(f)) return rc_shell_composite(f, ix, dcams, ncams, vf, rec_leaf, rec_node, npix, A, B, I, tune, st);
     FoldCtx C = make_fold_ctx(f, ix, dcams, ncams, vf, rec_leaf, rec_node);
     unsigned grid = stride_grid(vf->cap_rec, 256, tuned(tune, 1, 256 * 16));
     for (int l = ix->maxlevel - 1; l >= 1; l--) {

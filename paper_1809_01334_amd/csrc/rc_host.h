@@ -31,12 +31,35 @@ inline size_t backward_ws_bytes(int64_t cap_cand, int64_t cap_vis, int64_t ncams
 
 inline rc_status check_forest(const rc_forest* f) {
     if (!f || f->nleaves < 1 || !f->level || !f->x || !f->y || !f->z) return RC_EINVAL;
-    if (f->geom != RC_GEOM_UNIT_CUBE) return RC_EUNSUPPORTED;
-    if (f->ntrees != 1) return RC_EUNSUPPORTED;
-    if (f->tree_begin && (f->tree_begin[0] != 0 || f->tree_begin[1] != f->nleaves)) return RC_EINVAL;
+    if (f->geom == RC_GEOM_UNIT_CUBE) {
+        if (f->ntrees != 1) return RC_EUNSUPPORTED;
+    } else if (f->geom == RC_GEOM_SHELL6) {
+        if (f->ntrees != 6 || !f->geom_table || !f->tree_begin) return RC_EINVAL;
+    } else {
+        return RC_EUNSUPPORTED;
+    }
+    if (f->tree_begin) {
+        if (f->tree_begin[0] != 0 || f->tree_begin[f->ntrees] != f->nleaves) return RC_EINVAL;
+        for (int k = 0; k < f->ntrees; k++)
+            if (f->tree_begin[k + 1] < f->tree_begin[k]) return RC_EINVAL;
+    }
     if (f->nleaves > (int64_t)0x7ffffffe) return RC_EUNSUPPORTED;
     return RC_OK;
 }
+
+inline bool is_shell(const rc_forest* f) { return f->geom == RC_GEOM_SHELL6; }
+
+// Curved six-tree shell variants of rc_segments and rc_composite (arguments
+// already validated by the entry points).
+rc_status rc_shell_segments(const rc_forest* f, const rc_fields* fl, const void* dcams, const rc_vforest* vf,
+                            const rc_integrator* in, float* rec_leaf, uint8_t* hit, double* sio,
+                            const rc_tuning* tune, hipStream_t st);
+rc_status rc_shell_composite(const rc_forest* f, const rc_index* ix, const void* dcams, int32_t ncams,
+                             const rc_vforest* vf, const float* rec_leaf, float* rec_node, int64_t npix, float* A,
+                             float* B, float* I, const rc_tuning* tune, hipStream_t st);
+
+// Workspace layout of rc_forest_index.
+constexpr size_t IX_STATUS = 0, IX_COUNT = 64, IX_TREES = 256, IX_ROOTS = 1280, IX_CUR = 1536;
 
 inline rc_status check_index(const rc_index* ix) {
     if (!ix || !ix->child || !ix->level || !ix->x || !ix->y || !ix->z) return RC_EINVAL;

@@ -18,11 +18,25 @@ __device__ inline uint64_t morton(uint32_t x, uint32_t y, uint32_t z) {
     return k;
 }
 
+// Tree of leaf i from the tree offsets.
+__device__ inline int tree_of(const int64_t* tb, int ntrees, int64_t i) {
+    int k = 0;
+    while (k + 1 < ntrees && i >= tb[k + 1]) k++;
+    return k;
+}
+
+__device__ inline bool tree_start(const int64_t* tb, int ntrees, int64_t i) {
+    for (int k = 0; k <= ntrees; k++)
+        if (tb[k] == i) return true;
+    return false;
+}
+
 // status[0]: error flags, status[1]: maximum level
 __global__ void k_validate(int64_t n, const uint8_t* level, const uint32_t* x, const uint32_t* y, const uint32_t* z,
-                           int* status) {
+                           const int64_t* tb, int ntrees, int maxallowed, int* status) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    if (level[i] > maxallowed) atomicOr(&status[0], 8);
     int l = level[i];
     if (l > QMAX) {
         atomicOr(&status[0], 1);
@@ -35,7 +49,7 @@ __global__ void k_validate(int64_t n, const uint8_t* level, const uint32_t* x, c
         return;
     }
     atomicMax(&status[1], l);
-    if (i > 0) {
+    if (i > 0 && !tree_start(tb, ntrees, i)) {
         int lp = level[i - 1];
         if (lp > QMAX) return;
         uint64_t kp = morton(x[i - 1], y[i - 1], z[i - 1]);
@@ -58,11 +72,13 @@ struct OpenSrc {
     const uint8_t* level;
     const uint32_t *x, *y, *z;
     int l;
+    const int64_t* tb;
+    int ntrees;
     __device__ OpenItem operator()(int64_t i) const {
         OpenItem it;
         it.val = 0;
         if (level[i] <= l) return it;
-        if (i == 0 || level[i - 1] <= l) {
+        if (i == 0 || level[i - 1] <= l || tree_start(tb, ntrees, i)) {
             it.val = 1;
             return it;
         }
@@ -84,12 +100,19 @@ struct OpenDst {
     int32_t* child;
     uint8_t* nlevel;
     uint32_t *nx, *ny, *nz;
+    uint8_t* ntree;
+    const int64_t* tb;
+    int ntrees;
+    int32_t* roots;
     int64_t* count;
     __device__ void operator()(int64_t i, int64_t pre, const OpenItem& it) const {
         if (level[i] <= l) return;
         int64_t node = base + pre + it.val - 1;  // node of level l holding leaf i
         int sh = QMAX - l;
         if (it.val && node < cap) {
+            int tr = tree_of(tb, ntrees, i);
+            ntree[node] = (uint8_t)tr;
+            if (l == 0) roots[tr] = (int32_t)node;
             nlevel[node] = (uint8_t)l;
             nx[node] = (x[i] >> sh) << sh;
             ny[node] = (y[i] >> sh) << sh;
@@ -122,26 +145,46 @@ extern "C" rc_status rc_forest_index(const rc_forest* f, rc_index* ix, void* ws,
     if (!ws || ws_bytes < rc_workspace_bytes(f, nullptr, 1, nullptr)) return RC_EWORKSPACE;
     hipStream_t st = (hipStream_t)stream;
     int64_t N = f->nleaves;
+    int nt = f->ntrees;
     char* w = (char*)ws;
-    int* status = (int*)w;
-    int64_t* dcount = (int64_t*)(w + 64);
-    int32_t* cur = (int32_t*)(w + 256);
-    int64_t* partial = (int64_t*)(w + 256 + align_up((size_t)N * 4));
+    int* status = (int*)(w + IX_STATUS);
+    int64_t* dcount = (int64_t*)(w + IX_COUNT);
+    int64_t* dtb = (int64_t*)(w + IX_TREES);
+    int32_t* droots = (int32_t*)(w + IX_ROOTS);
+    int32_t* cur = (int32_t*)(w + IX_CUR);
+    int64_t* partial = (int64_t*)(w + IX_CUR + align_up((size_t)N * 4));
 
+    int64_t htb[RC_MAXTREES + 1];
+    int32_t hroots[RC_MAXTREES];
+    for (int k = 0; k <= nt; k++) htb[k] = f->tree_begin ? f->tree_begin[k] : (k == 0 ? 0 : N);
+    for (int k = 0; k < nt; k++) hroots[k] = htb[k + 1] > htb[k] ? (int32_t)(-2 - htb[k]) : RC_ABSENT;
+    int maxallowed = RC_QMAXLEVEL;
+    if (is_shell(f)) {
+        double L = 0.0;
+        RC_HIP(hipMemcpyAsync(&L, f->geom_table + 2, sizeof(double), hipMemcpyDeviceToHost, st));
+        RC_HIP(hipStreamSynchronize(st));
+        if (!(L >= 0.0 && L <= RC_QMAXLEVEL && L == (double)(int)L)) return RC_EINVAL;
+        maxallowed = (int)L;
+    }
+    RC_HIP(hipMemcpyAsync(dtb, htb, sizeof(int64_t) * (nt + 1), hipMemcpyHostToDevice, st));
+    RC_HIP(hipMemcpyAsync(droots, hroots, sizeof(int32_t) * nt, hipMemcpyHostToDevice, st));
     RC_HIP(hipMemsetAsync(status, 0, 64, st));
     unsigned nb = (unsigned)((N + 255) / 256);
-    hipLaunchKernelGGL(k_validate, dim3(nb), dim3(256), 0, st, N, f->level, f->x, f->y, f->z, status);
+    hipLaunchKernelGGL(k_validate, dim3(nb), dim3(256), 0, st, N, f->level, f->x, f->y, f->z, (const int64_t*)dtb, nt,
+                       maxallowed, status);
     RC_HIP(hipGetLastError());
     int hs[2];
     RC_HIP(hipMemcpyAsync(hs, status, sizeof(hs), hipMemcpyDeviceToHost, st));
     RC_HIP(hipStreamSynchronize(st));
     if (hs[0] != 0) return RC_EFOREST;
     int maxlevel = hs[1];
-    if (maxlevel == 0 && N != 1) return RC_EFOREST;
+    for (int k = 0; k < nt; k++)
+        if (maxlevel == 0 && htb[k + 1] - htb[k] > 1) return RC_EFOREST;
     ix->maxlevel = maxlevel;
+    ix->ntrees = nt;
 
     // all capacity-guarded: a first pass with too little room still counts
-    bool have = ix->child && ix->level && ix->x && ix->y && ix->z && ix->cap_internal > 0;
+    bool have = ix->child && ix->level && ix->x && ix->y && ix->z && ix->tree && ix->cap_internal > 0;
     int64_t cap = have ? ix->cap_internal : 0;
     if (have) {
         unsigned g = (unsigned)((cap * 8 + 255) / 256);
@@ -153,13 +196,9 @@ extern "C" rc_status rc_forest_index(const rc_forest* f, rc_index* ix, void* ws,
     int64_t base = 0;
     for (int l = 0; l < maxlevel; l++) {
         ix->level_begin[l] = base;
-        OpenSrc src{f->level, f->x, f->y, f->z, l};
-        OpenDst dst{f->level, f->x,  f->y,  f->z,  l,     base,  cap,
-                    cur,      ix->child, ix->level, ix->x, ix->y, ix->z, dcount};
-        if (!have) {
-            // counting only: route writes to nowhere by a zero capacity
-            dst.child = nullptr;
-        }
+        OpenSrc src{f->level, f->x, f->y, f->z, l, (const int64_t*)dtb, nt};
+        OpenDst dst{f->level, f->x,  f->y,  f->z,  l,     base,     cap,      cur,    ix->child,
+                    ix->level, ix->x, ix->y, ix->z, ix->tree, (const int64_t*)dtb, nt, droots, dcount};
         RC_HIP(launch_scan<int64_t>(N, src, dst, partial, st));
         int64_t cnt = 0;
         RC_HIP(hipMemcpyAsync(&cnt, dcount, sizeof(cnt), hipMemcpyDeviceToHost, st));
@@ -168,7 +207,10 @@ extern "C" rc_status rc_forest_index(const rc_forest* f, rc_index* ix, void* ws,
     }
     for (int l = maxlevel; l < RC_QMAXLEVEL + 2; l++) ix->level_begin[l] = base;
     ix->ninternal = base;
-    ix->root = maxlevel == 0 ? -2 : 0;
     if (base > cap) return RC_ECAPACITY;
+    RC_HIP(hipMemcpyAsync(hroots, droots, sizeof(int32_t) * nt, hipMemcpyDeviceToHost, st));
+    RC_HIP(hipStreamSynchronize(st));
+    for (int k = 0; k < RC_MAXTREES; k++) ix->roots[k] = k < nt ? hroots[k] : RC_ABSENT;
+    ix->root = hroots[0];
     return RC_OK;
 }

@@ -6,6 +6,7 @@
 // coarsening hierarchy used by compositing.
 #include "rc_host.h"
 #include "rc_internal.h"
+#include "rc_shell.h"
 
 namespace rc {
 namespace {
@@ -25,13 +26,23 @@ struct PruneSrc {
     const uint32_t *nx, *ny, *nz;
     int64_t N, nleafitems;
     SlotLayout L;
+    const double* geom;      // shell table, or null for the unit cube
+    int64_t tb[RC_MAXTREES + 1];
+    int ntrees;
     __device__ Item operator()(int64_t i) const {
         Item it;
         double lo[3], hi[3];
         if (i < nleafitems) {
             int64_t cam = divu(i, N), l = i - cam * N;
-            node_box(level[l], x[l], y[l], z[l], lo, hi);
-            it.r = box_rect(cams[cam], lo, hi);
+            if (geom) {
+                int k = 0;
+                while (k + 1 < ntrees && l >= tb[k + 1]) k++;
+                ShellElem e = shell_elem(geom, k, level[l], x[l], y[l], z[l]);
+                it.r = shell_rect(cams[cam], e);
+            } else {
+                node_box(level[l], x[l], y[l], z[l], lo, hi);
+                it.r = box_rect(cams[cam], lo, hi);
+            }
             it.val = it.r.empty() ? I64x3{0, 0, 0} : I64x3{1, it.r.area(), 0};
         } else {
             int64_t s = i - nleafitems;
@@ -87,6 +98,65 @@ struct PruneDst {
     }
 };
 
+// Curved geometry: a node's rectangle is the union of its children's, level by
+// level from the deepest (the lenient boxes of curved elements do not nest).
+__global__ __launch_bounds__(256) void k_union_level(const int32_t* child, const int32_t* leaf_vis,
+                                                     const int16_t* vis_rect, int16_t* node_rect, int64_t N, int l,
+                                                     SlotLayout L) {
+    int64_t s0 = L.slot_begin[l], s1 = L.slot_begin[l + 1];
+    int64_t M = L.level_begin[l + 1] - L.level_begin[l];
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t s = s0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < s1; s += stride) {
+        int64_t loc = s - s0;
+        int64_t cam = divu(loc, M);
+        int64_t m = L.level_begin[l] + (loc - cam * M);
+        Rect u{1, 0, 1, 0};
+        for (int q = 0; q < 8; q++) {
+            int32_t ref = child[m * 8 + q];
+            Rect r{1, 0, 1, 0};
+            if (ref <= -2) {
+                int32_t v = leaf_vis[cam * N + (-2 - (int64_t)ref)];
+                if (v >= 0) r = load_rect(vis_rect + 4 * (int64_t)v);
+            } else if (ref >= 0) {
+                int lc = l + 1;
+                int64_t Mc = L.level_begin[lc + 1] - L.level_begin[lc];
+                r = load_rect(node_rect + 4 * (L.slot_begin[lc] + cam * Mc + (ref - L.level_begin[lc])));
+            }
+            if (r.empty()) continue;
+            if (u.empty()) {
+                u = r;
+            } else {
+                u.i0 = r.i0 < u.i0 ? r.i0 : u.i0;
+                u.i1 = r.i1 > u.i1 ? r.i1 : u.i1;
+                u.j0 = r.j0 < u.j0 ? r.j0 : u.j0;
+                u.j1 = r.j1 > u.j1 ? r.j1 : u.j1;
+            }
+        }
+        store_rect(node_rect + 4 * s, u);
+    }
+}
+
+struct AreaItem {
+    int64_t val;
+};
+
+struct NodeAreaSrc {
+    const int16_t* node_rect;
+    __device__ AreaItem operator()(int64_t s) const { return AreaItem{load_rect(node_rect + 4 * s).area()}; }
+};
+
+struct NodeAreaDst {
+    int64_t nslots, cap_rec;
+    int64_t* node_offset;
+    int64_t* counts;
+    __device__ void operator()(int64_t s, int64_t pre, const AreaItem&) const { node_offset[s] = pre; }
+    __device__ void total(int64_t t) const {
+        node_offset[nslots] = t;
+        counts[2] = t;
+        if (t > cap_rec) counts[3] |= 2;
+    }
+};
+
 // table[w] = the item k whose range [off[k], off[k+1]) holds index 64 w.
 __device__ inline void chunk_entry(const int64_t* off, int64_t n, int64_t w, int32_t* table) {
     table[w] = (int32_t)upper_index(off, 0, n, w * WAVE);
@@ -108,6 +178,7 @@ struct DescArgs {
     const int64_t* counts;
     ChildDesc* desc;
     SlotLayout L;
+    int natural;  // 1: children in Morton order (curved geometry), 0: view order
 };
 
 __device__ inline void child_desc_entry(const DescArgs& a, int64_t t) {
@@ -116,7 +187,7 @@ __device__ inline void child_desc_entry(const DescArgs& a, int64_t t) {
     int64_t cam = divu(dslot, a.ninternal);
     int64_t m = dslot - cam * a.ninternal;
     int l = a.nlevel[m];
-    int sb = view_bits(a.cams[cam], l, a.nx[m], a.ny[m], a.nz[m]);
+    int sb = a.natural ? 0 : view_bits(a.cams[cam], l, a.nx[m], a.ny[m], a.nz[m]);
     int32_t ref = a.child[m * 8 + (q ^ sb)];
     Rect r{1, 0, 1, 0};
     int64_t off = 0;
@@ -184,17 +255,50 @@ extern "C" rc_status rc_prune_visible(const rc_forest* f, const rc_index* ix, co
     SlotLayout L = make_layout(ix, ncams);
     int64_t nslots = rc_node_slots(ix, ncams);
     int64_t nleafitems = N * (int64_t)ncams;
-    PruneSrc src{cams, f->level, f->x, f->y, f->z, ix->level, ix->x, ix->y, ix->z, N, nleafitems, L};
+    bool shell = is_shell(f);
+    PruneSrc src;
+    src.cams = cams;
+    src.level = f->level;
+    src.x = f->x;
+    src.y = f->y;
+    src.z = f->z;
+    src.nlevel = ix->level;
+    src.nx = ix->x;
+    src.ny = ix->y;
+    src.nz = ix->z;
+    src.N = N;
+    src.nleafitems = nleafitems;
+    src.L = L;
+    src.geom = shell ? f->geom_table : nullptr;
+    src.ntrees = f->ntrees;
+    for (int k = 0; k <= RC_MAXTREES; k++) src.tb[k] = k <= f->ntrees ? (f->tree_begin ? f->tree_begin[k] : N) : N;
     PruneDst dst{N,           nleafitems,      nslots,      vf->cap_vis,   vf->cap_cand,
                  vf->cap_rec, vf->vis_leaf,    vf->vis_cam, vf->vis_rect,  vf->cand_offset,
-                 vf->leaf_vis, vf->node_rect,  nslots > 0 ? vf->node_offset : vf->node_offset, vf->counts};
-    RC_HIP(launch_scan<I64x3>(nleafitems + nslots, src, dst, (I64x3*)ws, st));
+                 vf->leaf_vis, vf->node_rect,  vf->node_offset, vf->counts};
+    if (!shell) {
+        RC_HIP(launch_scan<I64x3>(nleafitems + nslots, src, dst, (I64x3*)ws, st));
+    } else {
+        // leaves first; node rectangles are unions of their children's
+        RC_HIP(launch_scan<I64x3>(nleafitems, src, dst, (I64x3*)ws, st));
+        for (int l = ix->maxlevel - 1; l >= 1; l--) {
+            int64_t cnt = L.slot_begin[l + 1] - L.slot_begin[l];
+            if (cnt == 0) continue;
+            hipLaunchKernelGGL(k_union_level, dim3(stride_grid(cnt, 256, 4096)), dim3(256), 0, st, ix->child,
+                               vf->leaf_vis, vf->vis_rect, vf->node_rect, N, l, L);
+            RC_HIP(hipGetLastError());
+        }
+        if (nslots > 0) {
+            NodeAreaSrc as{vf->node_rect};
+            NodeAreaDst ad{nslots, vf->cap_rec, vf->node_offset, vf->counts};
+            RC_HIP(launch_scan<int64_t>(nslots, as, ad, (int64_t*)ws, st));
+        }
+    }
 
     DescArgs da{cams,          N,            ix->ninternal,   ix->ninternal * ncams * 8,
                 ix->child,     ix->level,    ix->x,           ix->y,
                 ix->z,         vf->leaf_vis, vf->vis_rect,    vf->cand_offset,
                 vf->node_rect, vf->node_offset, vf->counts,   (ChildDesc*)vf->child_desc,
-                L};
+                L,             shell ? 1 : 0};
     int64_t nc1 = vf->cap_cand / WAVE + 1, nc2 = nslots > 0 ? vf->cap_rec / WAVE + 1 : 0;
     hipLaunchKernelGGL(k_tables, dim3(stride_grid(nc1 + nc2 + da.total, 256, 256 * 32)), dim3(256), 0, st, da, nslots,
                        nc1, nc2, vf->cand_chunk, vf->rec_chunk);

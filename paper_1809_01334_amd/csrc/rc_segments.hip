@@ -161,6 +161,7 @@ extern "C" rc_status rc_segments(const rc_forest* f, const rc_fields* fl, const 
     if ((s = check_vforest(vf, false)) != RC_OK) return s;
     if (!dcams || ncams <= 0 || !rec_leaf || !vf->cand_chunk) return RC_EINVAL;
     hipStream_t st = (hipStream_t)stream;
+    if (is_shell(f)) return rc_shell_segments(f, fl, dcams, vf, in, rec_leaf, hit, sio, tune, st);
     SegArgs a{(const Cam*)dcams, f->level,       f->x,           f->y,         f->z,        f->nleaves,
               fl->kappa,        fl->eps,        in->substeps,   vf->vis_leaf, vf->vis_cam, vf->vis_rect,
               vf->cand_offset,  vf->counts,     vf->cand_chunk, vf->cap_cand, (float2*)rec_leaf, hit,

@@ -1,0 +1,396 @@
+// rc_shell.hip -- segments and compositing for the curved six-tree shell.
+//
+// A ray meets a shell element in at most two intervals, so every record of a
+// leaf or node holds two (s_in, s_out, A, B) intervals (an empty one has
+// s_out <= s_in).  Segment values integrate the ODE with RK4 over equal
+// substeps; the field points are mapped back to reference coordinates by FP64
+// Newton on the tree map (Sec. 2.1 smooth per-tree transformations).  Curved
+// children are not ordered by a fixed permutation along a ray, so a node's
+// record merges its children's intervals by depth, combining touching
+// intervals with the group operation (Sec. 2.4) -- the merge step of the
+// paper's per-pixel segment lists (Sec. 3.5).
+#include "rc_composite.h"
+#include "rc_shell.h"
+
+using namespace rc;
+
+namespace rc {
+namespace {
+
+__device__ inline float4 empty_iv() { return make_float4(0.0f, 0.0f, 1.0f, 0.0f); }
+__device__ inline bool iv_valid(const float4& v) { return v.y > v.x; }
+
+struct ShellSegArgs {
+    const Cam* cams;
+    const uint8_t* level;
+    const uint32_t *x, *y, *z;
+    int64_t N;
+    const float *kappa, *eps;
+    int kind;  // RC_FIELD_CONST or RC_FIELD_TRILINEAR
+    const double* geom;
+    int64_t tb[RC_MAXTREES + 1];
+    int ntrees;
+    const int32_t* vis_leaf;
+    const int16_t* vis_cam;
+    const int16_t* vis_rect;
+    const int64_t* cand_offset;
+    const int64_t* counts;
+    const int32_t* cand_chunk;
+    int64_t cap_cand;
+    float4* rec;    // 2 per candidate
+    uint8_t* hit;   // number of intervals
+    double* sio;    // 4 per candidate
+};
+
+// RK4 over NSUB substeps of one interval, field points from Newton inversion
+// (NSUB = 0: analytic, constant fields).
+template <int NSUB>
+__device__ inline float2 shell_integrate(const ShellSegArgs& a, int64_t leaf, const ShellElem& e, const double rho[3],
+                                         const double r[3], double s_in, double s_out) {
+    if constexpr (NSUB == 0) {
+        // constant coefficients: the closed form of eq. ABconstant
+        double rn = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+        return seg_const(a.kappa[leaf], a.eps[leaf], (float)((s_out - s_in) * rn));
+    }
+    constexpr int NP = 2 * (NSUB > 0 ? NSUB : 1) + 1;
+    float kc[8], ec[8];
+    if (a.kind == RC_FIELD_TRILINEAR) {
+        const float4* kp = reinterpret_cast<const float4*>(a.kappa + leaf * 8);
+        const float4* ep = reinterpret_cast<const float4*>(a.eps + leaf * 8);
+        float4 k0 = kp[0], k1 = kp[1], e0 = ep[0], e1 = ep[1];
+        kc[0] = k0.x; kc[1] = k0.y; kc[2] = k0.z; kc[3] = k0.w;
+        kc[4] = k1.x; kc[5] = k1.y; kc[6] = k1.z; kc[7] = k1.w;
+        ec[0] = e0.x; ec[1] = e0.y; ec[2] = e0.z; ec[3] = e0.w;
+        ec[4] = e1.x; ec[5] = e1.y; ec[6] = e1.z; ec[7] = e1.w;
+    } else {
+#pragma unroll
+        for (int q = 0; q < 8; q++) {
+            kc[q] = a.kappa[leaf];
+            ec[q] = a.eps[leaf];
+        }
+    }
+    double h = ldexp(1.0, -e.level);
+    double scale = ldexp(1.0, e.level);
+    double t[3] = {e.tlo[0] + 0.5 * h, e.tlo[1] + 0.5 * h, e.tlo[2] + 0.5 * h};
+    float bs[NP], gs[NP];
+    double ds = s_out - s_in;
+#pragma unroll
+    for (int p = 0; p < NP; p++) {
+        double s = s_out - ds * ((double)p / (double)(2 * NSUB));
+        double pt[3] = {rho[0] + s * r[0], rho[1] + s * r[1], rho[2] + s * r[2]};
+        shell_newton(e, pt, t);
+        float xi0 = (float)((t[0] - e.tlo[0]) * scale);
+        float xi1 = (float)((t[1] - e.tlo[1]) * scale);
+        float xi2 = (float)((t[2] - e.tlo[2]) * scale);
+        bs[p] = trilin(kc, xi0, xi1, xi2);
+        gs[p] = trilin(ec, xi0, xi1, xi2);
+    }
+    double rn = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    float hstep = (float)(ds * rn) / (float)NSUB;
+    float2 acc = make_float2(1.0f, 0.0f);
+#pragma unroll
+    for (int q = 0; q < NSUB; q++) {
+        float2 st = rk4_step(bs[2 * q], bs[2 * q + 1], bs[2 * q + 2], gs[2 * q], gs[2 * q + 1], gs[2 * q + 2], hstep);
+        acc = seg_combine(st, acc);
+    }
+    return acc;
+}
+
+template <int NSUB>
+__global__ __launch_bounds__(256) void k_segments_shell(ShellSegArgs a) {
+    if (a.counts[3]) return;
+    int64_t nvis = a.counts[0];
+    int64_t ncand = a.counts[1] < a.cap_cand ? a.counts[1] : a.cap_cand;
+    int lane = threadIdx.x & (WAVE - 1);
+    int64_t wave = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    int64_t nw = (int64_t)gridDim.x * (blockDim.x / WAVE);
+    for (int64_t w = wave; w * WAVE < ncand; w += nw) {
+        int64_t g = w * WAVE + lane;
+        if (g >= ncand) continue;
+        int64_t v = cand_pair(a.cand_offset, a.cand_chunk, g, w, nvis, ncand);
+        int32_t leaf = a.vis_leaf[v];
+        const Cam& c = a.cams[a.vis_cam[v]];
+        Rect rc = load_rect(a.vis_rect + 4 * v);
+        int kk = (int)(g - a.cand_offset[v]);
+        int wr = rc.width();
+        int j = rc.j0 + kk / wr;
+        int i = rc.i0 + (kk - (kk / wr) * wr);
+        int tr = 0;
+        while (tr + 1 < a.ntrees && leaf >= a.tb[tr + 1]) tr++;
+        ShellElem e = shell_elem(a.geom, tr, a.level[leaf], a.x[leaf], a.y[leaf], a.z[leaf]);
+        double rho[3], r[3], iv[4] = {0.0, 0.0, 0.0, 0.0};
+        pixel_ray(c, i, j, rho, r);
+        int n = shell_pair(c, e, rho, r, iv);
+        float4 out[2] = {empty_iv(), empty_iv()};
+        for (int hh = 0; hh < n; hh++) {
+            float2 ab = shell_integrate<NSUB>(a, leaf, e, rho, r, iv[2 * hh], iv[2 * hh + 1]);
+            float4 o = make_float4((float)iv[2 * hh], (float)iv[2 * hh + 1], ab.x, ab.y);
+            if (hh == 0)
+                out[0] = o;
+            else
+                out[1] = o;
+        }
+        a.rec[2 * g] = out[0];
+        a.rec[2 * g + 1] = out[1];
+        if (a.hit) a.hit[g] = (uint8_t)n;
+        if (a.sio) {
+            a.sio[4 * g] = iv[0];
+            a.sio[4 * g + 1] = iv[1];
+            a.sio[4 * g + 2] = n > 1 ? iv[2] : 0.0;
+            a.sio[4 * g + 3] = n > 1 ? iv[3] : 0.0;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// compositing by depth-ordered interval merging
+// ---------------------------------------------------------------------------
+
+struct ShellFold {
+    FoldCtx C;
+    const float4* rec_leaf;  // 2 per candidate
+    const float4* rec_node;  // 2 per record
+};
+
+__device__ inline void child_intervals(const ShellFold& S, const ChildDesc& d, int i, int j, float4& a, float4& b) {
+    if (!desc_has(d, i, j)) {
+        a = empty_iv();
+        b = empty_iv();
+        return;
+    }
+    int64_t k = desc_index(d, i, j);
+    const float4* p = d.off >= 0 ? S.rec_node + 2 * (d.off + k) : S.rec_leaf + 2 * (-1 - d.off + k);
+    a = p[0];
+    b = p[1];
+}
+
+__device__ inline float4 join_iv(const float4& p, const float4& q) {
+    float2 m = seg_combine(make_float2(p.z, p.w), make_float2(q.z, q.w));
+    return make_float4(p.x, q.y > p.y ? q.y : p.y, m.x, m.y);
+}
+
+// Merge the children's intervals (up to 16) into the node's, at most two.
+// Taken nearest first; an interval that starts where the previous one ends
+// (or before) extends it.  A third run can only come from rounding at a
+// shared face (the node meets a ray in at most two intervals), so the two
+// runs with the smallest gap between them are joined: empty space between
+// them is the identity of the group, so the value is unchanged.
+template <int NQ>
+__device__ inline void merge_runs(const float4 (&iv)[NQ], float4& o0, float4& o1) {
+    uint32_t used = 0;
+    int nout = 0;
+    o0 = empty_iv();
+    o1 = empty_iv();
+    for (int it = 0; it < NQ; it++) {
+        float best = INFINITY;
+        float4 cur = empty_iv();
+        int bq = -1;
+#pragma unroll
+        for (int q = 0; q < NQ; q++) {
+            bool ok = iv_valid(iv[q]) && !((used >> q) & 1u) && iv[q].x < best;
+            if (ok) {
+                best = iv[q].x;
+                cur = iv[q];
+                bq = q;
+            }
+        }
+        if (bq < 0) break;
+        used |= 1u << bq;
+        if (nout == 0) {
+            o0 = cur;
+            nout = 1;
+        } else if (nout == 1) {
+            if (cur.x <= o0.y) {
+                o0 = join_iv(o0, cur);
+            } else {
+                o1 = cur;
+                nout = 2;
+            }
+        } else if (cur.x <= o1.y) {
+            o1 = join_iv(o1, cur);
+        } else if (o1.x - o0.y < cur.x - o1.y) {
+            o0 = join_iv(o0, o1);
+            o1 = cur;
+        } else {
+            o1 = join_iv(o1, cur);
+        }
+    }
+}
+
+template <bool UNIFORM>
+__device__ inline void shell_node(const ShellFold& S, int64_t dslot, int i, int j, float4& o0, float4& o1) {
+    float4 iv[16];
+#pragma unroll
+    for (int q = 0; q < 8; q++) {
+        ChildDesc d = UNIFORM ? load_desc_scalar(S.C.desc, dslot * 8 + q) : load_desc(S.C.desc + dslot * 8 + q);
+        child_intervals(S, d, i, j, iv[2 * q], iv[2 * q + 1]);
+    }
+    merge_runs<16>(iv, o0, o1);
+}
+
+__device__ inline void shell_node_auto(const ShellFold& S, int64_t dslot, bool active, int i, int j, float4& o0,
+                                       float4& o1) {
+    int64_t d0 = uniform64(dslot);
+    if (__all(!active || dslot == d0))
+        shell_node<true>(S, d0, i, j, o0, o1);
+    else
+        shell_node<false>(S, dslot, i, j, o0, o1);
+}
+
+__global__ __launch_bounds__(256) void k_fold_level_shell(ShellFold S, int l, float4* out) {
+    const FoldCtx& C = S.C;
+    if (C.counts[3]) return;
+    int64_t s0 = C.L.slot_begin[l], s1 = C.L.slot_begin[l + 1];
+    int64_t R0 = C.node_offset[s0], R1 = C.node_offset[s1], Rtot = C.node_offset[C.nslots];
+    int64_t M = C.L.level_begin[l + 1] - C.L.level_begin[l];
+    int lane = threadIdx.x & (WAVE - 1);
+    int64_t wave = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    int64_t nw = (int64_t)gridDim.x * (blockDim.x / WAVE);
+    for (int64_t w = R0 / WAVE + wave; w * WAVE < R1; w += nw) {
+        int64_t g = w * WAVE + lane;
+        bool act = g >= R0 && g < R1;
+        int64_t gg = act ? g : (g < R0 ? R0 : R1 - 1);
+        int64_t slot = record_slot(C, gg, w, s0, s1, Rtot);
+        int64_t loc = slot - s0;
+        int64_t cam = divu(loc, M);
+        int64_t m = C.L.level_begin[l] + (loc - cam * M);
+        Rect r = load_rect(C.node_rect + 4 * slot);
+        int k = (int)(gg - C.node_offset[slot]);
+        int wr = r.width();
+        int j = r.j0 + k / wr;
+        int i = r.i0 + (k - (k / wr) * wr);
+        float4 o0, o1;
+        shell_node_auto(S, cam * C.ninternal + m, act, i, j, o0, o1);
+        if (act) {
+            out[2 * g] = o0;
+            out[2 * g + 1] = o1;
+        }
+    }
+}
+
+// Roots: each tree's intervals, then all trees folded front to back.
+__global__ __launch_bounds__(256) void k_fold_root_shell(ShellFold S, int ntrees, int32_t r0, int32_t r1, int32_t r2,
+                                                         int32_t r3, int32_t r4, int32_t r5, int64_t npix, float* A,
+                                                         float* B, float* I, const int32_t* leaf_vis,
+                                                         const int16_t* vis_rect, const int64_t* cand_offset) {
+    const FoldCtx& C = S.C;
+    if (C.counts[3]) return;
+    int32_t roots[6] = {r0, r1, r2, r3, r4, r5};
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < npix; p += stride) {
+        int cam = camera_of_pixel(C.cams, C.ncams, p);
+        const Cam& c = C.cams[cam];
+        int64_t loc = p - c.img_off;
+        int j = (int)(loc / c.w);
+        int i = (int)(loc - (int64_t)j * c.w);
+        float4 iv[12];
+#pragma unroll
+        for (int t = 0; t < 6; t++) {
+            iv[2 * t] = empty_iv();
+            iv[2 * t + 1] = empty_iv();
+            int32_t root = t < ntrees ? roots[t] : RC_ABSENT;
+            if (root >= 0) {
+                shell_node_auto(S, (int64_t)cam * C.ninternal + root, true, i, j, iv[2 * t], iv[2 * t + 1]);
+            } else if (root <= -2) {
+                int32_t v = leaf_vis[(int64_t)cam * C.N + (-2 - (int64_t)root)];
+                if (v >= 0) {
+                    Rect r = load_rect(vis_rect + 4 * (int64_t)v);
+                    if (r.contains(i, j)) {
+                        const float4* q = S.rec_leaf + 2 * (cand_offset[v] + (int64_t)(j - r.j0) * r.width() + (i - r.i0));
+                        iv[2 * t] = q[0];
+                        iv[2 * t + 1] = q[1];
+                    }
+                }
+            }
+        }
+        // every interval in depth order; gaps between them hold nothing
+        uint32_t used = 0;
+        float2 acc = make_float2(1.0f, 0.0f);
+        for (int it = 0; it < 12; it++) {
+            float best = INFINITY;
+            float4 cur = empty_iv();
+            int bq = -1;
+#pragma unroll
+            for (int q = 0; q < 12; q++) {
+                bool ok = iv_valid(iv[q]) && !((used >> q) & 1u) && iv[q].x < best;
+                if (ok) {
+                    best = iv[q].x;
+                    cur = iv[q];
+                    bq = q;
+                }
+            }
+            if (bq < 0) break;
+            used |= 1u << bq;
+            acc = seg_combine(acc, make_float2(cur.z, cur.w));
+        }
+        A[p] = acc.x;
+        B[p] = acc.y;
+        I[p] = fmaf(acc.x, (float)c.bg, acc.y);
+    }
+}
+
+}  // namespace
+}  // namespace rc
+
+// Called by rc_segments and rc_composite for RC_GEOM_SHELL6 forests.
+rc_status rc::rc_shell_segments(const rc_forest* f, const rc_fields* fl, const void* dcams, const rc_vforest* vf,
+                            const rc_integrator* in, float* rec_leaf, uint8_t* hit, double* sio,
+                            const rc_tuning* tune, hipStream_t st) {
+    ShellSegArgs a;
+    a.cams = (const Cam*)dcams;
+    a.level = f->level;
+    a.x = f->x;
+    a.y = f->y;
+    a.z = f->z;
+    a.N = f->nleaves;
+    a.kappa = fl->kappa;
+    a.eps = fl->eps;
+    a.kind = fl->kind;
+    a.geom = f->geom_table;
+    for (int k = 0; k <= RC_MAXTREES; k++) a.tb[k] = k <= f->ntrees ? f->tree_begin[k] : f->nleaves;
+    a.ntrees = f->ntrees;
+    a.vis_leaf = vf->vis_leaf;
+    a.vis_cam = vf->vis_cam;
+    a.vis_rect = vf->vis_rect;
+    a.cand_offset = vf->cand_offset;
+    a.counts = vf->counts;
+    a.cand_chunk = vf->cand_chunk;
+    a.cap_cand = vf->cap_cand;
+    a.rec = (float4*)rec_leaf;
+    a.hit = hit;
+    a.sio = sio;
+    dim3 G(stride_grid(vf->cap_cand, 256, tuned(tune, 0, 256 * 8))), B(256);
+    int ns = in->method == RC_INT_ANALYTIC ? 0 : in->substeps;
+    switch (ns) {
+        case 0: hipLaunchKernelGGL((k_segments_shell<0>), G, B, 0, st, a); break;
+        case 1: hipLaunchKernelGGL((k_segments_shell<1>), G, B, 0, st, a); break;
+        case 2: hipLaunchKernelGGL((k_segments_shell<2>), G, B, 0, st, a); break;
+        case 4: hipLaunchKernelGGL((k_segments_shell<4>), G, B, 0, st, a); break;
+        case 8: hipLaunchKernelGGL((k_segments_shell<8>), G, B, 0, st, a); break;
+        default: return RC_EUNSUPPORTED;
+    }
+    RC_HIP(hipGetLastError());
+    return RC_OK;
+}
+
+rc_status rc::rc_shell_composite(const rc_forest* f, const rc_index* ix, const void* dcams, int32_t ncams,
+                             const rc_vforest* vf, const float* rec_leaf, float* rec_node, int64_t npix, float* A,
+                             float* B, float* I, const rc_tuning* tune, hipStream_t st) {
+    ShellFold S;
+    S.C = make_fold_ctx(f, ix, dcams, ncams, vf, rec_leaf, rec_node);
+    S.rec_leaf = (const float4*)rec_leaf;
+    S.rec_node = (const float4*)rec_node;
+    unsigned grid = stride_grid(vf->cap_rec, 256, tuned(tune, 1, 256 * 16));
+    for (int l = ix->maxlevel - 1; l >= 1; l--) {
+        if (ix->level_begin[l + 1] == ix->level_begin[l]) continue;
+        hipLaunchKernelGGL(k_fold_level_shell, dim3(grid), dim3(256), 0, st, S, l, (float4*)rec_node);
+        RC_HIP(hipGetLastError());
+    }
+    int32_t r[6];
+    for (int k = 0; k < 6; k++) r[k] = k < ix->ntrees ? ix->roots[k] : RC_ABSENT;
+    hipLaunchKernelGGL(k_fold_root_shell, dim3(stride_grid(npix, 256, tuned(tune, 2, 256 * 16))), dim3(256), 0, st, S,
+                       ix->ntrees, r[0], r[1], r[2], r[3], r[4], r[5], npix, A, B, I, vf->leaf_vis, vf->vis_rect,
+                       vf->cand_offset);
+    RC_HIP(hipGetLastError());
+    return RC_OK;
+}

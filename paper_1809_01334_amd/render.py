@@ -30,9 +30,10 @@ def _empty(n, dtype, device):
 
 
 class DeviceForest:
-    """Leaves of one forest share on the device (SFC order, unit-cube geometry)."""
+    """Leaves of one forest share on the device (SFC order).  Geometry: the
+    unit cube (one tree), or with ``geom_table`` the six-tree shell."""
 
-    def __init__(self, level, x, y, z, device, tree_begin=None):
+    def __init__(self, level, x, y, z, device, tree_begin=None, geom_table=None):
         self.device = torch.device(device)
         self.nleaves = int(len(level))
         self.level = torch.from_numpy(np.ascontiguousarray(level, np.uint8)).to(self.device)
@@ -41,13 +42,22 @@ class DeviceForest:
         self.z = torch.from_numpy(np.ascontiguousarray(z, np.uint32).view(np.int32)).to(self.device)
         tb = np.array([0, self.nleaves], np.int64) if tree_begin is None else np.asarray(tree_begin, np.int64)
         self.tree_begin = np.ascontiguousarray(tb)
-        self.struct = L.RcForest(int(len(tb) - 1), L.RC_GEOM_UNIT_CUBE, self.nleaves,
+        self.geom = L.RC_GEOM_UNIT_CUBE if geom_table is None else L.RC_GEOM_SHELL6
+        self.geom_table = None
+        if geom_table is not None:
+            self.geom_table = torch.from_numpy(np.ascontiguousarray(geom_table, np.float64)).to(self.device)
+        self.struct = L.RcForest(int(len(tb) - 1), self.geom, self.nleaves,
                                  self.tree_begin.ctypes.data_as(ctypes.c_void_p), _ptr(self.level), _ptr(self.x),
-                                 _ptr(self.y), _ptr(self.z))
+                                 _ptr(self.y), _ptr(self.z), _ptr(self.geom_table))
+
+    @property
+    def shell(self) -> bool:
+        return self.geom == L.RC_GEOM_SHELL6
 
     @classmethod
     def from_synth(cls, forest, device):
-        return cls(forest.level, forest.x, forest.y, forest.z, device, forest.tree_begin)
+        table = forest.geom_params if forest.geom == "shell6" else None
+        return cls(forest.level, forest.x, forest.y, forest.z, device, forest.tree_begin, table)
 
 
 class DeviceFields:
@@ -101,10 +111,11 @@ class DeviceIndex:
         self.x = _empty(cap, torch.int32, d)
         self.y = _empty(cap, torch.int32, d)
         self.z = _empty(cap, torch.int32, d)
+        self.tree = _empty(cap, torch.uint8, d)
         s = self.struct
         s.cap_internal = max(int(cap), 1)
-        s.child, s.level, s.x, s.y, s.z = (_ptr(self.child), _ptr(self.level), _ptr(self.x), _ptr(self.y),
-                                           _ptr(self.z))
+        s.child, s.level, s.x, s.y, s.z, s.tree = (_ptr(self.child), _ptr(self.level), _ptr(self.x), _ptr(self.y),
+                                                   _ptr(self.z), _ptr(self.tree))
 
     @property
     def maxlevel(self):
@@ -116,6 +127,9 @@ class DeviceIndex:
 
     def level_begin(self):
         return np.array(list(self.struct.level_begin), np.int64)
+
+    def roots(self):
+        return [int(r) for r in self.struct.roots[:int(self.struct.ntrees)]]
 
 
 class VForest:
@@ -242,6 +256,8 @@ class Renderer:
         self.fields = fields if isinstance(fields, DeviceFields) else DeviceFields.from_synth(fields, self.device)
         raw = cameras if isinstance(cameras, np.ndarray) else np.stack([c.raw() for c in cameras])
         self.cams = rc_camera_prepare(raw, self.device)
+        # floats per record: (A, B), or two (s_in, s_out, A, B) intervals on the shell
+        self.rec_floats = 8 if self.forest.shell else 2
         self.method = METHODS[method] if isinstance(method, str) else int(method)
         self.substeps = int(substeps)
         self.index = index if index is not None else rc_forest_index(self.forest)
@@ -255,17 +271,22 @@ class Renderer:
     # -- sizing -----------------------------------------------------------
     def plan(self, slack: float = 1.0):
         N, nc = self.forest.nleaves, self.cams.ncams
-        vf = VForest(self.device, N, nc, self.nslots, 0, 0, 0, self.index.ninternal)
         ws = _empty(workspace_bytes(self.forest, self.index, nc, None), torch.uint8, self.device)
-        rc_prune_visible(self.forest, self.index, self.cams, vf, ws)
-        c = vf.read_counts()
-        cap_vis = int(c["nvis"] * slack) + 1
-        cap_cand = int(c["ncand"] * slack) + 1
-        cap_rec = int(c["nrec"] * slack) + 1
+        caps = (0, 0, 0)
+        # a pass with too little room still counts; on the curved shell the
+        # node record count needs the leaf rectangles, so it settles one pass later
+        for _ in range(3):
+            vf = VForest(self.device, N, nc, self.nslots, *caps, self.index.ninternal)
+            rc_prune_visible(self.forest, self.index, self.cams, vf, ws)
+            c = vf.read_counts()
+            if c["status"] == 0 and caps[0] > 0:
+                break
+            caps = tuple(int(c[k] * slack) + 1 for k in ("nvis", "ncand", "nrec"))
+        cap_vis, cap_cand, cap_rec = caps
         self.vf = VForest(self.device, N, nc, self.nslots, cap_vis, cap_cand, cap_rec, self.index.ninternal)
         self.ws = _empty(workspace_bytes(self.forest, self.index, nc, self.vf), torch.uint8, self.device)
-        self.rec_leaf = _empty(2 * cap_cand, torch.float32, self.device)
-        self.rec_node = _empty(2 * cap_rec, torch.float32, self.device)
+        self.rec_leaf = _empty(self.rec_floats * cap_cand, torch.float32, self.device)
+        self.rec_node = _empty(self.rec_floats * cap_rec, torch.float32, self.device)
         P = self.cams.npix
         self.A = _empty(P, torch.float32, self.device)
         self.B = _empty(P, torch.float32, self.device)
@@ -346,17 +367,18 @@ class Renderer:
         self.fields = DeviceFields(kappa, eps)
 
     def debug_segments(self, intervals: bool = True):
-        """Run rc_segments with the pairing outputs: (hit u8, (s_in, s_out) f64 or None) per candidate."""
+        """Run rc_segments with the pairing outputs per candidate: hits (u8; 0/1, or
+        0..2 intervals on the shell) and the intervals in FP64 (2 or 4 doubles) or None."""
         n = self.vf.cap_cand
         hit = _empty(n, torch.uint8, self.device)
-        sio = _empty(2 * n, torch.float64, self.device) if intervals else None
+        sio = _empty((4 if self.forest.shell else 2) * n, torch.float64, self.device) if intervals else None
         self.segments(hit, sio)
         return hit, sio
 
     def count_segments(self) -> int:
         """Number of hit segments (one rc_segments pass with the hit flags)."""
         hit, _ = self.debug_segments(intervals=False)
-        return int(hit[:self.counts["ncand"]].sum(dtype=torch.int64).item())
+        return int(hit[:self.counts["ncand"]].to(torch.int64).sum().item())
 
     def image(self, t: torch.Tensor, k: int = 0) -> torch.Tensor:
         return self.cams.image(t, k)

@@ -112,3 +112,34 @@ def test_product_path_has_no_cpu_fallback():
         if fn.endswith(".py"):
             src = open(os.path.join(pkg, fn)).read()
             assert "oracle" not in src, fn
+
+
+def test_ctypes_structs_match_the_header_layout(tmp_path):
+    """sizeof and offsetof of every struct in rc.h, from a C probe built with gcc."""
+    import shutil
+    import subprocess
+
+    from paper_1809_01334_amd import _lib as L
+
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    structs = {"rc_forest": L.RcForest, "rc_fields": L.RcFields, "rc_integrator": L.RcIntegrator,
+               "rc_tuning": L.RcTuning, "rc_index": L.RcIndex, "rc_vforest": L.RcVforest}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "rc.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            if fname.startswith("pad"):
+                continue
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("return 0; }")
+    src = tmp_path / "probe.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "probe"
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    out = subprocess.check_output([str(exe)], text=True).split("\n")
+    for line in filter(None, out):
+        cname, fname, val = line.split()
+        py = structs[cname]
+        want = ctypes.sizeof(py) if fname == "sizeof" else getattr(py, fname).offset
+        assert int(val) == want, (cname, fname, int(val), want)
