@@ -4,7 +4,7 @@ Step = one full render of the adaptive workload: visibility/compaction,
 segment generation (RK4 x 4 on trilinear fields) and sort-free compositing,
 with all inputs resident in HBM.  Prints one JSON line.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-bwd]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-bwd] [--no-batch] [--no-shell]
 """
 
 from __future__ import annotations
@@ -67,6 +67,7 @@ def main():
     ap.add_argument("--no-bwd", action="store_true")
     ap.add_argument("--res", type=int, default=1024)
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-shell", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the forest share of one "
@@ -166,6 +167,8 @@ def main():
         out["adjoint_workload"] = bench_adjoint(torch, P, synth, max(args.steps // 2, 5))
     if not args.no_batch:
         out["batched_workload"] = bench_batched(torch, P, synth, r, max(args.steps // 10, 3))
+    if not args.no_shell:
+        out["shell_workload"] = bench_shell(torch, P, synth, max(args.steps // 10, 3))
 
     if not args.no_cpu:
         log("[bench] timing the CPU oracle")
@@ -234,6 +237,39 @@ def bench_batched(torch, P, synth, r, steps):
             "segments": S, "batched_ms": t_batch, "plain_sum_ms": t_plain, "plain_over_batched": t_plain / t_batch,
             "ray_segments_per_s": S / (t_batch * 1e-3), "images_per_s": len(cams) / (t_batch * 1e-3),
             "tuning": tune["tuning"]}
+
+
+def bench_shell(torch, P, synth, steps):
+    """Six-tree cubed-sphere shell, levels 3-7, trilinear fields, 2048x2048 view:
+    curved pairing (planes and spheres, up to two intervals), RK4 x 4 with FP64
+    Newton field points, depth-merging fold."""
+    log("[bench] shell workload: generating")
+    sc = synth.config_scene(3)
+    r = P.Renderer(sc.forest, sc.fields, sc.cameras, "rk4", 4, device="cuda:0")
+    c = r.counts
+    S = r.count_segments()
+    log(f"[bench] shell: {sc.forest.nleaves} leaves, visible {c['nvis']}, candidates {c['ncand']}, segments {S}, "
+        f"node records {c['nrec']}")
+    for _ in range(2):
+        r.forward()
+    ms_eager = time_region(torch, r.forward, steps)
+    r.capture()
+    r.replay()
+    ms = time_region(torch, r.replay, steps)
+    t_prune = time_region(torch, r.prune, steps)
+    t_seg = time_region(torch, r.segments, steps)
+    t_comp = time_region(torch, r.composite, steps)
+    log(f"[bench] shell: forward {ms:.2f} ms (graph), {ms_eager:.2f} ms (eager); prune {t_prune:.2f}, "
+        f"segments {t_seg:.2f}, composite {t_comp:.2f} ms")
+    out = {"workload": f"6-tree cubed-sphere shell r in [0.55, 1], levels 3-7 ({sc.forest.nleaves} leaves), "
+                       f"trilinear kappa/eps, 2048x2048 perspective view, RK4 x 4, FP64 Newton field points",
+           "leaves": sc.forest.nleaves, "visible": c["nvis"], "candidates": c["ncand"], "segments": S,
+           "node_records": c["nrec"], "ms_per_step": ms, "forward_eager_ms": ms_eager,
+           "ray_segments_per_s": S / (ms * 1e-3), "images_per_s": 1e3 / ms,
+           "phase_ms": {"prune": t_prune, "segments": t_seg, "composite": t_comp}}
+    del r
+    torch.cuda.empty_cache()
+    return out
 
 
 if __name__ == "__main__":

@@ -23,6 +23,10 @@ struct ShellElem {
     double r0, r1;
 };
 
+// Component k (0..2, known only at run time) of a 3-vector, by selects so the
+// vector stays in registers.
+__device__ inline double pick(const double v[3], int k) { return k == 0 ? v[0] : (k == 1 ? v[1] : v[2]); }
+
 // geom = [r0, r1, L, tan table (2^L + 1 entries)]
 __device__ inline ShellElem shell_elem(const double* geom, int k, int level, uint32_t x, uint32_t y, uint32_t z) {
 #pragma clang fp contract(off)
@@ -63,13 +67,9 @@ __device__ inline Rect shell_rect(const Cam& c, const ShellElem& e) {
     for (int q = 0; q < 4; q++) {
         double a = av[q & 1], b = bv[q >> 1];
         double nrm = sqrt((1.0 + a * a) + b * b);
-        double v[3];
-        v[e.m1] = a / nrm;
-        v[e.m2] = b / nrm;
-        v[e.m] = e.sg / nrm;
-        cd[q][0] = v[0];
-        cd[q][1] = v[1];
-        cd[q][2] = v[2];
+        double va = a / nrm, vb = b / nrm, vc = e.sg / nrm;
+#pragma unroll
+        for (int k = 0; k < 3; k++) cd[q][k] = k == e.m1 ? va : (k == e.m2 ? vb : vc);
     }
     double mean[3];
 #pragma unroll
@@ -117,8 +117,8 @@ __device__ inline Rect shell_rect(const Cam& c, const ShellElem& e) {
 __device__ inline bool shell_plane(const ShellElem& e, int mt, double a, bool lower, const double rho[3],
                                    const double r[3], double& sa, double& sb) {
 #pragma clang fp contract(off)
-    double Pr = r[mt] - a * (e.sg * r[e.m]);
-    double Pp = rho[mt] - a * (e.sg * rho[e.m]);
+    double Pr = pick(r, mt) - a * (e.sg * pick(r, e.m));
+    double Pp = pick(rho, mt) - a * (e.sg * pick(rho, e.m));
     if (Pr != 0.0) {
         double sx = -(Pp / Pr);
         bool ge = lower ? (Pr > 0.0) : (Pr < 0.0);
@@ -178,46 +178,101 @@ __device__ inline int shell_pair(const Cam& c, const ShellElem& e, const double 
     }
     double a1 = i1 > sa ? i1 : sa;
     if (sb > a1) {
-        iv[2 * n] = a1;
-        iv[2 * n + 1] = sb;
+        if (n == 0) {
+            iv[0] = a1;
+            iv[1] = sb;
+        } else {
+            iv[2] = a1;
+            iv[3] = sb;
+        }
         n++;
     }
     return n;
 }
 
-// Newton inversion of the tree map in FP64: reference t (in/out, warm start)
-// for the real point x, in the tree frame X = (x[m1], x[m2], sg x[m]) where the
-// map reads X = (r / rho) (a, b, 1).  Converged to a residual of 1e-13 or after
-// 8 steps.
-__device__ inline void shell_newton(const ShellElem& e, const double x[3], double t[3]) {
-    const double qpi = 0.78539816339744830962;  // pi / 4
-    const double hpi = 1.57079632679489661923;  // pi / 2
-    double X1 = x[e.m1], X2 = x[e.m2], X3 = e.sg * x[e.m];
-    double dr = e.r1 - e.r0;
-    for (int it = 0; it < 8; it++) {
-        double a = tan(qpi * (2.0 * t[0] - 1.0));
-        double b = tan(qpi * (2.0 * t[1] - 1.0));
-        double r = e.r0 + dr * t[2];
-        double rho2 = 1.0 + a * a + b * b;
-        double rho = sqrt(rho2);
-        double f = r / rho;
-        double F1 = f * a - X1, F2 = f * b - X2, F3 = f - X3;
-        if (fmax(fabs(F1), fmax(fabs(F2), fabs(F3))) <= 1e-13) break;
-        double r3 = r / (rho2 * rho);
-        double da = hpi * (1.0 + a * a), db = hpi * (1.0 + b * b);
-        // Jacobian columns d/dt1, d/dt2, d/dt3
-        double J11 = r3 * (1.0 + b * b) * da, J21 = -r3 * a * b * da, J31 = -r3 * a * da;
-        double J12 = -r3 * a * b * db, J22 = r3 * (1.0 + a * a) * db, J32 = -r3 * b * db;
-        double J13 = a / rho * dr, J23 = b / rho * dr, J33 = dr / rho;
-        double det = J11 * (J22 * J33 - J23 * J32) - J12 * (J21 * J33 - J23 * J31) + J13 * (J21 * J32 - J22 * J31);
-        double id = 1.0 / det;
-        double d1 = (F1 * (J22 * J33 - J23 * J32) - J12 * (F2 * J33 - J23 * F3) + J13 * (F2 * J32 - J22 * F3)) * id;
-        double d2 = (J11 * (F2 * J33 - J23 * F3) - F1 * (J21 * J33 - J23 * J31) + J13 * (J21 * F3 - F2 * J31)) * id;
-        double d3 = (J11 * (J22 * F3 - F2 * J32) - J12 * (J21 * F3 - F2 * J31) + F1 * (J21 * J32 - J22 * J31)) * id;
-        t[0] -= d1;
-        t[1] -= d2;
-        t[2] -= d3;
+// Inversion of the tree map in FP64.  The map sends rays from the centre to
+// rays, so j_k(t) = x splits into tan(theta1(t1)) = X1 / X3,
+// tan(theta2(t2)) = X2 / X3 and r(t3) = |x| in the tree frame
+// X = (x[m1], x[m2], sg x[m]), with theta(t) = pi/4 (2 t - 1).  The angular
+// equations are solved by Newton's method on theta, warm-started along the
+// ray; the radial one is linear.
+
+// tan(d) for |d| <= 0.1 from its Taylor series (coefficients from the
+// Bernoulli numbers); the first omitted term is below 2e-18.
+__device__ inline double tan_small(double d) {
+    double z = d * d;
+    double p = 929569.0 / 638512875.0;
+    p = fma(p, z, 21844.0 / 6081075.0);
+    p = fma(p, z, 1382.0 / 155925.0);
+    p = fma(p, z, 62.0 / 2835.0);
+    p = fma(p, z, 17.0 / 315.0);
+    p = fma(p, z, 2.0 / 15.0);
+    p = fma(p, z, 1.0 / 3.0);
+    return fma(d * z, p, d);
+}
+
+// tan(d) for |d| <= 0.8: halve until |d| <= 0.1, then double back with
+// tan(2 x) = 2 tan(x) / (1 - tan(x)^2).
+__device__ inline double tan_step(double d) {
+    int k = 0;
+    while (fabs(d) > 0.1 && k < 3) {
+        d *= 0.5;
+        k++;
     }
+    double t = tan_small(d);
+    for (int i = 0; i < k; i++) t = (t + t) / fma(-t, t, 1.0);
+    return t;
+}
+
+// Newton for theta with tan(theta) = A from the pair (theta, T = tan(theta)):
+// theta += d, d = -(T - A) / (1 + T^2) limited to |d| <= 0.5 (the tree spans
+// pi/2 in theta), and T advanced by the addition theorem.  Stops at
+// |T - A| <= 1e-13.
+__device__ inline void angle_newton(double A, double& th, double& T) {
+    for (int it = 0; it < 24; it++) {
+        double res = T - A;
+        if (fabs(res) <= 1e-13) break;
+        double d = -res / fma(T, T, 1.0);
+        d = fmin(fmax(d, -0.5), 0.5);
+        th += d;
+        double tau = tan_step(d);
+        T = (T + tau) / fma(-T, tau, 1.0);
+    }
+}
+
+// Leaf reference coordinates of the real point x (three floats in [0, 1] up
+// to rounding), updating the angle state (th1, T1), (th2, T2).
+struct ShellRef {
+    double th_lo1, th_lo2, k_ang, k_rad, r0, tlo3;
+    double th1, T1, th2, T2;
+};
+
+__device__ inline ShellRef shell_ref_init(const ShellElem& e) {
+    const double hpi = 1.57079632679489661923;  // pi / 2
+    const double qpi = 0.78539816339744830962;  // pi / 4
+    ShellRef s;
+    double scale = ldexp(1.0, e.level);
+    s.th_lo1 = hpi * e.tlo[0] - qpi;
+    s.th_lo2 = hpi * e.tlo[1] - qpi;
+    s.k_ang = scale / hpi;
+    s.k_rad = scale / (e.r1 - e.r0);
+    s.r0 = e.r0;
+    s.tlo3 = e.tlo[2] * scale;
+    s.th1 = s.th_lo1;  // start at the element's low corner, where tan is the table value
+    s.T1 = e.alo;
+    s.th2 = s.th_lo2;
+    s.T2 = e.blo;
+    return s;
+}
+
+__device__ inline void shell_ref_point(const ShellElem& e, ShellRef& s, const double x[3], float xi[3]) {
+    double X1 = pick(x, e.m1), X2 = pick(x, e.m2), X3 = e.sg * pick(x, e.m);
+    angle_newton(X1 / X3, s.th1, s.T1);
+    angle_newton(X2 / X3, s.th2, s.T2);
+    double rr = sqrt(fma(X1, X1, fma(X2, X2, X3 * X3)));
+    xi[0] = (float)((s.th1 - s.th_lo1) * s.k_ang);
+    xi[1] = (float)((s.th2 - s.th_lo2) * s.k_ang);
+    xi[2] = (float)(fma(rr - s.r0, s.k_rad, -s.tlo3));
 }
 
 }  // namespace rc

@@ -52,7 +52,7 @@ __device__ inline float2 shell_integrate(const ShellSegArgs& a, int64_t leaf, co
         double rn = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
         return seg_const(a.kappa[leaf], a.eps[leaf], (float)((s_out - s_in) * rn));
     }
-    constexpr int NP = 2 * (NSUB > 0 ? NSUB : 1) + 1;
+    constexpr int NS = NSUB > 0 ? NSUB : 1;
     float kc[8], ec[8];
     if (a.kind == RC_FIELD_TRILINEAR) {
         const float4* kp = reinterpret_cast<const float4*>(a.kappa + leaf * 8);
@@ -69,77 +69,141 @@ __device__ inline float2 shell_integrate(const ShellSegArgs& a, int64_t leaf, co
             ec[q] = a.eps[leaf];
         }
     }
-    double h = ldexp(1.0, -e.level);
-    double scale = ldexp(1.0, e.level);
-    double t[3] = {e.tlo[0] + 0.5 * h, e.tlo[1] + 0.5 * h, e.tlo[2] + 0.5 * h};
-    float bs[NP], gs[NP];
+    ShellRef sr = shell_ref_init(e);
     double ds = s_out - s_in;
-#pragma unroll
-    for (int p = 0; p < NP; p++) {
-        double s = s_out - ds * ((double)p / (double)(2 * NSUB));
+    // field values at the point p / (2 NSUB) of the way from the far end
+    auto field_at = [&](int p, float& bv, float& gv) {
+        double s = s_out - ds * ((double)p / (double)(2 * NS));
         double pt[3] = {rho[0] + s * r[0], rho[1] + s * r[1], rho[2] + s * r[2]};
-        shell_newton(e, pt, t);
-        float xi0 = (float)((t[0] - e.tlo[0]) * scale);
-        float xi1 = (float)((t[1] - e.tlo[1]) * scale);
-        float xi2 = (float)((t[2] - e.tlo[2]) * scale);
-        bs[p] = trilin(kc, xi0, xi1, xi2);
-        gs[p] = trilin(ec, xi0, xi1, xi2);
-    }
+        float xi[3];
+        shell_ref_point(e, sr, pt, xi);
+        bv = trilin(kc, xi[0], xi[1], xi[2]);
+        gv = trilin(ec, xi[0], xi[1], xi[2]);
+    };
     double rn = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
-    float hstep = (float)(ds * rn) / (float)NSUB;
+    float hstep = (float)(ds * rn) / (float)NS;
+    float b0, g0;
+    field_at(0, b0, g0);
     float2 acc = make_float2(1.0f, 0.0f);
-#pragma unroll
+#pragma unroll 1
     for (int q = 0; q < NSUB; q++) {
-        float2 st = rk4_step(bs[2 * q], bs[2 * q + 1], bs[2 * q + 2], gs[2 * q], gs[2 * q + 1], gs[2 * q + 2], hstep);
-        acc = seg_combine(st, acc);
+        float bm, gm, b1, g1;
+        field_at(2 * q + 1, bm, gm);
+        field_at(2 * q + 2, b1, g1);
+        acc = seg_combine(rk4_step(b0, bm, b1, g0, gm, g1, hstep), acc);
+        b0 = b1;
+        g0 = g1;
     }
     return acc;
 }
 
+// Curved pairing runs one candidate per lane; each hit interval goes to a
+// per-wave LDS queue and is integrated 64 at a time (the Newton inversions
+// dominate, so the integration runs with every lane busy whatever the hit
+// rate).  An entry keeps what is needed to rebuild the ray and the element.
+constexpr int SQCAP = 192;  // < 64 waiting + up to 2 x 64 new
+struct ShellQueue {
+    int64_t slot[SQCAP];  // 2 g + interval
+    int32_t leaf[SQCAP];
+    int32_t cam[SQCAP];
+    int32_t pix[SQCAP];  // i | j << 16
+    double s_in[SQCAP], s_out[SQCAP];
+};
+
+template <int NSUB>
+__device__ inline void shell_drain(const ShellSegArgs& a, const ShellQueue& q, int k) {
+    int32_t leaf = q.leaf[k];
+    const Cam& c = a.cams[q.cam[k]];
+    int i = q.pix[k] & 0xffff, j = q.pix[k] >> 16;
+    int tr = 0;
+    while (tr + 1 < a.ntrees && leaf >= a.tb[tr + 1]) tr++;
+    ShellElem e = shell_elem(a.geom, tr, a.level[leaf], a.x[leaf], a.y[leaf], a.z[leaf]);
+    double rho[3], r[3];
+    pixel_ray(c, i, j, rho, r);
+    double s0 = q.s_in[k], s1 = q.s_out[k];
+    float2 ab = shell_integrate<NSUB>(a, leaf, e, rho, r, s0, s1);
+    a.rec[q.slot[k]] = make_float4((float)s0, (float)s1, ab.x, ab.y);
+}
+
+__device__ inline void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <int NSUB>
 __global__ __launch_bounds__(256) void k_segments_shell(ShellSegArgs a) {
+    __shared__ ShellQueue Q[256 / WAVE];
     if (a.counts[3]) return;
     int64_t nvis = a.counts[0];
     int64_t ncand = a.counts[1] < a.cap_cand ? a.counts[1] : a.cap_cand;
     int lane = threadIdx.x & (WAVE - 1);
+    ShellQueue& q = Q[threadIdx.x / WAVE];
     int64_t wave = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
     int64_t nw = (int64_t)gridDim.x * (blockDim.x / WAVE);
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int qn = 0;  // queued intervals, the same in every lane
     for (int64_t w = wave; w * WAVE < ncand; w += nw) {
         int64_t g = w * WAVE + lane;
-        if (g >= ncand) continue;
-        int64_t v = cand_pair(a.cand_offset, a.cand_chunk, g, w, nvis, ncand);
-        int32_t leaf = a.vis_leaf[v];
-        const Cam& c = a.cams[a.vis_cam[v]];
-        Rect rc = load_rect(a.vis_rect + 4 * v);
-        int kk = (int)(g - a.cand_offset[v]);
-        int wr = rc.width();
-        int j = rc.j0 + kk / wr;
-        int i = rc.i0 + (kk - (kk / wr) * wr);
-        int tr = 0;
-        while (tr + 1 < a.ntrees && leaf >= a.tb[tr + 1]) tr++;
-        ShellElem e = shell_elem(a.geom, tr, a.level[leaf], a.x[leaf], a.y[leaf], a.z[leaf]);
-        double rho[3], r[3], iv[4] = {0.0, 0.0, 0.0, 0.0};
-        pixel_ray(c, i, j, rho, r);
-        int n = shell_pair(c, e, rho, r, iv);
-        float4 out[2] = {empty_iv(), empty_iv()};
-        for (int hh = 0; hh < n; hh++) {
-            float2 ab = shell_integrate<NSUB>(a, leaf, e, rho, r, iv[2 * hh], iv[2 * hh + 1]);
-            float4 o = make_float4((float)iv[2 * hh], (float)iv[2 * hh + 1], ab.x, ab.y);
-            if (hh == 0)
-                out[0] = o;
-            else
-                out[1] = o;
+        int n = 0, cam = 0, pix = 0;
+        int32_t leaf = 0;
+        double iv[4] = {0.0, 0.0, 0.0, 0.0};
+        if (g < ncand) {
+            int64_t v = cand_pair(a.cand_offset, a.cand_chunk, g, w, nvis, ncand);
+            leaf = a.vis_leaf[v];
+            cam = a.vis_cam[v];
+            const Cam& c = a.cams[cam];
+            Rect rc = load_rect(a.vis_rect + 4 * v);
+            int kk = (int)(g - a.cand_offset[v]);
+            int wr = rc.width();
+            int j = rc.j0 + kk / wr;
+            int i = rc.i0 + (kk - (kk / wr) * wr);
+            pix = i | (j << 16);
+            int tr = 0;
+            while (tr + 1 < a.ntrees && leaf >= a.tb[tr + 1]) tr++;
+            ShellElem e = shell_elem(a.geom, tr, a.level[leaf], a.x[leaf], a.y[leaf], a.z[leaf]);
+            double rho[3], r[3];
+            pixel_ray(c, i, j, rho, r);
+            n = shell_pair(c, e, rho, r, iv);
+            if (n < 2) a.rec[2 * g + 1] = empty_iv();
+            if (n < 1) a.rec[2 * g] = empty_iv();
+            if (a.hit) a.hit[g] = (uint8_t)n;
+            if (a.sio) {
+                a.sio[4 * g] = iv[0];
+                a.sio[4 * g + 1] = iv[1];
+                a.sio[4 * g + 2] = n > 1 ? iv[2] : 0.0;
+                a.sio[4 * g + 3] = n > 1 ? iv[3] : 0.0;
+            }
         }
-        a.rec[2 * g] = out[0];
-        a.rec[2 * g + 1] = out[1];
-        if (a.hit) a.hit[g] = (uint8_t)n;
-        if (a.sio) {
-            a.sio[4 * g] = iv[0];
-            a.sio[4 * g + 1] = iv[1];
-            a.sio[4 * g + 2] = n > 1 ? iv[2] : 0.0;
-            a.sio[4 * g + 3] = n > 1 ? iv[3] : 0.0;
+        uint64_t m1 = __ballot(n >= 1), m2 = __ballot(n >= 2);
+        int c1 = __popcll(m1);
+        if (n >= 1) {
+            int pos = qn + __popcll(m1 & below);
+            q.slot[pos] = 2 * g;
+            q.leaf[pos] = leaf;
+            q.cam[pos] = cam;
+            q.pix[pos] = pix;
+            q.s_in[pos] = iv[0];
+            q.s_out[pos] = iv[1];
+        }
+        if (n >= 2) {
+            int pos = qn + c1 + __popcll(m2 & below);
+            q.slot[pos] = 2 * g + 1;
+            q.leaf[pos] = leaf;
+            q.cam[pos] = cam;
+            q.pix[pos] = pix;
+            q.s_in[pos] = iv[2];
+            q.s_out[pos] = iv[3];
+        }
+        qn += c1 + __popcll(m2);
+        wave_sync_lds();
+        while (qn >= WAVE) {
+            shell_drain<NSUB>(a, q, qn - WAVE + lane);
+            qn -= WAVE;
+            wave_sync_lds();
         }
     }
+    if (lane < qn) shell_drain<NSUB>(a, q, lane);
 }
 
 // ---------------------------------------------------------------------------
