@@ -102,8 +102,10 @@ extern "C" size_t rc_workspace_bytes(const rc_forest* f, const rc_index* ix, int
     // rc_forest_index: status words, per-leaf current node, scan partials
     size_t bi = rc::IX_CUR + rc::align_up((size_t)N * 4) + rc::scan_partial_bytes(N, 8);
     b = bi > b ? bi : b;
-    // rc_prune_visible: partials of the joint scan over leaves and node slots
-    size_t bp = rc::scan_partial_bytes(N * nc + (ix ? rc_node_slots(ix, ncams) : 0), sizeof(rc::I64x3));
+    // rc_prune_visible: partials of the joint scan over leaves and node slots,
+    // then the rectangles of the reduce pass (8 bytes per item)
+    int64_t items = N * nc + (ix ? rc_node_slots(ix, ncams) : 0);
+    size_t bp = rc::align_up(rc::scan_partial_bytes(items, sizeof(rc::I64x3))) + rc::align_up((size_t)items * 8);
     b = bp > b ? bp : b;
     // rc_segments_backward: gradient partials per (wave chunk, visible pair)
     if (vf) {

@@ -580,6 +580,27 @@ inline hipError_t launch_scan_n(int64_t n, int64_t nb, Src src, Dst dst, T* part
     return hipGetLastError();
 }
 
+// As launch_scan_n, with separate item sources for the reduce and the apply
+// passes (they must agree on every item's value).
+template <typename T, int ITEMS, typename SrcR, typename SrcA, typename Dst>
+inline hipError_t launch_scan2_n(int64_t n, int64_t nb, SrcR sr, SrcA sa, Dst dst, T* partial, hipStream_t st) {
+    hipLaunchKernelGGL((k_scan_reduce<T, ITEMS, SrcR>), dim3((unsigned)nb), dim3(SCAN_NT), 0, st, n, sr, partial);
+    hipLaunchKernelGGL((k_scan_partials<T>), dim3(1), dim3(SCAN_NT), 0, st, nb, partial);
+    hipLaunchKernelGGL((k_scan_apply<T, ITEMS, SrcA, Dst>), dim3((unsigned)nb), dim3(SCAN_NT), 0, st, n, nb, sa,
+                       dst, (const T*)partial);
+    return hipGetLastError();
+}
+
+template <typename T, typename SrcR, typename SrcA, typename Dst>
+inline hipError_t launch_scan2(int64_t n, SrcR sr, SrcA sa, Dst dst, T* partial, hipStream_t st) {
+    int64_t nb = scan_blocks(n);
+    switch (scan_items(n)) {
+        case 1: return launch_scan2_n<T, 1>(n, nb, sr, sa, dst, partial, st);
+        case 4: return launch_scan2_n<T, 4>(n, nb, sr, sa, dst, partial, st);
+        default: return launch_scan2_n<T, SCAN_MAX_ITEMS>(n, nb, sr, sa, dst, partial, st);
+    }
+}
+
 template <typename T, typename Src, typename Dst>
 inline hipError_t launch_scan(int64_t n, Src src, Dst dst, T* partial, hipStream_t st) {
     int64_t nb = scan_blocks(n);

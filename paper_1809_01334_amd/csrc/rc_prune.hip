@@ -29,7 +29,13 @@ struct PruneSrc {
     const double* geom;      // shell table, or null for the unit cube
     int64_t tb[RC_MAXTREES + 1];
     int ntrees;
+    int16_t* stash;          // every item's rectangle, for the apply pass
     __device__ Item operator()(int64_t i) const {
+        Item it = compute(i);
+        store_rect(stash + 4 * i, it.r);
+        return it;
+    }
+    __device__ Item compute(int64_t i) const {
         Item it;
         double lo[3], hi[3];
         if (i < nleafitems) {
@@ -56,6 +62,21 @@ struct PruneSrc {
             it.r = box_rect(cams[cam], lo, hi);
             it.val = I64x3{0, 0, it.r.area()};
         }
+        return it;
+    }
+};
+
+// The apply pass reads the rectangles the reduce pass computed.
+struct StashSrc {
+    const int16_t* stash;
+    int64_t nleafitems;
+    __device__ Item operator()(int64_t i) const {
+        Item it;
+        it.r = load_rect(stash + 4 * i);
+        if (i < nleafitems)
+            it.val = it.r.empty() ? I64x3{0, 0, 0} : I64x3{1, it.r.area(), 0};
+        else
+            it.val = I64x3{0, 0, it.r.area()};
         return it;
     }
 };
@@ -272,14 +293,17 @@ extern "C" rc_status rc_prune_visible(const rc_forest* f, const rc_index* ix, co
     src.geom = shell ? f->geom_table : nullptr;
     src.ntrees = f->ntrees;
     for (int k = 0; k <= RC_MAXTREES; k++) src.tb[k] = k <= f->ntrees ? (f->tree_begin ? f->tree_begin[k] : N) : N;
+    int64_t items = shell ? nleafitems : nleafitems + nslots;
+    src.stash = (int16_t*)((char*)ws + align_up(scan_partial_bytes(nleafitems + nslots, sizeof(I64x3))));
+    StashSrc stash{src.stash, nleafitems};
     PruneDst dst{N,           nleafitems,      nslots,      vf->cap_vis,   vf->cap_cand,
                  vf->cap_rec, vf->vis_leaf,    vf->vis_cam, vf->vis_rect,  vf->cand_offset,
                  vf->leaf_vis, vf->node_rect,  vf->node_offset, vf->counts};
     if (!shell) {
-        RC_HIP(launch_scan<I64x3>(nleafitems + nslots, src, dst, (I64x3*)ws, st));
+        RC_HIP(launch_scan2<I64x3>(items, src, stash, dst, (I64x3*)ws, st));
     } else {
         // leaves first; node rectangles are unions of their children's
-        RC_HIP(launch_scan<I64x3>(nleafitems, src, dst, (I64x3*)ws, st));
+        RC_HIP(launch_scan2<I64x3>(items, src, stash, dst, (I64x3*)ws, st));
         for (int l = ix->maxlevel - 1; l >= 1; l--) {
             int64_t cnt = L.slot_begin[l + 1] - L.slot_begin[l];
             if (cnt == 0) continue;
