@@ -22,12 +22,35 @@ sys.path.insert(0, ROOT)
 
 METRIC = "ray-segments/s + images/s at 1 GPU, % HBM roofline; fwd+bwd vs fwd time"
 HBM_PEAK_GBS = 8000.0
-# FP32 vector peak without packed FP32 instructions: 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
+# FP32 vector peak without packed FP32 instructions (and the FP64 vector
+# peak): 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz = 78.6 TFLOP/s
 FP32_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
-# algorithmic cost model of the segment kernel (per hit segment / per candidate)
-SEG_FLOPS_RK4 = 570  # 9 points x 2 fields trilinear (378) + points (54) + 4 RK4 steps (128) + 3 combines (9)
-CAND_FLOPS_FP64 = 60  # ray, three reciprocals and the slab test
+# Algorithmic cost per unit (the work the method must do, not what a kernel
+# happens to issue):
+#   trilinear segment: cubic restriction ~120, field values at the RK4 stage
+#   points 16 x 2 fields x Horner 6 = 192, four RK4 steps ~160, combines 9
+#   -> ~480 FP32 flop per segment; ray and slab predicate ~20 FP64 per candidate;
+#   shell segment: Newton inversion at 16 stage points x 2-3 iterations x ~80
+#   -> ~3500 FP64 flop per segment on top.
+SEG_FLOPS_FP32 = 480
+CAND_FLOPS_FP64 = 20
+SHELL_SEG_FLOPS_FP64 = 3500
+#   compositing: every leaf record read once (8 B; shell 2 x 16 B + 1 B) and
+#   A, B, I written (12 B per pixel);  visibility: 13 B read per leaf and
+#   about 20 B written per visible pair.
+REC_BYTES = 8
+SHELL_REC_BYTES = 33
+PIX_BYTES = 12
+
+# HBM traffic of the dominant kernel per launch, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE (calibrated on a 256 MiB device copy: x2.0 and x1.0), valid for
+# the kernel sources whose SHA-256 is given.
+MEASURED_TRAFFIC = {
+    "k_segments_rk4<2, 4>": {"bytes": 246438142, "sources": ("rc_segments.hip", "rc_internal.h"),
+                             "sha256": "136efcdb71b3281b8587b1310d6a3950e626fd87b290132dfe42f84ccb23cf01"},
+}
+COPY_CALIB_BYTES = 256 << 20
 
 
 def log(msg):
@@ -43,6 +66,21 @@ def time_region(torch, fn, steps):
     end.record()
     torch.cuda.synchronize()
     return start.elapsed_time(end) / steps  # ms
+
+
+def measured_traffic(kernel):
+    """Calibrated HBM bytes per launch, or None when the kernel's sources
+    changed since the counters were taken."""
+    import hashlib
+
+    m = MEASURED_TRAFFIC.get(kernel)
+    if not m or m["bytes"] is None:
+        return None
+    h = hashlib.sha256()
+    for f in m["sources"]:
+        with open(os.path.join(ROOT, "paper_1809_01334_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return m["bytes"] if h.hexdigest() == m["sha256"] else None
 
 
 def cpu_baseline(scene):
@@ -68,6 +106,8 @@ def main():
     ap.add_argument("--res", type=int, default=1024)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-shell", action="store_true")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="end with plain 256 MiB device copies, the reference for HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the forest share of one "
@@ -132,16 +172,24 @@ def main():
         "forward_eager_ms": ms_eager,
         "phase_ms": {"prune": t_prune, "segments": t_seg, "composite": t_comp},
     }
-    # dominant kernel: segment generation (one launch of k_segments per call)
-    flops = S * SEG_FLOPS_RK4
+    # dominant kernel: segment generation, one launch of k_segments_rk4<2, 4> per call
+    flops = SEG_FLOPS_FP32 * S + CAND_FLOPS_FP64 * C
     achieved = flops / (t_seg * 1e-3) / 1e12
     out["roofline"] = {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                       "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None, "kernel": "k_segments<2>"}
-    # compositing: algorithmic bytes = read every leaf record once + write A, B, I
-    comp_bytes = C * 8 + r.cams.npix * 12
-    out["composite_hbm"] = {"achieved_GBs": comp_bytes / (t_comp * 1e-3) / 1e9, "peak_GBs": HBM_PEAK_GBS,
-                            "frac": comp_bytes / (t_comp * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                            "algorithmic_bytes": comp_bytes}
+                       "frac": achieved / FP32_PEAK_TFLOPS, "traffic": measured_traffic("k_segments_rk4<2, 4>"),
+                       "kernel": "k_segments_rk4<2, 4>", "flop_per_launch": flops,
+                       "per_unit": f"{SEG_FLOPS_FP32} FP32/segment + {CAND_FLOPS_FP64} FP64/candidate"}
+    # the other steps against their own bounds
+    comp_bytes = C * REC_BYTES + r.cams.npix * PIX_BYTES
+    prune_bytes = scene.forest.nleaves * 13 + counts["nvis"] * 20
+    out["steps"] = {
+        "composite": {"bound": "hbm", "algorithmic_bytes": comp_bytes,
+                      "achieved_GBs": comp_bytes / (t_comp * 1e-3) / 1e9,
+                      "frac": comp_bytes / (t_comp * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "prune": {"bound": "hbm", "algorithmic_bytes": prune_bytes,
+                  "achieved_GBs": prune_bytes / (t_prune * 1e-3) / 1e9,
+                  "frac": prune_bytes / (t_prune * 1e-3) / 1e9 / HBM_PEAK_GBS},
+    }
 
     if not args.no_bwd:
         g = torch.ones(r.cams.npix, device="cuda:0")
@@ -170,6 +218,15 @@ def main():
     if not args.no_shell:
         out["shell_workload"] = bench_shell(torch, P, synth, max(args.steps // 10, 3))
 
+    if args.copy_calib:
+        # a plain copy of known size: 256 MiB read + 256 MiB written per launch
+        src = torch.ones(COPY_CALIB_BYTES // 4, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copy calibration: 3 copies of {COPY_CALIB_BYTES} bytes")
+        del src, dst
     if not args.no_cpu:
         log("[bench] timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(scene)
@@ -267,6 +324,15 @@ def bench_shell(torch, P, synth, steps):
            "node_records": c["nrec"], "ms_per_step": ms, "forward_eager_ms": ms_eager,
            "ray_segments_per_s": S / (ms * 1e-3), "images_per_s": 1e3 / ms,
            "phase_ms": {"prune": t_prune, "segments": t_seg, "composite": t_comp}}
+    flops = (SEG_FLOPS_FP32 + SHELL_SEG_FLOPS_FP64) * S + CAND_FLOPS_FP64 * c["ncand"]
+    ach = flops / (t_seg * 1e-3) / 1e12
+    out["roofline"] = {"bound": "alu", "kernel": "k_segments_shell<4>", "achieved": ach, "peak": FP32_PEAK_TFLOPS,
+                       "unit": "TFLOP/s", "frac": ach / FP32_PEAK_TFLOPS, "flop_per_launch": flops,
+                       "per_unit": f"{SEG_FLOPS_FP32} FP32 + {SHELL_SEG_FLOPS_FP64} FP64 per segment, "
+                                   f"{CAND_FLOPS_FP64} FP64 per candidate"}
+    cb = c["ncand"] * SHELL_REC_BYTES + r.cams.npix * PIX_BYTES
+    out["composite"] = {"bound": "hbm", "algorithmic_bytes": cb, "achieved_GBs": cb / (t_comp * 1e-3) / 1e9,
+                        "frac": cb / (t_comp * 1e-3) / 1e9 / HBM_PEAK_GBS}
     del r
     torch.cuda.empty_cache()
     return out
