@@ -109,9 +109,8 @@ __global__ __launch_bounds__(256) void k_adj_level(FoldCtx C, int l, float2* adj
         int64_t m = C.L.level_begin[l] + (loc - cam * M);
         Rect r = load_rect(C.node_rect + 4 * slot);
         int k = (int)(gg - C.node_offset[slot]);
-        int wr = r.width();
-        int j = r.j0 + k / wr;
-        int i = r.i0 + (k - (k / wr) * wr);
+        int i, j;
+        rect_pixel(r, k, i, j);
         float2 a = adj_node[gg];
         push_children_auto(C, cam * C.ninternal + m, act, i, j, a.x, a.y, adj_leaf, adj_node);
     }

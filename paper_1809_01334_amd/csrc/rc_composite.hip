@@ -30,9 +30,8 @@ __global__ __launch_bounds__(256) void k_fold_level(FoldCtx C, int l, float2* ou
         int64_t m = C.L.level_begin[l] + (loc - cam * M);
         Rect r = load_rect(C.node_rect + 4 * slot);
         int k = (int)(gg - C.node_offset[slot]);
-        int wr = r.width();
-        int j = r.j0 + k / wr;
-        int i = r.i0 + (k - (k / wr) * wr);
+        int i, j;
+        rect_pixel(r, k, i, j);
         float2 v = fold_desc_auto(C, cam * C.ninternal + m, act, i, j);
         if (act) out[g] = v;
     }

@@ -36,6 +36,30 @@ struct Rect {
     __device__ __host__ bool contains(int i, int j) const { return i >= i0 && i <= i1 && j >= j0 && j <= j1; }
 };
 
+// Pixel (i, j) of the k-th pixel (row-major) of rectangle r.  Below 2^22 the
+// row comes from an FP32 reciprocal estimate (relative error under 2e-7, so
+// off by at most one) and one exact correction step.
+__device__ inline void rect_pixel(const Rect& r, int k, int& i, int& j) {
+    int wr = r.width();
+    if (k < (1 << 22)) {
+        int q = (int)((float)k * __builtin_amdgcn_rcpf((float)wr));
+        int rem = k - q * wr;
+        if (rem < 0) {
+            q--;
+            rem += wr;
+        } else if (rem >= wr) {
+            q++;
+            rem -= wr;
+        }
+        j = r.j0 + q;
+        i = r.i0 + rem;
+    } else {
+        int q = (int)((uint32_t)k / (uint32_t)wr);
+        j = r.j0 + q;
+        i = r.i0 + (k - q * wr);
+    }
+}
+
 __device__ inline Rect load_rect(const int16_t* r4) {
     // one 64-bit load of four int16
     uint64_t bits = *reinterpret_cast<const uint64_t*>(r4);
@@ -161,10 +185,8 @@ __device__ inline bool slab_hit(const Cam& c, const double rho[3], const double 
             double inv = 1.0 / r[k];
             double t0 = (lo[k] - rho[k]) * inv;
             double t1 = (hi[k] - rho[k]) * inv;
-            double tmin = t0 < t1 ? t0 : t1;
-            double tmax = t0 < t1 ? t1 : t0;
-            if (tmin > a) a = tmin;
-            if (tmax < b) b = tmax;
+            a = fmax(a, fmin(t0, t1));
+            b = fmin(b, fmax(t0, t1));
         } else if (!(rho[k] >= lo[k] && rho[k] < hi[k])) {
             ok = false;
         }
@@ -256,8 +278,9 @@ __device__ inline SegGeom seg_geom(const double rho[3], const double r[3], doubl
         g.xf[k] = (float)((pf - lo[k]) * scale);
         g.dxi[k] = (float)((s_in - s_out) * r[k] * scale);
     }
-    double rn = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
-    g.dx = (float)((s_out - s_in) * rn);
+    // the ray's length scale is needed to FP32 accuracy only
+    float rn = sqrtf((float)(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]));
+    g.dx = (float)(s_out - s_in) * rn;
     return g;
 }
 
@@ -422,9 +445,8 @@ __device__ inline Pairing pair_candidate(const Args& a, int64_t g, int64_t w, in
     const Cam& c = a.cams[a.vis_cam[v]];
     Rect r = load_rect(a.vis_rect + 4 * v);
     int k = (int)(g - a.cand_offset[v]);
-    int wr = r.width();
-    int j = r.j0 + k / wr;
-    int i = r.i0 + (k - (k / wr) * wr);
+    int i, j;
+    rect_pixel(r, k, i, j);
     p.lv = a.level[p.leaf];
     double hi[3];
     node_box(p.lv, a.x[p.leaf], a.y[p.leaf], a.z[p.leaf], p.lo, hi);

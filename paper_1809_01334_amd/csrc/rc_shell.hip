@@ -155,9 +155,8 @@ __global__ __launch_bounds__(256) void k_segments_shell(ShellSegArgs a) {
             const Cam& c = a.cams[cam];
             Rect rc = load_rect(a.vis_rect + 4 * v);
             int kk = (int)(g - a.cand_offset[v]);
-            int wr = rc.width();
-            int j = rc.j0 + kk / wr;
-            int i = rc.i0 + (kk - (kk / wr) * wr);
+            int i, j;
+            rect_pixel(rc, kk, i, j);
             pix = i | (j << 16);
             int tr = 0;
             while (tr + 1 < a.ntrees && leaf >= a.tb[tr + 1]) tr++;
@@ -320,9 +319,8 @@ __global__ __launch_bounds__(256) void k_fold_level_shell(ShellFold S, int l, fl
         int64_t m = C.L.level_begin[l] + (loc - cam * M);
         Rect r = load_rect(C.node_rect + 4 * slot);
         int k = (int)(gg - C.node_offset[slot]);
-        int wr = r.width();
-        int j = r.j0 + k / wr;
-        int i = r.i0 + (k - (k / wr) * wr);
+        int i, j;
+        rect_pixel(r, k, i, j);
         float4 o0, o1;
         shell_node_auto(S, cam * C.ninternal + m, act, i, j, o0, o1);
         if (act) {
