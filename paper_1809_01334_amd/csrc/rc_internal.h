@@ -249,6 +249,18 @@ __device__ inline ChildDesc load_desc_scalar(const ChildDesc* base, int64_t idx)
     return d;
 }
 
+// Camera through the scalar cache: `idx` must be wave-uniform.
+typedef const __attribute__((address_space(4))) uint64_t* const_u64_ptr;
+__device__ inline Cam load_cam_scalar(const Cam* cams, int idx) {
+    static_assert(sizeof(Cam) % 8 == 0, "Cam is copied as 64-bit words");
+    Cam c;
+    const_u64_ptr src = (const_u64_ptr)(cams + idx);
+    uint64_t* dst = reinterpret_cast<uint64_t*>(&c);
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(Cam) / 8); k++) dst[k] = src[k];
+    return c;
+}
+
 // ---------------------------------------------------------------------------
 // segment group (eq. aggregate): near (+) far
 // ---------------------------------------------------------------------------
@@ -417,6 +429,24 @@ __device__ inline int64_t upper_index(const int64_t* off, int64_t lo, int64_t hi
     return lo;
 }
 
+// upper_index with seven independent probes per step: about log8 of the range
+// in dependent load rounds instead of log2.
+__device__ inline int64_t upper_index_wide(const int64_t* off, int64_t lo, int64_t hi, int64_t g) {
+    while (hi - lo > 8) {
+        int64_t step = (hi - lo) >> 3;
+        int64_t v[7];
+#pragma unroll
+        for (int k = 0; k < 7; k++) v[k] = off[lo + (k + 1) * step];
+        int c = 0;
+#pragma unroll
+        for (int k = 0; k < 7; k++) c += v[k] <= g ? 1 : 0;
+        int64_t nlo = lo + c * step;
+        if (c < 7) hi = nlo + step;
+        lo = nlo;
+    }
+    return upper_index(off, lo, hi, g);
+}
+
 // Visible pair holding candidate g of wave chunk w: between the pairs of the
 // chunk's first candidate and the next chunk's (at most 64 pairs apart).
 __device__ inline int64_t cand_pair(const int64_t* cand_offset, const int32_t* cand_chunk, int64_t g, int64_t w,
@@ -436,13 +466,9 @@ struct Pairing {
 };
 
 template <typename Args>
-__device__ inline Pairing pair_candidate(const Args& a, int64_t g, int64_t w, int64_t nvis, int64_t ncand,
-                                         int64_t* vout = nullptr) {
+__device__ inline Pairing pair_with(const Args& a, int64_t g, int64_t v, const Cam& c) {
     Pairing p;
-    int64_t v = cand_pair(a.cand_offset, a.cand_chunk, g, w, nvis, ncand);
-    if (vout) *vout = v;
     p.leaf = a.vis_leaf[v];
-    const Cam& c = a.cams[a.vis_cam[v]];
     Rect r = load_rect(a.vis_rect + 4 * v);
     int k = (int)(g - a.cand_offset[v]);
     int i, j;
@@ -453,6 +479,22 @@ __device__ inline Pairing pair_candidate(const Args& a, int64_t g, int64_t w, in
     pixel_ray(c, i, j, p.rho, p.rr);
     p.hit = slab_hit(c, p.rho, p.rr, p.lo, hi, p.s_in, p.s_out);
     return p;
+}
+
+// The camera comes through the scalar cache when the wave's candidates share
+// it (all but the waves that straddle two images).
+template <typename Args>
+__device__ inline Pairing pair_candidate(const Args& a, int64_t g, int64_t w, int64_t nvis, int64_t ncand,
+                                         int64_t* vout = nullptr) {
+    int64_t v = cand_pair(a.cand_offset, a.cand_chunk, g, w, nvis, ncand);
+    if (vout) *vout = v;
+    int cam = a.vis_cam[v];
+    int c0 = __builtin_amdgcn_readfirstlane(cam);
+    if (__all(cam == c0)) {
+        Cam cs = load_cam_scalar(a.cams, c0);
+        return pair_with(a, g, v, cs);
+    }
+    return pair_with(a, g, v, a.cams[cam]);
 }
 
 // Camera of a pixel in the concatenated images.

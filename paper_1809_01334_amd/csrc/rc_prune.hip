@@ -47,7 +47,13 @@ struct PruneSrc {
                 it.r = shell_rect(cams[cam], e);
             } else {
                 node_box(level[l], x[l], y[l], z[l], lo, hi);
-                it.r = box_rect(cams[cam], lo, hi);
+                int c0 = __builtin_amdgcn_readfirstlane((int)cam);
+                if (__all(cam == c0)) {
+                    Cam cs = load_cam_scalar(cams, c0);
+                    it.r = box_rect(cs, lo, hi);
+                } else {
+                    it.r = box_rect(cams[cam], lo, hi);
+                }
             }
             it.val = it.r.empty() ? I64x3{0, 0, 0} : I64x3{1, it.r.area(), 0};
         } else {
@@ -180,7 +186,7 @@ struct NodeAreaDst {
 
 // table[w] = the item k whose range [off[k], off[k+1]) holds index 64 w.
 __device__ inline void chunk_entry(const int64_t* off, int64_t n, int64_t w, int32_t* table) {
-    table[w] = (int32_t)upper_index(off, 0, n, w * WAVE);
+    table[w] = (int32_t)upper_index_wide(off, 0, n, w * WAVE);
 }
 
 // Children of every (camera, internal node) in view order with their
