@@ -471,31 +471,13 @@ __global__ __launch_bounds__(256) void k_adj_leaf(LeafAdjArgs a) {
     if (tail - head > 0) adj_drain<KIND, NSUB>(a, q, head, tail, tail - head, lane, carry, carry_key);
 }
 
-// Per (visible pair, parameter): add the pair's chunk partials in chunk order.
-__global__ __launch_bounds__(256) void k_grad_pairs(const int64_t* counts, int64_t cap_cand, const int64_t* cand_offset,
-                                                    const float* partial, float* gvis, int npar) {
-    if (counts[3]) return;
-    int64_t nvis = counts[0];
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nvis * GRAD_MAX; t += stride) {
-        int64_t v = t >> 4;  // GRAD_MAX = 16
-        int c = (int)(t - v * GRAD_MAX);
-        if (c >= npar) continue;
-        int64_t c0 = cand_offset[v], c1 = cand_offset[v + 1];
-        if (c1 > cap_cand) c1 = cap_cand;
-        float acc = 0.0f;
-        if (c1 > c0) {
-            int64_t w0 = c0 / WAVE, w1 = (c1 - 1) / WAVE;
-            for (int64_t w = w0; w <= w1; w++) acc += partial[(w + v) * GRAD_MAX + c];
-        }
-        gvis[v * GRAD_MAX + c] = acc;
-    }
-}
-
-// Per (leaf, parameter): sum over cameras in camera order into the
-// leaf-major coefficient layout.
+// Per (leaf, parameter): over the cameras in order, add the chunk partials of
+// the leaf's visible pair in chunk order, into the leaf-major coefficient
+// layout.  A fixed order, so the sums are deterministic.
 __global__ __launch_bounds__(256) void k_grad_leaves(const int64_t* counts, int64_t N, int ncams, const int32_t* leaf_vis,
-                                                     const float* gvis, int nc, float* dk, float* de, int accumulate) {
+                                                     const int64_t* cand_offset, int64_t cap_cand,
+                                                     const float* partial, int nc, float* dk, float* de,
+                                                     int accumulate) {
     if (counts[3]) return;
     int64_t npar = 2 * nc;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -505,7 +487,12 @@ __global__ __launch_bounds__(256) void k_grad_leaves(const int64_t* counts, int6
         float acc = 0.0f;
         for (int cam = 0; cam < ncams; cam++) {
             int32_t v = leaf_vis[(int64_t)cam * N + l];
-            if (v >= 0) acc += gvis[(int64_t)v * GRAD_MAX + c];
+            if (v < 0) continue;
+            int64_t c0 = cand_offset[v], c1 = cand_offset[v + 1];
+            if (c1 > cap_cand) c1 = cap_cand;
+            if (c1 <= c0) continue;
+            int64_t w0 = c0 / WAVE, w1 = (c1 - 1) / WAVE;
+            for (int64_t w = w0; w <= w1; w++) acc += partial[(w + v) * GRAD_MAX + c];
         }
         float* dst = c < nc ? dk + l * nc + c : de + l * nc + (c - nc);
         *dst = accumulate ? *dst + acc : acc;
@@ -551,7 +538,6 @@ extern "C" rc_status rc_segments_backward(const rc_forest* f, const rc_index* ix
 
     int64_t nchunks = (vf->cap_cand + WAVE - 1) / WAVE;
     float* partial = (float*)ws;
-    float* gvis = (float*)((char*)ws + align_up((size_t)(nchunks + vf->cap_vis + 1) * GRAD_MAX * sizeof(float)));
     LeafAdjArgs la{(const Cam*)dcams, f->level,       f->x,          f->y,         f->z,
                    f->nleaves,        fl->kappa,      fl->eps,       in->substeps, vf->vis_leaf,
                    vf->vis_cam,       vf->vis_rect,   vf->cand_offset, vf->counts, vf->cand_chunk,
@@ -582,13 +568,9 @@ extern "C" rc_status rc_segments_backward(const rc_forest* f, const rc_index* ix
         }
     }
     RC_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_grad_pairs, dim3(stride_grid(vf->cap_vis * GRAD_MAX, 256, 256 * 32)), dim3(256), 0, st,
-                       vf->counts,
-                       vf->cap_cand, vf->cand_offset, partial, gvis, 2 * nc);
-    RC_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_grad_leaves, dim3(stride_grid(f->nleaves * 2 * nc, 256, 256 * 32)), dim3(256), 0, st,
-                       vf->counts,
-                       f->nleaves, ncams, vf->leaf_vis, gvis, nc, dk, de, accumulate);
+                       vf->counts, f->nleaves, ncams, vf->leaf_vis, vf->cand_offset, vf->cap_cand, partial, nc, dk,
+                       de, accumulate);
     RC_HIP(hipGetLastError());
     return RC_OK;
 }

@@ -14,14 +14,12 @@ constexpr int GRAD_MAX = 16;  // 8 kappa + 8 eps corners per leaf
 inline size_t align_up(size_t b, size_t a = 256) { return (b + a - 1) / a * a; }
 
 // Workspace of rc_segments_backward: per-(wave chunk, visible pair) gradient
-// partials and per-visible-pair gradients.
+// partials.
 inline size_t backward_ws_bytes(int64_t cap_cand, int64_t cap_vis, int64_t ncams, int64_t N) {
     (void)ncams;
     (void)N;
     int64_t nchunks = (cap_cand + WAVE - 1) / WAVE;
-    size_t partial = align_up((size_t)(nchunks + cap_vis + 1) * GRAD_MAX * sizeof(float));
-    size_t gvis = align_up((size_t)(cap_vis + 1) * GRAD_MAX * sizeof(float));
-    return partial + gvis;
+    return align_up((size_t)(nchunks + cap_vis + 1) * GRAD_MAX * sizeof(float));
 }
 
 #define RC_HIP(call)                                 \

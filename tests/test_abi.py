@@ -143,3 +143,27 @@ def test_ctypes_structs_match_the_header_layout(tmp_path):
         py = structs[cname]
         want = ctypes.sizeof(py) if fname == "sizeof" else getattr(py, fname).offset
         assert int(val) == want, (cname, fname, int(val), want)
+
+
+def test_shell_forest_validation():
+    """The six-tree shell needs six trees, their leaf offsets and the geometry table."""
+    L = _lib()
+    lib = L.lib()
+    ix = L.RcIndex()
+    p = ctypes.c_void_p(16)
+    tb6 = np.array([0, 2, 4, 6, 8, 10, 12], np.int64)
+    ptb6 = tb6.ctypes.data_as(ctypes.c_void_p)
+
+    def status(ntrees, tb, table, n=12):
+        f = L.RcForest(ntrees, L.RC_GEOM_SHELL6, n, tb, p, p, p, p, table)
+        return lib.rc_forest_index(ctypes.byref(f), ctypes.byref(ix), None, 0, None)
+
+    assert status(1, ptb6, p) == L.RC_EINVAL          # one tree
+    assert status(6, None, p) == L.RC_EINVAL          # no tree offsets
+    assert status(6, ptb6, None) == L.RC_EINVAL       # no geometry table
+    bad = np.array([0, 2, 4, 3, 8, 10, 12], np.int64)  # offsets not monotone
+    assert status(6, bad.ctypes.data_as(ctypes.c_void_p), p) == L.RC_EINVAL
+    assert status(6, ptb6, p, n=11) == L.RC_EINVAL    # last offset != leaves
+    assert status(6, ptb6, p) == L.RC_EWORKSPACE      # valid forest, no workspace
+    f = L.RcForest(6, 7, 12, ptb6, p, p, p, p, p)     # unknown geometry
+    assert lib.rc_forest_index(ctypes.byref(f), ctypes.byref(ix), None, 0, None) == L.RC_EUNSUPPORTED
