@@ -1,0 +1,78 @@
+"""GPU parity at the full sizes of the batched and the adjoint workloads.
+
+* 64 cameras of resolutions from {256, 512, 1024, 2048}^2 on the 839959-leaf adaptive
+  forest, rendered in one launch sequence: sampled pixels of four views against the oracle
+  (1e-5), and two views bit for bit against rendering them alone.
+* The 512^2 adjoint workload (785604 leaves, background 0.5): the loss
+  L = sum (I - I_target)^2 over 2000 sampled pixels, dL/dI taken from the oracle's images
+  and handed to both adjoints; the gradients with respect to all per-corner coefficients
+  within 1e-4.
+"""
+
+import numpy as np
+import pytest
+
+import synth
+from test_gpu_parity import GRAD_TOL, PIX_TOL, _torch, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.timeout(600)
+def test_batched_64_views_full_size(oracle_mod):
+    torch = _torch()
+    import paper_1809_01334_amd as P
+
+    scene = synth.config_scene(2)
+    cams = synth.config4_cameras()
+    print(f"[case] 64 views, {sum(c.npix for c in cams)} pixels, N={scene.forest.nleaves}", flush=True)
+    rb = P.Renderer(scene.forest, scene.fields, cams, "rk4", 4)
+    A, B, I = (t.clone() for t in rb.forward())
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(44)
+    sizes = [c.w for c in cams]
+    views = sorted({sizes.index(s) for s in set(sizes)})[:4]
+    for k in views:
+        cam = cams[k]
+        pix = np.sort(rng.choice(cam.npix, 1000, replace=False))
+        ref = oracle_mod.render(scene.forest, scene.fields, cam, "rk4", 4, pixels=pix)
+        lo = rb.cams.img_off[k]
+        for nm, x, y in (("A", A, ref["A"]), ("B", B, ref["B"]), ("I", I, ref["I"])):
+            got = x[lo:lo + cam.npix].cpu().numpy()[pix]
+            e = rel_err(got, y)
+            assert e <= PIX_TOL, (k, cam.w, nm, e)
+    for k in views[:2]:
+        rs = P.Renderer(rb.forest, rb.fields, [cams[k]], "rk4", 4, index=rb.index)
+        _, _, Is = rs.forward()
+        sl = slice(rb.cams.img_off[k], rb.cams.img_off[k + 1])
+        assert torch.equal(Is, I[sl]), k
+
+
+@pytest.mark.timeout(600)
+def test_adjoint_workload_full_size_sampled_loss(oracle_mod):
+    torch = _torch()
+    import paper_1809_01334_amd as P
+
+    scene = synth.config_scene(5)
+    cam = scene.cameras[0]
+    tf = scene.extra["target_fields"]
+    print(f"[case] adjoint workload N={scene.forest.nleaves} {cam.w}x{cam.h}", flush=True)
+    r = P.Renderer(scene.forest, scene.fields, scene.cameras, scene.method, scene.substeps)
+    r.forward()
+    pix = np.sort(np.random.default_rng(55).choice(cam.npix, 2000, replace=False))
+    # dL/dI from the oracle's own images: I and I_target differ by a small
+    # perturbation, so the difference is taken in FP64 once and handed to both
+    # adjoints (the GPU's input may come from the oracle, never the reverse)
+    ref = oracle_mod.render(scene.forest, scene.fields, cam, scene.method, scene.substeps, pixels=pix)
+    reft = oracle_mod.render(scene.forest, tf, cam, scene.method, scene.substeps, pixels=pix)
+    go = 2.0 * (ref["I"] - reft["I"])
+    g = torch.zeros(r.cams.npix, dtype=torch.float32, device=r.device)
+    g[torch.from_numpy(pix).to(r.device)] = torch.from_numpy(go.astype(np.float32)).to(r.device)
+    dk, de = r.backward(g.contiguous())
+    torch.cuda.synchronize()
+    gk, ge = oracle_mod.grad(scene.forest, scene.fields, cam, go.astype(np.float32).astype(np.float64),
+                             scene.method, scene.substeps, pixels=pix)
+    assert np.abs(gk).max() > 0 and np.abs(ge).max() > 0
+    ek = rel_err(dk.cpu().numpy().T, gk)
+    ee = rel_err(de.cpu().numpy().T, ge)
+    assert ek <= GRAD_TOL and ee <= GRAD_TOL, (ek, ee)
