@@ -46,12 +46,12 @@ def lib():
         L.or_pairs.restype = I64
         L.or_pairs.argtypes = [I64, P, P, P, P, P, P, P, P, I64]
         L.or_render.restype = I32
-        L.or_render.argtypes = [I64, P, P, P, P, I32, P, P, I32, I32, P, I64, P, P, P, P, P, P]
+        L.or_render.argtypes = [I64, P, P, P, P, I32, P, P, I32, I32, D, P, I64, P, P, P, P, P, P]
         L.or_grad.restype = I32
-        L.or_grad.argtypes = [I64, P, P, P, P, I32, P, P, I32, I32, P, I64, P, P, P, P]
+        L.or_grad.argtypes = [I64, P, P, P, P, I32, P, P, I32, I32, D, P, I64, P, P, P, P]
         L.or_segment.restype = I32
         L.or_segment.argtypes = [I32, P, P, ctypes.c_uint8, ctypes.c_uint32, ctypes.c_uint32,
-                                 ctypes.c_uint32, P, P, D, D, I32, I32, P, P]
+                                 ctypes.c_uint32, P, P, D, D, I32, I32, D, P, P]
         L.or_march.restype = I32
         L.or_march.argtypes = [I64, P, P, P, P, I32, P, P, P, I32, P, P, P]
         L.or_shell_prune.restype = I64
@@ -59,7 +59,7 @@ def lib():
         L.or_shell_pairs.restype = I64
         L.or_shell_pairs.argtypes = [I64, P, I32, P, P, P, P, P, P, P, P, P, I64]
         L.or_shell_render.restype = I32
-        L.or_shell_render.argtypes = [I64, I32, P, P, P, P, P, P, I32, P, P, I32, I32, P, I64, P, P, P, P, P, P]
+        L.or_shell_render.argtypes = [I64, I32, P, P, P, P, P, P, I32, P, P, I32, I32, D, P, I64, P, P, P, P, P, P]
         L.or_shell_march.restype = I32
         L.or_shell_march.argtypes = [I64, I32, P, P, P, P, P, P, I32, P, P, P, I32, P, P, P]
         L.or_shell_map.argtypes = [P, I32, P, P]
@@ -91,9 +91,11 @@ def _forest_args(forest):
 
 
 def _field_args(fields, kappa=None, eps=None):
+    """Field kind 1: trilinear corners; 0: constant (kappa, eps); 2: constant
+    (kappa, equilibrium intensity I) with eps = kappa I (eq. BIrelation)."""
     k = _c(fields.kappa if kappa is None else kappa, np.float64)
     e = _c(fields.eps if eps is None else eps, np.float64)
-    kind = 1 if k.shape[0] == 8 else 0
+    kind = 1 if k.shape[0] == 8 else (2 if getattr(fields, "kind", "") == "const_eq" else 0)
     return kind, k, e
 
 
@@ -136,14 +138,14 @@ def rk4_step(beta4, gamma4, h):
     return o
 
 
-def segment(kind, kap, eps, level, x, y, z, rho, r, s_in, s_out, method, substeps=4):
+def segment(kind, kap, eps, level, x, y, z, rho, r, s_in, s_out, method, substeps=4, c_rk=0.0):
     """(A, B) and d(A, B)/d(kappa corners, eps corners) of one segment."""
-    nc = 8 if kind else 1
+    nc = 8 if kind == 1 else 1
     k, e = _c(kap, np.float64), _c(eps, np.float64)
     rh, rr = _c(rho, np.float64), _c(r, np.float64)
     ab, dab = np.zeros(2), np.zeros((2, 2 * nc))
     lib().or_segment(int(kind), _p(k), _p(e), int(level), int(x), int(y), int(z), _p(rh), _p(rr),
-                     float(s_in), float(s_out), int(method), int(substeps), _p(ab), _p(dab))
+                     float(s_in), float(s_out), int(method), int(substeps), float(c_rk), _p(ab), _p(dab))
     return ab, dab
 
 
@@ -213,11 +215,11 @@ def pairs(forest, cam_raw, leaves=None):
 
 # ---------------------------------------------------------------- render / grad
 
-METHODS = {"analytic": 0, "rk4": 1}
+METHODS = {"analytic": 0, "rk4": 1, "gauss2": 2, "simpson": 3}
 
 
 def render(forest, fields, cam, method="rk4", substeps=4, pixels=None, kappa=None, eps=None,
-           background=None):
+           background=None, c_rk=0.0):
     """FP64 oracle image of one camera.  Returns dict with A, B, I, nseg (flat, row j=0 first)."""
     raw = cam.raw() if hasattr(cam, "raw") else np.asarray(cam, np.float64).copy()
     if background is not None:
@@ -238,15 +240,16 @@ def render(forest, fields, cam, method="rk4", substeps=4, pixels=None, kappa=Non
     if _shell(forest):
         nt, tb, gp = _shell_args(forest)
         lib().or_shell_render(forest.nleaves, nt, _p(tb), _p(gp), _p(lv), _p(x), _p(y), _p(z), kind, _p(k), _p(e),
-                              METHODS[method], int(substeps), _p(raw), nsel, _p(pix), _p(A), _p(B), _p(I), _p(nseg),
+                              METHODS[method], int(substeps), float(c_rk), _p(raw), nsel, _p(pix), _p(A), _p(B), _p(I),
+                              _p(nseg),
                               _p(stats))
         return {"A": A, "B": B, "I": I, "nseg": nseg, "segments": int(stats[0]), "overlaps": int(stats[1])}
     lib().or_render(forest.nleaves, _p(lv), _p(x), _p(y), _p(z), kind, _p(k), _p(e), METHODS[method],
-                    int(substeps), _p(raw), nsel, _p(pix), _p(A), _p(B), _p(I), _p(nseg), _p(stats))
+                    int(substeps), float(c_rk), _p(raw), nsel, _p(pix), _p(A), _p(B), _p(I), _p(nseg), _p(stats))
     return {"A": A, "B": B, "I": I, "nseg": nseg, "segments": int(stats[0]), "overlaps": int(stats[1])}
 
 
-def grad(forest, fields, cam, g, method="rk4", substeps=4, pixels=None, kappa=None, eps=None):
+def grad(forest, fields, cam, g, method="rk4", substeps=4, pixels=None, kappa=None, eps=None, c_rk=0.0):
     """dL/dkappa, dL/deps ([nc][N]) for per-pixel dL/dI = g."""
     raw = cam.raw() if hasattr(cam, "raw") else np.asarray(cam, np.float64)
     lv, x, y, z = _forest_args(forest)
@@ -259,7 +262,7 @@ def grad(forest, fields, cam, g, method="rk4", substeps=4, pixels=None, kappa=No
         nsel = pix.shape[0]
     gk, ge = np.zeros_like(k), np.zeros_like(e)
     lib().or_grad(forest.nleaves, _p(lv), _p(x), _p(y), _p(z), kind, _p(k), _p(e), METHODS[method],
-                  int(substeps), _p(_c(raw, np.float64)), nsel, _p(pix), _p(gg), _p(gk), _p(ge))
+                  int(substeps), float(c_rk), _p(_c(raw, np.float64)), nsel, _p(pix), _p(gg), _p(gk), _p(ge))
     return gk, ge
 
 

@@ -142,6 +142,20 @@ static dn dn_exp(dn a, int np)
     for (int k = 0; k < np; k++) r.d[k] = r.v * a.d[k];
     return r;
 }
+static dn dn_div(dn a, dn b, int np)
+{
+    dn r;
+    r.v = a.v / b.v;
+    for (int k = 0; k < np; k++) r.d[k] = (a.d[k] - r.v * b.d[k]) / b.v;
+    return r;
+}
+static dn dn_sqrt(dn a, int np)
+{
+    dn r;
+    r.v = sqrt(a.v);
+    for (int k = 0; k < np; k++) r.d[k] = a.d[k] / (2.0 * r.v);
+    return r;
+}
 /* phi(x) = (1 - e^{-x}) / x with phi(0) = 1, and its derivative. */
 static dn dn_phi(dn x, int np)
 {
@@ -268,60 +282,188 @@ static void cube_ref(const void *ctx, const double *x, double *xi)
  * the far end s_out toward the camera.  Returns (A,B) as dual numbers over the
  * leaf's parameters: kappa corners 0..nc-1 then eps corners nc..2nc-1. */
 static void segment_dn_ref(const leaffield *F, ref_fn ref, const void *ctx, const double *rho, const double *r,
-                           double rnorm, double s_in, double s_out, int method, int substeps, int np, dn *Aout,
-                           dn *Bout);
+                           double rnorm, double s_in, double s_out, int method, int substeps, double c_rk, int np,
+                           dn *Aout, dn *Bout);
 
 static void segment_dn(const leaffield *F, const leafbox *bx, const double *rho, const double *r,
-                       double rnorm, double s_in, double s_out, int method, int substeps, int np,
+                       double rnorm, double s_in, double s_out, int method, int substeps, double c_rk, int np,
                        dn *Aout, dn *Bout)
 {
-    segment_dn_ref(F, cube_ref, bx, rho, r, rnorm, s_in, s_out, method, substeps, np, Aout, Bout);
+    segment_dn_ref(F, cube_ref, bx, rho, r, rnorm, s_in, s_out, method, substeps, c_rk, np, Aout, Bout);
+}
+
+/* Coefficients at ray parameter s (Sec. 2.3): trilinear in the leaf's reference
+ * coordinates (kind 1) or constant per leaf; kind 2 holds the equilibrium
+ * intensity I = gamma / beta of eq. BIrelation in place of gamma, so that
+ * gamma = beta I.  Dual parts: kappa parameters first, then eps (or I). */
+static void field_dn(const leaffield *F, ref_fn ref, const void *ctx, const double *rho, const double *r, double s,
+                     int np, dn *beta, dn *gamma)
+{
+    int nc = F->kind == 1 ? 8 : 1;
+    if (F->kind == 1) {
+        double xi[3], pt[3];
+        for (int k = 0; k < 3; k++) pt[k] = rho[k] + s * r[k];
+        ref(ctx, pt, xi);
+        *beta = trilin_dn(F->kap, xi, np, 0);
+        *gamma = trilin_dn(F->eps, xi, np, nc);
+        return;
+    }
+    dn e = dn_c(F->eps[0], np);
+    *beta = dn_c(F->kap[0], np);
+    if (np > 0) {
+        beta->d[0] = 1.0;
+        e.d[nc] = 1.0;
+    }
+    *gamma = F->kind == 2 ? dn_mul(*beta, e, np) : e;
+}
+
+/* ------------------------------------------------------------------------ */
+/* integrators over dyadic pieces of a segment (Sec. 2.7)                   */
+/* ------------------------------------------------------------------------ */
+
+#define OR_ADAPT_MAXDEPTH 16
+
+typedef struct {
+    const leaffield *F;
+    ref_fn ref;
+    const void *ctx;
+    const double *rho, *r;
+    double rnorm, s_in, s_out, c_rk;
+    int method, np;
+} segjob;
+
+/* Stage positions c_i of each method, measured from the far end x1 of a piece
+ * (xi_i = x1 + c_i dx): RK4 (0, 1/2, 1/2, 1), Gauss (1/2 -+ sqrt(3)/6),
+ * Simpson (0, 1/2, 1). */
+static int stage_c(int method, double *c)
+{
+    if (method == 1) {
+        c[0] = 0.0; c[1] = 0.5; c[2] = 0.5; c[3] = 1.0;
+        return 4;
+    }
+    if (method == 2) {
+        c[0] = 0.5 - sqrt(3.0) / 6.0;
+        c[1] = 0.5 + sqrt(3.0) / 6.0;
+        return 2;
+    }
+    c[0] = 0.0; c[1] = 0.5; c[2] = 1.0;
+    return 3;
+}
+
+/* Piece k of depth d covers the fraction [k, k+1] / 2^d of the segment,
+ * counted from its near end; s(u) = s_in + u (s_out - s_in). */
+static double piece_s(const segjob *J, int64_t k, int d, double c)
+{
+    double u = ((double)(k + 1) - c) * ldexp(1.0, -d);
+    return J->s_in + u * (J->s_out - J->s_in);
+}
+
+static double piece_dx(const segjob *J, int64_t k, int d)
+{
+    return (piece_s(J, k, d, 0.0) - piece_s(J, k, d, 1.0)) * J->rnorm;
+}
+
+/* One step of the method over piece (k, d), from (A, B) = (1, 0). */
+static void piece_step(const segjob *J, int64_t k, int d, dn *A, dn *B)
+{
+    int np = J->np;
+    double c[4], dx = piece_dx(J, k, d);
+    int m = stage_c(J->method, c);
+    dn be[4], ga[4];
+    for (int i = 0; i < m; i++) field_dn(J->F, J->ref, J->ctx, J->rho, J->r, piece_s(J, k, d, c[i]), np, &be[i], &ga[i]);
+    if (J->method == 1) {
+        rk4_step_dn(be, ga, dx, np, A, B);
+    } else if (J->method == 2) {
+        /* implicit Gauss, 2 stages (eq. gaussAB, eq. gaussABab) */
+        dn a1 = dn_scale(dn_add(be[0], be[1], np), dx / 4.0, np);
+        dn a2 = dn_scale(dn_mul(be[0], be[1], np), dx * dx / 12.0, np);
+        dn b1 = dn_scale(dn_add(ga[0], ga[1], np), dx / 2.0, np);
+        dn b2 = dn_scale(dn_sub(dn_mul(be[0], ga[1], np), dn_mul(be[1], ga[0], np), np), dx * dx * sqrt(3.0) / 12.0,
+                         np);
+        dn den = dn_add(dn_add(dn_c(1.0, np), a1, np), a2, np);
+        *A = dn_div(dn_add(dn_sub(dn_c(1.0, np), a1, np), a2, np), den, np);
+        *B = dn_div(dn_add(b1, b2, np), den, np);
+    } else {
+        /* Simpson quadrature of the closed form (eq. simpson), weights 1/6, 4/6, 1/6 */
+        dn sb = dn_add(dn_add(be[0], dn_scale(be[1], 4.0, np), np), be[2], np);
+        *A = dn_exp(dn_scale(sb, -dx / 6.0, np), np);
+        dn t0 = dn_mul(*A, ga[0], np);
+        dn t1 = dn_scale(dn_mul(dn_sqrt(*A, np), ga[1], np), 4.0, np);
+        *B = dn_scale(dn_add(dn_add(t0, t1, np), ga[2], np), dx / 6.0, np);
+    }
+}
+
+/* Alg. adaptiverk: a piece whose stage coefficients give dx beta(xi_i) > c_RK
+ * is replaced by its two halves, the nearer one on the left of (+). */
+static void piece_eval(const segjob *J, int64_t k, int d, dn *A, dn *B)
+{
+    if (J->c_rk > 0.0 && d < OR_ADAPT_MAXDEPTH) {
+        double c[4], dx = piece_dx(J, k, d);
+        int m = stage_c(J->method, c), split = 0;
+        for (int i = 0; i < m && !split; i++) {
+            dn be, ga;
+            field_dn(J->F, J->ref, J->ctx, J->rho, J->r, piece_s(J, k, d, c[i]), 0, &be, &ga);
+            if (dx * be.v > J->c_rk) split = 1;
+        }
+        if (split) {
+            int np = J->np;
+            dn An, Bn, Af, Bf;
+            piece_eval(J, 2 * k, d + 1, &An, &Bn);
+            piece_eval(J, 2 * k + 1, d + 1, &Af, &Bf);
+            *A = dn_mul(An, Af, np);
+            *B = dn_add(Bn, dn_mul(An, Bf, np), np);
+            return;
+        }
+    }
+    piece_step(J, k, d, A, B);
 }
 
 static void segment_dn_ref(const leaffield *F, ref_fn ref, const void *ctx, const double *rho, const double *r,
-                           double rnorm, double s_in, double s_out, int method, int substeps, int np, dn *Aout,
-                           dn *Bout)
+                           double rnorm, double s_in, double s_out, int method, int substeps, double c_rk, int np,
+                           dn *Aout, dn *Bout)
 {
-    int nc = F->kind ? 8 : 1;
+    int nc = F->kind == 1 ? 8 : 1;
     if (method == 0) {
-        /* analytic: constant coefficients, eq. ABconstant */
-        dn beta = dn_c(F->kap[0], np), gamma = dn_c(F->eps[0], np);
-        if (np > 0) {
-            beta.d[0] = 1.0;
-            gamma.d[nc] = 1.0;
-        }
+        /* analytic: constant coefficients, eq. ABconstant (kind 2: gamma = beta I) */
+        dn beta, gamma;
+        field_dn(F, ref, ctx, rho, r, s_in, np, &beta, &gamma);
         seg_const_dn(beta, gamma, (s_out - s_in) * rnorm, np, Aout, Bout);
         return;
     }
-    /* RK4 over `substeps` equal substeps, farthest first, combined with (+). */
-    double ds = (s_out - s_in) / substeps;
-    double h = ds * rnorm;
-    dn A = dn_c(1.0, np), B = dn_c(0.0, np);
-    for (int q = 0; q < substeps; q++) {
-        double s_far = s_out - q * ds;
-        double sp[4] = {s_far, s_far - 0.5 * ds, s_far - 0.5 * ds, s_far - ds};
-        dn beta[4], gamma[4];
-        for (int i = 0; i < 4; i++) {
-            double xi[3], pt[3];
-            for (int k = 0; k < 3; k++) pt[k] = rho[k] + sp[i] * r[k];
-            ref(ctx, pt, xi);
-            if (F->kind) {
-                beta[i] = trilin_dn(F->kap, xi, np, 0);
-                gamma[i] = trilin_dn(F->eps, xi, np, nc);
-            } else {
-                beta[i] = dn_c(F->kap[0], np);
-                gamma[i] = dn_c(F->eps[0], np);
-                if (np > 0) {
-                    beta[i].d[0] = 1.0;
-                    gamma[i].d[nc] = 1.0;
-                }
-            }
+    if (method == 1 && c_rk <= 0.0) {
+        /* RK4 over `substeps` equal substeps, farthest first, combined with (+). */
+        double ds = (s_out - s_in) / substeps;
+        double h = ds * rnorm;
+        dn A = dn_c(1.0, np), B = dn_c(0.0, np);
+        for (int q = 0; q < substeps; q++) {
+            double s_far = s_out - q * ds;
+            double sp[4] = {s_far, s_far - 0.5 * ds, s_far - 0.5 * ds, s_far - ds};
+            dn beta[4], gamma[4];
+            for (int i = 0; i < 4; i++) field_dn(F, ref, ctx, rho, r, sp[i], np, &beta[i], &gamma[i]);
+            dn a, b;
+            rk4_step_dn(beta, gamma, h, np, &a, &b);
+            /* (A,B) <- (a,b) (+) (A,B): the new substep is nearer to the camera */
+            dn nA = dn_mul(a, A, np);
+            dn nB = dn_add(b, dn_mul(a, B, np), np);
+            A = nA;
+            B = nB;
         }
+        *Aout = A;
+        *Bout = B;
+        return;
+    }
+    /* RK4 with recursion, Gauss or Simpson: `substeps` = 2^d0 equal pieces, each
+     * evaluated by piece_eval, combined nearest first. */
+    (void)nc;
+    segjob J = {F, ref, ctx, rho, r, rnorm, s_in, s_out, c_rk, method, np};
+    int d0 = 0;
+    while ((1 << d0) < substeps) d0++;
+    dn A = dn_c(1.0, np), B = dn_c(0.0, np);
+    for (int64_t k = 0; k < ((int64_t)1 << d0); k++) {
         dn a, b;
-        rk4_step_dn(beta, gamma, h, np, &a, &b);
-        /* (A,B) <- (a,b) (+) (A,B): the new substep is nearer to the camera */
-        dn nA = dn_mul(a, A, np);
-        dn nB = dn_add(b, dn_mul(a, B, np), np);
+        piece_eval(&J, k, d0, &a, &b);
+        dn nA = dn_mul(A, a, np);
+        dn nB = dn_add(B, dn_mul(A, b, np), np);
         A = nA;
         B = nB;
     }
@@ -567,7 +709,7 @@ static int seg_cmp(const void *pa, const void *pb)
 static void leaf_field(int kind, int64_t n, int64_t l, const double *kap, const double *eps, leaffield *F)
 {
     F->kind = kind;
-    int nc = kind ? 8 : 1;
+    int nc = kind == 1 ? 8 : 1;
     for (int c = 0; c < nc; c++) {
         F->kap[c] = kap[(int64_t)c * n + l];
         F->eps[c] = eps[(int64_t)c * n + l];
@@ -626,16 +768,19 @@ static void selected_ij(const orcam *c, int64_t npix_sel, const int64_t *pix_sel
 }
 
 /*
- * Render one camera.  kap/eps: [nc][n] doubles (nc = 1 for kind 0, 8 for kind 1).
- * method 0 = analytic (constant), 1 = RK4 over `substeps` substeps.
+ * Render one camera.  kap/eps: [nc][n] doubles (nc = 8 for kind 1, else 1; kind 2
+ * holds the equilibrium intensity I in eps).  method 0 = analytic (constant),
+ * 1 = RK4, 2 = implicit Gauss (2 stages), 3 = Simpson, over `substeps` equal
+ * substeps (a power of two for methods 2, 3 and for c_rk > 0); c_rk > 0 turns
+ * on the recursion of Alg. adaptiverk with that stability parameter.
  * Pixels: all (npix_sel < 0, outputs have w*h entries, row j = 0 at the bottom)
  * or the listed pixel indices p = j*w + i (outputs have npix_sel entries).
  * stats[0] = segments, stats[1] = overlaps beyond 1e-12 relative,
  * stats[2] = candidates tested.  Returns 0.
  */
 int or_render(int64_t n, const uint8_t *level, const uint32_t *x, const uint32_t *y, const uint32_t *z,
-              int kind, const double *kap, const double *eps, int method, int substeps, const double *cam,
-              int64_t npix_sel, const int64_t *pix_sel, double *Aout, double *Bout, double *Iout,
+              int kind, const double *kap, const double *eps, int method, int substeps, double c_rk,
+              const double *cam, int64_t npix_sel, const int64_t *pix_sel, double *Aout, double *Bout, double *Iout,
               int32_t *nseg_pix, int64_t *stats)
 {
     orcam c;
@@ -655,7 +800,7 @@ int or_render(int64_t n, const uint8_t *level, const uint32_t *x, const uint32_t
         leaffield F;
         leaf_field(kind, n, s->leaf, kap, eps, &F);
         dn A, B;
-        segment_dn(&F, &b, rho, r, ray_norm(r), s->s_in, s->s_out, method, substeps, 0, &A, &B);
+        segment_dn(&F, &b, rho, r, ray_norm(r), s->s_in, s->s_out, method, substeps, c_rk, 0, &A, &B);
         s->A = A.v;
         s->B = B.v;
     }
@@ -702,12 +847,12 @@ int or_render(int64_t n, const uint8_t *level, const uint32_t *x, const uint32_t
  * segment k from behind; segment derivatives come from dual numbers.
  */
 int or_grad(int64_t n, const uint8_t *level, const uint32_t *x, const uint32_t *y, const uint32_t *z,
-            int kind, const double *kap, const double *eps, int method, int substeps, const double *cam,
-            int64_t npix_sel, const int64_t *pix_sel, const double *g, double *gk, double *ge)
+            int kind, const double *kap, const double *eps, int method, int substeps, double c_rk,
+            const double *cam, int64_t npix_sel, const int64_t *pix_sel, const double *g, double *gk, double *ge)
 {
     orcam c;
     cam_parse(cam, &c);
-    int nc = kind ? 8 : 1, np = 2 * nc;
+    int nc = kind == 1 ? 8 : 1, np = 2 * nc;
     int64_t ns = 0;
     orseg *segs = gather(&c, n, level, x, y, z, npix_sel, pix_sel, &ns);
     for (int64_t q = 0; q < (int64_t)nc * n; q++) {
@@ -726,7 +871,7 @@ int or_grad(int64_t n, const uint8_t *level, const uint32_t *x, const uint32_t *
         leaffield F;
         leaf_field(kind, n, s->leaf, kap, eps, &F);
         dn A, B;
-        segment_dn(&F, &b, rho, r, ray_norm(r), s->s_in, s->s_out, method, substeps, 0, &A, &B);
+        segment_dn(&F, &b, rho, r, ray_norm(r), s->s_in, s->s_out, method, substeps, c_rk, 0, &A, &B);
         s->A = A.v;
         s->B = B.v;
     }
@@ -761,7 +906,7 @@ int or_grad(int64_t n, const uint8_t *level, const uint32_t *x, const uint32_t *
         leaffield F;
         leaf_field(kind, n, s->leaf, kap, eps, &F);
         dn A, B;
-        segment_dn(&F, &b, rho, r, ray_norm(r), s->s_in, s->s_out, method, substeps, np, &A, &B);
+        segment_dn(&F, &b, rho, r, ray_norm(r), s->s_in, s->s_out, method, substeps, c_rk, np, &A, &B);
         for (int p = 0; p < nc; p++) {
             gk[(int64_t)p * n + s->leaf] += dIdA[m] * A.d[p] + dIdB[m] * B.d[p];
             ge[(int64_t)p * n + s->leaf] += dIdA[m] * A.d[nc + p] + dIdB[m] * B.d[nc + p];
@@ -777,18 +922,18 @@ int or_grad(int64_t n, const uint8_t *level, const uint32_t *x, const uint32_t *
  * AB[2] and dAB[2][np] with np = 2 * nc. */
 int or_segment(int kind, const double *kap, const double *eps, uint8_t level, uint32_t x, uint32_t y,
                uint32_t z, const double *rho, const double *r, double s_in, double s_out, int method,
-               int substeps, double *AB, double *dAB)
+               int substeps, double c_rk, double *AB, double *dAB)
 {
     leafbox b = leaf_box(level, x, y, z);
     leaffield F;
     F.kind = kind;
-    int nc = kind ? 8 : 1, np = 2 * nc;
+    int nc = kind == 1 ? 8 : 1, np = 2 * nc;
     for (int cc = 0; cc < nc; cc++) {
         F.kap[cc] = kap[cc];
         F.eps[cc] = eps[cc];
     }
     dn A, B;
-    segment_dn(&F, &b, rho, r, ray_norm(r), s_in, s_out, method, substeps, np, &A, &B);
+    segment_dn(&F, &b, rho, r, ray_norm(r), s_in, s_out, method, substeps, c_rk, np, &A, &B);
     AB[0] = A.v;
     AB[1] = B.v;
     if (dAB)
@@ -847,7 +992,7 @@ int or_march(int64_t n, const uint8_t *level, const uint32_t *x, const uint32_t 
                 int64_t l = locate(n, level, x, y, z, pt, &bx);
                 if (l < 0) continue;
                 double kv, ev;
-                if (kind) {
+                if (kind == 1) {
                     double xi[3], kc[8], ec[8];
                     for (int k = 0; k < 3; k++) xi[k] = (pt[k] - bx.lo[k]) / bx.hlen;
                     for (int cc = 0; cc < 8; cc++) {
@@ -858,7 +1003,7 @@ int or_march(int64_t n, const uint8_t *level, const uint32_t *x, const uint32_t 
                     ev = trilin_dn(ec, xi, 0, 0).v;
                 } else {
                     kv = kap[l];
-                    ev = eps[l];
+                    ev = kind == 2 ? kap[l] * eps[l] : eps[l];
                 }
                 dn A, B;
                 seg_const_dn(dn_c(kv, 0), dn_c(ev, 0), ds * rn, 0, &A, &B);
@@ -1132,7 +1277,7 @@ int64_t or_shell_pairs(int64_t nlist, const int64_t *list, int ntrees, const int
  * layout and the geometry table. */
 int or_shell_render(int64_t n, int ntrees, const int64_t *tree_begin, const double *geom, const uint8_t *level,
                     const uint32_t *x, const uint32_t *y, const uint32_t *z, int kind, const double *kap,
-                    const double *eps, int method, int substeps, const double *cam, int64_t npix_sel,
+                    const double *eps, int method, int substeps, double c_rk, const double *cam, int64_t npix_sel,
                     const int64_t *pix_sel, double *Aout, double *Bout, double *Iout, int32_t *nseg_pix,
                     int64_t *stats)
 {
@@ -1189,7 +1334,7 @@ int or_shell_render(int64_t n, int ntrees, const int64_t *tree_begin, const doub
         leaffield F;
         leaf_field(kind, n, l, kap, eps, &F);
         dn A, B;
-        segment_dn_ref(&F, shell_ref, &e, rho, r, ray_norm(r), s->s_in, s->s_out, method, substeps, 0, &A, &B);
+        segment_dn_ref(&F, shell_ref, &e, rho, r, ray_norm(r), s->s_in, s->s_out, method, substeps, c_rk, 0, &A, &B);
         s->A = A.v;
         s->B = B.v;
     }
@@ -1300,7 +1445,7 @@ int or_shell_march(int64_t n, int ntrees, const int64_t *tree_begin, const doubl
                 double xi[3];
                 shell_ref(&e, pt, xi);
                 double kv, ev;
-                if (kind) {
+                if (kind == 1) {
                     double kc[8], ec[8];
                     for (int cc = 0; cc < 8; cc++) {
                         kc[cc] = kap[(int64_t)cc * n + found];
@@ -1310,7 +1455,7 @@ int or_shell_march(int64_t n, int ntrees, const int64_t *tree_begin, const doubl
                     ev = trilin_dn(ec, xi, 0, 0).v;
                 } else {
                     kv = kap[found];
-                    ev = eps[found];
+                    ev = kind == 2 ? kap[found] * eps[found] : eps[found];
                 }
                 dn Ad, Bd;
                 seg_const_dn(dn_c(kv, 0), dn_c(ev, 0), ds * rn, 0, &Ad, &Bd);

@@ -31,4 +31,5 @@ from .scene import (  # noqa: F401
     perturb_fields,
     trilinear_fields_from_gaussians,
     constant_fields,
+    equilibrium_fields,
 )

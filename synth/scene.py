@@ -60,7 +60,7 @@ class Forest:
 
 @dataclasses.dataclass
 class Fields:
-    kind: str  # "const" or "trilinear"
+    kind: str  # "const", "trilinear", or "const_eq" (eps holds the equilibrium intensity I)
     kappa: np.ndarray  # float32 [ncorner][N]
     eps: np.ndarray  # float32 [ncorner][N]
 
@@ -350,6 +350,12 @@ def corner_points(forest: Forest) -> np.ndarray:
 def constant_fields(kappa: np.ndarray, eps: np.ndarray) -> Fields:
     return Fields("const", np.asarray(kappa, np.float32)[None, :].copy(),
                   np.asarray(eps, np.float32)[None, :].copy())
+
+
+def equilibrium_fields(kappa: np.ndarray, intensity: np.ndarray) -> Fields:
+    """Per-leaf constant absorption and equilibrium intensity I (emission kappa I)."""
+    return Fields("const_eq", np.asarray(kappa, np.float32)[None, :].copy(),
+                  np.asarray(intensity, np.float32)[None, :].copy())
 
 
 def trilinear_fields_from_gaussians(forest: Forest, centers, sigmas,
