@@ -108,6 +108,7 @@ def main():
     ap.add_argument("--res", type=int, default=1024)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-shell", action="store_true")
+    ap.add_argument("--no-integrators", action="store_true")
     ap.add_argument("--copy-calib", action="store_true",
                     help="end with plain 256 MiB device copies, the reference for HBM byte counters")
     args = ap.parse_args()
@@ -215,6 +216,8 @@ def main():
 
     if not args.no_bwd:
         out["adjoint_workload"] = bench_adjoint(torch, P, synth, max(args.steps // 2, 5))
+    if not args.no_integrators:
+        out["integrators"] = bench_integrators(torch, P, r, max(args.steps // 5, 3))
     if not args.no_batch:
         out["batched_workload"] = bench_batched(torch, P, synth, r, max(args.steps // 10, 3))
     if not args.no_shell:
@@ -296,6 +299,22 @@ def bench_batched(torch, P, synth, r, steps):
             "segments": S, "batched_ms": t_batch, "plain_sum_ms": t_plain, "plain_over_batched": t_plain / t_batch,
             "ray_segments_per_s": S / (t_batch * 1e-3), "images_per_s": len(cams) / (t_batch * 1e-3),
             "tuning": tune["tuning"]}
+
+
+def bench_integrators(torch, P, r, steps):
+    """Segment phase of the adaptive workload with each integrator (Sec. 2.7):
+    RK4, implicit Gauss and Simpson over 4 pieces, and RK4 with the recursion."""
+    out = {}
+    for name, method, sub, c_rk in (("rk4_x4", "rk4", 4, 0.0), ("gauss2_x4", "gauss2", 4, 0.0),
+                                    ("simpson_x4", "simpson", 4, 0.0), ("rk4_adaptive_c0.5", "rk4", 1, 0.5),
+                                    ("gauss2_adaptive_c0.5", "gauss2", 1, 0.5)):
+        ri = P.Renderer(r.forest, r.fields, r.cams.raw, method, sub, device="cuda:0", index=r.index, c_rk=c_rk)
+        ri.segments()
+        t = time_region(torch, ri.segments, steps)
+        out[name] = {"segments_ms": t}
+        log(f"[bench] integrator {name}: segments phase {t:.3f} ms")
+        del ri
+    return out
 
 
 def bench_shell(torch, P, synth, steps):

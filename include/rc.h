@@ -68,8 +68,9 @@ typedef int32_t rc_status;
 #define RC_MAXTREES 64
 
 enum { RC_GEOM_UNIT_CUBE = 0, RC_GEOM_SHELL6 = 1 };
-enum { RC_FIELD_CONST = 0, RC_FIELD_TRILINEAR = 1 };
-enum { RC_INT_ANALYTIC = 0, RC_INT_RK4 = 1 };
+enum { RC_FIELD_CONST = 0, RC_FIELD_TRILINEAR = 1, RC_FIELD_CONST_EQ = 2 };
+enum { RC_INT_ANALYTIC = 0, RC_INT_RK4 = 1, RC_INT_GAUSS2 = 2, RC_INT_SIMPSON = 3 };
+#define RC_ADAPT_MAXDEPTH 16  /* deepest halving of the adaptive recursion */
 
 /* One process's share of a forest (Sec. 2.1): leaves in SFC order.
  *
@@ -98,17 +99,32 @@ typedef struct rc_forest {
  * values (corner c = bx + 2 by + 4 bz, 32-byte aligned rows) for trilinear
  * data interpolated in leaf reference coordinates. */
 typedef struct rc_fields {
-    int32_t kind;               /* RC_FIELD_CONST or RC_FIELD_TRILINEAR */
+    int32_t kind;               /* RC_FIELD_CONST, RC_FIELD_TRILINEAR or RC_FIELD_CONST_EQ (constant
+                                   kappa and equilibrium intensity I = eps / kappa in place of eps,
+                                   eq. BIrelation: B = I (1 - A); analytic integration only) */
     int32_t nch;                /* channels; 1 */
     const float *kappa;         /* [device] N * ncorner, 16-byte aligned */
     const float *eps;           /* [device] N * ncorner, 16-byte aligned */
 } rc_fields;
 
-/* Segment integrator (Sec. 2.3, 2.7): closed form for constant coefficients,
- * or `substeps` equal classical RK4 steps combined with the group operation. */
+/* Segment integrator (Sec. 2.3, 2.7):
+ *  RC_INT_ANALYTIC  closed form for constant coefficients (eq. ABconstant);
+ *  RC_INT_RK4       classical RK4 steps of eq. RKresultAB;
+ *  RC_INT_GAUSS2    implicit Gauss, two stages at 1/2 -+ sqrt(3)/6 (eq. gaussAB);
+ *  RC_INT_SIMPSON   Simpson quadrature of the closed form (eq. simpson).
+ * A segment is split into `substeps` equal pieces combined with the group
+ * operation, nearest first.  c_rk > 0 adds the recursion of Alg. adaptiverk: a
+ * piece whose stage points give dx kappa(xi_i) > c_rk is replaced by its two
+ * halves, down to RC_ADAPT_MAXDEPTH halvings.  The pieces are the dyadic
+ * fractions [k, k+1] / 2^d of the segment counted from its near end, their
+ * stage points at ray parameter s_in + ((k + 1 - c_i) / 2^d) (s_out - s_in)
+ * in FP64, and the split test uses FP64 trilinear values, so that the
+ * decisions are reproducible.  Gauss, Simpson and c_rk > 0 need a power of
+ * two `substeps`. */
 typedef struct rc_integrator {
-    int32_t method;             /* RC_INT_ANALYTIC (needs RC_FIELD_CONST) or RC_INT_RK4 */
-    int32_t substeps;           /* RK4 substeps per segment, 1 .. 64 */
+    int32_t method;             /* RC_INT_* (analytic needs constant fields) */
+    int32_t substeps;           /* pieces per segment, 1 .. 64 */
+    double c_rk;                /* stability parameter of the recursion; 0 = off */
 } rc_integrator;
 
 /* Launch shapes of the grid-stride kernels, in 256-thread workgroups; 0 (or a

@@ -25,8 +25,9 @@ RC_CAMERA_DOUBLES = 20
 RC_GEOM_UNIT_CUBE, RC_GEOM_SHELL6 = 0, 1
 RC_MAXTREES = 64
 RC_ABSENT = -1
-RC_FIELD_CONST, RC_FIELD_TRILINEAR = 0, 1
-RC_INT_ANALYTIC, RC_INT_RK4 = 0, 1
+RC_FIELD_CONST, RC_FIELD_TRILINEAR, RC_FIELD_CONST_EQ = 0, 1, 2
+RC_INT_ANALYTIC, RC_INT_RK4, RC_INT_GAUSS2, RC_INT_SIMPSON = 0, 1, 2, 3
+RC_ADAPT_MAXDEPTH = 16
 
 
 class RcForest(ctypes.Structure):
@@ -39,7 +40,7 @@ class RcFields(ctypes.Structure):
 
 
 class RcIntegrator(ctypes.Structure):
-    _fields_ = [("method", c_i32), ("substeps", c_i32)]
+    _fields_ = [("method", c_i32), ("substeps", c_i32), ("c_rk", ctypes.c_double)]
 
 
 class RcTuning(ctypes.Structure):

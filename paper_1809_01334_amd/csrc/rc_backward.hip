@@ -513,6 +513,7 @@ extern "C" rc_status rc_segments_backward(const rc_forest* f, const rc_index* ix
     if (is_shell(f)) return RC_EUNSUPPORTED;
     if ((s = check_index(ix)) != RC_OK) return s;
     if ((s = check_fields(fl, in)) != RC_OK) return s;
+    if (!adjoint_supported(fl, in)) return RC_EUNSUPPORTED;
     if ((s = check_vforest(vf, ix->maxlevel >= 1)) != RC_OK) return s;
     if (!dcams || ncams <= 0 || npix <= 0 || !rec_leaf || !dLdI || !adj_leaf || !dk || !de || vf->cap_cand < 1)
         return RC_EINVAL;

@@ -77,16 +77,33 @@ inline rc_status check_vforest(const rc_vforest* vf, bool need_nodes) {
 inline rc_status check_fields(const rc_fields* fl, const rc_integrator* in) {
     if (!fl || !fl->kappa || !fl->eps || !in) return RC_EINVAL;
     if (fl->nch != 1) return RC_EUNSUPPORTED;
-    if (fl->kind != RC_FIELD_CONST && fl->kind != RC_FIELD_TRILINEAR) return RC_EUNSUPPORTED;
-    if (in->method == RC_INT_ANALYTIC) {
-        if (fl->kind != RC_FIELD_CONST) return RC_EUNSUPPORTED;
-    } else if (in->method == RC_INT_RK4) {
-        if (in->substeps < 1 || in->substeps > 64) return RC_EINVAL;
-    } else {
+    if (fl->kind != RC_FIELD_CONST && fl->kind != RC_FIELD_TRILINEAR && fl->kind != RC_FIELD_CONST_EQ)
         return RC_EUNSUPPORTED;
+    if (in->method == RC_INT_ANALYTIC) {
+        if (fl->kind == RC_FIELD_TRILINEAR) return RC_EUNSUPPORTED;
+        return RC_OK;
     }
+    if (in->method != RC_INT_RK4 && in->method != RC_INT_GAUSS2 && in->method != RC_INT_SIMPSON)
+        return RC_EUNSUPPORTED;
+    if (fl->kind == RC_FIELD_CONST_EQ) return RC_EUNSUPPORTED;
+    if (in->substeps < 1 || in->substeps > 64) return RC_EINVAL;
+    if (!(in->c_rk >= 0.0)) return RC_EINVAL;  // also rejects NaN
+    bool dyadic = in->method != RC_INT_RK4 || in->c_rk > 0.0;
+    if (dyadic && (in->substeps & (in->substeps - 1))) return RC_EINVAL;
     return RC_OK;
 }
+
+// The hand-written adjoint covers the fixed-step RK4 and the closed form with
+// (kappa, eps) fields.
+inline bool adjoint_supported(const rc_fields* fl, const rc_integrator* in) {
+    if (fl->kind == RC_FIELD_CONST_EQ) return false;
+    return in->method == RC_INT_ANALYTIC || (in->method == RC_INT_RK4 && in->c_rk == 0.0);
+}
+
+// Integrators beyond the closed form and fixed-step RK4: rc_integrators.hip.
+rc_status rc_segments_general(const rc_forest* f, const rc_fields* fl, const void* dcams, const rc_vforest* vf,
+                              const rc_integrator* in, float* rec_leaf, uint8_t* hit, double* sio,
+                              const rc_tuning* tune, hipStream_t st);
 
 // The per-call tables written by rc_prune_visible and read by later calls.
 inline rc_status check_tables(const rc_vforest* vf, const rc_index* ix, int32_t ncams) {

@@ -399,6 +399,13 @@ __device__ inline float2 seg_rk4_const(float k, float e, float dx, int nsub) {
 }
 
 // Constant coefficients (eq. ABconstant): A = e^{-k dx}, B = e dx (1 - A)/(k dx).
+// Constant absorption k and equilibrium intensity I (eq. BIrelation):
+// A = exp(-k dx), B = I (1 - A).
+__device__ inline float2 seg_const_eq(float k, float I, float dx) {
+    float x = k * dx;
+    return make_float2(expf(-x), -I * expm1f(-x));
+}
+
 __device__ inline float2 seg_const(float k, float e, float dx) {
     float x = k * dx;
     float A = expf(-x);

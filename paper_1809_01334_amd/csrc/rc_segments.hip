@@ -27,6 +27,7 @@ struct SegArgs {
     float2* rec;
     uint8_t* hit;
     double2* sio;
+    int eq;  // RC_FIELD_CONST_EQ: eps holds the equilibrium intensity I
 };
 
 template <int KIND, int NSUB>
@@ -58,7 +59,8 @@ __global__ __launch_bounds__(256) void k_segments_analytic(SegArgs a) {
         float2 ab = make_float2(1.0f, 0.0f);
         if (p.hit) {
             SegGeom sg = seg_geom(p.rho, p.rr, p.s_in, p.s_out, p.lo, p.lv);
-            ab = seg_const(a.kappa[p.leaf], a.eps[p.leaf], sg.dx);
+            ab = a.eq ? seg_const_eq(a.kappa[p.leaf], a.eps[p.leaf], sg.dx)
+                      : seg_const(a.kappa[p.leaf], a.eps[p.leaf], sg.dx);
         }
         a.rec[g] = ab;
         if (a.hit) a.hit[g] = p.hit ? 1 : 0;
@@ -162,10 +164,12 @@ extern "C" rc_status rc_segments(const rc_forest* f, const rc_fields* fl, const 
     if (!dcams || ncams <= 0 || !rec_leaf || !vf->cand_chunk) return RC_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     if (is_shell(f)) return rc_shell_segments(f, fl, dcams, vf, in, rec_leaf, hit, sio, tune, st);
+    if (in->method != RC_INT_ANALYTIC && (in->method != RC_INT_RK4 || in->c_rk > 0.0))
+        return rc_segments_general(f, fl, dcams, vf, in, rec_leaf, hit, sio, tune, st);
     SegArgs a{(const Cam*)dcams, f->level,       f->x,           f->y,         f->z,        f->nleaves,
               fl->kappa,        fl->eps,        in->substeps,   vf->vis_leaf, vf->vis_cam, vf->vis_rect,
               vf->cand_offset,  vf->counts,     vf->cand_chunk, vf->cap_cand, (float2*)rec_leaf, hit,
-              (double2*)sio};
+              (double2*)sio, fl->kind == RC_FIELD_CONST_EQ ? 1 : 0};
     unsigned grid = stride_grid(vf->cap_cand, 256, tuned(tune, 0, 256 * 8));
     dim3 G(grid), B(256);
     if (in->method == RC_INT_ANALYTIC) {

@@ -398,6 +398,9 @@ __global__ __launch_bounds__(256) void k_fold_root_shell(ShellFold S, int ntrees
 rc_status rc::rc_shell_segments(const rc_forest* f, const rc_fields* fl, const void* dcams, const rc_vforest* vf,
                             const rc_integrator* in, float* rec_leaf, uint8_t* hit, double* sio,
                             const rc_tuning* tune, hipStream_t st) {
+    if (fl->kind == RC_FIELD_CONST_EQ || (in->method != RC_INT_ANALYTIC && in->method != RC_INT_RK4) ||
+        in->c_rk > 0.0)
+        return RC_EUNSUPPORTED;
     ShellSegArgs a;
     a.cams = (const Cam*)dcams;
     a.level = f->level;

@@ -61,14 +61,19 @@ class DeviceForest:
 
 
 class DeviceFields:
-    """Coefficients leaf-major: kappa, eps of shape [N, ncorner] (ncorner 1 or 8)."""
+    """Coefficients leaf-major: kappa, eps of shape [N, ncorner] (ncorner 1 or 8).
+    equilibrium=True: constant kappa and the equilibrium intensity I in place of eps."""
 
-    def __init__(self, kappa: torch.Tensor, eps: torch.Tensor):
+    def __init__(self, kappa: torch.Tensor, eps: torch.Tensor, equilibrium: bool = False):
         assert kappa.shape == eps.shape and kappa.dim() == 2 and kappa.shape[1] in (1, 8)
         assert kappa.dtype == torch.float32 and eps.dtype == torch.float32
+        assert not (equilibrium and kappa.shape[1] != 1)
         self.kappa = kappa.contiguous()
         self.eps = eps.contiguous()
-        self.kind = L.RC_FIELD_TRILINEAR if kappa.shape[1] == 8 else L.RC_FIELD_CONST
+        if equilibrium:
+            self.kind = L.RC_FIELD_CONST_EQ
+        else:
+            self.kind = L.RC_FIELD_TRILINEAR if kappa.shape[1] == 8 else L.RC_FIELD_CONST
         self.struct = L.RcFields(self.kind, 1, _ptr(self.kappa), _ptr(self.eps))
 
     @staticmethod
@@ -79,7 +84,7 @@ class DeviceFields:
     @classmethod
     def from_synth(cls, fields, device):
         return cls(torch.from_numpy(cls.leaf_major(fields.kappa)).to(device),
-                   torch.from_numpy(cls.leaf_major(fields.eps)).to(device))
+                   torch.from_numpy(cls.leaf_major(fields.eps)).to(device), fields.kind == "const_eq")
 
 
 class DeviceCameras:
@@ -210,8 +215,8 @@ def _tune(t: Optional[L.RcTuning]):
 
 def rc_segments(forest: DeviceForest, fields: DeviceFields, cams: DeviceCameras, vf: VForest, method: int,
                 substeps: int, rec_leaf: torch.Tensor, hit: Optional[torch.Tensor] = None,
-                sio: Optional[torch.Tensor] = None, tuning: Optional[L.RcTuning] = None):
-    integ = L.RcIntegrator(int(method), int(substeps))
+                sio: Optional[torch.Tensor] = None, tuning: Optional[L.RcTuning] = None, c_rk: float = 0.0):
+    integ = L.RcIntegrator(int(method), int(substeps), float(c_rk))
     L.call("rc_segments", ctypes.byref(forest.struct), ctypes.byref(fields.struct), _ptr(cams.buf), cams.ncams,
            ctypes.byref(vf.struct), ctypes.byref(integ), _ptr(rec_leaf), _ptr(hit), _ptr(sio), _tune(tuning),
            _stream(forest.device))
@@ -226,8 +231,8 @@ def rc_composite(forest: DeviceForest, index: DeviceIndex, cams: DeviceCameras, 
 
 def rc_segments_backward(forest: DeviceForest, index: DeviceIndex, fields: DeviceFields, cams: DeviceCameras,
                          vf: VForest, method: int, substeps: int, rec_leaf, rec_node, dLdI, adj_leaf, adj_node, dk,
-                         de, accumulate: bool, ws, tuning: Optional[L.RcTuning] = None):
-    integ = L.RcIntegrator(int(method), int(substeps))
+                         de, accumulate: bool, ws, tuning: Optional[L.RcTuning] = None, c_rk: float = 0.0):
+    integ = L.RcIntegrator(int(method), int(substeps), float(c_rk))
     L.call("rc_segments_backward", ctypes.byref(forest.struct), ctypes.byref(index.struct),
            ctypes.byref(fields.struct), _ptr(cams.buf), cams.ncams, ctypes.byref(vf.struct), ctypes.byref(integ),
            _ptr(rec_leaf), _ptr(rec_node), cams.npix, _ptr(dLdI), _ptr(adj_leaf), _ptr(adj_node), _ptr(dk), _ptr(de),
@@ -236,7 +241,8 @@ def rc_segments_backward(forest: DeviceForest, index: DeviceIndex, fields: Devic
 
 # ---------------------------------------------------------------------------- renderer
 
-METHODS = {"analytic": L.RC_INT_ANALYTIC, "rk4": L.RC_INT_RK4}
+METHODS = {"analytic": L.RC_INT_ANALYTIC, "rk4": L.RC_INT_RK4, "gauss2": L.RC_INT_GAUSS2,
+           "simpson": L.RC_INT_SIMPSON}
 
 
 class Renderer:
@@ -247,7 +253,7 @@ class Renderer:
     """
 
     def __init__(self, forest, fields, cameras, method="rk4", substeps=4, device="cuda:0", index=None,
-                 tuning: Optional[dict] = None):
+                 tuning: Optional[dict] = None, c_rk: float = 0.0):
         self.device = torch.device(device)
         if not torch.cuda.is_available():
             raise RuntimeError("the rc renderer needs a GPU")
@@ -260,6 +266,7 @@ class Renderer:
         self.rec_floats = 8 if self.forest.shell else 2
         self.method = METHODS[method] if isinstance(method, str) else int(method)
         self.substeps = int(substeps)
+        self.c_rk = float(c_rk)  # > 0: the adaptive recursion with this stability parameter
         self.index = index if index is not None else rc_forest_index(self.forest)
         self.tuning = L.RcTuning(**(tuning or {}))
         self.nslots = node_slots(self.index, self.cams.ncams)
@@ -310,7 +317,7 @@ class Renderer:
 
     def segments(self, hit=None, sio=None):
         rc_segments(self.forest, self.fields, self.cams, self.vf, self.method, self.substeps, self.rec_leaf, hit, sio,
-                    self.tuning)
+                    self.tuning, self.c_rk)
 
     def composite(self):
         rc_composite(self.forest, self.index, self.cams, self.vf, self.rec_leaf, self.rec_node, self.A, self.B,
@@ -331,7 +338,7 @@ class Renderer:
             de = torch.empty_like(self.fields.eps)
         rc_segments_backward(self.forest, self.index, self.fields, self.cams, self.vf, self.method, self.substeps,
                              self.rec_leaf, self.rec_node, dLdI.contiguous(), self.adj_leaf, self.adj_node, dk, de,
-                             accumulate, self.ws, self.tuning)
+                             accumulate, self.ws, self.tuning, self.c_rk)
         return dk, de
 
     # -- graph capture -----------------------------------------------------
@@ -364,7 +371,7 @@ class Renderer:
         return self.A, self.B, self.I
 
     def set_fields(self, kappa: torch.Tensor, eps: torch.Tensor):
-        self.fields = DeviceFields(kappa, eps)
+        self.fields = DeviceFields(kappa, eps, self.fields.kind == L.RC_FIELD_CONST_EQ)
 
     def debug_segments(self, intervals: bool = True):
         """Run rc_segments with the pairing outputs per candidate: hits (u8; 0/1, or

@@ -167,3 +167,34 @@ def test_shell_forest_validation():
     assert status(6, ptb6, p) == L.RC_EWORKSPACE      # valid forest, no workspace
     f = L.RcForest(6, 7, 12, ptb6, p, p, p, p, p)     # unknown geometry
     assert lib.rc_forest_index(ctypes.byref(f), ctypes.byref(ix), None, 0, None) == L.RC_EUNSUPPORTED
+
+
+def test_integrator_validation():
+    """Gauss, Simpson and the recursion need a power-of-two piece count; the
+    equilibrium-intensity fields take the closed form only."""
+    L = _lib()
+    lib = L.lib()
+    p = ctypes.c_void_p(16)
+    f = L.RcForest(1, 0, 8, None, p, p, p, p)
+    vf = L.RcVforest()
+
+    def seg(kind, method, sub, c_rk=0.0):
+        fl = L.RcFields(kind, 1, p, p)
+        integ = L.RcIntegrator(method, sub, c_rk)
+        return lib.rc_segments(ctypes.byref(f), ctypes.byref(fl), p, 1, ctypes.byref(vf), ctypes.byref(integ), p,
+                               None, None, None, None)
+
+    T, C, E = L.RC_FIELD_TRILINEAR, L.RC_FIELD_CONST, L.RC_FIELD_CONST_EQ
+    assert seg(T, L.RC_INT_GAUSS2, 3) == L.RC_EINVAL
+    assert seg(T, L.RC_INT_SIMPSON, 6) == L.RC_EINVAL
+    assert seg(T, L.RC_INT_RK4, 3, 0.5) == L.RC_EINVAL       # recursion: power of two
+    assert seg(T, L.RC_INT_RK4, 4, -0.1) == L.RC_EINVAL
+    assert seg(T, L.RC_INT_RK4, 4, float("nan")) == L.RC_EINVAL
+    assert seg(T, 7, 4) == L.RC_EUNSUPPORTED
+    assert seg(T, L.RC_INT_ANALYTIC, 1) == L.RC_EUNSUPPORTED
+    assert seg(E, L.RC_INT_RK4, 4) == L.RC_EUNSUPPORTED
+    assert seg(E, L.RC_INT_GAUSS2, 4) == L.RC_EUNSUPPORTED
+    # valid combinations get past validation and stop at the empty vforest
+    for kind, method, sub, c_rk in ((T, L.RC_INT_GAUSS2, 4, 0.0), (C, L.RC_INT_SIMPSON, 2, 0.3),
+                                    (E, L.RC_INT_ANALYTIC, 1, 0.0), (T, L.RC_INT_RK4, 3, 0.0)):
+        assert seg(kind, method, sub, c_rk) == L.RC_EINVAL  # null vforest arrays
