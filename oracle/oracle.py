@@ -62,6 +62,14 @@ def lib():
         L.or_shell_render.argtypes = [I64, I32, P, P, P, P, P, P, I32, P, P, I32, I32, D, P, I64, P, P, P, P, P, P]
         L.or_shell_march.restype = I32
         L.or_shell_march.argtypes = [I64, I32, P, P, P, P, P, P, I32, P, P, P, I32, P, P, P]
+        L.or_share_units.restype = I64
+        L.or_share_units.argtypes = [I64, P, P, P, P, P, P, P, P, I64]
+        L.or_share_lists.restype = I64
+        L.or_share_lists.argtypes = [I64, P, P, P, P, I32, P, P, I32, I32, D, P, P, P, I64]
+        L.or_merge_pixel.restype = I64
+        L.or_merge_pixel.argtypes = [I64, P, P]
+        L.or_merge_sorted.restype = I64
+        L.or_merge_sorted.argtypes = [I64, P, P, P]
         L.or_shell_map.argtypes = [P, I32, P, P]
         L.or_shell_inverse.argtypes = [P, I32, P, P]
         for nm in ("or_combine", "or_average"):
@@ -264,6 +272,58 @@ def grad(forest, fields, cam, g, method="rk4", substeps=4, pixels=None, kappa=No
     lib().or_grad(forest.nleaves, _p(lv), _p(x), _p(y), _p(z), kind, _p(k), _p(e), METHODS[method],
                   int(substeps), float(c_rk), _p(_c(raw, np.float64)), nsel, _p(pix), _p(gg), _p(gk), _p(ge))
     return gk, ge
+
+
+# ---------------------------------------------------------------- one process's share (Sec. 3.3, 3.5, 2.5)
+
+
+def share_units(forest):
+    """Maximal complete subtrees of a share (level u8, x, y, z u32), in curve order."""
+    lv, x, y, z = _forest_args(forest)
+    n = forest.nleaves
+    m = lib().or_share_units(n, _p(lv), _p(x), _p(y), _p(z), None, None, None, None, 0)
+    ul = np.zeros(max(m, 1), np.uint8)
+    ux, uy, uz = (np.zeros(max(m, 1), np.uint32) for _ in range(3))
+    lib().or_share_units(n, _p(lv), _p(x), _p(y), _p(z), _p(ul), _p(ux), _p(uy), _p(uz), m)
+    return ul[:m], ux[:m], uy[:m], uz[:m]
+
+
+def share_lists(forest, fields, cam, method="rk4", substeps=4, c_rk=0.0):
+    """Per-pixel entry lists (offsets [P + 1], entries [m, 4] = s_in, s_out, A, B) of a share."""
+    raw = cam.raw() if hasattr(cam, "raw") else np.asarray(cam, np.float64)
+    lv, x, y, z = _forest_args(forest)
+    kind, k, e = _field_args(fields)
+    P_ = int(raw[14]) * int(raw[15])
+    off = np.zeros(P_ + 1, np.int64)
+    args = (forest.nleaves, _p(lv), _p(x), _p(y), _p(z), kind, _p(k), _p(e), METHODS[method], int(substeps),
+            float(c_rk), _p(_c(raw, np.float64)), _p(off))
+    m = lib().or_share_lists(*args, None, 0)
+    ent = np.zeros((max(m, 1), 4), np.float64)
+    lib().or_share_lists(*args, _p(ent), m)
+    return off, ent[:m]
+
+
+def merge_pixel(entries):
+    """(A, B) of one pixel's entries sorted by s_in, with cut/average of overlaps; and the overlap count."""
+    e = _c(entries, np.float64).reshape(-1, 4)
+    ab = np.zeros(2)
+    ov = lib().or_merge_pixel(e.shape[0], _p(e), _p(ab))
+    return ab, int(ov)
+
+
+def merge_lists(lists, P_, background=0.0):
+    """Merge per-pixel lists of several shares (each (offsets, entries)): A, B, I and overlaps."""
+    pix = np.concatenate([np.repeat(np.arange(P_), np.diff(off)) for off, _ in lists])
+    ent = np.concatenate([e for _, e in lists]).reshape(-1, 4)
+    order = np.lexsort((ent[:, 1], ent[:, 0], pix))  # the sort step: by pixel, then depth
+    ent = _c(ent[order], np.float64)
+    off = np.zeros(P_ + 1, np.int64)
+    np.add.at(off, pix + 1, 1)
+    off = np.cumsum(off)
+    ab = np.zeros((P_, 2))
+    ov = lib().or_merge_sorted(P_, _p(off), _p(ent), _p(ab))
+    A, B = ab[:, 0], ab[:, 1]
+    return {"A": A, "B": B, "I": A * background + B, "overlaps": int(ov)}
 
 
 def march(forest, fields, cam, M=1024):

@@ -969,6 +969,207 @@ static int64_t locate(int64_t n, const uint8_t *level, const uint32_t *x, const 
  * eq. ABconstant, and is folded front to back.  Converges to the exact
  * integral as M grows; shares neither pairing nor tree order with or_render.
  */
+/* ------------------------------------------------------------------------ */
+/* one process's share: maximal complete subtrees and per-pixel lists       */
+/* (Sec. 3.3 coarsening to the share's maximal subtrees, Sec. 3.5 lists,    */
+/* Sec. 2.5 cutting and averaging overlapping segments)                     */
+/* ------------------------------------------------------------------------ */
+
+static uint64_t key_of(uint32_t x, uint32_t y, uint32_t z)
+{
+    uint64_t k = 0;
+    for (int b = 0; b < OR_QMAX; b++) {
+        k |= (uint64_t)((x >> b) & 1u) << (3 * b);
+        k |= (uint64_t)((y >> b) & 1u) << (3 * b + 1);
+        k |= (uint64_t)((z >> b) & 1u) << (3 * b + 2);
+    }
+    return k;
+}
+
+static void anchor_of(uint64_t k, uint32_t *x, uint32_t *y, uint32_t *z)
+{
+    *x = *y = *z = 0;
+    for (int b = 0; b < OR_QMAX; b++) {
+        *x |= (uint32_t)((k >> (3 * b)) & 1u) << b;
+        *y |= (uint32_t)((k >> (3 * b + 1)) & 1u) << b;
+        *z |= (uint32_t)((k >> (3 * b + 2)) & 1u) << b;
+    }
+}
+
+/* The share's leaves tile the curve interval [S, E) of the finest-level keys;
+ * its maximal complete subtrees are the largest aligned blocks of that
+ * interval, taken greedily from S.  Returns their number (written when
+ * ulevel != NULL, up to cap). */
+int64_t or_share_units(int64_t n, const uint8_t *level, const uint32_t *x, const uint32_t *y, const uint32_t *z,
+                       uint8_t *ulevel, uint32_t *ux, uint32_t *uy, uint32_t *uz, int64_t cap)
+{
+    if (n <= 0) return 0;
+    uint64_t S = key_of(x[0], y[0], z[0]);
+    uint64_t E = key_of(x[n - 1], y[n - 1], z[n - 1]) + ((uint64_t)1 << (3 * (OR_QMAX - level[n - 1])));
+    int64_t m = 0;
+    uint64_t p = S;
+    while (p < E) {
+        int l = 0;
+        for (; l <= OR_QMAX; l++) {
+            uint64_t size = (uint64_t)1 << (3 * (OR_QMAX - l));
+            if (p % size == 0 && p + size <= E) break;
+        }
+        if (ulevel && m < cap) {
+            ulevel[m] = (uint8_t)l;
+            anchor_of(p, &ux[m], &uy[m], &uz[m]);
+        }
+        m++;
+        p += (uint64_t)1 << (3 * (OR_QMAX - l));
+    }
+    return m;
+}
+
+/* Per-pixel lists of one share for one camera: for every pixel, one entry per
+ * maximal subtree that its ray meets, (s_in, s_out) the canonical slab interval
+ * of the subtree's box and (A, B) the nearest-first fold of the share's
+ * segments inside it; entries in depth order.  offsets[P + 1]; entries[4 per
+ * entry] written when entries != NULL (up to cap).  Returns the entry count. */
+int64_t or_share_lists(int64_t n, const uint8_t *level, const uint32_t *x, const uint32_t *y, const uint32_t *z,
+                       int kind, const double *kap, const double *eps, int method, int substeps, double c_rk,
+                       const double *cam, int64_t *offsets, double *entries, int64_t cap)
+{
+    orcam c;
+    cam_parse(cam, &c);
+    int64_t P = (int64_t)c.w * c.h;
+    int64_t nu = or_share_units(n, level, x, y, z, NULL, NULL, NULL, NULL, 0);
+    uint8_t *ul = (uint8_t *)malloc((size_t)(nu > 0 ? nu : 1));
+    uint32_t *ux = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(nu > 0 ? nu : 1));
+    uint32_t *uy = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(nu > 0 ? nu : 1));
+    uint32_t *uz = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(nu > 0 ? nu : 1));
+    or_share_units(n, level, x, y, z, ul, ux, uy, uz, nu);
+    /* unit of every leaf: units and leaves are both in curve order */
+    int64_t *lunit = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    int64_t u = 0;
+    for (int64_t l = 0; l < n; l++) {
+        uint64_t k = key_of(x[l], y[l], z[l]);
+        while (u + 1 < nu && key_of(ux[u + 1], uy[u + 1], uz[u + 1]) <= k) u++;
+        lunit[l] = u;
+    }
+    int64_t ns = 0;
+    orseg *segs = gather(&c, n, level, x, y, z, -1, NULL, &ns);
+    for (int64_t k = 0; k < ns; k++) {
+        orseg *sg = &segs[k];
+        int i = (int)(sg->pix % c.w), j = (int)(sg->pix / c.w);
+        double rho[3], r[3];
+        pixel_ray(&c, i, j, rho, r);
+        leafbox b = leaf_box(level[sg->leaf], x[sg->leaf], y[sg->leaf], z[sg->leaf]);
+        leaffield F;
+        leaf_field(kind, n, sg->leaf, kap, eps, &F);
+        dn A, B;
+        segment_dn(&F, &b, rho, r, ray_norm(r), sg->s_in, sg->s_out, method, substeps, c_rk, 0, &A, &B);
+        sg->A = A.v;
+        sg->B = B.v;
+    }
+    for (int64_t q = 0; q <= P; q++) offsets[q] = 0;
+    int64_t m = 0, k = 0;
+    while (k < ns) {
+        int64_t pix = segs[k].pix;
+        while (k < ns && segs[k].pix == pix) {
+            int64_t un = lunit[segs[k].leaf];
+            double acc[2] = {1.0, 0.0};
+            for (; k < ns && segs[k].pix == pix && lunit[segs[k].leaf] == un; k++) {
+                double sgab[2] = {segs[k].A, segs[k].B}, t[2];
+                or_combine(acc, sgab, t);
+                acc[0] = t[0];
+                acc[1] = t[1];
+            }
+            leafbox ub = leaf_box(ul[un], ux[un], uy[un], uz[un]);
+            double rho[3], r[3], a, bb;
+            pixel_ray(&c, (int)(pix % c.w), (int)(pix / c.w), rho, r);
+            if (!slab(&c, rho, r, ub.lo, ub.hi, &a, &bb)) continue; /* cannot happen for a tiled unit */
+            if (entries && m < cap) {
+                entries[4 * m] = a;
+                entries[4 * m + 1] = bb;
+                entries[4 * m + 2] = acc[0];
+                entries[4 * m + 3] = acc[1];
+            }
+            offsets[pix + 1]++;
+            m++;
+        }
+    }
+    for (int64_t q = 0; q < P; q++) offsets[q + 1] += offsets[q];
+    free(segs);
+    free(lunit);
+    free(ul);
+    free(ux);
+    free(uy);
+    free(uz);
+    return m;
+}
+
+/* One pixel's entries of all shares, sorted by s_in: cut where a segment starts
+ * inside the previous one (eq. segsplit), average the overlapping parts
+ * (eq. segaverage), and fold nearest first.  Returns the number of overlaps. */
+int64_t or_merge_pixel(int64_t m, const double *e, double *AB)
+{
+    double acc[2] = {1.0, 0.0}, pend[4] = {0, 0, 1, 0}, t[2];
+    int have = 0;
+    int64_t overlaps = 0;
+    for (int64_t q = 0; q < m; q++) {
+        const double *x = e + 4 * q;
+        if (!have) {
+            for (int k = 0; k < 4; k++) pend[k] = x[k];
+            have = 1;
+            continue;
+        }
+        if (x[0] >= pend[1]) {
+            or_combine(acc, pend + 2, t);
+            acc[0] = t[0];
+            acc[1] = t[1];
+            for (int k = 0; k < 4; k++) pend[k] = x[k];
+            continue;
+        }
+        overlaps++;
+        double near_[2], far_[2];
+        or_split(pend + 2, (x[0] - pend[0]) / (pend[1] - pend[0]), near_, far_);
+        or_combine(acc, near_, t);
+        acc[0] = t[0];
+        acc[1] = t[1];
+        double mid = pend[1] < x[1] ? pend[1] : x[1];
+        double pa[2], pb[2], xa[2], xb[2], avg[2];
+        or_split(far_, (mid - x[0]) / (pend[1] - x[0]), pa, pb);
+        or_split(x + 2, (mid - x[0]) / (x[1] - x[0]), xa, xb);
+        or_average(pa, xa, avg);
+        or_combine(acc, avg, t);
+        acc[0] = t[0];
+        acc[1] = t[1];
+        if (pend[1] > x[1]) {
+            pend[0] = mid;
+            pend[2] = pb[0];
+            pend[3] = pb[1];
+        } else if (x[1] > pend[1]) {
+            pend[0] = mid;
+            pend[1] = x[1];
+            pend[2] = xb[0];
+            pend[3] = xb[1];
+        } else {
+            have = 0;
+        }
+    }
+    if (have) {
+        or_combine(acc, pend + 2, t);
+        acc[0] = t[0];
+        acc[1] = t[1];
+    }
+    AB[0] = acc[0];
+    AB[1] = acc[1];
+    return overlaps;
+}
+
+/* or_merge_pixel over every pixel: off[P + 1] into entries sorted by s_in within
+ * each pixel; AB[2 P]; returns the total number of overlaps. */
+int64_t or_merge_sorted(int64_t P, const int64_t *off, const double *e, double *AB)
+{
+    int64_t ov = 0;
+    for (int64_t p = 0; p < P; p++) ov += or_merge_pixel(off[p + 1] - off[p], e + 4 * off[p], AB + 2 * p);
+    return ov;
+}
+
 int or_march(int64_t n, const uint8_t *level, const uint32_t *x, const uint32_t *y, const uint32_t *z, int kind,
              const double *kap, const double *eps, const double *cam, int M, double *Aout, double *Bout,
              double *Iout)

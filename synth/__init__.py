@@ -32,4 +32,5 @@ from .scene import (  # noqa: F401
     trilinear_fields_from_gaussians,
     constant_fields,
     equilibrium_fields,
+    split_shares,
 )

@@ -352,6 +352,19 @@ def constant_fields(kappa: np.ndarray, eps: np.ndarray) -> Fields:
                   np.asarray(eps, np.float32)[None, :].copy())
 
 
+def split_shares(forest: Forest, fields: Fields, cuts) -> List[tuple]:
+    """One-tree forest cut into contiguous curve-order ranges at the leaf
+    indices `cuts`: a list of (Forest, Fields), one per process share."""
+    assert forest.ntrees == 1
+    bounds = [0] + [int(c) for c in cuts] + [forest.nleaves]
+    out = []
+    for a, b in zip(bounds[:-1], bounds[1:]):
+        f = Forest(forest.level[a:b].copy(), forest.x[a:b].copy(), forest.y[a:b].copy(), forest.z[a:b].copy(),
+                   np.array([0, b - a], np.int64), forest.geom, forest.geom_params)
+        out.append((f, Fields(fields.kind, fields.kappa[:, a:b].copy(), fields.eps[:, a:b].copy())))
+    return out
+
+
 def equilibrium_fields(kappa: np.ndarray, intensity: np.ndarray) -> Fields:
     """Per-leaf constant absorption and equilibrium intensity I (emission kappa I)."""
     return Fields("const_eq", np.asarray(kappa, np.float32)[None, :].copy(),
