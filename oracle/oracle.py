@@ -315,7 +315,7 @@ def merge_lists(lists, P_, background=0.0):
     """Merge per-pixel lists of several shares (each (offsets, entries)): A, B, I and overlaps."""
     pix = np.concatenate([np.repeat(np.arange(P_), np.diff(off)) for off, _ in lists])
     ent = np.concatenate([e for _, e in lists]).reshape(-1, 4)
-    order = np.lexsort((ent[:, 1], ent[:, 0], pix))  # the sort step: by pixel, then depth
+    order = np.lexsort((ent[:, 3], ent[:, 2], ent[:, 1], ent[:, 0], pix))  # by pixel, then (s_in, s_out, A, B)
     ent = _c(ent[order], np.float64)
     off = np.zeros(P_ + 1, np.int64)
     np.add.at(off, pix + 1, 1)

@@ -1102,60 +1102,70 @@ int64_t or_share_lists(int64_t n, const uint8_t *level, const uint32_t *x, const
     return m;
 }
 
-/* One pixel's entries of all shares, sorted by s_in: cut where a segment starts
- * inside the previous one (eq. segsplit), average the overlapping parts
- * (eq. segaverage), and fold nearest first.  Returns the number of overlaps. */
+static int cmp_double(const void *a, const void *b)
+{
+    double x = *(const double *)a, y = *(const double *)b;
+    return (x > y) - (x < y);
+}
+
+/* One pixel's entries of all shares, sorted by (s_in, s_out).  The depths where
+ * an entry starts or ends cut the ray into elementary intervals; over each,
+ * every entry covering it contributes the piece of its own length fraction
+ * (eq. segsplit), and where several cover it their pieces are averaged: the
+ * geometric mean of the A and the arithmetic mean of the B (eq. segaverage,
+ * taken over all covering entries).  The intervals are folded nearest first;
+ * a zero-length entry is folded whole at its depth.  Returns the number of
+ * overlaps: entries starting before the end of an entry that started earlier. */
 int64_t or_merge_pixel(int64_t m, const double *e, double *AB)
 {
-    double acc[2] = {1.0, 0.0}, pend[4] = {0, 0, 1, 0}, t[2];
-    int have = 0;
+    double acc[2] = {1.0, 0.0}, t[2];
     int64_t overlaps = 0;
     for (int64_t q = 0; q < m; q++) {
-        const double *x = e + 4 * q;
-        if (!have) {
-            for (int k = 0; k < 4; k++) pend[k] = x[k];
-            have = 1;
-            continue;
+        if (!(e[4 * q + 1] > e[4 * q])) continue;
+        for (int64_t r = 0; r < q; r++)
+            if (e[4 * r + 1] > e[4 * r] && e[4 * r] <= e[4 * q] && e[4 * q] < e[4 * r + 1]) {
+                overlaps++;
+                break;
+            }
+    }
+    double *bp = (double *)malloc(sizeof(double) * (size_t)(2 * m > 0 ? 2 * m : 1));
+    int64_t nb = 0;
+    for (int64_t q = 0; q < m; q++) {
+        bp[nb++] = e[4 * q];
+        bp[nb++] = e[4 * q + 1];
+    }
+    qsort(bp, (size_t)nb, sizeof(double), cmp_double);
+    int64_t u = 0;
+    for (int64_t k = 0; k < nb; k++)
+        if (u == 0 || bp[k] != bp[u - 1]) bp[u++] = bp[k];
+    for (int64_t k = 0; k < u; k++) {
+        for (int64_t q = 0; q < m; q++) /* zero-length entries at this depth */
+            if (!(e[4 * q + 1] > e[4 * q]) && e[4 * q] == bp[k]) {
+                or_combine(acc, e + 4 * q + 2, t);
+                acc[0] = t[0];
+                acc[1] = t[1];
+            }
+        if (k + 1 == u) break;
+        double lo = bp[k], hi = bp[k + 1], logA = 0.0, sumB = 0.0, one[2] = {1.0, 0.0};
+        int n = 0;
+        for (int64_t q = 0; q < m; q++) {
+            const double *x = e + 4 * q;
+            if (!(x[1] > x[0]) || x[0] > lo || x[1] < hi) continue;
+            double piece[2], rest[2];
+            or_split(x + 2, (hi - lo) / (x[1] - x[0]), piece, rest);
+            logA += log(piece[0]);
+            sumB += piece[1];
+            one[0] = piece[0];
+            one[1] = piece[1];
+            n++;
         }
-        if (x[0] >= pend[1]) {
-            or_combine(acc, pend + 2, t);
-            acc[0] = t[0];
-            acc[1] = t[1];
-            for (int k = 0; k < 4; k++) pend[k] = x[k];
-            continue;
-        }
-        overlaps++;
-        double near_[2], far_[2];
-        or_split(pend + 2, (x[0] - pend[0]) / (pend[1] - pend[0]), near_, far_);
-        or_combine(acc, near_, t);
-        acc[0] = t[0];
-        acc[1] = t[1];
-        double mid = pend[1] < x[1] ? pend[1] : x[1];
-        double pa[2], pb[2], xa[2], xb[2], avg[2];
-        or_split(far_, (mid - x[0]) / (pend[1] - x[0]), pa, pb);
-        or_split(x + 2, (mid - x[0]) / (x[1] - x[0]), xa, xb);
-        or_average(pa, xa, avg);
+        if (n == 0) continue;
+        double avg[2] = {n == 1 ? one[0] : exp(logA / n), n == 1 ? one[1] : sumB / n};
         or_combine(acc, avg, t);
         acc[0] = t[0];
         acc[1] = t[1];
-        if (pend[1] > x[1]) {
-            pend[0] = mid;
-            pend[2] = pb[0];
-            pend[3] = pb[1];
-        } else if (x[1] > pend[1]) {
-            pend[0] = mid;
-            pend[1] = x[1];
-            pend[2] = xb[0];
-            pend[3] = xb[1];
-        } else {
-            have = 0;
-        }
     }
-    if (have) {
-        or_combine(acc, pend + 2, t);
-        acc[0] = t[0];
-        acc[1] = t[1];
-    }
+    free(bp);
     AB[0] = acc[0];
     AB[1] = acc[1];
     return overlaps;

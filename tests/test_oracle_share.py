@@ -83,3 +83,30 @@ def test_cut_and_average_of_overlapping_segments(oracle_mod):
     # one segment nested inside a longer one
     ab, ov = O.merge_pixel([medium(0, 3), medium(1, 2)])
     assert ov == 1 and math.isclose(ab[0], ref[2], rel_tol=1e-13) and math.isclose(ab[1], ref[3], rel_tol=1e-13)
+
+
+def test_merge_of_more_than_two_overlapping_entries(oracle_mod):
+    """Where several entries cover a depth, the average runs over all of them: three
+    copies of one medium on overlapping intervals give the medium over their union;
+    three different media on one interval give the geometric mean of the A and the
+    arithmetic mean of the B; a zero-length opaque entry inside a medium is folded
+    whole at its depth."""
+    O = oracle_mod
+
+    def medium(a, b, beta=0.7, gamma=0.3):
+        A = math.exp(-beta * (b - a))
+        return [a, b, A, gamma / beta * (1 - A)]
+
+    ab, ov = O.merge_pixel([medium(0, 2), medium(1, 3), medium(1.5, 2.5)])
+    ref = medium(0, 3)
+    assert ov == 2
+    assert math.isclose(ab[0], ref[2], rel_tol=1e-13) and math.isclose(ab[1], ref[3], rel_tol=1e-13)
+    media = [medium(1, 2, 0.5, 0.2), medium(1, 2, 1.5, 0.9), medium(1, 2, 3.0, 0.1)]
+    ab, ov = O.merge_pixel(media)
+    assert ov == 2
+    assert math.isclose(ab[0], (media[0][2] * media[1][2] * media[2][2]) ** (1 / 3), rel_tol=1e-13)
+    assert math.isclose(ab[1], sum(m[3] for m in media) / 3, rel_tol=1e-13)
+    Is = 0.8
+    ab, ov = O.merge_pixel([medium(0, 2), [1.0, 1.0, 0.0, Is]])
+    near = medium(0, 1)
+    assert ov == 0 and ab[0] == 0.0 and math.isclose(ab[1], near[3] + near[2] * Is, rel_tol=1e-13)
