@@ -66,6 +66,7 @@ typedef int32_t rc_status;
 #define RC_ABSENT (-1)        /* child slot without a node in this share */
 
 #define RC_MAXTREES 64
+#define RC_MAXLISTS 16     /* shares rc_merge_lists takes at once */
 
 enum { RC_GEOM_UNIT_CUBE = 0, RC_GEOM_SHELL6 = 1 };
 enum { RC_FIELD_CONST = 0, RC_FIELD_TRILINEAR = 1, RC_FIELD_CONST_EQ = 2 };
@@ -272,6 +273,53 @@ rc_status rc_segments(const rc_forest *forest, const rc_fields *fields, const vo
 rc_status rc_composite(const rc_forest *forest, const rc_index *index, const void *dcams, int32_t ncams,
                        const rc_vforest *vf, const float *rec_leaf, float *rec_node, int64_t total_pixels,
                        float *A, float *B, float *I, const rc_tuning *tune, void *stream);
+
+/*
+ * One share's image as per-pixel lists (Sec. 3.3 coarsening stopped at the
+ * share's maximal complete subtrees, Sec. 3.5 per-pixel segment lists).  The
+ * forest is a share: a contiguous curve-order range of a larger forest's
+ * leaves, indexed on its own (missing children are RC_ABSENT).  A node is
+ * complete when all eight children are leaves or complete nodes; the units
+ * are the leaves and complete nodes under an incomplete parent, and the root
+ * when it is complete.  For every pixel whose ray crosses a unit's box, one
+ * entry (s_in, s_out, A, B) [4 floats]: the canonical slab interval of the
+ * box (FP64, stored as float) and the unit's record there (its children
+ * folded in view order, as rc_composite does).  Every pixel's entries are
+ * sorted by (s_in, s_out, A, B).  Call after rc_prune_visible and
+ * rc_segments of the share; rec_node as for rc_composite (rewritten here).
+ * list_offset [device, total_pixels + 1 int64]: pixel p's entries are
+ * [list_offset[p], list_offset[p + 1]) of entries [device, cap_entries * 4
+ * floats]; *n_entries [device] receives the total.  Entries are written only
+ * when the total fits cap_entries (cap_entries = 0 asks for the count only);
+ * the caller reads n_entries and calls again with more room otherwise.
+ * ws [device, rc_lists_workspace_bytes()].  RC_GEOM_SHELL6: RC_EUNSUPPORTED.
+ */
+size_t rc_lists_workspace_bytes(const rc_index *index, int32_t ncams, int64_t total_pixels);
+rc_status rc_composite_lists(const rc_forest *forest, const rc_index *index, const void *dcams, int32_t ncams,
+                             const rc_vforest *vf, const float *rec_leaf, float *rec_node, int64_t total_pixels,
+                             int64_t *list_offset, float *entries, int64_t cap_entries, int64_t *n_entries,
+                             void *ws, size_t ws_bytes, const rc_tuning *tune, void *stream);
+
+/*
+ * Merge the lists of nlists (1 .. RC_MAXLISTS) shares into images (Sec. 3.5,
+ * Sec. 2.5).  Per pixel, the depths where entries start or end cut the ray
+ * into elementary intervals; over each, every entry covering it contributes
+ * the piece of its length fraction (eq. segsplit, the ratio (1 - A^f) / (1 - A)
+ * evaluated through expm1), several covering entries are averaged (geometric
+ * mean of the A, arithmetic mean of the B: eq. segaverage over all of them),
+ * and the intervals are folded nearest first (eq. aggregate).  A zero-length
+ * entry is folded whole at its depth.  list_offsets, entries [host arrays of
+ * nlists device pointers] in the layout rc_composite_lists writes, for the
+ * same cameras: within one list, a pixel's entries are sorted and disjoint
+ * (they may touch); a pixel whose list breaks this gets NaN.  A, B and
+ * I = A I_b + B [device, total_pixels floats each].  overlaps [device, one
+ * int64, or NULL] is incremented by the number of entries that start inside
+ * an entry of another list.  Shares of one forest meet at shared faces with
+ * bitwise equal depths, so their lists touch and never overlap.
+ */
+rc_status rc_merge_lists(const void *dcams, int32_t ncams, int64_t total_pixels, int32_t nlists,
+                         const int64_t *const *list_offsets, const float *const *entries, float *A, float *B,
+                         float *I, int64_t *overlaps, void *stream);
 
 /*
  * Adjoint of the images with respect to the coefficients.  Given

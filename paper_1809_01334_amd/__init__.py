@@ -11,9 +11,13 @@ from .render import (  # noqa: F401
     RenderFn,
     Renderer,
     VForest,
+    lists_workspace_bytes,
+    merge_lists,
     rc_camera_prepare,
     rc_composite,
+    rc_composite_lists,
     rc_forest_index,
+    rc_merge_lists,
     rc_prune_visible,
     rc_segments,
     rc_segments_backward,

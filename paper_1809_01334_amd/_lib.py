@@ -24,6 +24,7 @@ RC_QMAXLEVEL = 19
 RC_CAMERA_DOUBLES = 20
 RC_GEOM_UNIT_CUBE, RC_GEOM_SHELL6 = 0, 1
 RC_MAXTREES = 64
+RC_MAXLISTS = 16
 RC_ABSENT = -1
 RC_FIELD_CONST, RC_FIELD_TRILINEAR, RC_FIELD_CONST_EQ = 0, 1, 2
 RC_INT_ANALYTIC, RC_INT_RK4, RC_INT_GAUSS2, RC_INT_SIMPSON = 0, 1, 2, 3
@@ -74,6 +75,10 @@ _SIGS = {
                             P(RcTuning), c_vp]),
     "rc_composite": (c_i32, [P(RcForest), P(RcIndex), c_vp, c_i32, P(RcVforest), c_vp, c_vp, c_i64, c_vp, c_vp, c_vp,
                              P(RcTuning), c_vp]),
+    "rc_lists_workspace_bytes": (c_sz, [P(RcIndex), c_i32, c_i64]),
+    "rc_composite_lists": (c_i32, [P(RcForest), P(RcIndex), c_vp, c_i32, P(RcVforest), c_vp, c_vp, c_i64, c_vp,
+                                   c_vp, c_i64, c_vp, c_vp, c_sz, P(RcTuning), c_vp]),
+    "rc_merge_lists": (c_i32, [c_vp, c_i32, c_i64, c_i32, P(c_vp), P(c_vp), c_vp, c_vp, c_vp, c_vp, c_vp]),
     "rc_segments_backward": (c_i32, [P(RcForest), P(RcIndex), P(RcFields), c_vp, c_i32, P(RcVforest),
                                      P(RcIntegrator), c_vp, c_vp, c_i64, c_vp, c_vp, c_vp, c_vp, c_vp, c_i32, c_vp,
                                      c_sz, P(RcTuning), c_vp]),

@@ -110,4 +110,8 @@ __device__ inline int64_t record_slot(const FoldCtx& C, int64_t g, int64_t w, in
     return upper_index(C.node_offset, lo, hi, g);
 }
 
+// Node records of levels maxlevel-1 .. 1 (rc_composite.hip).
+rc_status fold_levels(const FoldCtx& C, const rc_index* ix, const rc_vforest* vf, float* rec_node,
+                      const rc_tuning* tune, hipStream_t st);
+
 }  // namespace rc

@@ -66,6 +66,19 @@ __global__ __launch_bounds__(256) void k_fold_root(FoldCtx C, int32_t root, int6
 }
 
 }  // namespace
+
+// Node records of levels maxlevel-1 .. 1, deepest first.
+rc_status fold_levels(const FoldCtx& C, const rc_index* ix, const rc_vforest* vf, float* rec_node,
+                      const rc_tuning* tune, hipStream_t st) {
+    unsigned grid = stride_grid(vf->cap_rec, 256, tuned(tune, 1, 256 * 16));
+    for (int l = ix->maxlevel - 1; l >= 1; l--) {
+        if (ix->level_begin[l + 1] == ix->level_begin[l]) continue;
+        hipLaunchKernelGGL(k_fold_level, dim3(grid), dim3(256), 0, st, C, l, (float2*)rec_node);
+        RC_HIP(hipGetLastError());
+    }
+    return RC_OK;
+}
+
 }  // namespace rc
 
 extern "C" rc_status rc_composite(const rc_forest* f, const rc_index* ix, const void* dcams, int32_t ncams,
@@ -81,12 +94,7 @@ extern "C" rc_status rc_composite(const rc_forest* f, const rc_index* ix, const 
     hipStream_t st = (hipStream_t)stream;
     if (is_shell(f)) return rc_shell_composite(f, ix, dcams, ncams, vf, rec_leaf, rec_node, npix, A, B, I, tune, st);
     FoldCtx C = make_fold_ctx(f, ix, dcams, ncams, vf, rec_leaf, rec_node);
-    unsigned grid = stride_grid(vf->cap_rec, 256, tuned(tune, 1, 256 * 16));
-    for (int l = ix->maxlevel - 1; l >= 1; l--) {
-        if (ix->level_begin[l + 1] == ix->level_begin[l]) continue;
-        hipLaunchKernelGGL(k_fold_level, dim3(grid), dim3(256), 0, st, C, l, (float2*)rec_node);
-        RC_HIP(hipGetLastError());
-    }
+    if ((s = fold_levels(C, ix, vf, rec_node, tune, st)) != RC_OK) return s;
     hipLaunchKernelGGL(k_fold_root, dim3(stride_grid(npix, 256, tuned(tune, 2, 256 * 16))), dim3(256), 0, st, C,
                        ix->root, npix, A,
                        B, I, vf->leaf_vis, vf->vis_rect, vf->cand_offset);

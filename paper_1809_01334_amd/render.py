@@ -229,6 +229,38 @@ def rc_composite(forest: DeviceForest, index: DeviceIndex, cams: DeviceCameras, 
            _tune(tuning), _stream(forest.device))
 
 
+def lists_workspace_bytes(index: DeviceIndex, ncams: int, npix: int) -> int:
+    return int(L.lib().rc_lists_workspace_bytes(ctypes.byref(index.struct), int(ncams), int(npix)))
+
+
+def rc_composite_lists(forest: DeviceForest, index: DeviceIndex, cams: DeviceCameras, vf: VForest, rec_leaf,
+                       rec_node, list_offset, entries, n_entries, ws, tuning: Optional[L.RcTuning] = None):
+    cap = entries.numel() // 4 if entries is not None else 0
+    L.call("rc_composite_lists", ctypes.byref(forest.struct), ctypes.byref(index.struct), _ptr(cams.buf),
+           cams.ncams, ctypes.byref(vf.struct), _ptr(rec_leaf), _ptr(rec_node), cams.npix, _ptr(list_offset),
+           _ptr(entries), cap, _ptr(n_entries), _ptr(ws), ws.numel(), _tune(tuning), _stream(forest.device))
+
+
+def rc_merge_lists(cams: DeviceCameras, lists, A, B, I, overlaps: Optional[torch.Tensor] = None):
+    """Merge the per-pixel lists [(offsets, entries), ...] of several shares into A, B, I."""
+    n = len(lists)
+    if not 1 <= n <= L.RC_MAXLISTS:
+        raise ValueError(f"between 1 and {L.RC_MAXLISTS} lists, got {n}")
+    offs = (ctypes.c_void_p * n)(*[off.data_ptr() for off, _ in lists])
+    ents = (ctypes.c_void_p * n)(*[e.data_ptr() for _, e in lists])
+    L.call("rc_merge_lists", _ptr(cams.buf), cams.ncams, cams.npix, n, offs, ents, _ptr(A), _ptr(B), _ptr(I),
+           _ptr(overlaps), _stream(A.device))
+
+
+def merge_lists(cams: DeviceCameras, lists):
+    """Images (A, B, I) and the overlap count of the merged lists of several shares."""
+    dev = cams.buf.device
+    A, B, I = (_empty(cams.npix, torch.float32, dev) for _ in range(3))
+    ov = torch.zeros(1, dtype=torch.int64, device=dev)
+    rc_merge_lists(cams, lists, A, B, I, ov)
+    return A, B, I, int(ov.item())
+
+
 def rc_segments_backward(forest: DeviceForest, index: DeviceIndex, fields: DeviceFields, cams: DeviceCameras,
                          vf: VForest, method: int, substeps: int, rec_leaf, rec_node, dLdI, adj_leaf, adj_node, dk,
                          de, accumulate: bool, ws, tuning: Optional[L.RcTuning] = None, c_rk: float = 0.0):
@@ -322,6 +354,30 @@ class Renderer:
     def composite(self):
         rc_composite(self.forest, self.index, self.cams, self.vf, self.rec_leaf, self.rec_node, self.A, self.B,
                      self.I, self.tuning)
+
+    def composite_lists(self):
+        """This share's per-pixel lists after prune and segments: offsets [P + 1]
+        (int64) and entries [m, 4] (s_in, s_out, A, B; float32).  The entry buffer
+        grows to the count on first use (one host read-back)."""
+        P = self.cams.npix
+        if getattr(self, "list_offset", None) is None:
+            self.lists_ws = _empty(lists_workspace_bytes(self.index, self.cams.ncams, P), torch.uint8, self.device)
+            self.list_offset = _empty(P + 1, torch.int64, self.device)
+            self.n_entries = _empty(1, torch.int64, self.device)
+            self.entries = None
+        for _ in range(2):
+            rc_composite_lists(self.forest, self.index, self.cams, self.vf, self.rec_leaf, self.rec_node,
+                               self.list_offset, self.entries, self.n_entries, self.lists_ws, self.tuning)
+            n = int(self.n_entries.item())
+            if self.entries is not None and n <= self.entries.numel() // 4:
+                return self.list_offset, self.entries[:4 * n].view(n, 4)
+            self.entries = _empty(4 * max(n, 1), torch.float32, self.device)
+        raise RuntimeError("list entry count changed between two identical passes")
+
+    def forward_lists(self):
+        self.prune()
+        self.segments()
+        return self.composite_lists()
 
     def forward(self):
         self.prune()
