@@ -109,6 +109,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-shell", action="store_true")
     ap.add_argument("--no-integrators", action="store_true")
+    ap.add_argument("--no-shares", action="store_true")
     ap.add_argument("--copy-calib", action="store_true",
                     help="end with plain 256 MiB device copies, the reference for HBM byte counters")
     args = ap.parse_args()
@@ -222,6 +223,8 @@ def main():
         out["batched_workload"] = bench_batched(torch, P, synth, r, max(args.steps // 10, 3))
     if not args.no_shell:
         out["shell_workload"] = bench_shell(torch, P, synth, max(args.steps // 10, 3))
+    if not args.no_shares:
+        out["shares"] = bench_shares(torch, P, synth, scene, r, max(args.steps // 5, 3))
 
     if args.copy_calib:
         # a plain copy of known size: 256 MiB read + 256 MiB written per launch
@@ -357,6 +360,45 @@ def bench_shell(torch, P, synth, steps):
     del r
     torch.cuda.empty_cache()
     return out
+
+
+def bench_shares(torch, P, synth, scene, r, steps, nshares=8):
+    """The headline workload cut into equal curve-order leaf ranges, one per
+    process share (Sec. 3.3): each share's per-pixel lists of its maximal
+    complete subtrees, then the merge of all lists into the image (Sec. 3.5)."""
+    N = scene.forest.nleaves
+    cuts = [N * k // nshares for k in range(1, nshares)]
+    shares = []
+    for f, fl in synth.split_shares(scene.forest, scene.fields, cuts):
+        rs = P.Renderer(f, fl, r.cams.raw, "rk4", 4, device="cuda:0")
+        rs.forward_lists()
+        shares.append(rs)
+    lists = [(rs.list_offset, rs.entries) for rs in shares]
+    npix = r.cams.npix
+    A, B, I = (torch.empty(npix, device="cuda:0") for _ in range(3))
+    ov = torch.zeros(1, dtype=torch.int64, device="cuda:0")
+    P.rc_merge_lists(r.cams, lists, A, B, I, ov)
+    torch.cuda.synchronize()
+    n_ent = [int(rs.n_entries.item()) for rs in shares]
+    diff = float((I - r.I).abs().max().item())
+    t_lists = [time_region(torch, rs.lists_step, steps) for rs in shares]
+    t_fwd = [time_region(torch, rs.forward_lists_enqueue, steps) for rs in shares]
+    t_merge = time_region(torch, lambda: P.rc_merge_lists(r.cams, lists, A, B, I, None), steps)
+    E = sum(n_ent)
+    # lists: every leaf record read (8 B), every entry written (16 B), one offset per pixel
+    lb = sum(rs.counts["ncand"] for rs in shares) * REC_BYTES + E * 16 + nshares * (npix + 1) * 8
+    # merge: every entry read, every list's offsets read, A, B, I written
+    mb = E * 16 + nshares * (npix + 1) * 8 + npix * PIX_BYTES
+    log(f"[bench] {nshares} shares: {E} entries, overlaps {int(ov.item())}, max |I - I_full| {diff:.2e}; "
+        f"lists {sum(t_lists):.3f} ms, share forwards {sum(t_fwd):.3f} ms, merge {t_merge:.3f} ms")
+    return {"workload": f"headline workload cut into {nshares} equal curve-order leaf ranges",
+            "shares": nshares, "entries": E, "entries_per_share": n_ent, "overlaps": int(ov.item()),
+            "max_abs_diff_vs_full_render": diff,
+            "lists_ms": t_lists, "share_forward_ms": t_fwd, "merge_ms": t_merge,
+            "lists": {"bound": "hbm", "algorithmic_bytes": lb, "achieved_GBs": lb / (sum(t_lists) * 1e-3) / 1e9,
+                      "frac": lb / (sum(t_lists) * 1e-3) / 1e9 / HBM_PEAK_GBS},
+            "merge": {"bound": "hbm", "algorithmic_bytes": mb, "achieved_GBs": mb / (t_merge * 1e-3) / 1e9,
+                      "frac": mb / (t_merge * 1e-3) / 1e9 / HBM_PEAK_GBS}}
 
 
 if __name__ == "__main__":

@@ -374,10 +374,21 @@ class Renderer:
             self.entries = _empty(4 * max(n, 1), torch.float32, self.device)
         raise RuntimeError("list entry count changed between two identical passes")
 
+    def lists_step(self):
+        """Enqueue rc_composite_lists into the buffers sized by composite_lists()."""
+        rc_composite_lists(self.forest, self.index, self.cams, self.vf, self.rec_leaf, self.rec_node,
+                           self.list_offset, self.entries, self.n_entries, self.lists_ws, self.tuning)
+
     def forward_lists(self):
         self.prune()
         self.segments()
         return self.composite_lists()
+
+    def forward_lists_enqueue(self):
+        """prune, segments and lists into the buffers sized by composite_lists(), with no host read."""
+        self.prune()
+        self.segments()
+        self.lists_step()
 
     def forward(self):
         self.prune()
