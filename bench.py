@@ -384,17 +384,39 @@ def bench_shares(torch, P, synth, scene, r, steps, nshares=8):
     t_lists = [time_region(torch, rs.lists_step, steps) for rs in shares]
     t_fwd = [time_region(torch, rs.forward_lists_enqueue, steps) for rs in shares]
     t_merge = time_region(torch, lambda: P.rc_merge_lists(r.cams, lists, A, B, I, None), steps)
+
+    def step():
+        for rs in shares:
+            rs.forward_lists_enqueue()
+        P.rc_merge_lists(r.cams, lists, A, B, I, None)
+
+    # the whole share pipeline (every share's prune, segments and lists, then the merge) as one HIP graph
+    cur = torch.cuda.current_stream()
+    s = torch.cuda.Stream()
+    s.wait_stream(cur)
+    with torch.cuda.stream(s):
+        for _ in range(2):
+            step()
+    cur.wait_stream(s)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step()
+    g.replay()
+    t_graph = time_region(torch, g.replay, steps)
+    diff_graph = float((I - r.I).abs().max().item())
     E = sum(n_ent)
     # lists: every leaf record read (8 B), every entry written (16 B), one offset per pixel
     lb = sum(rs.counts["ncand"] for rs in shares) * REC_BYTES + E * 16 + nshares * (npix + 1) * 8
     # merge: every entry read, every list's offsets read, A, B, I written
     mb = E * 16 + nshares * (npix + 1) * 8 + npix * PIX_BYTES
     log(f"[bench] {nshares} shares: {E} entries, overlaps {int(ov.item())}, max |I - I_full| {diff:.2e}; "
-        f"lists {sum(t_lists):.3f} ms, share forwards {sum(t_fwd):.3f} ms, merge {t_merge:.3f} ms")
+        f"lists {sum(t_lists):.3f} ms, share forwards {sum(t_fwd):.3f} ms, merge {t_merge:.3f} ms; "
+        f"all shares + merge in one graph {t_graph:.3f} ms (max |I - I_full| {diff_graph:.2e})")
     return {"workload": f"headline workload cut into {nshares} equal curve-order leaf ranges",
             "shares": nshares, "entries": E, "entries_per_share": n_ent, "overlaps": int(ov.item()),
             "max_abs_diff_vs_full_render": diff,
-            "lists_ms": t_lists, "share_forward_ms": t_fwd, "merge_ms": t_merge,
+            "lists_ms": t_lists, "share_forward_ms": t_fwd, "merge_ms": t_merge, "pipeline_graph_ms": t_graph,
+            "pipeline_graph_max_abs_diff": diff_graph,
             "lists": {"bound": "hbm", "algorithmic_bytes": lb, "achieved_GBs": lb / (sum(t_lists) * 1e-3) / 1e9,
                       "frac": lb / (sum(t_lists) * 1e-3) / 1e9 / HBM_PEAK_GBS},
             "merge": {"bound": "hbm", "algorithmic_bytes": mb, "achieved_GBs": mb / (t_merge * 1e-3) / 1e9,

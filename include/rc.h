@@ -278,8 +278,9 @@ rc_status rc_composite(const rc_forest *forest, const rc_index *index, const voi
  * One share's image as per-pixel lists (Sec. 3.3 coarsening stopped at the
  * share's maximal complete subtrees, Sec. 3.5 per-pixel segment lists).  The
  * forest is a share: a contiguous curve-order range of a larger forest's
- * leaves, indexed on its own (missing children are RC_ABSENT).  A node is
- * complete when all eight children are leaves or complete nodes; the units
+ * leaves that tile the curve interval from the first leaf's anchor to the end
+ * of the last leaf, indexed on its own (missing children are RC_ABSENT).  A
+ * node is complete when its curve interval lies inside the share's; the units
  * are the leaves and complete nodes under an incomplete parent, and the root
  * when it is complete.  For every pixel whose ray crosses a unit's box, one
  * entry (s_in, s_out, A, B) [4 floats]: the canonical slab interval of the

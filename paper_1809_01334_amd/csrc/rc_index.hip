@@ -8,16 +8,6 @@
 namespace rc {
 namespace {
 
-__device__ inline uint64_t morton(uint32_t x, uint32_t y, uint32_t z) {
-    uint64_t k = 0;
-    for (int b = 0; b < QMAX; b++) {
-        k |= (uint64_t)((x >> b) & 1u) << (3 * b);
-        k |= (uint64_t)((y >> b) & 1u) << (3 * b + 1);
-        k |= (uint64_t)((z >> b) & 1u) << (3 * b + 2);
-    }
-    return k;
-}
-
 // Tree of leaf i from the tree offsets.
 __device__ inline int tree_of(const int64_t* tb, int ntrees, int64_t i) {
     int k = 0;

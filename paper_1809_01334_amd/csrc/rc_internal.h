@@ -77,6 +77,20 @@ __device__ inline void store_rect(int16_t* r4, const Rect& r) {
     *reinterpret_cast<uint64_t*>(r4) = bits;
 }
 
+// Position of a node's anchor on the space-filling curve (Morton order, x in
+// the lowest bit of every triple), and the curve length a level-l node spans.
+__device__ inline uint64_t morton(uint32_t x, uint32_t y, uint32_t z) {
+    uint64_t k = 0;
+    for (int b = 0; b < QMAX; b++) {
+        k |= (uint64_t)((x >> b) & 1u) << (3 * b);
+        k |= (uint64_t)((y >> b) & 1u) << (3 * b + 1);
+        k |= (uint64_t)((z >> b) & 1u) << (3 * b + 2);
+    }
+    return k;
+}
+
+__device__ inline uint64_t curve_span(int level) { return (uint64_t)1 << (3 * (QMAX - level)); }
+
 // Box of a node in the unit cube: exact dyadic values.
 __device__ inline void node_box(int level, uint32_t x, uint32_t y, uint32_t z, double lo[3], double hi[3]) {
     uint32_t len = 1u << (QMAX - level);

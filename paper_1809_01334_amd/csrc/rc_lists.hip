@@ -15,16 +15,19 @@
 namespace rc {
 namespace {
 
-// complete[m]: every child slot of node m holds a leaf or a complete node.
-__global__ __launch_bounds__(256) void k_complete(const int32_t* child, int64_t m0, int64_t m1, uint8_t* complete) {
+// complete[m]: the curve interval of node m lies inside the share's, from its
+// first leaf's anchor to the end of its last leaf; the share's leaves tile that
+// interval, so m's leaves are all in the share.
+__global__ __launch_bounds__(256) void k_complete(const uint8_t* nlevel, const uint32_t* nx, const uint32_t* ny,
+                                                  const uint32_t* nz, int64_t nint, const uint8_t* level,
+                                                  const uint32_t* x, const uint32_t* y, const uint32_t* z, int64_t N,
+                                                  uint8_t* complete) {
+    uint64_t S = morton(x[0], y[0], z[0]);
+    uint64_t E = morton(x[N - 1], y[N - 1], z[N - 1]) + curve_span(level[N - 1]);
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t m = m0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < m1; m += stride) {
-        bool ok = true;
-        for (int c = 0; c < 8; c++) {
-            int32_t ref = child[m * 8 + c];
-            if (ref == RC_ABSENT || (ref >= 0 && !complete[ref])) ok = false;
-        }
-        complete[m] = ok ? 1 : 0;
+    for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < nint; m += stride) {
+        uint64_t k0 = morton(nx[m], ny[m], nz[m]);
+        complete[m] = (k0 >= S && k0 + curve_span(nlevel[m]) <= E) ? 1 : 0;
     }
 }
 
@@ -184,7 +187,6 @@ struct PassArgs {
     const int64_t* uoff;
     const int16_t* stash;
     int32_t* cnt;
-    int32_t* cursor;
     const int64_t* loff;
     float4* entries;
     int64_t cap;
@@ -220,7 +222,7 @@ __global__ __launch_bounds__(256) void k_unit_pixels(PassArgs P) {
             atomicAdd(&P.cnt[pg], 1);
             continue;
         }
-        int pos = atomicAdd(&P.cursor[pg], 1);
+        int pos = atomicSub(&P.cnt[pg], 1) - 1;  // the count pass left cnt[pg] slots
         int64_t e = P.loff[pg] + pos;
         if (e >= P.cap) continue;
         float2 ab;
@@ -395,7 +397,7 @@ using namespace rc;
 namespace {
 
 struct ListsLayout {
-    size_t complete, uoff, stash, cnt, cursor, partial, total;
+    size_t complete, uoff, stash, cnt, partial, total;
 };
 
 ListsLayout lists_layout(const rc_index* ix, int32_t ncams, int64_t npix) {
@@ -409,8 +411,6 @@ ListsLayout lists_layout(const rc_index* ix, int32_t ncams, int64_t npix) {
     L.stash = o;
     o += align_up((size_t)nitems * 8);
     L.cnt = o;
-    o += align_up((size_t)npix * 4);
-    L.cursor = o;
     o += align_up((size_t)npix * 4);
     L.partial = o;
     size_t p1 = scan_partial_bytes(nitems, 8), p2 = scan_partial_bytes(npix, 8);
@@ -452,14 +452,11 @@ extern "C" rc_status rc_composite_lists(const rc_forest* f, const rc_index* ix, 
     int64_t* uoff = (int64_t*)(w + WL.uoff);
     int16_t* stash = (int16_t*)(w + WL.stash);
     int32_t* cnt = (int32_t*)(w + WL.cnt);
-    int32_t* cursor = (int32_t*)(w + WL.cursor);
     void* partial = (void*)(w + WL.partial);
 
-    for (int l = ix->maxlevel - 1; l >= 0; l--) {
-        int64_t m0 = ix->level_begin[l], m1 = ix->level_begin[l + 1];
-        if (m1 == m0) continue;
-        hipLaunchKernelGGL(k_complete, dim3(stride_grid(m1 - m0, 256, 4096)), dim3(256), 0, st, ix->child, m0, m1,
-                           complete);
+    if (ix->ninternal > 0) {
+        hipLaunchKernelGGL(k_complete, dim3(stride_grid(ix->ninternal, 256, 4096)), dim3(256), 0, st, ix->level,
+                           ix->x, ix->y, ix->z, ix->ninternal, f->level, f->x, f->y, f->z, f->nleaves, complete);
         RC_HIP(hipGetLastError());
     }
     UnitArgs ua;
@@ -489,9 +486,8 @@ extern "C" rc_status rc_composite_lists(const rc_forest* f, const rc_index* ix, 
                                  (int64_t*)partial, st));
     int64_t ng = (int64_t)npix;
     hipLaunchKernelGGL(k_zero_i32, dim3(stride_grid(ng, 256, 4096)), dim3(256), 0, st, ng, cnt);
-    hipLaunchKernelGGL(k_zero_i32, dim3(stride_grid(ng, 256, 4096)), dim3(256), 0, st, ng, cursor);
     RC_HIP(hipGetLastError());
-    PassArgs P{ua, C, nitems, uoff, stash, cnt, cursor, list_offset, (float4*)entries, cap_entries};
+    PassArgs P{ua, C, nitems, uoff, stash, cnt, list_offset, (float4*)entries, cap_entries};
     unsigned grid = stride_grid(vf->cap_cand + npix, 256, tuned(tune, 0, 256 * 8));
     hipLaunchKernelGGL((k_unit_pixels<false>), dim3(grid), dim3(256), 0, st, P);
     RC_HIP(hipGetLastError());
