@@ -70,6 +70,8 @@ def lib():
         L.or_merge_pixel.argtypes = [I64, P, P]
         L.or_merge_sorted.restype = I64
         L.or_merge_sorted.argtypes = [I64, P, P, P]
+        L.or_surface_render.restype = I32
+        L.or_surface_render.argtypes = [I64, I32, P, P, P, P, P, P, P, P, I64, P, P, P, P, P, P]
         L.or_shell_map.argtypes = [P, I32, P, P]
         L.or_shell_inverse.argtypes = [P, I32, P, P]
         for nm in ("or_combine", "or_average"):
@@ -324,6 +326,40 @@ def merge_lists(lists, P_, background=0.0):
     ov = lib().or_merge_sorted(P_, _p(off), _p(ent), _p(ab))
     A, B = ab[:, 0], ab[:, 1]
     return {"A": A, "B": B, "I": A * background + B, "overlaps": int(ov)}
+
+
+def _surface(forest):
+    return getattr(forest, "geom", "unit_cube") == "surface"
+
+
+def surface_render(forest, fields, cam, pixels=None, hits=False):
+    """FP64 oracle image of a surface forest (bilinear tree patches, Sec. 2.8 surface
+    model).  fields.kappa / fields.eps hold the corner transparency A_s and intensity I_s
+    ([4][N]).  hits=True adds hit_leaf / hit_s [npix][2 ntrees] (depth order, leaf -1 after
+    the last hit)."""
+    raw = cam.raw() if hasattr(cam, "raw") else np.asarray(cam, np.float64)
+    lv, x, y, _ = _forest_args(forest)
+    As = _c(fields.kappa, np.float64)
+    Is = _c(fields.eps, np.float64)
+    assert As.shape == (4, forest.nleaves) and Is.shape == (4, forest.nleaves)
+    W, H = int(raw[14]), int(raw[15])
+    if pixels is None:
+        npo, pix, nsel = W * H, None, -1
+    else:
+        pix = _c(pixels, np.int64)
+        npo = nsel = pix.shape[0]
+    A, B, I = np.zeros(npo), np.zeros(npo), np.zeros(npo)
+    nh = 2 * forest.ntrees
+    hl = np.zeros((npo, nh), np.int32) if hits else None
+    hs = np.zeros((npo, nh)) if hits else None
+    lib().or_surface_render(forest.nleaves, forest.ntrees, _p(_c(forest.tree_begin, np.int64)),
+                            _p(_c(forest.geom_params, np.float64)), _p(lv), _p(x), _p(y), _p(As), _p(Is),
+                            _p(_c(raw, np.float64)), nsel, _p(pix), _p(A), _p(B), _p(I), _p(hl), _p(hs))
+    out = {"A": A, "B": B, "I": I}
+    if hits:
+        out["hit_leaf"] = hl
+        out["hit_s"] = hs
+    return out
 
 
 def march(forest, fields, cam, M=1024):

@@ -1682,3 +1682,219 @@ int or_shell_march(int64_t n, int ntrees, const int64_t *tree_begin, const doubl
     }
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* surfaces: quadtree leaves on bilinear tree patches                       */
+/* (Sec. 2.8 thin and opaque surfaces, eq. ABphi; App. A.1 ray against a    */
+/* tensor-product surface, the bilinear case by a quadratic)                */
+/* ------------------------------------------------------------------------ */
+
+/* Tree k's patch J(t1, t2) = a + b t1 + c t2 + d t1 t2 from its corners
+ * P00, P10, P01, P11 (12 doubles per tree: corner q at t = (q & 1, q >> 1)). */
+typedef struct {
+    double a[3], b[3], c[3], d[3];
+} orpatch;
+
+static orpatch patch_of(const double *P)
+{
+    orpatch S;
+    for (int k = 0; k < 3; k++) {
+        S.a[k] = P[k];
+        S.b[k] = P[3 + k] - P[k];
+        S.c[k] = P[6 + k] - P[k];
+        S.d[k] = (P[9 + k] - P[3 + k]) - (P[6 + k] - P[k]);
+    }
+    return S;
+}
+
+static double dot3(const double *u, const double *w) { return (u[0] * w[0] + u[1] * w[1]) + u[2] * w[2]; }
+
+static void cross3(const double *u, const double *w, double *o)
+{
+    o[0] = u[1] * w[2] - u[2] * w[1];
+    o[1] = u[2] * w[0] - u[0] * w[2];
+    o[2] = u[0] * w[1] - u[1] * w[0];
+}
+
+/* Hits of the ray rho + s r with the patch for (t1, t2) in [0, 1]^2 and s in
+ * the clip range, nearest first (at most two).  App. A.1: with d1, d2 normal
+ * to r, the two projections d_j . (J(t1, t2) - rho) = 0 are bilinear in
+ * (t1, t2); eliminating t1 leaves a quadratic in t2, and t1 follows from the
+ * projection with the larger coefficient of t1.  d1 = r x e_k for the axis k
+ * of smallest |r_k|, d2 = r x d1.  A double root counts once. */
+static int surface_hits(const orcam *cm, const orpatch *S, const double *rho, const double *r, double *hs,
+                        double *ht1, double *ht2)
+{
+    int k = 0;
+    if (fabs(r[1]) < fabs(r[k])) k = 1;
+    if (fabs(r[2]) < fabs(r[k])) k = 2;
+    double ek[3] = {0.0, 0.0, 0.0}, d1[3], d2[3], e[3];
+    ek[k] = 1.0;
+    cross3(r, ek, d1);
+    cross3(r, d1, d2);
+    for (int q = 0; q < 3; q++) e[q] = S->a[q] - rho[q];
+    double A1 = dot3(d1, S->d), B1 = dot3(d1, S->b), C1 = dot3(d1, S->c), D1 = dot3(d1, e);
+    double A2 = dot3(d2, S->d), B2 = dot3(d2, S->b), C2 = dot3(d2, S->c), D2 = dot3(d2, e);
+    /* (A_j t2 + B_j) t1 + (C_j t2 + D_j) = 0 for j = 1, 2; the determinant in t1 vanishes */
+    double qa = A1 * C2 - A2 * C1;
+    double qb = (A1 * D2 - A2 * D1) + (B1 * C2 - B2 * C1);
+    double qc = B1 * D2 - B2 * D1;
+    double roots[2];
+    int nr = 0;
+    if (qa == 0.0) {
+        if (qb != 0.0) roots[nr++] = -qc / qb;
+    } else {
+        double disc = qb * qb - (4.0 * qa) * qc;
+        if (disc == 0.0) {
+            roots[nr++] = -qb / (2.0 * qa);
+        } else if (disc > 0.0) {
+            double sq = sqrt(disc);
+            double q = -0.5 * (qb + (qb >= 0.0 ? sq : -sq));
+            roots[nr++] = q / qa;
+            roots[nr++] = qc / q;
+        }
+    }
+    double rr = dot3(r, r);
+    int nh = 0;
+    for (int m = 0; m < nr; m++) {
+        double t2 = roots[m];
+        double den1 = A1 * t2 + B1, den2 = A2 * t2 + B2, t1;
+        if (fabs(den1) >= fabs(den2)) {
+            if (den1 == 0.0) continue;
+            t1 = -(C1 * t2 + D1) / den1;
+        } else {
+            t1 = -(C2 * t2 + D2) / den2;
+        }
+        if (!(t1 >= 0.0 && t1 <= 1.0 && t2 >= 0.0 && t2 <= 1.0)) continue;
+        double pr[3];
+        for (int q = 0; q < 3; q++) pr[q] = (((S->a[q] + S->b[q] * t1) + S->c[q] * t2) + S->d[q] * (t1 * t2)) - rho[q];
+        double s = dot3(pr, r) / rr;
+        if (!(s >= cm->smin && s <= cm->smax)) continue;
+        hs[nh] = s;
+        ht1[nh] = t1;
+        ht2[nh] = t2;
+        nh++;
+    }
+    if (nh == 2 && hs[1] < hs[0]) {
+        double t;
+        t = hs[0]; hs[0] = hs[1]; hs[1] = t;
+        t = ht1[0]; ht1[0] = ht1[1]; ht1[1] = t;
+        t = ht2[0]; ht2[0] = ht2[1]; ht2[1] = t;
+    }
+    return nh;
+}
+
+/* The leaf of tree [b, e) whose square holds (t1, t2): half-open squares on
+ * the finest grid, the tree's far edges closed.  -1 where no leaf covers it. */
+static int64_t surface_leaf(const uint8_t *level, const uint32_t *x, const uint32_t *y, int64_t b, int64_t e,
+                            double t1, double t2)
+{
+    double X = t1 * (double)(1u << OR_QMAX), Y = t2 * (double)(1u << OR_QMAX);
+    uint32_t top = (1u << OR_QMAX) - 1u;
+    uint32_t ix = X >= (double)top ? top : (uint32_t)X, iy = Y >= (double)top ? top : (uint32_t)Y;
+    uint64_t kp = key_of(ix, iy, 0);
+    int64_t lo = b, hi = e; /* last leaf with key <= kp */
+    if (b >= e || key_of(x[b], y[b], 0) > kp) return -1;
+    while (hi - lo > 1) {
+        int64_t mid = (lo + hi) / 2;
+        if (key_of(x[mid], y[mid], 0) <= kp)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    uint64_t span = (uint64_t)1 << (3 * (OR_QMAX - level[lo]));
+    return kp < key_of(x[lo], y[lo], 0) + span ? lo : -1;
+}
+
+/* Surface model at a hit (Sec. 2.8, eq. ABphi with eq. BIrelation): the
+ * transparency A_s and intensity I_s interpolated bilinearly from the leaf's
+ * corners at its local coordinates, A = A_s^(1 / cos phi) with phi the angle
+ * between the ray and the patch normal, B = I_s (1 - A). */
+static void surface_value(int64_t n, int64_t leaf, const uint8_t *level, const uint32_t *x, const uint32_t *y,
+                          const double *As, const double *Is, const orpatch *S, const double *r, double t1, double t2,
+                          double *A, double *B)
+{
+    double len = (double)(1u << (OR_QMAX - level[leaf]));
+    double u = (t1 * (double)(1u << OR_QMAX) - (double)x[leaf]) / len;
+    double v = (t2 * (double)(1u << OR_QMAX) - (double)y[leaf]) / len;
+    double w[4] = {(1.0 - u) * (1.0 - v), u * (1.0 - v), (1.0 - u) * v, u * v};
+    double as = 0.0, is = 0.0;
+    for (int q = 0; q < 4; q++) {
+        as += w[q] * As[(int64_t)q * n + leaf];
+        is += w[q] * Is[(int64_t)q * n + leaf];
+    }
+    double j1[3], j2[3], nr[3];
+    for (int q = 0; q < 3; q++) {
+        j1[q] = S->b[q] + S->d[q] * t2;
+        j2[q] = S->c[q] + S->d[q] * t1;
+    }
+    cross3(j1, j2, nr);
+    double cosphi = fabs(dot3(nr, r)) / sqrt(dot3(nr, nr) * dot3(r, r));
+    *A = pow(as, 1.0 / cosphi);
+    *B = is * (1.0 - *A);
+}
+
+/* Render a surface forest: per pixel, every tree's hits, each given to the
+ * leaf whose square holds it, folded front to back with the background.
+ * As, Is: [4][n] corner values.  nsel >= 0: only the pixels pix[0..nsel).
+ * hit_leaf, hit_s (optional, [npix][2 * ntrees]): the hits in depth order,
+ * leaf -1 past the last. */
+int or_surface_render(int64_t n, int ntrees, const int64_t *tree_begin, const double *corners, const uint8_t *level,
+                      const uint32_t *x, const uint32_t *y, const double *As, const double *Is, const double *cam,
+                      int64_t nsel, const int64_t *pix, double *Aout, double *Bout, double *Iout, int32_t *hit_leaf,
+                      double *hit_s)
+{
+    orcam c;
+    cam_parse(cam, &c);
+    int64_t P = nsel >= 0 ? nsel : (int64_t)c.w * c.h;
+    int H = 2 * ntrees;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t q = 0; q < P; q++) {
+        int64_t p = nsel >= 0 ? pix[q] : q;
+        int i = (int)(p % c.w), j = (int)(p / c.w);
+        double rho[3], r[3];
+        pixel_ray(&c, i, j, rho, r);
+        double hs[2 * 64], hA[2 * 64], hB[2 * 64];
+        int64_t hl[2 * 64];
+        int nh = 0;
+        for (int k = 0; k < ntrees; k++) {
+            orpatch S = patch_of(corners + 12 * k);
+            double s[2], t1[2], t2[2];
+            int m = surface_hits(&c, &S, rho, r, s, t1, t2);
+            for (int a = 0; a < m; a++) {
+                int64_t leaf = surface_leaf(level, x, y, tree_begin[k], tree_begin[k + 1], t1[a], t2[a]);
+                if (leaf < 0) continue;
+                surface_value(n, leaf, level, x, y, As, Is, &S, r, t1[a], t2[a], &hA[nh], &hB[nh]);
+                hs[nh] = s[a];
+                hl[nh] = leaf;
+                /* insertion in depth order; equal depths keep tree order */
+                for (int b = nh; b > 0 && hs[b] < hs[b - 1]; b--) {
+                    double t;
+                    int64_t tl;
+                    t = hs[b]; hs[b] = hs[b - 1]; hs[b - 1] = t;
+                    t = hA[b]; hA[b] = hA[b - 1]; hA[b - 1] = t;
+                    t = hB[b]; hB[b] = hB[b - 1]; hB[b - 1] = t;
+                    tl = hl[b]; hl[b] = hl[b - 1]; hl[b - 1] = tl;
+                }
+                nh++;
+            }
+        }
+        double acc[2] = {1.0, 0.0}, t[2];
+        for (int b = 0; b < nh; b++) {
+            double sg[2] = {hA[b], hB[b]};
+            or_combine(acc, sg, t);
+            acc[0] = t[0];
+            acc[1] = t[1];
+        }
+        Aout[q] = acc[0];
+        Bout[q] = acc[1];
+        Iout[q] = acc[0] * c.bg + acc[1];
+        if (hit_leaf) {
+            for (int b = 0; b < H; b++) {
+                hit_leaf[q * H + b] = b < nh ? (int32_t)hl[b] : -1;
+                hit_s[q * H + b] = b < nh ? hs[b] : 0.0;
+            }
+        }
+    }
+    return 0;
+}

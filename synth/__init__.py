@@ -34,3 +34,15 @@ from .scene import (  # noqa: F401
     equilibrium_fields,
     split_shares,
 )
+from .surface import (  # noqa: F401
+    hexagon_cameras,
+    hexagon_corners,
+    leaf_corner_points,
+    mandelbrot_count,
+    mandelbrot_fields,
+    mandelbrot_forest,
+    patch_point,
+    random_quadtree_forest,
+    random_surface_fields,
+    surface_forest,
+)
