@@ -36,6 +36,11 @@ FP32_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 SEG_FLOPS_FP32 = 480
 CAND_FLOPS_FP64 = 20
 SHELL_SEG_FLOPS_FP64 = 3500
+#   surface candidate: pixel ray ~12, two directions normal to the ray ~18,
+#   eight projections ~40, the quadratic ~20 and per root the other parameter,
+#   the point and its depth ~35 -> ~160 FP64 flop per candidate (plus ~30 FP32
+#   and two transcendentals per hit for the surface model)
+SURF_CAND_FLOPS_FP64 = 160
 #   compositing: every leaf record read once (8 B; shell 2 x 16 B + 1 B) and
 #   A, B, I written (12 B per pixel);  visibility: 13 B read per leaf and
 #   about 20 B written per visible pair.
@@ -110,6 +115,7 @@ def main():
     ap.add_argument("--no-shell", action="store_true")
     ap.add_argument("--no-integrators", action="store_true")
     ap.add_argument("--no-shares", action="store_true")
+    ap.add_argument("--no-surface", action="store_true")
     ap.add_argument("--copy-calib", action="store_true",
                     help="end with plain 256 MiB device copies, the reference for HBM byte counters")
     args = ap.parse_args()
@@ -223,6 +229,8 @@ def main():
         out["batched_workload"] = bench_batched(torch, P, synth, r, max(args.steps // 10, 3))
     if not args.no_shell:
         out["shell_workload"] = bench_shell(torch, P, synth, max(args.steps // 10, 3))
+    if not args.no_surface:
+        out["surface_workload"] = bench_surface(torch, P, synth, max(args.steps // 5, 3))
     if not args.no_shares:
         out["shares"] = bench_shares(torch, P, synth, scene, r, max(args.steps // 5, 3))
 
@@ -358,6 +366,48 @@ def bench_shell(torch, P, synth, steps):
     out["composite"] = {"bound": "hbm", "algorithmic_bytes": cb, "achieved_GBs": cb / (t_comp * 1e-3) / 1e9,
                         "frac": cb / (t_comp * 1e-3) / 1e9 / HBM_PEAK_GBS}
     del r
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_surface(torch, P, synth, steps):
+    """Mandelbrot surface (Sec. 4.1): two quadtrees on the hexagon, levels 4-11
+    refined where corner iteration counts differ; the two image instances
+    (opaque grey-to-white, transparent near-maximum highlight) at 1024^2, each
+    its own camera and transfer function."""
+    log("[bench] surface workload: generating")
+    f, val = synth.mandelbrot_forest(4, 11)
+    cams = synth.hexagon_cameras(1024, 1024)
+    out = {"workload": f"Mandelbrot surface on the hexagon, two quadtrees, levels 4-11 ({f.nleaves} leaves), "
+                       f"two 1024x1024 instances (opaque / transparent transfer)", "leaves": f.nleaves,
+           "instances": []}
+    index = None
+    for inst in (0, 1):
+        r = P.Renderer(f, synth.mandelbrot_fields(val, inst), [cams[inst]], "analytic", 1, device="cuda:0",
+                       index=index)
+        index = r.index
+        c = r.counts
+        hit, _ = r.debug_segments(intervals=False)
+        H = int(hit[:c["ncand"]].to(torch.int64).sum().item())
+        r.forward()
+        r.capture()
+        r.replay()
+        ms = time_region(torch, r.replay, steps)
+        t_prune = time_region(torch, r.prune, steps)
+        t_seg = time_region(torch, r.segments, steps)
+        t_comp = time_region(torch, r.composite, steps)
+        flops = SURF_CAND_FLOPS_FP64 * c["ncand"]
+        ach = flops / (t_seg * 1e-3) / 1e12
+        log(f"[bench] surface instance {inst}: visible {c['nvis']}, candidates {c['ncand']}, hits {H}; forward "
+            f"{ms:.3f} ms; prune {t_prune:.3f}, segments {t_seg:.3f}, composite {t_comp:.3f} ms")
+        out["instances"].append({
+            "visible": c["nvis"], "candidates": c["ncand"], "hits": H, "ms_per_step": ms,
+            "hits_per_s": H / (ms * 1e-3), "images_per_s": 1e3 / ms,
+            "phase_ms": {"prune": t_prune, "segments": t_seg, "composite": t_comp},
+            "roofline": {"bound": "alu", "kernel": "k_segments_surface", "achieved": ach,
+                         "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ach / FP32_PEAK_TFLOPS,
+                         "per_unit": f"{SURF_CAND_FLOPS_FP64} FP64 per candidate"}})
+        del r
     torch.cuda.empty_cache()
     return out
 

@@ -68,8 +68,8 @@ typedef int32_t rc_status;
 #define RC_MAXTREES 64
 #define RC_MAXLISTS 16     /* shares rc_merge_lists takes at once */
 
-enum { RC_GEOM_UNIT_CUBE = 0, RC_GEOM_SHELL6 = 1 };
-enum { RC_FIELD_CONST = 0, RC_FIELD_TRILINEAR = 1, RC_FIELD_CONST_EQ = 2 };
+enum { RC_GEOM_UNIT_CUBE = 0, RC_GEOM_SHELL6 = 1, RC_GEOM_SURFACE = 2 };
+enum { RC_FIELD_CONST = 0, RC_FIELD_TRILINEAR = 1, RC_FIELD_CONST_EQ = 2, RC_FIELD_SURFACE = 3 };
 enum { RC_INT_ANALYTIC = 0, RC_INT_RK4 = 1, RC_INT_GAUSS2 = 2, RC_INT_SIMPSON = 3 };
 #define RC_ADAPT_MAXDEPTH 16  /* deepest halving of the adaptive recursion */
 
@@ -83,26 +83,37 @@ enum { RC_INT_ANALYTIC = 0, RC_INT_RK4 = 1, RC_INT_GAUSS2 = 2, RC_INT_SIMPSON = 
  *   x = r (a e1 + b e2 + e3) / sqrt(1 + a^2 + b^2) with a = tan(pi/4 (2 t1 - 1)),
  *   b = tan(pi/4 (2 t2 - 1)), r = r0 + (r1 - r0) t3.  geom_table holds
  *   [r0, r1, L, tan(pi/4 (2 i / 2^L - 1)) for i = 0 .. 2^L] (entries 0, 2^(L-1),
- *   2^L exactly -1, 0, 1); leaves may not be finer than level L. */
+ *   2^L exactly -1, 0, 1); leaves may not be finer than level L.
+ * RC_GEOM_SURFACE: 1 .. 6 quadtrees, each placed in space by a bilinear map
+ *   J(t1, t2) = P00 (1-t1)(1-t2) + P10 t1 (1-t2) + P01 (1-t1) t2 + P11 t1 t2
+ *   (a surface, Sec. 2.8; the bilinear case of App. A.1).  Leaves have z = 0
+ *   and (x, y) anchors in the tree's parameter square.  geom_table holds 12
+ *   doubles per tree: P00, P10, P01, P11. */
 typedef struct rc_forest {
-    int32_t ntrees;             /* trees in the share: 1 (unit cube) or 6 (shell) */
-    int32_t geom;               /* RC_GEOM_UNIT_CUBE or RC_GEOM_SHELL6 */
+    int32_t ntrees;             /* trees in the share: 1 (unit cube), 6 (shell), 1 .. 6 (surface) */
+    int32_t geom;               /* RC_GEOM_UNIT_CUBE, RC_GEOM_SHELL6 or RC_GEOM_SURFACE */
     int64_t nleaves;            /* N >= 1 */
     const int64_t *tree_begin;  /* [host] ntrees + 1 leaf offsets per tree */
     const uint8_t *level;       /* [device] N leaf levels, 0 .. RC_QMAXLEVEL */
     const uint32_t *x, *y, *z;  /* [device] N anchors in units of 2^-19 */
-    const double *geom_table;   /* [device] geometry table (RC_GEOM_SHELL6), else NULL */
+    const double *geom_table;   /* [device] geometry table (RC_GEOM_SHELL6, RC_GEOM_SURFACE), else NULL */
 } rc_forest;
 
 /* Per-leaf coefficient data (Sec. 2.3): absorption kappa (beta in the paper)
  * and emission eps (gamma), single channel, leaf-major [leaf][corner] in SFC
  * order: one value per leaf for per-leaf constants, eight consecutive corner
  * values (corner c = bx + 2 by + 4 bz, 32-byte aligned rows) for trilinear
- * data interpolated in leaf reference coordinates. */
+ * data interpolated in leaf reference coordinates.  RC_FIELD_SURFACE (surface
+ * forests only, analytic method): kappa holds the surface's transparency A_s
+ * and eps its intensity I_s at the leaf's four corners (corner c = bx + 2 by),
+ * interpolated bilinearly at the hit; the hit contributes A = A_s^(1/cos phi),
+ * phi the angle between the ray and the patch normal, and B = I_s (1 - A)
+ * (eq. ABphi, eq. BIrelation; A_s = 0 is an opaque surface). */
 typedef struct rc_fields {
-    int32_t kind;               /* RC_FIELD_CONST, RC_FIELD_TRILINEAR or RC_FIELD_CONST_EQ (constant
+    int32_t kind;               /* RC_FIELD_CONST, RC_FIELD_TRILINEAR, RC_FIELD_CONST_EQ (constant
                                    kappa and equilibrium intensity I = eps / kappa in place of eps,
-                                   eq. BIrelation: B = I (1 - A); analytic integration only) */
+                                   eq. BIrelation: B = I (1 - A); analytic integration only) or
+                                   RC_FIELD_SURFACE */
     int32_t nch;                /* channels; 1 */
     const float *kappa;         /* [device] N * ncorner, 16-byte aligned */
     const float *eps;           /* [device] N * ncorner, 16-byte aligned */
@@ -243,11 +254,19 @@ rc_status rc_prune_visible(const rc_forest *forest, const rc_index *index, const
  * RC_GEOM_SHELL6 forests: a ray meets a curved element in up to two
  * intervals (bounded by two planes through the centre per tangent axis and
  * two spheres), so each candidate holds two records of four floats
- * (s_in, s_out, A, B), nearer first, an unused one (0, 0, 1, 0):
+ * (s_in, s_out, A, B), nearer first, an unused one (1, 0, 1, 0) (s_in > s_out):
  * rec_leaf[device, cap_cand * 8], hit[] the number of intervals (0..2) and
  * sio[device, cap_cand * 4] both intervals in FP64.  Field values at the RK4
  * points use the reference coordinates obtained by inverting the tree map
  * with Newton's method in FP64.
+ *
+ * RC_GEOM_SURFACE forests: the ray is intersected with the leaf's whole tree
+ * patch (App. A.1: projected onto two directions normal to the ray, the
+ * bilinear system leaves a quadratic in t2), and each hit inside the clip
+ * range belongs to the leaf whose half-open parameter square holds it, so a
+ * ray crossing shared leaf edges is counted once.  A candidate holds up to two
+ * zero-length records (s, s, A, B) in the layout of the shell, an unused one
+ * (1, 0, 1, 0); hit[] counts them and sio[] holds (s, s) per hit.
  */
 rc_status rc_segments(const rc_forest *forest, const rc_fields *fields, const void *dcams, int32_t ncams,
                       const rc_vforest *vf, const rc_integrator *integ, float *rec_leaf, uint8_t *hit,
@@ -268,7 +287,8 @@ rc_status rc_segments(const rc_forest *forest, const rc_fields *fields, const vo
  * RC_GEOM_SHELL6 forests: records hold two intervals as in rc_segments
  * (rec_node [device, cap_rec * 8]); a node's intervals are its children's
  * merged by depth, touching ones combined, and the six roots' intervals are
- * folded in depth order.
+ * folded in depth order.  RC_GEOM_SURFACE forests: the same with the hits as
+ * zero-length intervals (a tree's patch meets a ray at most twice).
  */
 rc_status rc_composite(const rc_forest *forest, const rc_index *index, const void *dcams, int32_t ncams,
                        const rc_vforest *vf, const float *rec_leaf, float *rec_node, int64_t total_pixels,
@@ -293,7 +313,7 @@ rc_status rc_composite(const rc_forest *forest, const rc_index *index, const voi
  * floats]; *n_entries [device] receives the total.  Entries are written only
  * when the total fits cap_entries (cap_entries = 0 asks for the count only);
  * the caller reads n_entries and calls again with more room otherwise.
- * ws [device, rc_lists_workspace_bytes()].  RC_GEOM_SHELL6: RC_EUNSUPPORTED.
+ * ws [device, rc_lists_workspace_bytes()].  RC_GEOM_SHELL6 and RC_GEOM_SURFACE: RC_EUNSUPPORTED.
  */
 size_t rc_lists_workspace_bytes(const rc_index *index, int32_t ncams, int64_t total_pixels);
 rc_status rc_composite_lists(const rc_forest *forest, const rc_index *index, const void *dcams, int32_t ncams,
@@ -332,7 +352,7 @@ rc_status rc_merge_lists(const void *dcams, int32_t ncams, int64_t total_pixels,
  * fixed order.  dL_dkappa, dL_deps [device, layout of rc_fields] are
  * overwritten, or added to when accumulate != 0.  adj_leaf [device,
  * cap_cand * 2] and adj_node [device, cap_rec * 2] are scratch.
- * RC_GEOM_SHELL6 forests return RC_EUNSUPPORTED.
+ * RC_GEOM_SHELL6 and RC_GEOM_SURFACE forests return RC_EUNSUPPORTED.
  */
 rc_status rc_segments_backward(const rc_forest *forest, const rc_index *index, const rc_fields *fields,
                                const void *dcams, int32_t ncams, const rc_vforest *vf,

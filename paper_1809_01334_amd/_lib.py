@@ -22,11 +22,11 @@ RC_EFOREST = -5
 RC_EHIP = -6
 RC_QMAXLEVEL = 19
 RC_CAMERA_DOUBLES = 20
-RC_GEOM_UNIT_CUBE, RC_GEOM_SHELL6 = 0, 1
+RC_GEOM_UNIT_CUBE, RC_GEOM_SHELL6, RC_GEOM_SURFACE = 0, 1, 2
 RC_MAXTREES = 64
 RC_MAXLISTS = 16
 RC_ABSENT = -1
-RC_FIELD_CONST, RC_FIELD_TRILINEAR, RC_FIELD_CONST_EQ = 0, 1, 2
+RC_FIELD_CONST, RC_FIELD_TRILINEAR, RC_FIELD_CONST_EQ, RC_FIELD_SURFACE = 0, 1, 2, 3
 RC_INT_ANALYTIC, RC_INT_RK4, RC_INT_GAUSS2, RC_INT_SIMPSON = 0, 1, 2, 3
 RC_ADAPT_MAXDEPTH = 16
 

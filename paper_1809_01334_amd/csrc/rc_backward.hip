@@ -510,7 +510,7 @@ extern "C" rc_status rc_segments_backward(const rc_forest* f, const rc_index* ix
                                           const rc_tuning* tune, void* stream) {
     rc_status s = check_forest(f);
     if (s != RC_OK) return s;
-    if (is_shell(f)) return RC_EUNSUPPORTED;
+    if (is_curved(f)) return RC_EUNSUPPORTED;
     if ((s = check_index(ix)) != RC_OK) return s;
     if ((s = check_fields(fl, in)) != RC_OK) return s;
     if (!adjoint_supported(fl, in)) return RC_EUNSUPPORTED;

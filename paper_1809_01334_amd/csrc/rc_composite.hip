@@ -92,7 +92,7 @@ extern "C" rc_status rc_composite(const rc_forest* f, const rc_index* ix, const 
     if (rc_node_slots(ix, ncams) > 0 && !rec_node) return RC_EINVAL;
     if ((s = check_tables(vf, ix, ncams)) != RC_OK) return s;
     hipStream_t st = (hipStream_t)stream;
-    if (is_shell(f)) return rc_shell_composite(f, ix, dcams, ncams, vf, rec_leaf, rec_node, npix, A, B, I, tune, st);
+    if (is_curved(f)) return rc_shell_composite(f, ix, dcams, ncams, vf, rec_leaf, rec_node, npix, A, B, I, tune, st);
     FoldCtx C = make_fold_ctx(f, ix, dcams, ncams, vf, rec_leaf, rec_node);
     if ((s = fold_levels(C, ix, vf, rec_node, tune, st)) != RC_OK) return s;
     hipLaunchKernelGGL(k_fold_root, dim3(stride_grid(npix, 256, tuned(tune, 2, 256 * 16))), dim3(256), 0, st, C,

@@ -33,6 +33,8 @@ inline rc_status check_forest(const rc_forest* f) {
         if (f->ntrees != 1) return RC_EUNSUPPORTED;
     } else if (f->geom == RC_GEOM_SHELL6) {
         if (f->ntrees != 6 || !f->geom_table || !f->tree_begin) return RC_EINVAL;
+    } else if (f->geom == RC_GEOM_SURFACE) {
+        if (f->ntrees < 1 || f->ntrees > 6 || !f->geom_table || !f->tree_begin) return RC_EINVAL;
     } else {
         return RC_EUNSUPPORTED;
     }
@@ -46,6 +48,10 @@ inline rc_status check_forest(const rc_forest* f) {
 }
 
 inline bool is_shell(const rc_forest* f) { return f->geom == RC_GEOM_SHELL6; }
+inline bool is_surface(const rc_forest* f) { return f->geom == RC_GEOM_SURFACE; }
+// Geometries whose records hold two depth-tagged intervals and whose node
+// rectangles are unions of the children's.
+inline bool is_curved(const rc_forest* f) { return is_shell(f) || is_surface(f); }
 
 // Curved six-tree shell variants of rc_segments and rc_composite (arguments
 // already validated by the entry points).
@@ -55,6 +61,11 @@ rc_status rc_shell_segments(const rc_forest* f, const rc_fields* fl, const void*
 rc_status rc_shell_composite(const rc_forest* f, const rc_index* ix, const void* dcams, int32_t ncams,
                              const rc_vforest* vf, const float* rec_leaf, float* rec_node, int64_t npix, float* A,
                              float* B, float* I, const rc_tuning* tune, hipStream_t st);
+// Surface forests: segments (rc_surface.hip); compositing is the shell's with
+// zero-length intervals.
+rc_status rc_surface_segments(const rc_forest* f, const rc_fields* fl, const void* dcams, const rc_vforest* vf,
+                              const rc_integrator* in, float* rec_leaf, uint8_t* hit, double* sio,
+                              const rc_tuning* tune, hipStream_t st);
 
 // Workspace layout of rc_forest_index.
 constexpr size_t IX_STATUS = 0, IX_COUNT = 64, IX_TREES = 256, IX_ROOTS = 1280, IX_CUR = 1536;
@@ -77,8 +88,10 @@ inline rc_status check_vforest(const rc_vforest* vf, bool need_nodes) {
 inline rc_status check_fields(const rc_fields* fl, const rc_integrator* in) {
     if (!fl || !fl->kappa || !fl->eps || !in) return RC_EINVAL;
     if (fl->nch != 1) return RC_EUNSUPPORTED;
-    if (fl->kind != RC_FIELD_CONST && fl->kind != RC_FIELD_TRILINEAR && fl->kind != RC_FIELD_CONST_EQ)
+    if (fl->kind != RC_FIELD_CONST && fl->kind != RC_FIELD_TRILINEAR && fl->kind != RC_FIELD_CONST_EQ &&
+        fl->kind != RC_FIELD_SURFACE)
         return RC_EUNSUPPORTED;
+    if (fl->kind == RC_FIELD_SURFACE) return in->method == RC_INT_ANALYTIC ? RC_OK : RC_EUNSUPPORTED;
     if (in->method == RC_INT_ANALYTIC) {
         if (fl->kind == RC_FIELD_TRILINEAR) return RC_EUNSUPPORTED;
         return RC_OK;
@@ -96,7 +109,7 @@ inline rc_status check_fields(const rc_fields* fl, const rc_integrator* in) {
 // The hand-written adjoint covers the fixed-step RK4 and the closed form with
 // (kappa, eps) fields.
 inline bool adjoint_supported(const rc_fields* fl, const rc_integrator* in) {
-    if (fl->kind == RC_FIELD_CONST_EQ) return false;
+    if (fl->kind == RC_FIELD_CONST_EQ || fl->kind == RC_FIELD_SURFACE) return false;
     return in->method == RC_INT_ANALYTIC || (in->method == RC_INT_RK4 && in->c_rk == 0.0);
 }
 

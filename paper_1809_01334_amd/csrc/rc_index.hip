@@ -23,7 +23,7 @@ __device__ inline bool tree_start(const int64_t* tb, int ntrees, int64_t i) {
 
 // status[0]: error flags, status[1]: maximum level
 __global__ void k_validate(int64_t n, const uint8_t* level, const uint32_t* x, const uint32_t* y, const uint32_t* z,
-                           const int64_t* tb, int ntrees, int maxallowed, int* status) {
+                           const int64_t* tb, int ntrees, int maxallowed, int flat, int* status) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     if (level[i] > maxallowed) atomicOr(&status[0], 8);
@@ -33,7 +33,7 @@ __global__ void k_validate(int64_t n, const uint8_t* level, const uint32_t* x, c
         return;
     }
     uint32_t len = 1u << (QMAX - l);
-    if ((x[i] & (len - 1)) || (y[i] & (len - 1)) || (z[i] & (len - 1)) || x[i] + len > (1u << QMAX) ||
+    if ((flat && z[i] != 0) || (x[i] & (len - 1)) || (y[i] & (len - 1)) || (z[i] & (len - 1)) || x[i] + len > (1u << QMAX) ||
         y[i] + len > (1u << QMAX) || z[i] + len > (1u << QMAX)) {
         atomicOr(&status[0], 2);
         return;
@@ -161,7 +161,7 @@ extern "C" rc_status rc_forest_index(const rc_forest* f, rc_index* ix, void* ws,
     RC_HIP(hipMemsetAsync(status, 0, 64, st));
     unsigned nb = (unsigned)((N + 255) / 256);
     hipLaunchKernelGGL(k_validate, dim3(nb), dim3(256), 0, st, N, f->level, f->x, f->y, f->z, (const int64_t*)dtb, nt,
-                       maxallowed, status);
+                       maxallowed, is_surface(f) ? 1 : 0, status);
     RC_HIP(hipGetLastError());
     int hs[2];
     RC_HIP(hipMemcpyAsync(hs, status, sizeof(hs), hipMemcpyDeviceToHost, st));

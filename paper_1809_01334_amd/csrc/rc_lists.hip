@@ -433,7 +433,7 @@ extern "C" rc_status rc_composite_lists(const rc_forest* f, const rc_index* ix, 
                                         void* stream) {
     rc_status s = check_forest(f);
     if (s != RC_OK) return s;
-    if (is_shell(f)) return RC_EUNSUPPORTED;
+    if (is_curved(f)) return RC_EUNSUPPORTED;
     if ((s = check_index(ix)) != RC_OK) return s;
     if ((s = check_vforest(vf, ix->maxlevel >= 1)) != RC_OK) return s;
     if (!dcams || ncams <= 0 || npix <= 0 || !rec_leaf || !list_offset || !n_entries || cap_entries < 0 ||

@@ -7,6 +7,7 @@
 #include "rc_host.h"
 #include "rc_internal.h"
 #include "rc_shell.h"
+#include "rc_surface.h"
 
 namespace rc {
 namespace {
@@ -26,7 +27,8 @@ struct PruneSrc {
     const uint32_t *nx, *ny, *nz;
     int64_t N, nleafitems;
     SlotLayout L;
-    const double* geom;      // shell table, or null for the unit cube
+    const double* geom;      // shell or surface table, or null for the unit cube
+    int surface;             // geom holds bilinear tree patches
     int64_t tb[RC_MAXTREES + 1];
     int ntrees;
     int16_t* stash;          // every item's rectangle, for the apply pass
@@ -43,8 +45,12 @@ struct PruneSrc {
             if (geom) {
                 int k = 0;
                 while (k + 1 < ntrees && l >= tb[k + 1]) k++;
-                ShellElem e = shell_elem(geom, k, level[l], x[l], y[l], z[l]);
-                it.r = shell_rect(cams[cam], e);
+                if (surface) {
+                    it.r = surf_rect(cams[cam], geom + 12 * k, level[l], x[l], y[l]);
+                } else {
+                    ShellElem e = shell_elem(geom, k, level[l], x[l], y[l], z[l]);
+                    it.r = shell_rect(cams[cam], e);
+                }
             } else {
                 node_box(level[l], x[l], y[l], z[l], lo, hi);
                 int c0 = __builtin_amdgcn_readfirstlane((int)cam);
@@ -282,7 +288,7 @@ extern "C" rc_status rc_prune_visible(const rc_forest* f, const rc_index* ix, co
     SlotLayout L = make_layout(ix, ncams);
     int64_t nslots = rc_node_slots(ix, ncams);
     int64_t nleafitems = N * (int64_t)ncams;
-    bool shell = is_shell(f);
+    bool shell = is_curved(f);  // node rectangles from the children's
     PruneSrc src;
     src.cams = cams;
     src.level = f->level;
@@ -297,6 +303,7 @@ extern "C" rc_status rc_prune_visible(const rc_forest* f, const rc_index* ix, co
     src.nleafitems = nleafitems;
     src.L = L;
     src.geom = shell ? f->geom_table : nullptr;
+    src.surface = is_surface(f) ? 1 : 0;
     src.ntrees = f->ntrees;
     for (int k = 0; k <= RC_MAXTREES; k++) src.tb[k] = k <= f->ntrees ? (f->tree_begin ? f->tree_begin[k] : N) : N;
     int64_t items = shell ? nleafitems : nleafitems + nslots;

@@ -163,6 +163,9 @@ extern "C" rc_status rc_segments(const rc_forest* f, const rc_fields* fl, const 
     if ((s = check_vforest(vf, false)) != RC_OK) return s;
     if (!dcams || ncams <= 0 || !rec_leaf || !vf->cand_chunk) return RC_EINVAL;
     hipStream_t st = (hipStream_t)stream;
+    // surface data goes with surface forests only
+    if (is_surface(f) != (fl->kind == RC_FIELD_SURFACE)) return RC_EUNSUPPORTED;
+    if (is_surface(f)) return rc_surface_segments(f, fl, dcams, vf, in, rec_leaf, hit, sio, tune, st);
     if (is_shell(f)) return rc_shell_segments(f, fl, dcams, vf, in, rec_leaf, hit, sio, tune, st);
     if (in->method != RC_INT_ANALYTIC && (in->method != RC_INT_RK4 || in->c_rk > 0.0))
         return rc_segments_general(f, fl, dcams, vf, in, rec_leaf, hit, sio, tune, st);

@@ -17,8 +17,13 @@ using namespace rc;
 namespace rc {
 namespace {
 
-__device__ inline float4 empty_iv() { return make_float4(0.0f, 0.0f, 1.0f, 0.0f); }
-__device__ inline bool iv_valid(const float4& v) { return v.y > v.x; }
+// An empty slot: s_in > s_out.  Shell intervals have positive length; a
+// surface hit is a zero-length interval (PTS), valid when s_in <= s_out.
+__device__ inline float4 empty_iv() { return make_float4(1.0f, 0.0f, 1.0f, 0.0f); }
+template <bool PTS>
+__device__ inline bool iv_valid(const float4& v) {
+    return PTS ? v.x <= v.y : v.y > v.x;
+}
 
 struct ShellSegArgs {
     const Cam* cams;
@@ -238,7 +243,7 @@ __device__ inline float4 join_iv(const float4& p, const float4& q) {
 // shared face (the node meets a ray in at most two intervals), so the two
 // runs with the smallest gap between them are joined: empty space between
 // them is the identity of the group, so the value is unchanged.
-template <int NQ>
+template <bool PTS, int NQ>
 __device__ inline void merge_runs(const float4 (&iv)[NQ], float4& o0, float4& o1) {
     uint32_t used = 0;
     int nout = 0;
@@ -250,7 +255,7 @@ __device__ inline void merge_runs(const float4 (&iv)[NQ], float4& o0, float4& o1
         int bq = -1;
 #pragma unroll
         for (int q = 0; q < NQ; q++) {
-            bool ok = iv_valid(iv[q]) && !((used >> q) & 1u) && iv[q].x < best;
+            bool ok = iv_valid<PTS>(iv[q]) && !((used >> q) & 1u) && iv[q].x < best;
             if (ok) {
                 best = iv[q].x;
                 cur = iv[q];
@@ -280,7 +285,7 @@ __device__ inline void merge_runs(const float4 (&iv)[NQ], float4& o0, float4& o1
     }
 }
 
-template <bool UNIFORM>
+template <bool PTS, bool UNIFORM>
 __device__ inline void shell_node(const ShellFold& S, int64_t dslot, int i, int j, float4& o0, float4& o1) {
     float4 iv[16];
 #pragma unroll
@@ -288,18 +293,20 @@ __device__ inline void shell_node(const ShellFold& S, int64_t dslot, int i, int 
         ChildDesc d = UNIFORM ? load_desc_scalar(S.C.desc, dslot * 8 + q) : load_desc(S.C.desc + dslot * 8 + q);
         child_intervals(S, d, i, j, iv[2 * q], iv[2 * q + 1]);
     }
-    merge_runs<16>(iv, o0, o1);
+    merge_runs<PTS, 16>(iv, o0, o1);
 }
 
+template <bool PTS>
 __device__ inline void shell_node_auto(const ShellFold& S, int64_t dslot, bool active, int i, int j, float4& o0,
                                        float4& o1) {
     int64_t d0 = uniform64(dslot);
     if (__all(!active || dslot == d0))
-        shell_node<true>(S, d0, i, j, o0, o1);
+        shell_node<PTS, true>(S, d0, i, j, o0, o1);
     else
-        shell_node<false>(S, dslot, i, j, o0, o1);
+        shell_node<PTS, false>(S, dslot, i, j, o0, o1);
 }
 
+template <bool PTS>
 __global__ __launch_bounds__(256) void k_fold_level_shell(ShellFold S, int l, float4* out) {
     const FoldCtx& C = S.C;
     if (C.counts[3]) return;
@@ -322,7 +329,7 @@ __global__ __launch_bounds__(256) void k_fold_level_shell(ShellFold S, int l, fl
         int i, j;
         rect_pixel(r, k, i, j);
         float4 o0, o1;
-        shell_node_auto(S, cam * C.ninternal + m, act, i, j, o0, o1);
+        shell_node_auto<PTS>(S, cam * C.ninternal + m, act, i, j, o0, o1);
         if (act) {
             out[2 * g] = o0;
             out[2 * g + 1] = o1;
@@ -331,6 +338,7 @@ __global__ __launch_bounds__(256) void k_fold_level_shell(ShellFold S, int l, fl
 }
 
 // Roots: each tree's intervals, then all trees folded front to back.
+template <bool PTS>
 __global__ __launch_bounds__(256) void k_fold_root_shell(ShellFold S, int ntrees, int32_t r0, int32_t r1, int32_t r2,
                                                          int32_t r3, int32_t r4, int32_t r5, int64_t npix, float* A,
                                                          float* B, float* I, const int32_t* leaf_vis,
@@ -352,7 +360,7 @@ __global__ __launch_bounds__(256) void k_fold_root_shell(ShellFold S, int ntrees
             iv[2 * t + 1] = empty_iv();
             int32_t root = t < ntrees ? roots[t] : RC_ABSENT;
             if (root >= 0) {
-                shell_node_auto(S, (int64_t)cam * C.ninternal + root, true, i, j, iv[2 * t], iv[2 * t + 1]);
+                shell_node_auto<PTS>(S, (int64_t)cam * C.ninternal + root, true, i, j, iv[2 * t], iv[2 * t + 1]);
             } else if (root <= -2) {
                 int32_t v = leaf_vis[(int64_t)cam * C.N + (-2 - (int64_t)root)];
                 if (v >= 0) {
@@ -374,7 +382,7 @@ __global__ __launch_bounds__(256) void k_fold_root_shell(ShellFold S, int ntrees
             int bq = -1;
 #pragma unroll
             for (int q = 0; q < 12; q++) {
-                bool ok = iv_valid(iv[q]) && !((used >> q) & 1u) && iv[q].x < best;
+                bool ok = iv_valid<PTS>(iv[q]) && !((used >> q) & 1u) && iv[q].x < best;
                 if (ok) {
                     best = iv[q].x;
                     cur = iv[q];
@@ -446,16 +454,24 @@ rc_status rc::rc_shell_composite(const rc_forest* f, const rc_index* ix, const v
     S.rec_leaf = (const float4*)rec_leaf;
     S.rec_node = (const float4*)rec_node;
     unsigned grid = stride_grid(vf->cap_rec, 256, tuned(tune, 1, 256 * 16));
+    bool pts = is_surface(f);
     for (int l = ix->maxlevel - 1; l >= 1; l--) {
         if (ix->level_begin[l + 1] == ix->level_begin[l]) continue;
-        hipLaunchKernelGGL(k_fold_level_shell, dim3(grid), dim3(256), 0, st, S, l, (float4*)rec_node);
+        if (pts)
+            hipLaunchKernelGGL(k_fold_level_shell<true>, dim3(grid), dim3(256), 0, st, S, l, (float4*)rec_node);
+        else
+            hipLaunchKernelGGL(k_fold_level_shell<false>, dim3(grid), dim3(256), 0, st, S, l, (float4*)rec_node);
         RC_HIP(hipGetLastError());
     }
     int32_t r[6];
     for (int k = 0; k < 6; k++) r[k] = k < ix->ntrees ? ix->roots[k] : RC_ABSENT;
-    hipLaunchKernelGGL(k_fold_root_shell, dim3(stride_grid(npix, 256, tuned(tune, 2, 256 * 16))), dim3(256), 0, st, S,
-                       ix->ntrees, r[0], r[1], r[2], r[3], r[4], r[5], npix, A, B, I, vf->leaf_vis, vf->vis_rect,
-                       vf->cand_offset);
+    dim3 rg(stride_grid(npix, 256, tuned(tune, 2, 256 * 16))), rb(256);
+    if (pts)
+        hipLaunchKernelGGL(k_fold_root_shell<true>, rg, rb, 0, st, S, ix->ntrees, r[0], r[1], r[2], r[3], r[4], r[5],
+                           npix, A, B, I, vf->leaf_vis, vf->vis_rect, vf->cand_offset);
+    else
+        hipLaunchKernelGGL(k_fold_root_shell<false>, rg, rb, 0, st, S, ix->ntrees, r[0], r[1], r[2], r[3], r[4], r[5],
+                           npix, A, B, I, vf->leaf_vis, vf->vis_rect, vf->cand_offset);
     RC_HIP(hipGetLastError());
     return RC_OK;
 }

@@ -31,9 +31,10 @@ def _empty(n, dtype, device):
 
 class DeviceForest:
     """Leaves of one forest share on the device (SFC order).  Geometry: the
-    unit cube (one tree), or with ``geom_table`` the six-tree shell."""
+    unit cube (one tree), or with ``geom_table`` the six-tree shell, or with
+    geom=RC_GEOM_SURFACE quadtrees on bilinear patches (12 corner doubles per tree)."""
 
-    def __init__(self, level, x, y, z, device, tree_begin=None, geom_table=None):
+    def __init__(self, level, x, y, z, device, tree_begin=None, geom_table=None, geom=None):
         self.device = torch.device(device)
         self.nleaves = int(len(level))
         self.level = torch.from_numpy(np.ascontiguousarray(level, np.uint8)).to(self.device)
@@ -42,7 +43,9 @@ class DeviceForest:
         self.z = torch.from_numpy(np.ascontiguousarray(z, np.uint32).view(np.int32)).to(self.device)
         tb = np.array([0, self.nleaves], np.int64) if tree_begin is None else np.asarray(tree_begin, np.int64)
         self.tree_begin = np.ascontiguousarray(tb)
-        self.geom = L.RC_GEOM_UNIT_CUBE if geom_table is None else L.RC_GEOM_SHELL6
+        if geom is None:
+            geom = L.RC_GEOM_UNIT_CUBE if geom_table is None else L.RC_GEOM_SHELL6
+        self.geom = int(geom)
         self.geom_table = None
         if geom_table is not None:
             self.geom_table = torch.from_numpy(np.ascontiguousarray(geom_table, np.float64)).to(self.device)
@@ -54,23 +57,32 @@ class DeviceForest:
     def shell(self) -> bool:
         return self.geom == L.RC_GEOM_SHELL6
 
+    @property
+    def curved(self) -> bool:
+        """Records hold two depth-tagged intervals (shell intervals, surface hits)."""
+        return self.geom in (L.RC_GEOM_SHELL6, L.RC_GEOM_SURFACE)
+
     @classmethod
     def from_synth(cls, forest, device):
-        table = forest.geom_params if forest.geom == "shell6" else None
-        return cls(forest.level, forest.x, forest.y, forest.z, device, forest.tree_begin, table)
+        geom = {"unit_cube": L.RC_GEOM_UNIT_CUBE, "shell6": L.RC_GEOM_SHELL6, "surface": L.RC_GEOM_SURFACE}[forest.geom]
+        table = forest.geom_params if geom != L.RC_GEOM_UNIT_CUBE else None
+        return cls(forest.level, forest.x, forest.y, forest.z, device, forest.tree_begin, table, geom)
 
 
 class DeviceFields:
     """Coefficients leaf-major: kappa, eps of shape [N, ncorner] (ncorner 1 or 8).
-    equilibrium=True: constant kappa and the equilibrium intensity I in place of eps."""
+    equilibrium=True: constant kappa and the equilibrium intensity I in place of eps.
+    surface=True: [N, 4] corner transparency A_s (kappa) and intensity I_s (eps)."""
 
-    def __init__(self, kappa: torch.Tensor, eps: torch.Tensor, equilibrium: bool = False):
-        assert kappa.shape == eps.shape and kappa.dim() == 2 and kappa.shape[1] in (1, 8)
+    def __init__(self, kappa: torch.Tensor, eps: torch.Tensor, equilibrium: bool = False, surface: bool = False):
+        assert kappa.shape == eps.shape and kappa.dim() == 2 and kappa.shape[1] in ((4,) if surface else (1, 8))
         assert kappa.dtype == torch.float32 and eps.dtype == torch.float32
         assert not (equilibrium and kappa.shape[1] != 1)
         self.kappa = kappa.contiguous()
         self.eps = eps.contiguous()
-        if equilibrium:
+        if surface:
+            self.kind = L.RC_FIELD_SURFACE
+        elif equilibrium:
             self.kind = L.RC_FIELD_CONST_EQ
         else:
             self.kind = L.RC_FIELD_TRILINEAR if kappa.shape[1] == 8 else L.RC_FIELD_CONST
@@ -84,7 +96,8 @@ class DeviceFields:
     @classmethod
     def from_synth(cls, fields, device):
         return cls(torch.from_numpy(cls.leaf_major(fields.kappa)).to(device),
-                   torch.from_numpy(cls.leaf_major(fields.eps)).to(device), fields.kind == "const_eq")
+                   torch.from_numpy(cls.leaf_major(fields.eps)).to(device), fields.kind == "const_eq",
+                   fields.kind == "surface")
 
 
 class DeviceCameras:
@@ -295,7 +308,7 @@ class Renderer:
         raw = cameras if isinstance(cameras, np.ndarray) else np.stack([c.raw() for c in cameras])
         self.cams = rc_camera_prepare(raw, self.device)
         # floats per record: (A, B), or two (s_in, s_out, A, B) intervals on the shell
-        self.rec_floats = 8 if self.forest.shell else 2
+        self.rec_floats = 8 if self.forest.curved else 2
         self.method = METHODS[method] if isinstance(method, str) else int(method)
         self.substeps = int(substeps)
         self.c_rk = float(c_rk)  # > 0: the adaptive recursion with this stability parameter
@@ -438,14 +451,15 @@ class Renderer:
         return self.A, self.B, self.I
 
     def set_fields(self, kappa: torch.Tensor, eps: torch.Tensor):
-        self.fields = DeviceFields(kappa, eps, self.fields.kind == L.RC_FIELD_CONST_EQ)
+        self.fields = DeviceFields(kappa, eps, self.fields.kind == L.RC_FIELD_CONST_EQ,
+                                   self.fields.kind == L.RC_FIELD_SURFACE)
 
     def debug_segments(self, intervals: bool = True):
         """Run rc_segments with the pairing outputs per candidate: hits (u8; 0/1, or
         0..2 intervals on the shell) and the intervals in FP64 (2 or 4 doubles) or None."""
         n = self.vf.cap_cand
         hit = _empty(n, torch.uint8, self.device)
-        sio = _empty((4 if self.forest.shell else 2) * n, torch.float64, self.device) if intervals else None
+        sio = _empty((4 if self.forest.curved else 2) * n, torch.float64, self.device) if intervals else None
         self.segments(hit, sio)
         return hit, sio
 

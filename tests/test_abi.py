@@ -198,3 +198,47 @@ def test_integrator_validation():
     for kind, method, sub, c_rk in ((T, L.RC_INT_GAUSS2, 4, 0.0), (C, L.RC_INT_SIMPSON, 2, 0.3),
                                     (E, L.RC_INT_ANALYTIC, 1, 0.0), (T, L.RC_INT_RK4, 3, 0.0)):
         assert seg(kind, method, sub, c_rk) == L.RC_EINVAL  # null vforest arrays
+
+
+def test_surface_validation():
+    """Surface forests take 1 to 6 trees with a corner table, surface data only, and the
+    closed-form surface model; the adjoint rejects them."""
+    L = _lib()
+    lib = L.lib()
+    ix = L.RcIndex()
+    p = ctypes.c_void_p(16)
+    tb = np.array([0, 4, 8], np.int64)
+    ptb = tb.ctypes.data_as(ctypes.c_void_p)
+
+    def index_status(ntrees, tb_, table, n=8):
+        f = L.RcForest(ntrees, L.RC_GEOM_SURFACE, n, tb_, p, p, p, p, table)
+        return lib.rc_forest_index(ctypes.byref(f), ctypes.byref(ix), None, 0, None)
+
+    assert index_status(0, ptb, p) == L.RC_EINVAL
+    t7 = np.arange(8, dtype=np.int64)
+    assert index_status(7, t7.ctypes.data_as(ctypes.c_void_p), p, n=7) == L.RC_EINVAL
+    assert index_status(2, ptb, None) == L.RC_EINVAL
+    assert index_status(2, None, p) == L.RC_EINVAL
+    assert index_status(2, ptb, p) == L.RC_EWORKSPACE
+
+    vf = L.RcVforest()
+    for name in ("vis_leaf", "vis_cam", "vis_rect", "cand_offset", "leaf_vis", "counts", "cand_chunk"):
+        setattr(vf, name, p)
+
+    def seg(geom, ntrees, tb_, table, kind, method):
+        f = L.RcForest(ntrees, geom, 8, tb_, p, p, p, p, table)
+        fl = L.RcFields(kind, 1, p, p)
+        integ = L.RcIntegrator(method, 1, 0.0)
+        return lib.rc_segments(ctypes.byref(f), ctypes.byref(fl), p, 1, ctypes.byref(vf), ctypes.byref(integ), p,
+                               None, None, None, None)
+
+    S, A = L.RC_FIELD_SURFACE, L.RC_INT_ANALYTIC
+    assert seg(L.RC_GEOM_SURFACE, 2, ptb, p, S, L.RC_INT_RK4) == L.RC_EUNSUPPORTED      # no ODE on a surface
+    assert seg(L.RC_GEOM_SURFACE, 2, ptb, p, L.RC_FIELD_CONST, A) == L.RC_EUNSUPPORTED  # volume data
+    assert seg(L.RC_GEOM_UNIT_CUBE, 1, None, None, S, A) == L.RC_EUNSUPPORTED           # surface data on a cube
+    f = L.RcForest(2, L.RC_GEOM_SURFACE, 8, ptb, p, p, p, p, p)
+    fl = L.RcFields(S, 1, p, p)
+    integ = L.RcIntegrator(A, 1, 0.0)
+    st = lib.rc_segments_backward(ctypes.byref(f), ctypes.byref(ix), ctypes.byref(fl), p, 1, ctypes.byref(vf),
+                                  ctypes.byref(integ), p, p, 1, p, p, p, p, p, 0, p, 0, None, None)
+    assert st == L.RC_EUNSUPPORTED
