@@ -71,6 +71,9 @@ def lib():
         L.or_merge_sorted.restype = I64
         L.or_merge_sorted.argtypes = [I64, P, P, P]
         L.or_surface_render.restype = I32
+        L.or_ho_surface_render.restype = I32
+        L.or_ho_surface_render.argtypes = [I64, I32, P, P, P, P, P, P, P, P, I64, P, P, P, P, P, P, I32]
+        L.or_ho_map.argtypes = [P, I32, I64, P, P]
         L.or_surface_render.argtypes = [I64, I32, P, P, P, P, P, P, P, P, I64, P, P, P, P, P, P]
         L.or_shell_map.argtypes = [P, I32, P, P]
         L.or_shell_inverse.argtypes = [P, I32, P, P]
@@ -359,6 +362,44 @@ def surface_render(forest, fields, cam, pixels=None, hits=False):
     if hits:
         out["hit_leaf"] = hl
         out["hit_s"] = hs
+    return out
+
+
+def ho_surface_render(forest, fields, cam, pixels=None, hits=False):
+    """FP64 oracle image of a degree-R surface forest (geom_params = [R, control points]);
+    as surface_render, with up to 2 R^2 hits per tree."""
+    raw = cam.raw() if hasattr(cam, "raw") else np.asarray(cam, np.float64)
+    lv, x, y, _ = _forest_args(forest)
+    As = _c(fields.kappa, np.float64)
+    Is = _c(fields.eps, np.float64)
+    geom = _c(forest.geom_params, np.float64)
+    R = int(geom[0])
+    W, H = int(raw[14]), int(raw[15])
+    if pixels is None:
+        npo, pix, nsel = W * H, None, -1
+    else:
+        pix = _c(pixels, np.int64)
+        npo = nsel = pix.shape[0]
+    A, B, I = np.zeros(npo), np.zeros(npo), np.zeros(npo)
+    hcap = min(2 * R * R * forest.ntrees, 64)
+    hl = np.zeros((npo, hcap), np.int32) if hits else None
+    hs = np.zeros((npo, hcap)) if hits else None
+    st = lib().or_ho_surface_render(forest.nleaves, forest.ntrees, _p(_c(forest.tree_begin, np.int64)), _p(geom),
+                                    _p(lv), _p(x), _p(y), _p(As), _p(Is), _p(_c(raw, np.float64)), nsel, _p(pix),
+                                    _p(A), _p(B), _p(I), _p(hl), _p(hs), hcap)
+    assert st == 0, "degree out of range"
+    out = {"A": A, "B": B, "I": I}
+    if hits:
+        out["hit_leaf"] = hl
+        out["hit_s"] = hs
+    return out
+
+
+def ho_map(geom, tree, t):
+    """Points J(t1, t2) of a degree-R tree map at parameters t [m, 2]."""
+    t = _c(np.atleast_2d(t), np.float64)
+    out = np.zeros((t.shape[0], 3))
+    lib().or_ho_map(_p(_c(geom, np.float64)), int(tree), t.shape[0], _p(t), _p(out))
     return out
 
 

@@ -1898,3 +1898,347 @@ int or_surface_render(int64_t n, int ntrees, const int64_t *tree_begin, const do
     }
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* high-order surfaces: degree-R tensor Lagrange maps on Gauss-Lobatto      */
+/* nodes (eq. nodal, eq. tensorgeom), hits by subdivision with Bernstein    */
+/* convex-hull exclusion and Newton's method (App. A.1)                     */
+/* ------------------------------------------------------------------------ */
+
+#define OR_HO_MAXR 3
+#define OR_HO_DEPTH 10    /* subdivision of the tree square before Newton */
+#define OR_HO_MAXDEPTH 24 /* squares where Newton leaves the square are split further, down to this */
+
+typedef struct {
+    int R;
+    double eta[OR_HO_MAXR + 1];
+    double einv[(OR_HO_MAXR + 1) * (OR_HO_MAXR + 1)]; /* equispaced values -> Bernstein coefficients */
+    const double *z;                                 /* (R+1)^2 control points, m1 fastest */
+} orho;
+
+static double binom(int n, int k)
+{
+    double b = 1.0;
+    for (int i = 1; i <= k; i++) b = b * (n - k + i) / i;
+    return b;
+}
+
+/* Gauss-Lobatto nodes on [0, 1]: the ends and the roots of P_R' mapped there. */
+static void ho_init(orho *H, int R, const double *z)
+{
+    H->R = R;
+    H->z = z;
+    H->eta[0] = 0.0;
+    H->eta[R] = 1.0;
+    if (R == 2) H->eta[1] = 0.5;
+    if (R == 3) {
+        H->eta[1] = 0.5 * (1.0 - 1.0 / sqrt(5.0));
+        H->eta[2] = 0.5 * (1.0 + 1.0 / sqrt(5.0));
+    }
+    /* E[j][k] = B_k(j / R); einv = E^-1 by Gauss-Jordan elimination */
+    int n = R + 1;
+    double a[OR_HO_MAXR + 1][2 * (OR_HO_MAXR + 1)];
+    for (int j = 0; j < n; j++)
+        for (int k = 0; k < n; k++) {
+            double u = (double)j / R;
+            a[j][k] = binom(R, k) * pow(u, k) * pow(1.0 - u, R - k);
+            a[j][n + k] = j == k ? 1.0 : 0.0;
+        }
+    for (int c = 0; c < n; c++) {
+        int piv = c;
+        for (int r = c + 1; r < n; r++)
+            if (fabs(a[r][c]) > fabs(a[piv][c])) piv = r;
+        for (int k = 0; k < 2 * n; k++) {
+            double t = a[c][k];
+            a[c][k] = a[piv][k];
+            a[piv][k] = t;
+        }
+        double d = a[c][c];
+        for (int k = 0; k < 2 * n; k++) a[c][k] /= d;
+        for (int r = 0; r < n; r++)
+            if (r != c) {
+                double f = a[r][c];
+                for (int k = 0; k < 2 * n; k++) a[r][k] -= f * a[c][k];
+            }
+    }
+    for (int j = 0; j < n; j++)
+        for (int k = 0; k < n; k++) H->einv[j * n + k] = a[j][n + k];
+}
+
+/* Lagrange basis psi_m(t) on the nodes and its derivative (eq. nodal). */
+static void ho_basis(const orho *H, double t, double *psi, double *dpsi)
+{
+    for (int m = 0; m <= H->R; m++) {
+        double p = 1.0, dp = 0.0;
+        for (int l = 0; l <= H->R; l++) {
+            if (l == m) continue;
+            double den = H->eta[m] - H->eta[l];
+            dp = dp * ((t - H->eta[l]) / den) + p / den;
+            p *= (t - H->eta[l]) / den;
+        }
+        psi[m] = p;
+        dpsi[m] = dp;
+    }
+}
+
+/* J(t1, t2) (eq. tensorgeom) and its partial derivatives. */
+static void ho_eval(const orho *H, double t1, double t2, double *J, double *J1, double *J2)
+{
+    double p1[OR_HO_MAXR + 1], d1[OR_HO_MAXR + 1], p2[OR_HO_MAXR + 1], d2[OR_HO_MAXR + 1];
+    ho_basis(H, t1, p1, d1);
+    ho_basis(H, t2, p2, d2);
+    int n = H->R + 1;
+    for (int k = 0; k < 3; k++) {
+        double v = 0.0, v1 = 0.0, v2 = 0.0;
+        for (int m2 = 0; m2 < n; m2++)
+            for (int m1 = 0; m1 < n; m1++) {
+                double zc = H->z[3 * (m1 + n * m2) + k];
+                v += zc * p1[m1] * p2[m2];
+                v1 += zc * d1[m1] * p2[m2];
+                v2 += zc * p1[m1] * d2[m2];
+            }
+        J[k] = v;
+        if (J1) J1[k] = v1;
+        if (J2) J2[k] = v2;
+    }
+}
+
+/* Does the patch over the square [a1, a1 + h] x [a2, a2 + h] possibly meet the
+ * planes d1 . (x - rho) = 0 and d2 . (x - rho) = 0?  The Bernstein coefficients
+ * of each projection over the square (from the values on an equispaced grid)
+ * bound it; a square whose coefficients of one projection share a strict sign,
+ * beyond a relative 1e-10 for rounding, holds no hit. */
+static int ho_square_may_hit(const orho *H, const double *rho, const double *d1, const double *d2, double a1,
+                             double a2, double h)
+{
+    int n = H->R + 1;
+    double g[2][(OR_HO_MAXR + 1) * (OR_HO_MAXR + 1)], tmp[(OR_HO_MAXR + 1) * (OR_HO_MAXR + 1)];
+    for (int j2 = 0; j2 < n; j2++)
+        for (int j1 = 0; j1 < n; j1++) {
+            double J[3], e[3];
+            ho_eval(H, a1 + h * j1 / H->R, a2 + h * j2 / H->R, J, NULL, NULL);
+            for (int k = 0; k < 3; k++) e[k] = J[k] - rho[k];
+            g[0][j1 + n * j2] = dot3(d1, e);
+            g[1][j1 + n * j2] = dot3(d2, e);
+        }
+    for (int f = 0; f < 2; f++) {
+        /* values -> Bernstein coefficients along t1, then along t2 */
+        for (int j2 = 0; j2 < n; j2++)
+            for (int k = 0; k < n; k++) {
+                double s = 0.0;
+                for (int j = 0; j < n; j++) s += H->einv[k * n + j] * g[f][j + n * j2];
+                tmp[k + n * j2] = s;
+            }
+        /* a coefficient within rounding of zero counts for both signs */
+        double c[(OR_HO_MAXR + 1) * (OR_HO_MAXR + 1)], big = 0.0;
+        for (int k1 = 0; k1 < n; k1++)
+            for (int k = 0; k < n; k++) {
+                double s = 0.0;
+                for (int j = 0; j < n; j++) s += H->einv[k * n + j] * tmp[k1 + n * j];
+                c[k1 + n * k] = s;
+                big = fmax(big, fabs(s));
+            }
+        double tol = 1e-10 * big;
+        int pos = 0, neg = 0;
+        for (int q = 0; q < n * n; q++) {
+            pos |= c[q] >= -tol;
+            neg |= c[q] <= tol;
+        }
+        if (!(pos && neg)) return 0;
+    }
+    return 1;
+}
+
+/* One Newton step on d_j . (J(t1, t2) - rho) = 0, j = 1, 2; the step in (s1, s2).
+ * Returns 0 at a singular Jacobian. */
+static int ho_newton(const orho *H, const double *rho, const double *d1, const double *d2, double *t1, double *t2,
+                     double *s1, double *s2)
+{
+    double J[3], J1[3], J2[3], e[3];
+    ho_eval(H, *t1, *t2, J, J1, J2);
+    for (int q = 0; q < 3; q++) e[q] = J[q] - rho[q];
+    double f1 = dot3(d1, e), f2 = dot3(d2, e);
+    double a = dot3(d1, J1), b = dot3(d1, J2), c = dot3(d2, J1), dd = dot3(d2, J2);
+    double det = a * dd - b * c;
+    if (det == 0.0) return 0;
+    *s1 = (dd * f1 - b * f2) / det;
+    *s2 = (a * f2 - c * f1) / det;
+    *t1 -= *s1;
+    *t2 -= *s2;
+    return 1;
+}
+
+/* Hits of the ray with a degree-R tree patch for (t1, t2) in [0, 1]^2 and s in
+ * the clip range, nearest first (up to cap): the tree square is subdivided
+ * OR_HO_DEPTH times, discarding squares that cannot hold a hit, and Newton's
+ * method runs from the centre of each square left; a root counts in the
+ * square whose half-open extent holds it (far tree edges closed).  A square
+ * whose Newton iteration does not end inside it is split again, down to
+ * OR_HO_MAXDEPTH, so that close roots near a tangency are separated. */
+static int ho_hits(const orcam *cm, const orho *H, const double *rho, const double *r, double *hs, double *ht1,
+                   double *ht2, int cap)
+{
+    int k = 0;
+    if (fabs(r[1]) < fabs(r[k])) k = 1;
+    if (fabs(r[2]) < fabs(r[k])) k = 2;
+    double ek[3] = {0.0, 0.0, 0.0}, d1[3], d2[3];
+    ek[k] = 1.0;
+    cross3(r, ek, d1);
+    cross3(r, d1, d2);
+    double rr = dot3(r, r);
+    int nh = 0;
+    /* depth-first over squares (index i1, i2 at depth d) */
+    int st_i1[4 * OR_HO_MAXDEPTH + 4], st_i2[4 * OR_HO_MAXDEPTH + 4], st_d[4 * OR_HO_MAXDEPTH + 4], sp = 0;
+    st_i1[0] = st_i2[0] = st_d[0] = 0;
+    sp = 1;
+    while (sp > 0) {
+        sp--;
+        int i1 = st_i1[sp], i2 = st_i2[sp], d = st_d[sp];
+        double h = ldexp(1.0, -d), a1 = i1 * h, a2 = i2 * h;
+        if (!ho_square_may_hit(H, rho, d1, d2, a1, a2, h)) continue;
+        if (d < OR_HO_DEPTH) {
+            for (int c = 3; c >= 0; c--) {
+                st_i1[sp] = 2 * i1 + (c & 1);
+                st_i2[sp] = 2 * i2 + (c >> 1);
+                st_d[sp] = d + 1;
+                sp++;
+            }
+            continue;
+        }
+        double t1 = a1 + 0.5 * h, t2 = a2 + 0.5 * h, J[3], e[3];
+        int ok = 0;
+        for (int it = 0; it < 40; it++) {
+            double s1, s2;
+            if (!ho_newton(H, rho, d1, d2, &t1, &t2, &s1, &s2)) break;
+            if (fabs(s1) + fabs(s2) < 1e-15) {
+                ok = 1;
+                break;
+            }
+        }
+        /* canonical polish: the same start for every square that converged to this
+         * root, so that exactly one square holds the result */
+        if (ok) {
+            const double g = 1099511627776.0; /* 2^40 */
+            t1 = nearbyint(t1 * g) / g;
+            t2 = nearbyint(t2 * g) / g;
+            double s1, s2;
+            for (int it = 0; it < 2; it++) ok = ok && ho_newton(H, rho, d1, d2, &t1, &t2, &s1, &s2);
+        }
+        int in1 = (t1 >= a1 && t1 < a1 + h) || (t1 == 1.0 && a1 + h == 1.0);
+        int in2 = (t2 >= a2 && t2 < a2 + h) || (t2 == 1.0 && a2 + h == 1.0);
+        if (!(ok && in1 && in2)) {
+            if (d < OR_HO_MAXDEPTH) {
+                for (int c = 3; c >= 0; c--) {
+                    st_i1[sp] = 2 * i1 + (c & 1);
+                    st_i2[sp] = 2 * i2 + (c >> 1);
+                    st_d[sp] = d + 1;
+                    sp++;
+                }
+            }
+            continue;
+        }
+        ho_eval(H, t1, t2, J, NULL, NULL);
+        for (int q = 0; q < 3; q++) e[q] = J[q] - rho[q];
+        double s = dot3(e, r) / rr;
+        if (!(s >= cm->smin && s <= cm->smax) || nh >= cap) continue;
+        /* insertion in depth order */
+        int b = nh++;
+        for (; b > 0 && hs[b - 1] > s; b--) {
+            hs[b] = hs[b - 1];
+            ht1[b] = ht1[b - 1];
+            ht2[b] = ht2[b - 1];
+        }
+        hs[b] = s;
+        ht1[b] = t1;
+        ht2[b] = t2;
+    }
+    return nh;
+}
+
+/* Render a degree-R surface forest (geom: [R, then (R+1)^2 control points of 3
+ * doubles per tree on the Gauss-Lobatto grid, m1 fastest]); arguments and
+ * outputs as or_surface_render, with up to 2 R^2 hits per tree. */
+int or_ho_surface_render(int64_t n, int ntrees, const int64_t *tree_begin, const double *geom, const uint8_t *level,
+                         const uint32_t *x, const uint32_t *y, const double *As, const double *Is, const double *cam,
+                         int64_t nsel, const int64_t *pix, double *Aout, double *Bout, double *Iout, int32_t *hit_leaf,
+                         double *hit_s, int hcap)
+{
+    orcam c;
+    cam_parse(cam, &c);
+    int R = (int)geom[0];
+    if (R < 2 || R > OR_HO_MAXR) return -1;
+    int npt = (R + 1) * (R + 1);
+    int64_t P = nsel >= 0 ? nsel : (int64_t)c.w * c.h;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t q = 0; q < P; q++) {
+        int64_t p = nsel >= 0 ? pix[q] : q;
+        int i = (int)(p % c.w), j = (int)(p / c.w);
+        double rho[3], r[3];
+        pixel_ray(&c, i, j, rho, r);
+        double hs[64], hA[64], hB[64];
+        int64_t hl[64];
+        int nh = 0;
+        for (int k = 0; k < ntrees; k++) {
+            orho H;
+            ho_init(&H, R, geom + 1 + 3 * npt * k);
+            double s[2 * OR_HO_MAXR * OR_HO_MAXR], t1[2 * OR_HO_MAXR * OR_HO_MAXR], t2[2 * OR_HO_MAXR * OR_HO_MAXR];
+            int m = ho_hits(&c, &H, rho, r, s, t1, t2, 2 * R * R);
+            for (int a = 0; a < m && nh < 64; a++) {
+                int64_t leaf = surface_leaf(level, x, y, tree_begin[k], tree_begin[k + 1], t1[a], t2[a]);
+                if (leaf < 0) continue;
+                /* the surface model with the normal of the degree-R map */
+                double len = (double)(1u << (OR_QMAX - level[leaf]));
+                double u = (t1[a] * (double)(1u << OR_QMAX) - (double)x[leaf]) / len;
+                double v = (t2[a] * (double)(1u << OR_QMAX) - (double)y[leaf]) / len;
+                double w[4] = {(1.0 - u) * (1.0 - v), u * (1.0 - v), (1.0 - u) * v, u * v};
+                double as = 0.0, is = 0.0;
+                for (int qq = 0; qq < 4; qq++) {
+                    as += w[qq] * As[(int64_t)qq * n + leaf];
+                    is += w[qq] * Is[(int64_t)qq * n + leaf];
+                }
+                double J[3], J1[3], J2[3], nr[3];
+                ho_eval(&H, t1[a], t2[a], J, J1, J2);
+                cross3(J1, J2, nr);
+                double cosphi = fabs(dot3(nr, r)) / sqrt(dot3(nr, nr) * dot3(r, r));
+                double Av = pow(as, 1.0 / cosphi);
+                int b = nh++;
+                for (; b > 0 && hs[b - 1] > s[a]; b--) {
+                    hs[b] = hs[b - 1];
+                    hA[b] = hA[b - 1];
+                    hB[b] = hB[b - 1];
+                    hl[b] = hl[b - 1];
+                }
+                hs[b] = s[a];
+                hA[b] = Av;
+                hB[b] = is * (1.0 - Av);
+                hl[b] = leaf;
+            }
+        }
+        double acc[2] = {1.0, 0.0}, t[2];
+        for (int b = 0; b < nh; b++) {
+            double sg[2] = {hA[b], hB[b]};
+            or_combine(acc, sg, t);
+            acc[0] = t[0];
+            acc[1] = t[1];
+        }
+        Aout[q] = acc[0];
+        Bout[q] = acc[1];
+        Iout[q] = acc[0] * c.bg + acc[1];
+        if (hit_leaf) {
+            for (int b = 0; b < hcap; b++) {
+                hit_leaf[q * hcap + b] = b < nh ? (int32_t)hl[b] : -1;
+                hit_s[q * hcap + b] = b < nh ? hs[b] : 0.0;
+            }
+        }
+    }
+    return 0;
+}
+
+/* J of a degree-R tree at parameter points (for tests and generators' checks). */
+void or_ho_map(const double *geom, int tree, int64_t m, const double *t, double *out)
+{
+    int R = (int)geom[0];
+    orho H;
+    ho_init(&H, R, geom + 1 + 3 * (R + 1) * (R + 1) * tree);
+    for (int64_t i = 0; i < m; i++) ho_eval(&H, t[2 * i], t[2 * i + 1], out + 3 * i, NULL, NULL);
+}

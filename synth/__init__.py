@@ -35,6 +35,12 @@ from .scene import (  # noqa: F401
     split_shares,
 )
 from .surface import (  # noqa: F401
+    gl_nodes,
+    ho_geom,
+    ho_hexagon_trees,
+    ho_random_forest,
+    ho_surface_forest,
+    ho_tree,
     hexagon_cameras,
     hexagon_corners,
     leaf_corner_points,

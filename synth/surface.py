@@ -174,3 +174,66 @@ def hexagon_cameras(w=1024, h=1024, background=0.2) -> List[Camera]:
     eye1 = c + 3.8 * np.array([-0.55, 0.35, 0.76])
     return [perspective_camera(eye0, c, [0.0, 0.0, 1.0], 1.0, 60.0, w, h, 10.0, background),
             perspective_camera(eye1, c, [0.0, 0.0, 1.0], 1.0, 60.0, w, h, 10.0, background)]
+
+
+# ----------------------------------------------------------------------------
+# degree-R trees (eq. nodal, eq. tensorgeom)
+# ----------------------------------------------------------------------------
+
+
+def gl_nodes(R: int) -> np.ndarray:
+    """Gauss-Lobatto nodes on [0, 1] for degree R (2 or 3)."""
+    if R == 2:
+        return np.array([0.0, 0.5, 1.0])
+    if R == 3:
+        a = 0.5 / math.sqrt(5.0)
+        return np.array([0.0, 0.5 - a, 0.5 + a, 1.0])
+    raise ValueError("degree 2 or 3")
+
+
+def ho_tree(fn, R: int) -> np.ndarray:
+    """Control points z_{m1, m2} = fn(eta_m1, eta_m2) of one tree: [(R+1)^2, 3], m1 fastest."""
+    eta = gl_nodes(R)
+    t2, t1 = np.meshgrid(eta, eta, indexing="ij")
+    return np.asarray(fn(t1.ravel(), t2.ravel()), np.float64).reshape(-1, 3)
+
+
+def ho_geom(trees, R: int) -> np.ndarray:
+    """geom_params of a degree-R surface forest: [R, control points of every tree]."""
+    return np.concatenate([[float(R)]] + [np.asarray(t, np.float64).ravel() for t in trees])
+
+
+def ho_hexagon_trees(R: int, height=None):
+    """The hexagon's two trees with the surface lifted to z = height(x, y) (None: flat),
+    interpolated at the Gauss-Lobatto grid of degree R."""
+    corners = hexagon_corners()
+    trees = []
+    for k in range(2):
+        def fn(t1, t2, k=k):
+            p = patch_point(corners[k], t1, t2)
+            if height is not None:
+                p[:, 2] = height(p[:, 0], p[:, 1])
+            return p
+        trees.append(ho_tree(fn, R))
+    return trees
+
+
+def ho_surface_forest(trees, R: int, level, x, y, tree) -> Forest:
+    nt = len(trees)
+    f = _sorted_forest(level, x, y, np.zeros(len(level), np.uint32), np.asarray(tree, np.int64), "surface_ho",
+                       ho_geom(trees, R), nt)
+    return f
+
+
+def ho_random_forest(rng, trees, R: int, lmin=1, lmax=4, p_split=0.5) -> Forest:
+    """Quadtrees refined at random on degree-R trees."""
+    lv, x, y, tr = uniform_quadtrees(len(trees), lmin)
+    done = [], [], [], []
+    for _ in range(lmin, lmax):
+        split = rng.random(len(lv)) < p_split
+        for acc, a in zip(done, (lv, x, y, tr)):
+            acc.append(a[~split])
+        lv, x, y, tr = _children(lv[split], x[split], y[split], tr[split])
+    for acc, a in zip(done, (lv, x, y, tr)):
+        acc.append(a)
+    return ho_surface_forest(trees, R, *(np.concatenate(a) for a in done))
