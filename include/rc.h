@@ -68,7 +68,7 @@ typedef int32_t rc_status;
 #define RC_MAXTREES 64
 #define RC_MAXLISTS 16     /* shares rc_merge_lists takes at once */
 
-enum { RC_GEOM_UNIT_CUBE = 0, RC_GEOM_SHELL6 = 1, RC_GEOM_SURFACE = 2 };
+enum { RC_GEOM_UNIT_CUBE = 0, RC_GEOM_SHELL6 = 1, RC_GEOM_SURFACE = 2, RC_GEOM_SURFACE2 = 3, RC_GEOM_SURFACE3 = 4 };
 enum { RC_FIELD_CONST = 0, RC_FIELD_TRILINEAR = 1, RC_FIELD_CONST_EQ = 2, RC_FIELD_SURFACE = 3 };
 enum { RC_INT_ANALYTIC = 0, RC_INT_RK4 = 1, RC_INT_GAUSS2 = 2, RC_INT_SIMPSON = 3 };
 #define RC_ADAPT_MAXDEPTH 16  /* deepest halving of the adaptive recursion */
@@ -88,10 +88,15 @@ enum { RC_INT_ANALYTIC = 0, RC_INT_RK4 = 1, RC_INT_GAUSS2 = 2, RC_INT_SIMPSON = 
  *   J(t1, t2) = P00 (1-t1)(1-t2) + P10 t1 (1-t2) + P01 (1-t1) t2 + P11 t1 t2
  *   (a surface, Sec. 2.8; the bilinear case of App. A.1).  Leaves have z = 0
  *   and (x, y) anchors in the tree's parameter square.  geom_table holds 12
- *   doubles per tree: P00, P10, P01, P11. */
+ *   doubles per tree: P00, P10, P01, P11.
+ * RC_GEOM_SURFACE2, RC_GEOM_SURFACE3: as RC_GEOM_SURFACE with each tree's map
+ *   the tensor product of degree-R Lagrange polynomials (R = 2, 3) on the
+ *   Gauss-Lobatto nodes of [0, 1] (eq. nodal, eq. tensorgeom): geom_table
+ *   holds (R+1)^2 control points z_{m1, m2} of 3 doubles per tree, m1 fastest
+ *   (the map's values at the node pairs). */
 typedef struct rc_forest {
-    int32_t ntrees;             /* trees in the share: 1 (unit cube), 6 (shell), 1 .. 6 (surface) */
-    int32_t geom;               /* RC_GEOM_UNIT_CUBE, RC_GEOM_SHELL6 or RC_GEOM_SURFACE */
+    int32_t ntrees;             /* trees in the share: 1 (unit cube), 6 (shell), 1 .. 6 (surfaces) */
+    int32_t geom;               /* RC_GEOM_* */
     int64_t nleaves;            /* N >= 1 */
     const int64_t *tree_begin;  /* [host] ntrees + 1 leaf offsets per tree */
     const uint8_t *level;       /* [device] N leaf levels, 0 .. RC_QMAXLEVEL */
@@ -267,6 +272,21 @@ rc_status rc_prune_visible(const rc_forest *forest, const rc_index *index, const
  * ray crossing shared leaf edges is counted once.  A candidate holds up to two
  * zero-length records (s, s, A, B) in the layout of the shell, an unused one
  * (1, 0, 1, 0); hit[] counts them and sio[] holds (s, s) per hit.
+ *
+ * RC_GEOM_SURFACE2 / 3 forests (App. A.1, higher degree): the two planes
+ * through the pixel's ray, applied to the control points moved to camera
+ * space (eq. camerapoints), give two polynomials whose Bernstein coefficients
+ * over the leaf square bound them.  The leaf square is searched depth first:
+ * sub-squares where either keeps one sign are dropped, Newton's method runs
+ * from the centre of the others (from two subdivisions down, splitting where
+ * it does not end in the sub-square, at most 16 deep), and a converged root is
+ * polished canonically on the tree's polynomials (snapped to a 2^-40 grid,
+ * two Newton steps) so that it counts once, in the leaf whose half-open square
+ * holds it.  The search visits at most 2048 sub-squares per candidate (a ray
+ * lying in the surface decides none).  A candidate keeps its two nearest
+ * hits; hit[] counts all.  Leaf
+ * rectangles come from the camera-aligned box of the leaf's Bernstein
+ * coefficients (App. A.2).
  */
 rc_status rc_segments(const rc_forest *forest, const rc_fields *fields, const void *dcams, int32_t ncams,
                       const rc_vforest *vf, const rc_integrator *integ, float *rec_leaf, uint8_t *hit,
@@ -287,8 +307,10 @@ rc_status rc_segments(const rc_forest *forest, const rc_fields *fields, const vo
  * RC_GEOM_SHELL6 forests: records hold two intervals as in rc_segments
  * (rec_node [device, cap_rec * 8]); a node's intervals are its children's
  * merged by depth, touching ones combined, and the six roots' intervals are
- * folded in depth order.  RC_GEOM_SURFACE forests: the same with the hits as
- * zero-length intervals (a tree's patch meets a ray at most twice).
+ * folded in depth order.  Surface forests: the same with the hits as
+ * zero-length intervals (a bilinear tree's patch meets a ray at most twice; a
+ * node of a degree-R tree keeps two runs of hits, joining the closest runs
+ * beyond that).
  */
 rc_status rc_composite(const rc_forest *forest, const rc_index *index, const void *dcams, int32_t ncams,
                        const rc_vforest *vf, const float *rec_leaf, float *rec_node, int64_t total_pixels,
@@ -313,7 +335,7 @@ rc_status rc_composite(const rc_forest *forest, const rc_index *index, const voi
  * floats]; *n_entries [device] receives the total.  Entries are written only
  * when the total fits cap_entries (cap_entries = 0 asks for the count only);
  * the caller reads n_entries and calls again with more room otherwise.
- * ws [device, rc_lists_workspace_bytes()].  RC_GEOM_SHELL6 and RC_GEOM_SURFACE: RC_EUNSUPPORTED.
+ * ws [device, rc_lists_workspace_bytes()].  RC_GEOM_SHELL6 and surface forests: RC_EUNSUPPORTED.
  */
 size_t rc_lists_workspace_bytes(const rc_index *index, int32_t ncams, int64_t total_pixels);
 rc_status rc_composite_lists(const rc_forest *forest, const rc_index *index, const void *dcams, int32_t ncams,
@@ -352,7 +374,7 @@ rc_status rc_merge_lists(const void *dcams, int32_t ncams, int64_t total_pixels,
  * fixed order.  dL_dkappa, dL_deps [device, layout of rc_fields] are
  * overwritten, or added to when accumulate != 0.  adj_leaf [device,
  * cap_cand * 2] and adj_node [device, cap_rec * 2] are scratch.
- * RC_GEOM_SHELL6 and RC_GEOM_SURFACE forests return RC_EUNSUPPORTED.
+ * RC_GEOM_SHELL6 and surface forests return RC_EUNSUPPORTED.
  */
 rc_status rc_segments_backward(const rc_forest *forest, const rc_index *index, const rc_fields *fields,
                                const void *dcams, int32_t ncams, const rc_vforest *vf,

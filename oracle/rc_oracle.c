@@ -2091,7 +2091,8 @@ static int ho_hits(const orcam *cm, const orho *H, const double *rho, const doub
     int st_i1[4 * OR_HO_MAXDEPTH + 4], st_i2[4 * OR_HO_MAXDEPTH + 4], st_d[4 * OR_HO_MAXDEPTH + 4], sp = 0;
     st_i1[0] = st_i2[0] = st_d[0] = 0;
     sp = 1;
-    while (sp > 0) {
+    /* a ray lying in the surface leaves every square undecided: bounded work */
+    for (long visits = 0; sp > 0 && visits < 1000000; visits++) {
         sp--;
         int i1 = st_i1[sp], i2 = st_i2[sp], d = st_d[sp];
         double h = ldexp(1.0, -d), a1 = i1 * h, a2 = i2 * h;

@@ -33,7 +33,7 @@ inline rc_status check_forest(const rc_forest* f) {
         if (f->ntrees != 1) return RC_EUNSUPPORTED;
     } else if (f->geom == RC_GEOM_SHELL6) {
         if (f->ntrees != 6 || !f->geom_table || !f->tree_begin) return RC_EINVAL;
-    } else if (f->geom == RC_GEOM_SURFACE) {
+    } else if (f->geom == RC_GEOM_SURFACE || f->geom == RC_GEOM_SURFACE2 || f->geom == RC_GEOM_SURFACE3) {
         if (f->ntrees < 1 || f->ntrees > 6 || !f->geom_table || !f->tree_begin) return RC_EINVAL;
     } else {
         return RC_EUNSUPPORTED;
@@ -48,7 +48,13 @@ inline rc_status check_forest(const rc_forest* f) {
 }
 
 inline bool is_shell(const rc_forest* f) { return f->geom == RC_GEOM_SHELL6; }
-inline bool is_surface(const rc_forest* f) { return f->geom == RC_GEOM_SURFACE; }
+inline bool is_surface(const rc_forest* f) {
+    return f->geom == RC_GEOM_SURFACE || f->geom == RC_GEOM_SURFACE2 || f->geom == RC_GEOM_SURFACE3;
+}
+// Degree of a surface forest's tree maps (1: bilinear).
+inline int surface_degree(const rc_forest* f) {
+    return f->geom == RC_GEOM_SURFACE2 ? 2 : f->geom == RC_GEOM_SURFACE3 ? 3 : 1;
+}
 // Geometries whose records hold two depth-tagged intervals and whose node
 // rectangles are unions of the children's.
 inline bool is_curved(const rc_forest* f) { return is_shell(f) || is_surface(f); }
@@ -63,6 +69,9 @@ rc_status rc_shell_composite(const rc_forest* f, const rc_index* ix, const void*
                              float* B, float* I, const rc_tuning* tune, hipStream_t st);
 // Surface forests: segments (rc_surface.hip); compositing is the shell's with
 // zero-length intervals.
+rc_status rc_surface_ho_segments(const rc_forest* f, const rc_fields* fl, const void* dcams, const rc_vforest* vf,
+                                 const rc_integrator* in, float* rec_leaf, uint8_t* hit, double* sio,
+                                 const rc_tuning* tune, hipStream_t st);
 rc_status rc_surface_segments(const rc_forest* f, const rc_fields* fl, const void* dcams, const rc_vforest* vf,
                               const rc_integrator* in, float* rec_leaf, uint8_t* hit, double* sio,
                               const rc_tuning* tune, hipStream_t st);

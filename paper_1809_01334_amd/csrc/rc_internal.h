@@ -150,20 +150,27 @@ __device__ inline void axis_pixels(const Cam& c, double e0, double e1, double z0
     }
 }
 
-__device__ inline Rect box_rect(const Cam& c, const double lo[3], const double hi[3]) {
+// Pixel rectangle of a camera-aligned box [x0, x1] x [y0, y1] x [z0, z1]
+// (coordinates along t, u and vh from the eye), clipped to depth [n, f].
+__device__ inline Rect cam_rect(const Cam& c, double x0, double x1, double y0, double y1, double z0, double z1) {
     Rect r{1, 0, 1, 0};
-    double z0 = extent_lo(c.vh, lo, hi, c.o);
-    double z1 = extent_hi(c.vh, lo, hi, c.o);
     if (z1 < c.n || z0 > c.zfar) return r;
     double zc0 = z0 < c.n ? c.n : z0;
     double zc1 = z1 > c.zfar ? c.zfar : z1;
-    double x0 = extent_lo(c.t, lo, hi, c.o), x1 = extent_hi(c.t, lo, hi, c.o);
-    double y0 = extent_lo(c.u, lo, hi, c.o), y1 = extent_hi(c.u, lo, hi, c.o);
     Rect q;
     axis_pixels(c, x0, x1, zc0, zc1, c.cx, c.w, q.i0, q.i1);
     axis_pixels(c, y0, y1, zc0, zc1, c.cy, c.h, q.j0, q.j1);
     if (q.empty()) return r;
     return q;
+}
+
+__device__ inline Rect box_rect(const Cam& c, const double lo[3], const double hi[3]) {
+    double z0 = extent_lo(c.vh, lo, hi, c.o);
+    double z1 = extent_hi(c.vh, lo, hi, c.o);
+    if (z1 < c.n || z0 > c.zfar) return Rect{1, 0, 1, 0};
+    double x0 = extent_lo(c.t, lo, hi, c.o), x1 = extent_hi(c.t, lo, hi, c.o);
+    double y0 = extent_lo(c.u, lo, hi, c.o), y1 = extent_hi(c.u, lo, hi, c.o);
+    return cam_rect(c, x0, x1, y0, y1, z0, z1);
 }
 
 // ---------------------------------------------------------------------------

@@ -8,6 +8,7 @@
 #include "rc_internal.h"
 #include "rc_shell.h"
 #include "rc_surface.h"
+#include "rc_surface_ho.h"
 
 namespace rc {
 namespace {
@@ -74,6 +75,30 @@ struct PruneSrc {
             it.r = box_rect(cams[cam], lo, hi);
             it.val = I64x3{0, 0, it.r.area()};
         }
+        return it;
+    }
+};
+
+// Leaves of a degree-R surface forest: rectangles from the camera-space
+// Bernstein coefficients of the leaf (App. A.2).
+template <int R>
+struct PruneSrcHo {
+    const Cam* cams;
+    const uint8_t* level;
+    const uint32_t *x, *y;
+    int64_t N;
+    HoGeom G;
+    int64_t tb[7];
+    int ntrees;
+    int16_t* stash;
+    __device__ Item operator()(int64_t i) const {
+        Item it;
+        int64_t cam = divu(i, N), l = i - cam * N;
+        int k = 0;
+        while (k + 1 < ntrees && l >= tb[k + 1]) k++;
+        it.r = ho_rect<R>(cams[cam], G, k, level[l], x[l], y[l]);
+        it.val = it.r.empty() ? I64x3{0, 0, 0} : I64x3{1, it.r.area(), 0};
+        store_rect(stash + 4 * i, it.r);
         return it;
     }
 };
@@ -316,7 +341,24 @@ extern "C" rc_status rc_prune_visible(const rc_forest* f, const rc_index* ix, co
         RC_HIP(launch_scan2<I64x3>(items, src, stash, dst, (I64x3*)ws, st));
     } else {
         // leaves first; node rectangles are unions of their children's
-        RC_HIP(launch_scan2<I64x3>(items, src, stash, dst, (I64x3*)ws, st));
+        int R = surface_degree(f);
+        if (is_surface(f) && R > 1) {
+            HoGeom G;
+            ho_geom_init(R, f->geom_table, G);
+            int64_t tb7[7];
+            for (int k = 0; k < 7; k++) tb7[k] = k <= f->ntrees ? f->tree_begin[k] : N;
+            if (R == 2) {
+                PruneSrcHo<2> hs{cams, f->level, f->x, f->y, N, G, {}, f->ntrees, src.stash};
+                for (int k = 0; k < 7; k++) hs.tb[k] = tb7[k];
+                RC_HIP(launch_scan2<I64x3>(items, hs, stash, dst, (I64x3*)ws, st));
+            } else {
+                PruneSrcHo<3> hs{cams, f->level, f->x, f->y, N, G, {}, f->ntrees, src.stash};
+                for (int k = 0; k < 7; k++) hs.tb[k] = tb7[k];
+                RC_HIP(launch_scan2<I64x3>(items, hs, stash, dst, (I64x3*)ws, st));
+            }
+        } else {
+            RC_HIP(launch_scan2<I64x3>(items, src, stash, dst, (I64x3*)ws, st));
+        }
         for (int l = ix->maxlevel - 1; l >= 1; l--) {
             int64_t cnt = L.slot_begin[l + 1] - L.slot_begin[l];
             if (cnt == 0) continue;

@@ -165,6 +165,8 @@ extern "C" rc_status rc_segments(const rc_forest* f, const rc_fields* fl, const 
     hipStream_t st = (hipStream_t)stream;
     // surface data goes with surface forests only
     if (is_surface(f) != (fl->kind == RC_FIELD_SURFACE)) return RC_EUNSUPPORTED;
+    if (is_surface(f) && surface_degree(f) > 1)
+        return rc_surface_ho_segments(f, fl, dcams, vf, in, rec_leaf, hit, sio, tune, st);
     if (is_surface(f)) return rc_surface_segments(f, fl, dcams, vf, in, rec_leaf, hit, sio, tune, st);
     if (is_shell(f)) return rc_shell_segments(f, fl, dcams, vf, in, rec_leaf, hit, sio, tune, st);
     if (in->method != RC_INT_ANALYTIC && (in->method != RC_INT_RK4 || in->c_rk > 0.0))

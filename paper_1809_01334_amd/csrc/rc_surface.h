@@ -174,22 +174,31 @@ __device__ inline Rect surf_rect(const Cam& c, const double* P, int level, uint3
 // corner transparency and intensity interpolated bilinearly at (u, v),
 // A = A_s^(1/cos phi) with cos phi = |n . r| / (|n| |r|) for the patch normal
 // n = dJ/dt1 x dJ/dt2 at the hit, B = I_s (1 - A).
-__device__ inline float2 surf_value(const float4& As, const float4& Is, const SurfPatch& S, const double r[3],
-                                    double t1, double t2, double u, double v) {
-    double j1[3], j2[3], n[3];
-#pragma unroll
-    for (int q = 0; q < 3; q++) {
-        j1[q] = S.b[q] + S.d[q] * t2;
-        j2[q] = S.c[q] + S.d[q] * t1;
-    }
-    scross(j1, j2, n);
-    float cphi = (float)(fabs(sdot(n, r)) / sqrt(sdot(n, n) * sdot(r, r)));
+__device__ inline float2 surf_model(const float4& As, const float4& Is, float cphi, double u, double v) {
     float uf = (float)u, vf = (float)v;
     float w0 = (1.0f - uf) * (1.0f - vf), w1 = uf * (1.0f - vf), w2 = (1.0f - uf) * vf, w3 = uf * vf;
     float as = w0 * As.x + w1 * As.y + w2 * As.z + w3 * As.w;
     float is = w0 * Is.x + w1 * Is.y + w2 * Is.z + w3 * Is.w;
     float A = as >= 1.0f ? 1.0f : exp2f(log2f(as) / cphi);
     return make_float2(A, is * (1.0f - A));
+}
+
+// cos phi between the ray r and the normal j1 x j2 of tangents j1, j2.
+__device__ inline float surf_cos(const double j1[3], const double j2[3], const double r[3]) {
+    double n[3];
+    scross(j1, j2, n);
+    return (float)(fabs(sdot(n, r)) / sqrt(sdot(n, n) * sdot(r, r)));
+}
+
+__device__ inline float2 surf_value(const float4& As, const float4& Is, const SurfPatch& S, const double r[3],
+                                    double t1, double t2, double u, double v) {
+    double j1[3], j2[3];
+#pragma unroll
+    for (int q = 0; q < 3; q++) {
+        j1[q] = S.b[q] + S.d[q] * t2;
+        j2[q] = S.c[q] + S.d[q] * t1;
+    }
+    return surf_model(As, Is, surf_cos(j1, j2, r), u, v);
 }
 
 }  // namespace rc

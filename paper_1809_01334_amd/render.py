@@ -60,12 +60,20 @@ class DeviceForest:
     @property
     def curved(self) -> bool:
         """Records hold two depth-tagged intervals (shell intervals, surface hits)."""
-        return self.geom in (L.RC_GEOM_SHELL6, L.RC_GEOM_SURFACE)
+        return self.geom in (L.RC_GEOM_SHELL6, L.RC_GEOM_SURFACE, L.RC_GEOM_SURFACE2, L.RC_GEOM_SURFACE3)
 
     @classmethod
     def from_synth(cls, forest, device):
-        geom = {"unit_cube": L.RC_GEOM_UNIT_CUBE, "shell6": L.RC_GEOM_SHELL6, "surface": L.RC_GEOM_SURFACE}[forest.geom]
-        table = forest.geom_params if geom != L.RC_GEOM_UNIT_CUBE else None
+        table = forest.geom_params
+        if forest.geom == "surface_ho":
+            # [R, control points]: the degree picks the geometry code
+            geom = {2: L.RC_GEOM_SURFACE2, 3: L.RC_GEOM_SURFACE3}[int(table[0])]
+            table = table[1:]
+        else:
+            geom = {"unit_cube": L.RC_GEOM_UNIT_CUBE, "shell6": L.RC_GEOM_SHELL6,
+                    "surface": L.RC_GEOM_SURFACE}[forest.geom]
+        if geom == L.RC_GEOM_UNIT_CUBE:
+            table = None
         return cls(forest.level, forest.x, forest.y, forest.z, device, forest.tree_begin, table, geom)
 
 
