@@ -116,6 +116,7 @@ def main():
     ap.add_argument("--no-integrators", action="store_true")
     ap.add_argument("--no-shares", action="store_true")
     ap.add_argument("--no-surface", action="store_true")
+    ap.add_argument("--no-surface-ho", action="store_true")
     ap.add_argument("--copy-calib", action="store_true",
                     help="end with plain 256 MiB device copies, the reference for HBM byte counters")
     args = ap.parse_args()
@@ -231,6 +232,8 @@ def main():
         out["shell_workload"] = bench_shell(torch, P, synth, max(args.steps // 10, 3))
     if not args.no_surface:
         out["surface_workload"] = bench_surface(torch, P, synth, max(args.steps // 5, 3))
+    if not args.no_surface_ho:
+        out["surface_ho_workload"] = bench_surface_ho(torch, P, synth, max(args.steps // 5, 3))
     if not args.no_shares:
         out["shares"] = bench_shares(torch, P, synth, scene, r, max(args.steps // 5, 3))
 
@@ -410,6 +413,36 @@ def bench_surface(torch, P, synth, steps):
         del r
     torch.cuda.empty_cache()
     return out
+
+
+def bench_surface_ho(torch, P, synth, steps):
+    """Degree-2 surface: the hexagon lifted to z = 0.35 sin(2x) cos(1.5y) and
+    interpolated on the Gauss-Lobatto grid of each tree, carrying the
+    Mandelbrot refinement (levels 4-11) and the transparent transfer, 1024^2."""
+    log("[bench] degree-2 surface workload: generating")
+    base, val = synth.mandelbrot_forest(4, 11)
+    trees = synth.ho_hexagon_trees(2, lambda x, y: 0.35 * np.sin(2 * x) * np.cos(1.5 * y))
+    f = synth.ho_surface_forest(trees, 2, base.level, base.x, base.y, base.tree_of_leaf())
+    cam = synth.hexagon_cameras(1024, 1024)[0]
+    r = P.Renderer(f, synth.mandelbrot_fields(val, 1), [cam], "analytic", 1, device="cuda:0")
+    c = r.counts
+    hit, _ = r.debug_segments(intervals=False)
+    H = int(hit[:c["ncand"]].to(torch.int64).sum().item())
+    r.forward()
+    r.capture()
+    r.replay()
+    ms = time_region(torch, r.replay, steps)
+    t_prune = time_region(torch, r.prune, steps)
+    t_seg = time_region(torch, r.segments, steps)
+    t_comp = time_region(torch, r.composite, steps)
+    log(f"[bench] degree-2 surface: visible {c['nvis']}, candidates {c['ncand']}, hits {H}; forward {ms:.3f} ms; "
+        f"prune {t_prune:.3f}, segments {t_seg:.3f}, composite {t_comp:.3f} ms")
+    del r
+    torch.cuda.empty_cache()
+    return {"workload": f"degree-2 lifted hexagon, Mandelbrot refinement levels 4-11 ({f.nleaves} leaves), "
+                        f"1024x1024, transparent transfer", "leaves": f.nleaves, "visible": c["nvis"],
+            "candidates": c["ncand"], "hits": H, "ms_per_step": ms, "hits_per_s": H / (ms * 1e-3),
+            "phase_ms": {"prune": t_prune, "segments": t_seg, "composite": t_comp}}
 
 
 def bench_shares(torch, P, synth, scene, r, steps, nshares=8):
