@@ -193,7 +193,7 @@ def main():
     # the other steps against their own bounds
     comp_bytes = C * REC_BYTES + r.cams.npix * PIX_BYTES
     prune_bytes = scene.forest.nleaves * 13 + counts["nvis"] * 20
-    out["steps"] = {
+    out["phase_roofline"] = {
         "composite": {"bound": "hbm", "algorithmic_bytes": comp_bytes,
                       "achieved_GBs": comp_bytes / (t_comp * 1e-3) / 1e9,
                       "frac": comp_bytes / (t_comp * 1e-3) / 1e9 / HBM_PEAK_GBS},
