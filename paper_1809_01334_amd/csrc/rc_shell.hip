@@ -285,15 +285,18 @@ __device__ inline void merge_runs(const float4 (&iv)[NQ], float4& o0, float4& o1
     }
 }
 
+// Children in Morton order; a surface (PTS) is a quadtree with z = 0, so only
+// the first four child slots can hold a child.
 template <bool PTS, bool UNIFORM>
 __device__ inline void shell_node(const ShellFold& S, int64_t dslot, int i, int j, float4& o0, float4& o1) {
-    float4 iv[16];
+    constexpr int NC = PTS ? 4 : 8;
+    float4 iv[2 * NC];
 #pragma unroll
-    for (int q = 0; q < 8; q++) {
+    for (int q = 0; q < NC; q++) {
         ChildDesc d = UNIFORM ? load_desc_scalar(S.C.desc, dslot * 8 + q) : load_desc(S.C.desc + dslot * 8 + q);
         child_intervals(S, d, i, j, iv[2 * q], iv[2 * q + 1]);
     }
-    merge_runs<PTS, 16>(iv, o0, o1);
+    merge_runs<PTS, 2 * NC>(iv, o0, o1);
 }
 
 template <bool PTS>
@@ -354,7 +357,7 @@ __global__ __launch_bounds__(256) void k_fold_root_shell(ShellFold S, int ntrees
         int j = (int)(loc / c.w);
         int i = (int)(loc - (int64_t)j * c.w);
         float4 iv[12];
-#pragma unroll
+#pragma clang loop unroll(full)
         for (int t = 0; t < 6; t++) {
             iv[2 * t] = empty_iv();
             iv[2 * t + 1] = empty_iv();
