@@ -66,6 +66,7 @@ typedef int32_t rc_status;
 #define RC_ABSENT (-1)        /* child slot without a node in this share */
 
 #define RC_MAXTREES 64
+#define RC_MAXCH 3          /* channels per call (RGB) */
 #define RC_MAXLISTS 16     /* shares rc_merge_lists takes at once */
 
 enum { RC_GEOM_UNIT_CUBE = 0, RC_GEOM_SHELL6 = 1, RC_GEOM_SURFACE = 2, RC_GEOM_SURFACE2 = 3, RC_GEOM_SURFACE3 = 4 };
@@ -105,10 +106,12 @@ typedef struct rc_forest {
 } rc_forest;
 
 /* Per-leaf coefficient data (Sec. 2.3): absorption kappa (beta in the paper)
- * and emission eps (gamma), single channel, leaf-major [leaf][corner] in SFC
- * order: one value per leaf for per-leaf constants, eight consecutive corner
- * values (corner c = bx + 2 by + 4 bz, 32-byte aligned rows) for trilinear
- * data interpolated in leaf reference coordinates.  RC_FIELD_SURFACE (surface
+ * and emission eps (gamma), leaf-major [leaf][corner] in SFC order: one value
+ * per leaf for per-leaf constants, eight consecutive corner values (corner
+ * c = bx + 2 by + 4 bz, 32-byte aligned rows) for trilinear data interpolated
+ * in leaf reference coordinates.  nch channels (1 .. RC_MAXCH, e.g. RGB, each
+ * converted to its own (A, B) as in Sec. 4.1) follow one another:
+ * kappa[ch][leaf][corner].  RC_FIELD_SURFACE (surface
  * forests only, analytic method): kappa holds the surface's transparency A_s
  * and eps its intensity I_s at the leaf's four corners (corner c = bx + 2 by),
  * interpolated bilinearly at the hit; the hit contributes A = A_s^(1/cos phi),
@@ -119,9 +122,9 @@ typedef struct rc_fields {
                                    kappa and equilibrium intensity I = eps / kappa in place of eps,
                                    eq. BIrelation: B = I (1 - A); analytic integration only) or
                                    RC_FIELD_SURFACE */
-    int32_t nch;                /* channels; 1 */
-    const float *kappa;         /* [device] N * ncorner, 16-byte aligned */
-    const float *eps;           /* [device] N * ncorner, 16-byte aligned */
+    int32_t nch;                /* channels, 1 .. RC_MAXCH */
+    const float *kappa;         /* [device] nch * N * ncorner, 16-byte aligned */
+    const float *eps;           /* [device] nch * N * ncorner, 16-byte aligned */
 } rc_fields;
 
 /* Segment integrator (Sec. 2.3, 2.7):
@@ -250,8 +253,11 @@ rc_status rc_prune_visible(const rc_forest *forest, const rc_index *index, const
  * whose shared faces give bitwise equal crossing depths) and integrate
  * I' = eps - kappa I over the hit interval from the far end toward the camera
  * (eq. ABconstant, or RK4 per eq. RKresultAB over equal substeps combined by
- * eq. aggregate).  rec_leaf[device, cap_cand * 2] receives (A, B) per
- * candidate, the identity (1, 0) on a miss.  Optional debug outputs (NULL to
+ * eq. aggregate).  rec_leaf[device, nch * cap_cand * 2] receives (A, B) per
+ * candidate and channel (channel-major blocks of cap_cand records), the
+ * identity (1, 0) on a miss.  With several channels the pairing runs once and
+ * every channel is integrated on the same segments (the unit cube's closed
+ * form and fixed-step RK4; the other paths take one channel at a time).  Optional debug outputs (NULL to
  * skip): hit[device, cap_cand] 1/0 and sio[device, cap_cand * 2] the hit
  * interval in the ray parameter (alpha for perspective, depth for
  * orthographic), zeros on a miss.
@@ -300,7 +306,8 @@ rc_status rc_segments(const rc_forest *forest, const rc_fields *fields, const vo
  * node's midplane), absent or invisible children acting as the identity.
  * The roots are folded straight into the images: A, B and I = A I_b + B
  * [device, total_pixels floats each; total_pixels as returned by
- * rc_camera_prepare].  rec_node [device, cap_rec * 2] holds the
+ * rc_camera_prepare].  One channel per call: for channel ch pass that
+ * channel's blocks of rec_leaf and rec_node and its images.  rec_node [device, cap_rec * 2] holds the
  * internal-node records (kept for the adjoint).  vf->cap_cand must be at
  * least 1: rec_leaf always holds at least one record.
  *
@@ -371,7 +378,8 @@ rc_status rc_merge_lists(const void *dcams, int32_t ncams, int64_t total_pixels,
  * entering it from behind; no division), so that a segment receives
  * dL/dA = g T J and dL/dB = g T; then differentiate each segment's
  * evaluation (recomputed from the coefficients) and reduce per leaf in a
- * fixed order.  dL_dkappa, dL_deps [device, layout of rc_fields] are
+ * fixed order.  Several channels: rec_leaf, rec_node, dL_dI and the gradients
+ * hold channel-major blocks as in rc_segments and rc_composite.  dL_dkappa, dL_deps [device, layout of rc_fields] are
  * overwritten, or added to when accumulate != 0.  adj_leaf [device,
  * cap_cand * 2] and adj_node [device, cap_rec * 2] are scratch.
  * RC_GEOM_SHELL6 and surface forests return RC_EUNSUPPORTED.

@@ -25,6 +25,7 @@ RC_CAMERA_DOUBLES = 20
 RC_GEOM_UNIT_CUBE, RC_GEOM_SHELL6, RC_GEOM_SURFACE, RC_GEOM_SURFACE2, RC_GEOM_SURFACE3 = 0, 1, 2, 3, 4
 RC_MAXTREES = 64
 RC_MAXLISTS = 16
+RC_MAXCH = 3
 RC_ABSENT = -1
 RC_FIELD_CONST, RC_FIELD_TRILINEAR, RC_FIELD_CONST_EQ, RC_FIELD_SURFACE = 0, 1, 2, 3
 RC_INT_ANALYTIC, RC_INT_RK4, RC_INT_GAUSS2, RC_INT_SIMPSON = 0, 1, 2, 3

@@ -502,6 +502,12 @@ __global__ __launch_bounds__(256) void k_grad_leaves(const int64_t* counts, int6
 }  // namespace
 }  // namespace rc
 
+static rc_status backward_one(const rc_forest* f, const rc_index* ix, const rc_fields* fl, const void* dcams,
+                              int32_t ncams, const rc_vforest* vf, const rc_integrator* in, const float* rec_leaf,
+                              const float* rec_node, int64_t npix, const float* dLdI, float* adj_leaf,
+                              float* adj_node, float* dk, float* de, int32_t accumulate, void* ws,
+                              const rc_tuning* tune, hipStream_t st);
+
 extern "C" rc_status rc_segments_backward(const rc_forest* f, const rc_index* ix, const rc_fields* fl,
                                           const void* dcams, int32_t ncams, const rc_vforest* vf,
                                           const rc_integrator* in, const float* rec_leaf, const float* rec_node,
@@ -524,7 +530,27 @@ extern "C" rc_status rc_segments_backward(const rc_forest* f, const rc_index* ix
     if ((s = check_tables(vf, ix, ncams)) != RC_OK) return s;
     if (!ws || ws_bytes < rc_workspace_bytes(f, ix, ncams, vf)) return RC_EWORKSPACE;
     hipStream_t st = (hipStream_t)stream;
+    // channels one after the other, in channel-major blocks of every per-channel array
+    int64_t fstride = f->nleaves * (fl->kind == RC_FIELD_TRILINEAR ? 8 : 1);
+    for (int ch = 0; ch < fl->nch; ch++) {
+        rc_fields one = *fl;
+        one.nch = 1;
+        one.kappa = fl->kappa + ch * fstride;
+        one.eps = fl->eps + ch * fstride;
+        s = backward_one(f, ix, &one, dcams, ncams, vf, in, rec_leaf + ch * vf->cap_cand * 2,
+                         nodes ? rec_node + ch * vf->cap_rec * 2 : rec_node, npix, dLdI + ch * npix, adj_leaf,
+                         adj_node, dk + ch * fstride, de + ch * fstride, accumulate, ws, tune, st);
+        if (s != RC_OK) return s;
+    }
+    return RC_OK;
+}
 
+// One channel of rc_segments_backward (arguments validated).
+static rc_status backward_one(const rc_forest* f, const rc_index* ix, const rc_fields* fl, const void* dcams,
+                              int32_t ncams, const rc_vforest* vf, const rc_integrator* in, const float* rec_leaf,
+                              const float* rec_node, int64_t npix, const float* dLdI, float* adj_leaf,
+                              float* adj_node, float* dk, float* de, int32_t accumulate, void* ws,
+                              const rc_tuning* tune, hipStream_t st) {
     FoldCtx C = make_fold_ctx(f, ix, dcams, ncams, vf, rec_leaf, rec_node);
     hipLaunchKernelGGL(k_adj_root, dim3(stride_grid(npix, 256, tuned(tune, 2, 256 * 16))), dim3(256), 0, st, C,
                        ix->root, npix, dLdI,

@@ -96,7 +96,7 @@ inline rc_status check_vforest(const rc_vforest* vf, bool need_nodes) {
 
 inline rc_status check_fields(const rc_fields* fl, const rc_integrator* in) {
     if (!fl || !fl->kappa || !fl->eps || !in) return RC_EINVAL;
-    if (fl->nch != 1) return RC_EUNSUPPORTED;
+    if (fl->nch < 1 || fl->nch > RC_MAXCH) return RC_EINVAL;
     if (fl->kind != RC_FIELD_CONST && fl->kind != RC_FIELD_TRILINEAR && fl->kind != RC_FIELD_CONST_EQ &&
         fl->kind != RC_FIELD_SURFACE)
         return RC_EUNSUPPORTED;

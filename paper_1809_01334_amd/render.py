@@ -78,14 +78,18 @@ class DeviceForest:
 
 
 class DeviceFields:
-    """Coefficients leaf-major: kappa, eps of shape [N, ncorner] (ncorner 1 or 8).
+    """Coefficients leaf-major: kappa, eps of shape [N, ncorner] (ncorner 1 or 8), or
+    [nch, N, ncorner] for several channels.
     equilibrium=True: constant kappa and the equilibrium intensity I in place of eps.
     surface=True: [N, 4] corner transparency A_s (kappa) and intensity I_s (eps)."""
 
     def __init__(self, kappa: torch.Tensor, eps: torch.Tensor, equilibrium: bool = False, surface: bool = False):
-        assert kappa.shape == eps.shape and kappa.dim() == 2 and kappa.shape[1] in ((4,) if surface else (1, 8))
+        assert kappa.shape == eps.shape and kappa.dim() in (2, 3)
+        self.nch = int(kappa.shape[0]) if kappa.dim() == 3 else 1
+        assert 1 <= self.nch <= L.RC_MAXCH
+        assert kappa.shape[-1] in ((4,) if surface else (1, 8))
         assert kappa.dtype == torch.float32 and eps.dtype == torch.float32
-        assert not (equilibrium and kappa.shape[1] != 1)
+        assert not (equilibrium and kappa.shape[-1] != 1)
         self.kappa = kappa.contiguous()
         self.eps = eps.contiguous()
         if surface:
@@ -93,13 +97,14 @@ class DeviceFields:
         elif equilibrium:
             self.kind = L.RC_FIELD_CONST_EQ
         else:
-            self.kind = L.RC_FIELD_TRILINEAR if kappa.shape[1] == 8 else L.RC_FIELD_CONST
-        self.struct = L.RcFields(self.kind, 1, _ptr(self.kappa), _ptr(self.eps))
+            self.kind = L.RC_FIELD_TRILINEAR if kappa.shape[-1] == 8 else L.RC_FIELD_CONST
+        self.struct = L.RcFields(self.kind, self.nch, _ptr(self.kappa), _ptr(self.eps))
 
     @staticmethod
     def leaf_major(a) -> np.ndarray:
-        """[ncorner][N] (the generators' layout) to [N][ncorner]."""
-        return np.ascontiguousarray(np.asarray(a, np.float32).T)
+        """[ncorner][N] (the generators' layout) to [N][ncorner]; [nch][ncorner][N] to [nch][N][ncorner]."""
+        a = np.asarray(a, np.float32)
+        return np.ascontiguousarray(a.T if a.ndim == 2 else a.transpose(0, 2, 1))
 
     @classmethod
     def from_synth(cls, fields, device):
@@ -345,12 +350,13 @@ class Renderer:
         cap_vis, cap_cand, cap_rec = caps
         self.vf = VForest(self.device, N, nc, self.nslots, cap_vis, cap_cand, cap_rec, self.index.ninternal)
         self.ws = _empty(workspace_bytes(self.forest, self.index, nc, self.vf), torch.uint8, self.device)
-        self.rec_leaf = _empty(self.rec_floats * cap_cand, torch.float32, self.device)
-        self.rec_node = _empty(self.rec_floats * cap_rec, torch.float32, self.device)
+        nch = self.fields.nch
+        self.rec_leaf = _empty(nch * self.rec_floats * cap_cand, torch.float32, self.device)
+        self.rec_node = _empty(nch * self.rec_floats * max(cap_rec, 1), torch.float32, self.device)
         P = self.cams.npix
-        self.A = _empty(P, torch.float32, self.device)
-        self.B = _empty(P, torch.float32, self.device)
-        self.I = _empty(P, torch.float32, self.device)
+        self.A = _empty(nch * P, torch.float32, self.device)
+        self.B = _empty(nch * P, torch.float32, self.device)
+        self.I = _empty(nch * P, torch.float32, self.device)
         self.bwd_ready = False
         self.prune()
         self.counts = self.vf.read_counts()
@@ -373,8 +379,12 @@ class Renderer:
                     self.tuning, self.c_rk)
 
     def composite(self):
-        rc_composite(self.forest, self.index, self.cams, self.vf, self.rec_leaf, self.rec_node, self.A, self.B,
-                     self.I, self.tuning)
+        # one channel per call, on that channel's blocks of the records and images
+        nl, nn, P = self.rec_floats * self.vf.cap_cand, self.rec_floats * max(self.vf.cap_rec, 1), self.cams.npix
+        for ch in range(self.fields.nch):
+            rc_composite(self.forest, self.index, self.cams, self.vf, self.rec_leaf[ch * nl:(ch + 1) * nl],
+                         self.rec_node[ch * nn:(ch + 1) * nn], self.A[ch * P:(ch + 1) * P],
+                         self.B[ch * P:(ch + 1) * P], self.I[ch * P:(ch + 1) * P], self.tuning)
 
     def composite_lists(self):
         """This share's per-pixel lists after prune and segments: offsets [P + 1]
@@ -476,8 +486,9 @@ class Renderer:
         hit, _ = self.debug_segments(intervals=False)
         return int(hit[:self.counts["ncand"]].to(torch.int64).sum().item())
 
-    def image(self, t: torch.Tensor, k: int = 0) -> torch.Tensor:
-        return self.cams.image(t, k)
+    def image(self, t: torch.Tensor, k: int = 0, ch: int = 0) -> torch.Tensor:
+        P = self.cams.npix
+        return self.cams.image(t[ch * P:(ch + 1) * P], k)
 
 
 class RenderFn(torch.autograd.Function):

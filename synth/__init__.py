@@ -33,6 +33,7 @@ from .scene import (  # noqa: F401
     constant_fields,
     equilibrium_fields,
     split_shares,
+    stack_channels,
 )
 from .surface import (  # noqa: F401
     gl_nodes,

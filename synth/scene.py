@@ -60,13 +60,30 @@ class Forest:
 
 @dataclasses.dataclass
 class Fields:
-    kind: str  # "const", "trilinear", or "const_eq" (eps holds the equilibrium intensity I)
-    kappa: np.ndarray  # float32 [ncorner][N]
-    eps: np.ndarray  # float32 [ncorner][N]
+    kind: str  # "const", "trilinear", "const_eq" (eps holds the equilibrium intensity I) or "surface"
+    kappa: np.ndarray  # float32 [ncorner][N], or [nch][ncorner][N] for several channels
+    eps: np.ndarray  # float32, as kappa
 
     @property
     def ncorner(self) -> int:
-        return int(self.kappa.shape[0])
+        return int(self.kappa.shape[-2])
+
+    @property
+    def nch(self) -> int:
+        return 1 if self.kappa.ndim == 2 else int(self.kappa.shape[0])
+
+    def channel(self, ch: int) -> "Fields":
+        """Single-channel fields of channel ch."""
+        if self.kappa.ndim == 2:
+            assert ch == 0
+            return self
+        return Fields(self.kind, self.kappa[ch], self.eps[ch])
+
+
+def stack_channels(fields: List["Fields"]) -> "Fields":
+    """Several single-channel fields of one kind as the channels of one."""
+    assert len({f.kind for f in fields}) == 1
+    return Fields(fields[0].kind, np.stack([f.kappa for f in fields]), np.stack([f.eps for f in fields]))
 
 
 @dataclasses.dataclass

@@ -85,9 +85,12 @@ def test_null_and_unsupported_arguments():
     integ = L.RcIntegrator(L.RC_INT_RK4, 65)
     assert lib.rc_segments(ctypes.byref(f), ctypes.byref(fl), ctypes.c_void_p(16), 1, ctypes.byref(vf),
                            ctypes.byref(integ), ctypes.c_void_p(16), None, None, None, None) == L.RC_EINVAL
-    fl = L.RcFields(L.RC_FIELD_CONST, 2, ctypes.c_void_p(16), ctypes.c_void_p(16))
-    assert lib.rc_segments(ctypes.byref(f), ctypes.byref(fl), ctypes.c_void_p(16), 1, ctypes.byref(vf),
-                           ctypes.byref(integ), ctypes.c_void_p(16), None, None, None, None) == L.RC_EUNSUPPORTED
+    # 1 .. RC_MAXCH channels
+    integ = L.RcIntegrator(L.RC_INT_RK4, 4)
+    for nch in (0, L.RC_MAXCH + 1):
+        fl = L.RcFields(L.RC_FIELD_CONST, nch, ctypes.c_void_p(16), ctypes.c_void_p(16))
+        assert lib.rc_segments(ctypes.byref(f), ctypes.byref(fl), ctypes.c_void_p(16), 1, ctypes.byref(vf),
+                               ctypes.byref(integ), ctypes.c_void_p(16), None, None, None, None) == L.RC_EINVAL
 
 
 def test_sizes_are_consistent():
