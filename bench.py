@@ -52,8 +52,8 @@ PIX_BYTES = 12
 # WRITE_SIZE (calibrated on a 256 MiB device copy: x2.0 and x1.0), valid for
 # the kernel sources whose SHA-256 is given.
 MEASURED_TRAFFIC = {
-    "k_segments_rk4<2, 4>": {"bytes": 242969979, "sources": ("rc_segments.hip", "rc_internal.h"),
-                             "sha256": "db3802722e717f700f9b202c00064f2df4b1e62f5772252aaf99be7d86c3ccad"},
+    "k_segments_rk4<2, 4, 1>": {"bytes": 242939382, "sources": ("rc_segments.hip", "rc_internal.h"),
+                             "sha256": "3449b588b9a29dfe6f0e601d1a0a1416437f4c90c6cd1afd2eaf2dae77fcc8b3"},
 }
 COPY_CALIB_BYTES = 256 << 20
 
@@ -117,6 +117,7 @@ def main():
     ap.add_argument("--no-shares", action="store_true")
     ap.add_argument("--no-surface", action="store_true")
     ap.add_argument("--no-surface-ho", action="store_true")
+    ap.add_argument("--no-channels", action="store_true")
     ap.add_argument("--copy-calib", action="store_true",
                     help="end with plain 256 MiB device copies, the reference for HBM byte counters")
     args = ap.parse_args()
@@ -183,12 +184,12 @@ def main():
         "forward_eager_ms": ms_eager,
         "phase_ms": {"prune": t_prune, "segments": t_seg, "composite": t_comp},
     }
-    # dominant kernel: segment generation, one launch of k_segments_rk4<2, 4> per call
+    # dominant kernel: segment generation, one launch of k_segments_rk4<2, 4, 1> per call
     flops = SEG_FLOPS_FP32 * S + CAND_FLOPS_FP64 * C
     achieved = flops / (t_seg * 1e-3) / 1e12
     out["roofline"] = {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                       "frac": achieved / FP32_PEAK_TFLOPS, "traffic": measured_traffic("k_segments_rk4<2, 4>"),
-                       "kernel": "k_segments_rk4<2, 4>", "flop_per_launch": flops,
+                       "frac": achieved / FP32_PEAK_TFLOPS, "traffic": measured_traffic("k_segments_rk4<2, 4, 1>"),
+                       "kernel": "k_segments_rk4<2, 4, 1>", "flop_per_launch": flops,
                        "per_unit": f"{SEG_FLOPS_FP32} FP32/segment + {CAND_FLOPS_FP64} FP64/candidate"}
     # the other steps against their own bounds
     comp_bytes = C * REC_BYTES + r.cams.npix * PIX_BYTES
@@ -226,6 +227,8 @@ def main():
         out["adjoint_workload"] = bench_adjoint(torch, P, synth, max(args.steps // 2, 5))
     if not args.no_integrators:
         out["integrators"] = bench_integrators(torch, P, r, max(args.steps // 5, 3))
+    if not args.no_channels:
+        out["channels"] = bench_channels(torch, P, synth, scene, r, max(args.steps // 5, 3))
     if not args.no_batch:
         out["batched_workload"] = bench_batched(torch, P, synth, r, max(args.steps // 10, 3))
     if not args.no_shell:
@@ -371,6 +374,26 @@ def bench_shell(torch, P, synth, steps):
     del r
     torch.cuda.empty_cache()
     return out
+
+
+def bench_channels(torch, P, synth, scene, r, steps):
+    """The headline view with three channels (RGB-like: the fields scaled per
+    channel): one pairing feeds all three integrations."""
+    f = scene.fields
+    rgb = synth.stack_channels([synth.Fields(f.kind, (f.kappa * s).astype(np.float32), (f.eps * t).astype(np.float32))
+                                for s, t in ((1.0, 1.0), (0.7, 1.3), (1.4, 0.6))])
+    r3 = P.Renderer(scene.forest, rgb, r.cams.raw, "rk4", 4, device="cuda:0", index=r.index)
+    r3.forward()
+    r3.capture()
+    r3.replay()
+    ms = time_region(torch, r3.replay, steps)
+    t_seg = time_region(torch, r3.segments, steps)
+    t_seg1 = time_region(torch, r.segments, steps)
+    log(f"[bench] 3 channels: forward {ms:.3f} ms, segments {t_seg:.3f} ms (one channel {t_seg1:.3f} ms)")
+    del r3
+    torch.cuda.empty_cache()
+    return {"channels": 3, "ms_per_step": ms, "segments_ms": t_seg, "segments_one_channel_ms": t_seg1,
+            "segments_ratio_to_one_channel": t_seg / t_seg1}
 
 
 def bench_surface(torch, P, synth, steps):
