@@ -47,13 +47,21 @@ SURF_CAND_FLOPS_FP64 = 160
 REC_BYTES = 8
 SHELL_REC_BYTES = 33
 PIX_BYTES = 12
+#   constant-coefficient segment: per visible leaf its level and anchor (13 B),
+#   kappa and eps (8 B), rectangle and candidate offset (16 B), read once.
+ANALYTIC_LEAF_BYTES = 37
 
 # HBM traffic of the dominant kernel per launch, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (calibrated on a 256 MiB device copy: x2.0 and x1.0), valid for
 # the kernel sources whose SHA-256 is given.
 MEASURED_TRAFFIC = {
-    "k_segments_rk4<2, 4, 1>": {"bytes": 242939382, "sources": ("rc_segments.hip", "rc_internal.h"),
+    "k_segments_rk4<2, 4, 1>": {"bytes": 242985411, "sources": ("rc_segments.hip", "rc_internal.h"),
                              "sha256": "3449b588b9a29dfe6f0e601d1a0a1416437f4c90c6cd1afd2eaf2dae77fcc8b3"},
+    "k_segments_analytic<1>": {"bytes": 182133349, "sources": ("rc_segments.hip", "rc_internal.h"),
+                               "sha256": "3449b588b9a29dfe6f0e601d1a0a1416437f4c90c6cd1afd2eaf2dae77fcc8b3"},
+    # per forward of the headline view: every fold launch of one rc_composite call
+    "composite": {"bytes": 404498267, "sources": ("rc_composite.hip", "rc_composite.h", "rc_internal.h"),
+                  "sha256": "1877c40b8d8a638875361b310e11e8a65607ff0b825a2e9ce7ab190c134c91ea"},
 }
 COPY_CALIB_BYTES = 256 << 20
 
@@ -118,6 +126,7 @@ def main():
     ap.add_argument("--no-surface", action="store_true")
     ap.add_argument("--no-surface-ho", action="store_true")
     ap.add_argument("--no-channels", action="store_true")
+    ap.add_argument("--no-analytic", action="store_true")
     ap.add_argument("--copy-calib", action="store_true",
                     help="end with plain 256 MiB device copies, the reference for HBM byte counters")
     args = ap.parse_args()
@@ -194,10 +203,14 @@ def main():
     # the other steps against their own bounds
     comp_bytes = C * REC_BYTES + r.cams.npix * PIX_BYTES
     prune_bytes = scene.forest.nleaves * 13 + counts["nvis"] * 20
+    comp_traffic = measured_traffic("composite")
     out["phase_roofline"] = {
         "composite": {"bound": "hbm", "algorithmic_bytes": comp_bytes,
                       "achieved_GBs": comp_bytes / (t_comp * 1e-3) / 1e9,
-                      "frac": comp_bytes / (t_comp * 1e-3) / 1e9 / HBM_PEAK_GBS},
+                      "frac": comp_bytes / (t_comp * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                      # measured HBM bytes, the node records of the coarsening included
+                      "traffic": comp_traffic,
+                      "traffic_GBs": comp_traffic / (t_comp * 1e-3) / 1e9 if comp_traffic else None},
         "prune": {"bound": "hbm", "algorithmic_bytes": prune_bytes,
                   "achieved_GBs": prune_bytes / (t_prune * 1e-3) / 1e9,
                   "frac": prune_bytes / (t_prune * 1e-3) / 1e9 / HBM_PEAK_GBS},
@@ -229,6 +242,8 @@ def main():
         out["integrators"] = bench_integrators(torch, P, r, max(args.steps // 5, 3))
     if not args.no_channels:
         out["channels"] = bench_channels(torch, P, synth, scene, r, max(args.steps // 5, 3))
+    if not args.no_analytic:
+        out["analytic_workload"] = bench_analytic(torch, P, synth, scene, r, max(args.steps // 5, 3))
     if not args.no_batch:
         out["batched_workload"] = bench_batched(torch, P, synth, r, max(args.steps // 10, 3))
     if not args.no_shell:
@@ -394,6 +409,32 @@ def bench_channels(torch, P, synth, scene, r, steps):
     torch.cuda.empty_cache()
     return {"channels": 3, "ms_per_step": ms, "segments_ms": t_seg, "segments_one_channel_ms": t_seg1,
             "segments_ratio_to_one_channel": t_seg / t_seg1}
+
+
+def bench_analytic(torch, P, synth, scene, r, steps):
+    """The headline forest and view with one (kappa, eps) per leaf, each leaf's
+    corner mean, in closed form (eq. ABconstant): the same visibility and
+    pairing, and segment generation priced against HBM."""
+    sc = synth.constant_variant(scene)
+    ra = P.Renderer(sc.forest, sc.fields, r.cams.raw, "analytic", 1, device="cuda:0", index=r.index)
+    c = ra.counts
+    S = ra.count_segments()
+    ra.forward()
+    ra.capture()
+    ra.replay()
+    ms = time_region(torch, ra.replay, steps)
+    t_seg = time_region(torch, ra.segments, steps)
+    nbytes = c["nvis"] * ANALYTIC_LEAF_BYTES + c["ncand"] * REC_BYTES
+    gbs = nbytes / (t_seg * 1e-3) / 1e9
+    log(f"[bench] constant coefficients: forward {ms:.3f} ms, segments {t_seg:.3f} ms ({gbs:.0f} GB/s algorithmic)")
+    del ra
+    torch.cuda.empty_cache()
+    return {"workload": "the headline forest and view, one (kappa, eps) per leaf (corner means), analytic segments",
+            "segments": S, "ms_per_step": ms, "ray_segments_per_s": S / (ms * 1e-3), "segments_ms": t_seg,
+            "roofline": {"bound": "hbm", "kernel": "k_segments_analytic<1>", "achieved": gbs, "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                         "traffic": measured_traffic("k_segments_analytic<1>"), "bytes_per_launch": nbytes,
+                         "per_unit": f"{ANALYTIC_LEAF_BYTES} B per visible leaf + {REC_BYTES} B per candidate"}}
 
 
 def bench_surface(torch, P, synth, steps):

@@ -31,6 +31,7 @@ from .scene import (  # noqa: F401
     perturb_fields,
     trilinear_fields_from_gaussians,
     constant_fields,
+    constant_variant,
     equilibrium_fields,
     split_shares,
     stack_channels,

@@ -369,6 +369,16 @@ def constant_fields(kappa: np.ndarray, eps: np.ndarray) -> Fields:
                   np.asarray(eps, np.float32)[None, :].copy())
 
 
+def constant_variant(scene: Scene) -> Scene:
+    """The scene with each leaf's corner values replaced by their mean, so that
+    every leaf holds constant coefficients and renders analytically: the same
+    forest, cameras, visibility and pairing, with one (kappa, eps) per leaf."""
+    f = scene.fields
+    assert f.kind == "trilinear" and f.nch == 1
+    fields = constant_fields(f.kappa.astype(np.float64).mean(axis=0), f.eps.astype(np.float64).mean(axis=0))
+    return Scene(scene.name + "_const", scene.forest, fields, scene.cameras, "analytic", 1, dict(scene.extra))
+
+
 def split_shares(forest: Forest, fields: Fields, cuts) -> List[tuple]:
     """One-tree forest cut into contiguous curve-order ranges at the leaf
     indices `cuts`: a list of (Forest, Fields), one per process share."""

@@ -204,6 +204,16 @@ def test_config2_full_size_sampled(oracle_mod):
     _check_images(r, scene, oracle_mod, pixels=pixels)
 
 
+def test_config2_constant_full_size_sampled(oracle_mod):
+    """The 1024^2 adaptive workload with one (kappa, eps) per leaf, each leaf's corner mean, in closed form
+    (eq. ABconstant): the segment kernel for constant coefficients at full size, sampled pixels."""
+    scene = synth.constant_variant(synth.config_scene(2))
+    r = _renderer(scene)
+    r.forward()
+    pixels = np.sort(np.random.default_rng(4).choice(scene.cameras[0].npix, 3000, replace=False))
+    _check_images(r, scene, oracle_mod, pixels=pixels)
+
+
 # ------------------------------------------------------------------ gradients
 
 
