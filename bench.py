@@ -51,9 +51,10 @@ PIX_BYTES = 12
 #   kappa and eps (8 B), rectangle and candidate offset (16 B), read once.
 ANALYTIC_LEAF_BYTES = 37
 
-# HBM traffic of the dominant kernel per launch, from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE (calibrated on a 256 MiB device copy: x2.0 and x1.0), valid for
-# the kernel sources whose SHA-256 is given.
+# HBM traffic per launch of the kernels priced here (per call for the
+# composite), from rocprofv3 FETCH_SIZE and WRITE_SIZE (calibrated on a
+# 256 MiB device copy: x2.0 and x1.0), valid for the kernel sources whose
+# SHA-256 is given.
 MEASURED_TRAFFIC = {
     "k_segments_rk4<2, 4, 1>": {"bytes": 242985411, "sources": ("rc_segments.hip", "rc_internal.h"),
                              "sha256": "3449b588b9a29dfe6f0e601d1a0a1416437f4c90c6cd1afd2eaf2dae77fcc8b3"},
