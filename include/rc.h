@@ -111,8 +111,8 @@ typedef struct rc_forest {
  * c = bx + 2 by + 4 bz, 32-byte aligned rows) for trilinear data interpolated
  * in leaf reference coordinates.  nch channels (1 .. RC_MAXCH, e.g. RGB, each
  * converted to its own (A, B) as in Sec. 4.1) follow one another:
- * kappa[ch][leaf][corner].  RC_FIELD_SURFACE (surface
- * forests only, analytic method): kappa holds the surface's transparency A_s
+ * kappa[ch][leaf][corner].  RC_FIELD_SURFACE (surface forests only,
+ * analytic method): kappa holds the surface's transparency A_s
  * and eps its intensity I_s at the leaf's four corners (corner c = bx + 2 by),
  * interpolated bilinearly at the hit; the hit contributes A = A_s^(1/cos phi),
  * phi the angle between the ray and the patch normal, and B = I_s (1 - A)
@@ -257,10 +257,10 @@ rc_status rc_prune_visible(const rc_forest *forest, const rc_index *index, const
  * candidate and channel (channel-major blocks of cap_cand records), the
  * identity (1, 0) on a miss.  With several channels the pairing runs once and
  * every channel is integrated on the same segments (the unit cube's closed
- * form and fixed-step RK4; the other paths take one channel at a time).  Optional debug outputs (NULL to
- * skip): hit[device, cap_cand] 1/0 and sio[device, cap_cand * 2] the hit
- * interval in the ray parameter (alpha for perspective, depth for
- * orthographic), zeros on a miss.
+ * form and fixed-step RK4; the other paths take one channel at a time).
+ * Optional debug outputs (NULL to skip): hit[device, cap_cand] 1/0 and
+ * sio[device, cap_cand * 2] the hit interval in the ray parameter (alpha for
+ * perspective, depth for orthographic), zeros on a miss.
  *
  * RC_GEOM_SHELL6 forests: a ray meets a curved element in up to two
  * intervals (bounded by two planes through the centre per tangent axis and
@@ -283,14 +283,15 @@ rc_status rc_prune_visible(const rc_forest *forest, const rc_index *index, const
  * through the pixel's ray, applied to the control points moved to camera
  * space (eq. camerapoints), give two polynomials whose Bernstein coefficients
  * over the leaf square bound them.  The leaf square is searched depth first:
- * sub-squares where either keeps one sign are dropped, Newton's method runs
- * from the centre of the others (from two subdivisions down, splitting where
- * it does not end in the sub-square, at most 16 deep), and a converged root is
- * polished canonically on the tree's polynomials (snapped to a 2^-40 grid,
- * two Newton steps) so that it counts once, in the leaf whose half-open square
- * holds it.  The search visits at most 2048 sub-squares per candidate (a ray
- * lying in the surface decides none).  A candidate keeps its two nearest
- * hits; hit[] counts all.  Leaf
+ * sub-squares where either keeps one sign (beyond a relative 1e-10) are
+ * dropped; on the others Krawczyk's test (the square widened by a relative
+ * 1e-9) decides no root, exactly one root (Newton's method from the centre) or
+ * undecided (split into four, at most 16 levels below the leaf, then Newton).
+ * A converged root is polished canonically on the tree's polynomials (snapped
+ * to a 2^-40 grid, two Newton steps) so that it counts once, in the leaf whose
+ * half-open square holds it.  The search visits at most 2048 sub-squares per
+ * candidate (a ray lying in the surface decides none).  A candidate keeps its
+ * two nearest hits; hit[] counts all.  Leaf
  * rectangles come from the camera-aligned box of the leaf's Bernstein
  * coefficients (App. A.2).
  */
@@ -307,9 +308,10 @@ rc_status rc_segments(const rc_forest *forest, const rc_fields *fields, const vo
  * The roots are folded straight into the images: A, B and I = A I_b + B
  * [device, total_pixels floats each; total_pixels as returned by
  * rc_camera_prepare].  One channel per call: for channel ch pass that
- * channel's blocks of rec_leaf and rec_node and its images.  rec_node [device, cap_rec * 2] holds the
- * internal-node records (kept for the adjoint).  vf->cap_cand must be at
- * least 1: rec_leaf always holds at least one record.
+ * channel's blocks of rec_leaf and rec_node and its images.  rec_node
+ * [device, cap_rec * 2] holds the internal-node records (kept for the
+ * adjoint).  vf->cap_cand must be at least 1: rec_leaf always holds at least
+ * one record.
  *
  * RC_GEOM_SHELL6 forests: records hold two intervals as in rc_segments
  * (rec_node [device, cap_rec * 8]); a node's intervals are its children's
@@ -342,7 +344,8 @@ rc_status rc_composite(const rc_forest *forest, const rc_index *index, const voi
  * floats]; *n_entries [device] receives the total.  Entries are written only
  * when the total fits cap_entries (cap_entries = 0 asks for the count only);
  * the caller reads n_entries and calls again with more room otherwise.
- * ws [device, rc_lists_workspace_bytes()].  RC_GEOM_SHELL6 and surface forests: RC_EUNSUPPORTED.
+ * ws [device, rc_lists_workspace_bytes()].  RC_GEOM_SHELL6 and surface
+ * forests: RC_EUNSUPPORTED.
  */
 size_t rc_lists_workspace_bytes(const rc_index *index, int32_t ncams, int64_t total_pixels);
 rc_status rc_composite_lists(const rc_forest *forest, const rc_index *index, const void *dcams, int32_t ncams,
@@ -378,18 +381,18 @@ rc_status rc_merge_lists(const void *dcams, int32_t ncams, int64_t total_pixels,
  * entering it from behind; no division), so that a segment receives
  * dL/dA = g T J and dL/dB = g T; then differentiate each segment's
  * evaluation (recomputed from the coefficients) and reduce per leaf in a
- * fixed order.  Several channels: rec_leaf, rec_node, dL_dI and the gradients
- * hold channel-major blocks as in rc_segments and rc_composite.  dL_dkappa, dL_deps [device, layout of rc_fields] are
- * overwritten, or added to when accumulate != 0.  adj_leaf [device,
- * cap_cand * 2] and adj_node [device, cap_rec * 2] are scratch.
+ * fixed order.  Several channels: rec_leaf, rec_node, dL_dI and the
+ * gradients hold channel-major blocks as in rc_segments and rc_composite.
+ * dL_dkappa, dL_deps [device, layout of rc_fields] are overwritten, or added
+ * to when accumulate != 0.  adj_leaf [device, cap_cand * 2] and adj_node
+ * [device, cap_rec * 2] are scratch.
  * RC_GEOM_SHELL6 and surface forests return RC_EUNSUPPORTED.
  */
 rc_status rc_segments_backward(const rc_forest *forest, const rc_index *index, const rc_fields *fields,
                                const void *dcams, int32_t ncams, const rc_vforest *vf,
                                const rc_integrator *integ, const float *rec_leaf, const float *rec_node,
                                int64_t total_pixels, const float *dL_dI, float *adj_leaf, float *adj_node,
-                               float *dL_dkappa,
-                               float *dL_deps, int32_t accumulate, void *ws, size_t ws_bytes,
+                               float *dL_dkappa, float *dL_deps, int32_t accumulate, void *ws, size_t ws_bytes,
                                const rc_tuning *tune, void *stream);
 
 #ifdef __cplusplus

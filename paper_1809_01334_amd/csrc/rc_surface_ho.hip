@@ -3,7 +3,8 @@
 // two planes through it; each plane's signed distance along the leaf is a
 // Bernstein polynomial over the leaf square (rc_surface_ho.h).  The leaf square
 // is searched depth first: sub-squares where either polynomial keeps one sign
-// are dropped, and Newton's method runs from the centre of the others.  A
+// are dropped; on the others Krawczyk's test decides no root, one root
+// (Newton's method from the centre) or undecided (split into four).  A
 // converged root is polished canonically on the tree's own polynomials (snap
 // to a 2^-40 grid, two Newton steps), so every leaf and sub-square that
 // reaches it computes the same bits, and it counts in the one sub-square, of
