@@ -326,6 +326,22 @@ rc_status rc_composite(const rc_forest *forest, const rc_index *index, const voi
                        float *A, float *B, float *I, const rc_tuning *tune, void *stream);
 
 /*
+ * rc_composite for nch channels (1 .. RC_MAXCH, Sec. 4.1: each channel its own
+ * (A, B)) in one call, on channel-major blocks: rec_leaf [device, nch *
+ * cap_cand * 2], rec_node [device, nch * cap_rec * 2] and A, B, I [device,
+ * nch * total_pixels floats each], channel ch's block at ch times the block
+ * size.  On the unit cube one pass locates each record's node and pixel and
+ * folds every channel there; each channel's images and records are bitwise
+ * those of rc_composite on that channel's blocks.  Other geometries (records
+ * of cap_cand * 8 and cap_rec * 8 floats per channel) run rc_composite per
+ * channel.  RC_EINVAL for nch outside 1 .. RC_MAXCH.
+ */
+rc_status rc_composite_channels(const rc_forest *forest, const rc_index *index, const void *dcams, int32_t ncams,
+                                const rc_vforest *vf, int32_t nch, const float *rec_leaf, float *rec_node,
+                                int64_t total_pixels, float *A, float *B, float *I, const rc_tuning *tune,
+                                void *stream);
+
+/*
  * One share's image as per-pixel lists (Sec. 3.3 coarsening stopped at the
  * share's maximal complete subtrees, Sec. 3.5 per-pixel segment lists).  The
  * forest is a share: a contiguous curve-order range of a larger forest's

@@ -255,6 +255,13 @@ def rc_composite(forest: DeviceForest, index: DeviceIndex, cams: DeviceCameras, 
            _tune(tuning), _stream(forest.device))
 
 
+def rc_composite_channels(forest: DeviceForest, index: DeviceIndex, cams: DeviceCameras, vf: VForest, nch: int,
+                          rec_leaf, rec_node, A, B, I, tuning: Optional[L.RcTuning] = None):
+    L.call("rc_composite_channels", ctypes.byref(forest.struct), ctypes.byref(index.struct), _ptr(cams.buf),
+           cams.ncams, ctypes.byref(vf.struct), int(nch), _ptr(rec_leaf), _ptr(rec_node), cams.npix, _ptr(A),
+           _ptr(B), _ptr(I), _tune(tuning), _stream(forest.device))
+
+
 def lists_workspace_bytes(index: DeviceIndex, ncams: int, npix: int) -> int:
     return int(L.lib().rc_lists_workspace_bytes(ctypes.byref(index.struct), int(ncams), int(npix)))
 
@@ -379,8 +386,17 @@ class Renderer:
                     self.tuning, self.c_rk)
 
     def composite(self):
-        # one channel per call, on that channel's blocks of the records and images
-        nl, nn, P = self.rec_floats * self.vf.cap_cand, self.rec_floats * max(self.vf.cap_rec, 1), self.cams.npix
+        if self.fields.nch > 1:
+            # every channel in one call, on the channel-major blocks
+            rc_composite_channels(self.forest, self.index, self.cams, self.vf, self.fields.nch, self.rec_leaf,
+                                  self.rec_node, self.A, self.B, self.I, self.tuning)
+        else:
+            rc_composite(self.forest, self.index, self.cams, self.vf, self.rec_leaf, self.rec_node, self.A, self.B,
+                         self.I, self.tuning)
+
+    def composite_per_channel(self):
+        """rc_composite once per channel, on that channel's blocks of the records and images."""
+        nl, nn, P = self.rec_floats * self.vf.cap_cand, self.rec_floats * self.vf.cap_rec, self.cams.npix
         for ch in range(self.fields.nch):
             rc_composite(self.forest, self.index, self.cams, self.vf, self.rec_leaf[ch * nl:(ch + 1) * nl],
                          self.rec_node[ch * nn:(ch + 1) * nn], self.A[ch * P:(ch + 1) * P],

@@ -91,6 +91,9 @@ def test_null_and_unsupported_arguments():
         fl = L.RcFields(L.RC_FIELD_CONST, nch, ctypes.c_void_p(16), ctypes.c_void_p(16))
         assert lib.rc_segments(ctypes.byref(f), ctypes.byref(fl), ctypes.c_void_p(16), 1, ctypes.byref(vf),
                                ctypes.byref(integ), ctypes.c_void_p(16), None, None, None, None) == L.RC_EINVAL
+        p = ctypes.c_void_p(16)
+        assert lib.rc_composite_channels(ctypes.byref(f), ctypes.byref(ix), p, 1, ctypes.byref(vf), nch, p, p, 1,
+                                         p, p, p, None, None) == L.RC_EINVAL
 
 
 def test_sizes_are_consistent():

@@ -63,6 +63,40 @@ def test_fused_channels_match_single_channel_renders(oracle_mod, kind, method, s
             assert e <= PIX_TOL, (ch, k, e)
 
 
+def _fused_vs_per_channel(r):
+    """Images and node records of the fused rc_composite_channels against rc_composite per channel."""
+    torch = _torch()
+    r.composite()
+    torch.cuda.synchronize()
+    A, B, I = (t.clone() for t in (r.A, r.B, r.I))
+    nodes = r.rec_node.clone()
+    for t in (r.A, r.B, r.I, r.rec_node):
+        t.fill_(-7.0)
+    r.composite_per_channel()
+    torch.cuda.synchronize()
+    assert torch.equal(r.A, A) and torch.equal(r.B, B) and torch.equal(r.I, I)
+    nrec, cap = r.vf.read_counts()["nrec"], r.vf.cap_rec
+    for ch in range(r.fields.nch):
+        sl = slice(ch * 2 * cap, ch * 2 * cap + 2 * nrec)
+        assert torch.equal(r.rec_node[sl], nodes[sl]), ch
+
+
+@pytest.mark.parametrize("nch", [2, 3])
+def test_fused_composite_is_bitwise_per_channel(nch):
+    """rc_composite_channels folds all channels in one pass: bit for bit rc_composite on each channel's blocks
+    (three cameras, one of them straddled by waves; a forest of one leaf; a one-level forest)."""
+    rng = np.random.default_rng(100 + nch)
+    scene = synth.small_scene(100 + nch, ncams=3, w=67, h=49, background=0.4)
+    print(f"[case] fused composite, {nch} channels, 3 cameras", flush=True)
+    _fused_vs_per_channel(_render(synth.stack_channels(_channels(rng, scene, nch, "trilinear")), scene, "rk4", 4))
+    for forest in (synth.uniform_forest(0), synth.uniform_forest(1)):
+        N = forest.nleaves
+        cams = [synth.random_perspective_camera(rng, 40, 30), synth.random_perspective_camera(rng, 23, 17)]
+        sc = synth.Scene(f"uniform{N}", forest, synth.constant_fields(np.ones(N), np.ones(N)), cams, "analytic", 1)
+        print(f"[case] fused composite, {nch} channels, {N} leaves", flush=True)
+        _fused_vs_per_channel(_render(synth.stack_channels(_channels(rng, sc, nch, "const")), sc, "analytic", 1))
+
+
 @pytest.mark.parametrize("which", ["shell", "gauss2"])
 def test_channel_loop_paths(oracle_mod, which):
     rng = np.random.default_rng(95)
