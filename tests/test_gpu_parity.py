@@ -159,6 +159,51 @@ def test_degenerate_cases(oracle_mod):
     assert r.counts["nvis"] == 0 and np.all(A == 1) and np.all(B == 0) and np.allclose(I, 0.7)
 
 
+def _ortho_camera(w, h, ell, view, up, center, dist=3.0, zfar=6.0):
+    vh = np.asarray(view, np.float64) / np.linalg.norm(view)
+    u = np.asarray(up, np.float64) - np.dot(up, vh) * vh
+    u /= np.linalg.norm(u)
+    return synth.Camera(np.asarray(center, np.float64) - dist * vh, vh.copy(), np.cross(vh, u), u, float(ell),
+                        float(zfar), w, h, True, 0.0)
+
+
+@pytest.mark.parametrize("shape", [(32767, 4), (3, 32767)])
+def test_maximum_image_sides(oracle_mod, shape):
+    """Images 32767 pixels wide or high (the int16 rectangle limit): visibility, pairing and 3000 pixels."""
+    w, h = shape
+    forest = synth.uniform_forest(2)
+    rng = np.random.default_rng(w + h)
+    fields = synth.constant_fields(rng.uniform(0.1, 2, 64), rng.uniform(0, 1, 64))
+    cam = _ortho_camera(w, h, 1.3 / max(w, h), [0.3, -0.2, -1.0], [0, 1, 0], [0.5, 0.5, 0.5])
+    scene = synth.Scene(f"strip{w}x{h}", forest, fields, [cam], "analytic", 1)
+    r = _renderer(scene)
+    r.forward()
+    cams, leaves, off = _check_prune(r, scene, oracle_mod)
+    _check_pairing(r, scene, oracle_mod, cams, leaves, off)
+    r.forward()
+    _check_images(r, scene, oracle_mod, pixels=np.sort(rng.choice(w * h, 3000, replace=False)))
+
+
+def test_leaf_rectangle_beyond_2_22_pixels(oracle_mod):
+    """One leaf filling a 2049 x 2049 view: 4.2 M candidates in one rectangle, past the FP32-reciprocal range of
+    the pixel-of-index step, in pairing and in the root fold of a one-leaf forest."""
+    forest = synth.uniform_forest(0)
+    fields = synth.constant_fields(np.array([1.3]), np.array([0.6]))
+    cam = synth.perspective_camera([0.45, 0.55, 1.7], [0.5, 0.5, 0.5], [0, 1, 0], 0.5, 42.0, 2049, 2049, 4.0,
+                                   background=0.25)
+    scene = synth.Scene("one_leaf_2049", forest, fields, [cam], "analytic", 1)
+    r = _renderer(scene)
+    r.forward()
+    cams, leaves, off = _check_prune(r, scene, oracle_mod)
+    assert int(off[-1]) == 2049 * 2049 > 1 << 22
+    _check_pairing(r, scene, oracle_mod, cams, leaves, off)
+    r.forward()
+    rng = np.random.default_rng(2049)
+    pixels = np.sort(np.concatenate([rng.choice(2049 * 2049, 3000, replace=False),
+                                     np.arange((1 << 22) - 50, (1 << 22) + 50)]))
+    _check_images(r, scene, oracle_mod, pixels=np.unique(pixels))
+
+
 def test_near_plane_clipping(oracle_mod):
     """Camera close to the cube: the near plane (projection plane) cuts leaves."""
     scene = synth.small_scene(8, w=64, h=64)
