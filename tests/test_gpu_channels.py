@@ -97,6 +97,17 @@ def test_fused_composite_is_bitwise_per_channel(nch):
         _fused_vs_per_channel(_render(synth.stack_channels(_channels(rng, sc, nch, "const")), sc, "analytic", 1))
 
 
+def test_fused_composite_many_small_views():
+    """300 views of 1..9 x 1..9 pixels and three channels: the fused fold's per-lane descriptor path, bit for bit
+    against rc_composite per channel."""
+    from test_gpu_parity import many_small_views
+
+    scene = many_small_views(307, 300)
+    rng = np.random.default_rng(307)
+    print("[case] fused composite, 3 channels, 300 small views", flush=True)
+    _fused_vs_per_channel(_render(synth.stack_channels(_channels(rng, scene, 3, "trilinear")), scene, "rk4", 4))
+
+
 @pytest.mark.parametrize("which", ["shell", "gauss2"])
 def test_channel_loop_paths(oracle_mod, which):
     rng = np.random.default_rng(95)

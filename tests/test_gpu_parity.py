@@ -204,6 +204,29 @@ def test_leaf_rectangle_beyond_2_22_pixels(oracle_mod):
     _check_images(r, scene, oracle_mod, pixels=np.unique(pixels))
 
 
+def many_small_views(seed, nviews):
+    """An adaptive scene seen by nviews cameras of 1..9 x 1..9 pixels with random backgrounds."""
+    rng = np.random.default_rng(seed)
+    scene = synth.small_scene(seed % 97, lmin=2, lmax=4)
+    scene.cameras = [synth.random_perspective_camera(rng, int(rng.integers(1, 10)), int(rng.integers(1, 10)),
+                                                     background=float(rng.uniform(0.0, 0.5)))
+                     for _ in range(nviews)]
+    return scene
+
+
+def test_many_small_views_mixed_in_every_wave(oracle_mod):
+    """600 views of 1..9 x 1..9 pixels: most waves hold candidates, records and pixels of several cameras, so the
+    per-lane camera and descriptor paths of pairing and of the folds carry the work. Visibility, all pairing and
+    every pixel against the oracle."""
+    scene = many_small_views(606, 600)
+    r = _renderer(scene)
+    r.forward()
+    cams, leaves, off = _check_prune(r, scene, oracle_mod)
+    _check_pairing(r, scene, oracle_mod, cams, leaves, off)
+    r.forward()
+    _check_images(r, scene, oracle_mod)
+
+
 def test_near_plane_clipping(oracle_mod):
     """Camera close to the cube: the near plane (projection plane) cuts leaves."""
     scene = synth.small_scene(8, w=64, h=64)
@@ -287,6 +310,32 @@ def _grad_case(oracle_mod, scene, background):
 def test_gradient_matches_oracle(oracle_mod, seed, method):
     scene = synth.small_scene(seed, w=70, h=52, method=method)
     _grad_case(oracle_mod, scene, 0.5)
+
+
+def test_gradient_many_small_views(oracle_mod):
+    """The adjoint over 150 views of 1..9 x 1..9 pixels (waves spanning several cameras in every pass): the
+    coefficient gradients of L = sum over views of sum (I - I*)^2 against the oracle's, summed over views."""
+    torch = _torch()
+    scene = many_small_views(151, 150)
+    r = _renderer(scene)
+    _, _, I = r.forward()
+    rng = np.random.default_rng(152)
+    target = rng.uniform(0.0, 0.3, I.shape[0])
+    g = (2.0 * (I.double() - torch.from_numpy(target).to(I.device))).float().contiguous()
+    dk, de = r.backward(g)
+    torch.cuda.synchronize()
+    gk = np.zeros((8, scene.forest.nleaves))  # [corner][leaf], the oracle's layout
+    ge = np.zeros((8, scene.forest.nleaves))
+    for k, cam in enumerate(scene.cameras):
+        lo, hi = r.cams.img_off[k], r.cams.img_off[k + 1]
+        ref = oracle_mod.render(scene.forest, scene.fields, cam, scene.method, scene.substeps)
+        a, b = oracle_mod.grad(scene.forest, scene.fields, cam, 2.0 * (ref["I"] - target[lo:hi]), scene.method,
+                               scene.substeps)
+        gk += a
+        ge += b
+    ek = rel_err(dk.cpu().numpy().T, gk)
+    ee = rel_err(de.cpu().numpy().T, ge)
+    assert ek <= GRAD_TOL and ee <= GRAD_TOL, (ek, ee)
 
 
 def test_autograd_function_and_accumulate(oracle_mod):
