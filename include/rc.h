@@ -403,7 +403,7 @@ rc_status rc_merge_lists(const void *dcams, int32_t ncams, int64_t total_pixels,
  * to when accumulate != 0.  adj_leaf [device, cap_cand * 2] and adj_node
  * [device, cap_rec * 2] are scratch.  RC_EUNSUPPORTED for RC_GEOM_SHELL6 and
  * surface forests, RC_FIELD_CONST_EQ fields, and integrators other than the
- * closed form and fixed-step RK4 (c_rk = 0).
+ * closed form and fixed-step RK4 (c_rk = 0) with 1, 2, 4 or 8 substeps.
  */
 rc_status rc_segments_backward(const rc_forest *forest, const rc_index *index, const rc_fields *fields,
                                const void *dcams, int32_t ncams, const rc_vforest *vf,
