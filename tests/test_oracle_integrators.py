@@ -142,3 +142,39 @@ def test_equilibrium_intensity_fields_match_emission_fields(oracle_mod):
         for k in ("A", "B", "I"):
             np.testing.assert_allclose(a[k], b[k], rtol=1e-12, atol=1e-14)
         assert a["segments"] > 0
+
+
+def test_integrator_gradients_match_finite_differences(oracle_mod):
+    """The oracle's coefficient gradients (dual numbers through eq. gaussAB and eq. simpson over equal pieces)
+    against central finite differences of its own loss L = sum (I - I*)^2, trilinear fields, background 0.4."""
+    O = oracle_mod
+    s = synth.small_scene(12, lmin=1, lmax=3, ngauss=3, w=24, h=18, background=0.4)
+    cam = s.cameras[0]
+    f = s.fields
+    kap0, eps0 = f.kappa.astype(np.float64), f.eps.astype(np.float64)
+    rng = np.random.default_rng(13)
+    for method, sub in (("gauss2", 4), ("simpson", 2), ("gauss2", 1)):
+        r = O.render(s.forest, f, cam, method, sub)
+        target = r["I"] + rng.normal(0, 0.05, r["I"].shape)
+
+        def loss(kap, eps):
+            return ((O.render(s.forest, f, cam, method, sub, kappa=kap, eps=eps)["I"] - target) ** 2).sum()
+
+        gk, ge = O.grad(s.forest, f, cam, 2 * (r["I"] - target), method, sub)
+        leaves = np.flatnonzero(np.abs(gk).sum(0) > 0)
+        assert len(leaves) >= 5
+        for l in rng.choice(leaves, 5, replace=False):
+            c = int(rng.integers(8))
+            for which in ("k", "e"):
+                kp, km, ep, em = kap0.copy(), kap0.copy(), eps0.copy(), eps0.copy()
+                base = kap0 if which == "k" else eps0
+                h = 1e-6 * max(1.0, abs(base[c, l]))
+                if which == "k":
+                    kp[c, l] += h
+                    km[c, l] -= h
+                else:
+                    ep[c, l] += h
+                    em[c, l] -= h
+                fd = (loss(kp, ep) - loss(km, em)) / (2 * h)
+                an = gk[c, l] if which == "k" else ge[c, l]
+                assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (method, sub, which, l, c, fd, an)
