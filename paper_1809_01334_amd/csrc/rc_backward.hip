@@ -10,6 +10,7 @@
 // leaves the segment evaluation is recomputed from the coefficients and
 // differentiated in reverse; the per-leaf sums use a fixed reduction order.
 #include "rc_composite.h"
+#include "rc_steps.h"
 
 using namespace rc;
 
@@ -167,6 +168,50 @@ __device__ inline void rk4_step_bwd(float b0, float bm, float b1, float g0, floa
     db0 -= hh * A1b;
 }
 
+// Reverse of the two-stage implicit Gauss step (eq. gaussAB with eq.
+// gaussABab, as evaluated by the forward): adds the adjoints of (b0, b1, g0,
+// g1), the stage values at 1/2 -+ sqrt(3)/6 of the piece from its far end,
+// given those of the step's (A, B).
+__device__ inline void gauss2_step_bwd(float b0, float b1, float g0, float g1, float h, float Abar, float Bbar,
+                                       float& db0, float& db1, float& dg0, float& dg1) {
+    const float r3_12 = 0.14433756729740643f;  // sqrt(3) / 12
+    float a1 = h * (b0 + b1) * 0.25f;
+    float a2 = h * h * b0 * b1 * (1.0f / 12.0f);
+    float c1 = h * (g0 + g1) * 0.5f;
+    float c2 = h * h * (b0 * g1 - b1 * g0) * r3_12;
+    float rd = 1.0f / (1.0f + a1 + a2);
+    float A = (1.0f - a1 + a2) * rd, B = (c1 + c2) * rd;
+    // A = (1 - a1 + a2) / den, B = (c1 + c2) / den, den = 1 + a1 + a2
+    float a1b = (-(1.0f + A) * Abar - B * Bbar) * rd;
+    float a2b = ((1.0f - A) * Abar - B * Bbar) * rd;
+    float cb = Bbar * rd;
+    float s1 = h * 0.25f * a1b, s2 = h * h * (1.0f / 12.0f) * a2b;
+    float t = h * 0.5f * cb, u = h * h * r3_12 * cb;
+    db0 += s1 + s2 * b1 + u * g1;
+    db1 += s1 + s2 * b0 - u * g0;
+    dg0 += t - u * b1;
+    dg1 += t + u * b0;
+}
+
+// Reverse of the Simpson step of the closed form (eq. simpson): stage values
+// at the far end, the middle and the near end of the piece.  B depends on the
+// exponent through A and sqrt(A) = exp(half the exponent), so no division.
+__device__ inline void simpson_step_bwd(float b0, float b1, float b2, float g0, float g1, float g2, float h,
+                                        float Abar, float Bbar, float& db0, float& db1, float& db2, float& dg0,
+                                        float& dg1, float& dg2) {
+    float h6 = h * (1.0f / 6.0f);
+    float A = expf(-h * (b0 + 4.0f * b1 + b2) * (1.0f / 6.0f));
+    float sA = sqrtf(A);
+    dg0 += h6 * A * Bbar;
+    dg1 += 4.0f * h6 * sA * Bbar;
+    dg2 += h6 * Bbar;
+    // d/d(b0 + 4 b1 + b2): A' = -h6 A, sqrt(A)' = -h6 sqrt(A) / 2
+    float sb = -h6 * (A * Abar + h6 * Bbar * (A * g0 + 2.0f * sA * g1));
+    db0 += sb;
+    db1 += 4.0f * sb;
+    db2 += sb;
+}
+
 // Reverse of field_cubic: corner adjoints vb[8] from the adjoints pb[4] of
 // the cubic's coefficients.
 __device__ inline void field_cubic_bwd(const float a[3], const float d[3], const float pb[4], float vb[8]) {
@@ -192,9 +237,23 @@ __device__ inline void field_cubic_bwd(const float a[3], const float d[3], const
     }
 }
 
+// Stage point p of NSUB equal pieces as a fraction of the segment from its far
+// end: RK4 and Simpson use the ends and middle of every piece (2 NSUB + 1
+// points, shared between neighbours), Gauss the two points 1/2 -+ sqrt(3)/6 of
+// every piece (2 NSUB points).
+template <int METHOD, int NSUB>
+__device__ inline float stage_t(int p) {
+    if (METHOD == RC_INT_GAUSS2) {
+        const float c0 = 0.21132486540518713f, c1 = 0.78867513459481287f;  // 1/2 -+ sqrt(3)/6
+        return ((float)(p >> 1) + ((p & 1) ? c1 : c0)) * (1.0f / (float)NSUB);
+    }
+    return (float)p * (0.5f / (float)NSUB);
+}
+
 // Gradient of one segment's (A, B) contribution: grad[0..nc) kappa corners,
 // grad[nc..2nc) eps corners.  gT = g T_front, J = intensity from behind.
-template <int KIND, int NSUB>
+// METHOD: RK4, Gauss or Simpson over NSUB equal pieces.
+template <int KIND, int NSUB, int METHOD>
 __device__ inline void segment_grad(const float kc[8], const float ec[8], const SegGeom& sg, float gT, float J,
                                     float grad[GRAD_MAX]) {
     if (KIND == 0) {
@@ -222,9 +281,9 @@ __device__ inline void segment_grad(const float kc[8], const float ec[8], const 
         grad[1] = gT * dBde;
         return;
     }
-    // forward: field values at the 2 NSUB + 1 stage points, substep values and
-    // the intensity entering each substep
-    constexpr int NP = 2 * NSUB + 1;
+    // forward: field values at the stage points, substep values and the
+    // intensity entering each substep
+    constexpr int NP = METHOD == RC_INT_GAUSS2 ? 2 * NSUB : 2 * NSUB + 1;
     const float inv = 1.0f / (float)NSUB;
     float h = sg.dx * inv;
     float pk[4], pe[4];
@@ -239,7 +298,7 @@ __device__ inline void segment_grad(const float kc[8], const float ec[8], const 
     float bs[NP], gs[NP];
 #pragma unroll
     for (int p = 0; p < NP; p++) {
-        float t = (float)p * (0.5f * inv);
+        float t = stage_t<METHOD, NSUB>(p);
         bs[p] = horner3(pk, t);
         gs[p] = horner3(pe, t);
     }
@@ -247,7 +306,13 @@ __device__ inline void segment_grad(const float kc[8], const float ec[8], const 
     float Ic = J;
 #pragma unroll
     for (int q = 0; q < NSUB; q++) {
-        float2 st = rk4_step(bs[2 * q], bs[2 * q + 1], bs[2 * q + 2], gs[2 * q], gs[2 * q + 1], gs[2 * q + 2], h);
+        float2 st;
+        if (METHOD == RC_INT_GAUSS2)
+            st = gauss2_step(bs[2 * q], bs[2 * q + 1], gs[2 * q], gs[2 * q + 1], h);
+        else if (METHOD == RC_INT_SIMPSON)
+            st = simpson_step(bs[2 * q], bs[2 * q + 1], bs[2 * q + 2], gs[2 * q], gs[2 * q + 1], gs[2 * q + 2], h);
+        else
+            st = rk4_step(bs[2 * q], bs[2 * q + 1], bs[2 * q + 2], gs[2 * q], gs[2 * q + 1], gs[2 * q + 2], h);
         Iin[q] = Ic;
         av[q] = st.x;
         Ic = fmaf(st.x, Ic, st.y);
@@ -262,8 +327,16 @@ __device__ inline void segment_grad(const float kc[8], const float ec[8], const 
     float G = gT;
 #pragma unroll
     for (int q = NSUB - 1; q >= 0; q--) {
-        rk4_step_bwd(bs[2 * q], bs[2 * q + 1], bs[2 * q + 2], gs[2 * q], gs[2 * q + 1], h, G * Iin[q], G,
-                     dbs[2 * q], dbs[2 * q + 1], dbs[2 * q + 2], dgs[2 * q], dgs[2 * q + 1], dgs[2 * q + 2]);
+        if (METHOD == RC_INT_GAUSS2)
+            gauss2_step_bwd(bs[2 * q], bs[2 * q + 1], gs[2 * q], gs[2 * q + 1], h, G * Iin[q], G, dbs[2 * q],
+                            dbs[2 * q + 1], dgs[2 * q], dgs[2 * q + 1]);
+        else if (METHOD == RC_INT_SIMPSON)
+            simpson_step_bwd(bs[2 * q], bs[2 * q + 1], bs[2 * q + 2], gs[2 * q], gs[2 * q + 1], gs[2 * q + 2], h,
+                             G * Iin[q], G, dbs[2 * q], dbs[2 * q + 1], dbs[2 * q + 2], dgs[2 * q], dgs[2 * q + 1],
+                             dgs[2 * q + 2]);
+        else
+            rk4_step_bwd(bs[2 * q], bs[2 * q + 1], bs[2 * q + 2], gs[2 * q], gs[2 * q + 1], h, G * Iin[q], G,
+                         dbs[2 * q], dbs[2 * q + 1], dbs[2 * q + 2], dgs[2 * q], dgs[2 * q + 1], dgs[2 * q + 2]);
         G *= av[q];
     }
     if (KIND == 1) {
@@ -281,7 +354,7 @@ __device__ inline void segment_grad(const float kc[8], const float ec[8], const 
     float pkb[4] = {0.0f, 0.0f, 0.0f, 0.0f}, peb[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int p = 0; p < NP; p++) {
-        float t = (float)p * (0.5f * inv);
+        float t = stage_t<METHOD, NSUB>(p);
         float tn = 1.0f;
 #pragma unroll
         for (int n = 0; n < 4; n++) {
@@ -334,7 +407,7 @@ struct AdjQueue {
     float xf0[BQCAP], xf1[BQCAP], xf2[BQCAP], d0[BQCAP], d1[BQCAP], d2[BQCAP], dx[BQCAP], gT[BQCAP], J[BQCAP];
 };
 
-template <int KIND, int NSUB>
+template <int KIND, int NSUB, int METHOD>
 __device__ inline void adj_drain(const LeafAdjArgs& a, AdjQueue& q, int head, int tail, int n, int lane,
                                  float* carry, int64_t& carry_key) {
     constexpr int NPAR = KIND == 2 ? 16 : 2;
@@ -371,7 +444,7 @@ __device__ inline void adj_drain(const LeafAdjArgs& a, AdjQueue& q, int head, in
                 ec[c] = a.eps[leaf];
             }
         }
-        segment_grad<KIND, NSUB>(kc, ec, sg, q.gT[e], q.J[e], grad);
+        segment_grad<KIND, NSUB, METHOD>(kc, ec, sg, q.gT[e], q.J[e], grad);
     }
     // segmented inclusive scan over lanes with equal keys
 #pragma unroll
@@ -407,7 +480,7 @@ __device__ inline void adj_drain(const LeafAdjArgs& a, AdjQueue& q, int head, in
     }
 }
 
-template <int KIND, int NSUB>
+template <int KIND, int NSUB, int METHOD>
 __global__ __launch_bounds__(256) void k_adj_leaf(LeafAdjArgs a) {
     __shared__ AdjQueue Q[256 / WAVE];
     if (a.counts[3]) return;
@@ -461,14 +534,14 @@ __global__ __launch_bounds__(256) void k_adj_leaf(LeafAdjArgs a) {
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         if (tail - head >= WAVE) {
-            adj_drain<KIND, NSUB>(a, q, head, tail, WAVE, lane, carry, carry_key);
+            adj_drain<KIND, NSUB, METHOD>(a, q, head, tail, WAVE, lane, carry, carry_key);
             head += WAVE;
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
     }
-    if (tail - head > 0) adj_drain<KIND, NSUB>(a, q, head, tail, tail - head, lane, carry, carry_key);
+    if (tail - head > 0) adj_drain<KIND, NSUB, METHOD>(a, q, head, tail, tail - head, lane, carry, carry_key);
 }
 
 // Per (leaf, parameter): over the cameras in order, add the chunk partials of
@@ -499,6 +572,19 @@ __global__ __launch_bounds__(256) void k_grad_leaves(const int64_t* counts, int6
     }
 }
 
+// The leaf adjoint for NSUB in {1, 2, 4, 8} pieces (checked before any launch).
+template <int KIND, int METHOD>
+rc_status launch_adj_leaf(int nsub, dim3 G, dim3 B, hipStream_t st, const LeafAdjArgs& la) {
+    switch (nsub) {
+        case 1: hipLaunchKernelGGL((k_adj_leaf<KIND, 1, METHOD>), G, B, 0, st, la); break;
+        case 2: hipLaunchKernelGGL((k_adj_leaf<KIND, 2, METHOD>), G, B, 0, st, la); break;
+        case 4: hipLaunchKernelGGL((k_adj_leaf<KIND, 4, METHOD>), G, B, 0, st, la); break;
+        case 8: hipLaunchKernelGGL((k_adj_leaf<KIND, 8, METHOD>), G, B, 0, st, la); break;
+        default: return RC_EUNSUPPORTED;
+    }
+    return RC_OK;
+}
+
 }  // namespace
 }  // namespace rc
 
@@ -525,7 +611,8 @@ extern "C" rc_status rc_segments_backward(const rc_forest* f, const rc_index* ix
         return RC_EINVAL;
     bool nodes = rc_node_slots(ix, ncams) > 0;
     if (nodes && (!rec_node || !adj_node)) return RC_EINVAL;
-    if (in->method == RC_INT_RK4 && in->substeps != 1 && in->substeps != 2 && in->substeps != 4 && in->substeps != 8)
+    if (in->method != RC_INT_ANALYTIC && in->substeps != 1 && in->substeps != 2 && in->substeps != 4 &&
+        in->substeps != 8)
         return RC_EUNSUPPORTED;
     if ((s = check_tables(vf, ix, ncams)) != RC_OK) return s;
     if (!ws || ws_bytes < rc_workspace_bytes(f, ix, ncams, vf)) return RC_EWORKSPACE;
@@ -575,24 +662,26 @@ static rc_status backward_one(const rc_forest* f, const rc_index* ix, const rc_f
     unsigned lg = stride_grid(nchunks * WAVE, 256, tuned(tune, 3, 256 * 8));
     int nc = fl->kind == RC_FIELD_TRILINEAR ? 8 : 1;
     dim3 G(lg), B(256);
+    rc_status s = RC_OK;
     if (in->method == RC_INT_ANALYTIC) {
-        hipLaunchKernelGGL((k_adj_leaf<0, 1>), G, B, 0, st, la);
-    } else if (fl->kind == RC_FIELD_CONST) {
-        switch (in->substeps) {
-            case 1: hipLaunchKernelGGL((k_adj_leaf<1, 1>), G, B, 0, st, la); break;
-            case 2: hipLaunchKernelGGL((k_adj_leaf<1, 2>), G, B, 0, st, la); break;
-            case 4: hipLaunchKernelGGL((k_adj_leaf<1, 4>), G, B, 0, st, la); break;
-            case 8: hipLaunchKernelGGL((k_adj_leaf<1, 8>), G, B, 0, st, la); break;
-            default: return RC_EUNSUPPORTED;
-        }
+        hipLaunchKernelGGL((k_adj_leaf<0, 1, RC_INT_ANALYTIC>), G, B, 0, st, la);
     } else {
-        switch (in->substeps) {
-            case 1: hipLaunchKernelGGL((k_adj_leaf<2, 1>), G, B, 0, st, la); break;
-            case 2: hipLaunchKernelGGL((k_adj_leaf<2, 2>), G, B, 0, st, la); break;
-            case 4: hipLaunchKernelGGL((k_adj_leaf<2, 4>), G, B, 0, st, la); break;
-            case 8: hipLaunchKernelGGL((k_adj_leaf<2, 8>), G, B, 0, st, la); break;
-            default: return RC_EUNSUPPORTED;
+        bool tri = fl->kind == RC_FIELD_TRILINEAR;
+        switch (in->method) {
+            case RC_INT_RK4:
+                s = tri ? launch_adj_leaf<2, RC_INT_RK4>(in->substeps, G, B, st, la)
+                        : launch_adj_leaf<1, RC_INT_RK4>(in->substeps, G, B, st, la);
+                break;
+            case RC_INT_GAUSS2:
+                s = tri ? launch_adj_leaf<2, RC_INT_GAUSS2>(in->substeps, G, B, st, la)
+                        : launch_adj_leaf<1, RC_INT_GAUSS2>(in->substeps, G, B, st, la);
+                break;
+            default:
+                s = tri ? launch_adj_leaf<2, RC_INT_SIMPSON>(in->substeps, G, B, st, la)
+                        : launch_adj_leaf<1, RC_INT_SIMPSON>(in->substeps, G, B, st, la);
+                break;
         }
+        if (s != RC_OK) return s;
     }
     RC_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_grad_leaves, dim3(stride_grid(f->nleaves * 2 * nc, 256, 256 * 32)), dim3(256), 0, st,

@@ -115,11 +115,13 @@ inline rc_status check_fields(const rc_fields* fl, const rc_integrator* in) {
     return RC_OK;
 }
 
-// The hand-written adjoint covers the fixed-step RK4 and the closed form with
-// (kappa, eps) fields.
+// The hand-written adjoint covers (kappa, eps) fields with the closed form and
+// with RK4, Gauss or Simpson over equal pieces (1, 2, 4 or 8, checked by the
+// entry point), not the recursion.
 inline bool adjoint_supported(const rc_fields* fl, const rc_integrator* in) {
     if (fl->kind == RC_FIELD_CONST_EQ || fl->kind == RC_FIELD_SURFACE) return false;
-    return in->method == RC_INT_ANALYTIC || (in->method == RC_INT_RK4 && in->c_rk == 0.0);
+    // fixed pieces: the closed form, RK4, Gauss and Simpson without the recursion
+    return in->c_rk == 0.0;
 }
 
 // Integrators beyond the closed form and fixed-step RK4: rc_integrators.hip.

@@ -16,7 +16,7 @@ from test_gpu_parity import _torch
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("method,substeps", [("analytic", 1), ("rk4", 4), ("rk4", 1)])
+@pytest.mark.parametrize("method,substeps", [("analytic", 1), ("rk4", 4), ("rk4", 1), ("gauss2", 4), ("simpson", 2)])
 def test_adjoint_matches_central_differences(method, substeps):
     torch = _torch()
     import paper_1809_01334_amd as P
