@@ -50,11 +50,6 @@ __device__ inline int64_t desc_index(const ChildDesc& d, int i, int j) {
     return (int64_t)(j - d.j0) * (d.i1 - d.i0 + 1) + (i - d.i0);
 }
 
-__device__ inline float2 desc_record(const FoldCtx& C, const ChildDesc& d, int i, int j) {
-    int64_t k = desc_index(d, i, j);
-    return d.off >= 0 ? C.rec_node[d.off + k] : C.rec_leaf[-1 - d.off + k];
-}
-
 // Address of the record of child d at (i, j), or of the first leaf record
 // (always present) when the child does not hold the pixel: every lane can
 // issue all eight loads at once and select afterwards.
