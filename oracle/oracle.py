@@ -331,10 +331,6 @@ def merge_lists(lists, P_, background=0.0):
     return {"A": A, "B": B, "I": A * background + B, "overlaps": int(ov)}
 
 
-def _surface(forest):
-    return getattr(forest, "geom", "unit_cube") == "surface"
-
-
 def surface_render(forest, fields, cam, pixels=None, hits=False):
     """FP64 oracle image of a surface forest (bilinear tree patches, Sec. 2.8 surface
     model).  fields.kappa / fields.eps hold the corner transparency A_s and intensity I_s
