@@ -115,19 +115,23 @@ inline rc_status check_fields(const rc_fields* fl, const rc_integrator* in) {
     return RC_OK;
 }
 
-// The hand-written adjoint covers (kappa, eps) fields with the closed form and
+// The hand-written adjoint covers (kappa, eps) fields with the closed form,
 // with RK4, Gauss or Simpson over equal pieces (1, 2, 4 or 8, checked by the
-// entry point), not the recursion.
+// entry point), and with the recursion of any of the three.
 inline bool adjoint_supported(const rc_fields* fl, const rc_integrator* in) {
-    if (fl->kind == RC_FIELD_CONST_EQ || fl->kind == RC_FIELD_SURFACE) return false;
-    // fixed pieces: the closed form, RK4, Gauss and Simpson without the recursion
-    return in->c_rk == 0.0;
+    (void)in;
+    return fl->kind != RC_FIELD_CONST_EQ && fl->kind != RC_FIELD_SURFACE;
 }
 
 // Integrators beyond the closed form and fixed-step RK4: rc_integrators.hip.
 rc_status rc_segments_general(const rc_forest* f, const rc_fields* fl, const void* dcams, const rc_vforest* vf,
                               const rc_integrator* in, float* rec_leaf, uint8_t* hit, double* sio,
                               const rc_tuning* tune, hipStream_t st);
+// Leaf adjoint of the recursion (c_rk > 0): per (chunk, pair) partials as the
+// fixed-piece leaf adjoint writes them (rc_integrators.hip).
+rc_status rc_adjoint_pieces(const rc_forest* f, const rc_fields* fl, const void* dcams, const rc_vforest* vf,
+                            const rc_integrator* in, const float* adj_leaf, float* partial, const rc_tuning* tune,
+                            hipStream_t st);
 
 // The per-call tables written by rc_prune_visible and read by later calls.
 inline rc_status check_tables(const rc_vforest* vf, const rc_index* ix, int32_t ncams) {

@@ -199,6 +199,203 @@ __global__ __launch_bounds__(256) void k_segments_general(GenArgs a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// adjoint with the recursion (c_rk > 0)
+// ---------------------------------------------------------------------------
+
+// Record of the subtree of piece (k0, dr): its pieces nearest first, the same
+// split decisions as integrate_pieces (forced above the initial depth d0).
+template <int KIND, int METHOD>
+__device__ inline float2 eval_subtree(const Piecewise& P, int64_t k0, int dr, int d0, double c_rk) {
+    float2 acc = make_float2(1.0f, 0.0f);
+    int64_t k = k0;
+    int d = dr;
+    for (;;) {
+        while (d < d0 || (d < RC_ADAPT_MAXDEPTH && split_test<KIND, METHOD>(P, k, d, c_rk))) {
+            k <<= 1;
+            d++;
+        }
+        acc = seg_combine(acc, piece_step<KIND, METHOD>(P, k, d));
+        while (d > dr && (k & 1)) {
+            k >>= 1;
+            d--;
+        }
+        if (d == dr) break;
+        k++;
+    }
+    return acc;
+}
+
+// One piece's step and its reverse: adds the corner adjoints of the stage
+// values for (Abar, Bbar), the adjoints of the piece's (A, B); returns (A, B).
+template <int KIND, int METHOD>
+__device__ inline float2 piece_grad(const Piecewise& P, int64_t k, int d, float Abar, float Bbar,
+                                    float grad[GRAD_MAX]) {
+    constexpr int M = METHOD == RC_INT_GAUSS2 ? 2 : 3;
+    float h = (float)piece_dx(P, k, d);
+    double cs[3] = {0.0, 0.5, 1.0};
+    if (METHOD == RC_INT_GAUSS2) {
+        cs[0] = gauss_c0();
+        cs[1] = gauss_c1();
+    }
+    double sp[3];
+    float b[3], g[3], db[3] = {0.0f, 0.0f, 0.0f}, dg[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int i = 0; i < M; i++) {
+        sp[i] = piece_s(P, k, d, cs[i]);
+        fields32<KIND>(P, sp[i], b[i], g[i]);
+    }
+    float2 st;
+    if (METHOD == RC_INT_GAUSS2) {
+        st = gauss2_step(b[0], b[1], g[0], g[1], h);
+        gauss2_step_bwd(b[0], b[1], g[0], g[1], h, Abar, Bbar, db[0], db[1], dg[0], dg[1]);
+    } else if (METHOD == RC_INT_SIMPSON) {
+        st = simpson_step(b[0], b[1], b[2], g[0], g[1], g[2], h);
+        simpson_step_bwd(b[0], b[1], b[2], g[0], g[1], g[2], h, Abar, Bbar, db[0], db[1], db[2], dg[0], dg[1],
+                         dg[2]);
+    } else {
+        st = rk4_step(b[0], b[1], b[2], g[0], g[1], g[2], h);
+        rk4_step_bwd(b[0], b[1], b[2], g[0], g[1], h, Abar, Bbar, db[0], db[1], db[2], dg[0], dg[1], dg[2]);
+    }
+#pragma unroll
+    for (int i = 0; i < M; i++) {
+        if (KIND == RC_FIELD_TRILINEAR) {
+            double xi[3];
+            piece_xi(P, sp[i], xi);
+            float x = (float)xi[0], y = (float)xi[1], z = (float)xi[2];
+#pragma unroll
+            for (int c = 0; c < 8; c++) {
+                float w = ((c & 1) ? x : 1.0f - x) * ((c & 2) ? y : 1.0f - y) * ((c & 4) ? z : 1.0f - z);
+                grad[c] = fmaf(db[i], w, grad[c]);
+                grad[8 + c] = fmaf(dg[i], w, grad[8 + c]);
+            }
+        } else {
+            grad[0] += db[i];
+            grad[1] += dg[i];
+        }
+    }
+    return st;
+}
+
+// Coefficient adjoints of one segment whose pieces follow the recursion.
+// The pieces are visited nearest first as in integrate_pieces, starting from
+// the whole segment (0, 0) with splits forced down to d0.  T, the product of
+// the A of the nearer pieces, runs along; Js[d * 256] holds the intensity
+// entering the current node at depth d from behind: on entering a node's near
+// half it is the far half's record applied to the node's, on moving to the far
+// half the node's own.  gT = g T_front and J enter the segment as in the
+// closed-form adjoint; a piece receives dL/dA = gT T J_piece and dL/dB = gT T.
+template <int KIND, int METHOD>
+__device__ inline void pieces_grad(const Piecewise& P, int d0, double c_rk, float gT, float J, float* Js,
+                                   float grad[GRAD_MAX]) {
+    Js[0] = J;
+    float T = 1.0f;
+    int64_t k = 0;
+    int d = 0;
+    for (;;) {
+        while (d < d0 || (d < RC_ADAPT_MAXDEPTH && split_test<KIND, METHOD>(P, k, d, c_rk))) {
+            float2 far = eval_subtree<KIND, METHOD>(P, 2 * k + 1, d + 1, d0, c_rk);
+            Js[(d + 1) * 256] = fmaf(far.x, Js[d * 256], far.y);
+            k <<= 1;
+            d++;
+        }
+        float gTT = gT * T;
+        float2 st = piece_grad<KIND, METHOD>(P, k, d, gTT * Js[d * 256], gTT, grad);
+        T *= st.x;
+        while (d > 0 && (k & 1)) {
+            k >>= 1;
+            d--;
+        }
+        if (d == 0) break;
+        k++;
+        Js[d * 256] = Js[(d - 1) * 256];
+    }
+}
+
+struct AdjGenArgs {
+    const Cam* cams;
+    const uint8_t* level;
+    const uint32_t *x, *y, *z;
+    int64_t N;
+    const float *kappa, *eps;
+    const int32_t* vis_leaf;
+    const int16_t* vis_cam;
+    const int16_t* vis_rect;
+    const int64_t* cand_offset;
+    const int64_t* counts;
+    const int32_t* cand_chunk;
+    int64_t cap_cand;
+    const float2* adj_leaf;  // (g T_front, J_behind) per candidate
+    float* partial;          // [(nchunks + nvis)][GRAD_MAX], entry (chunk w, pair v) at w + v
+    int d0;
+    double c_rk;
+};
+
+// One candidate per lane; the lanes of a wave chunk sum their gradients per
+// (chunk w, pair v) key with a segmented shuffle scan (keys are
+// non-decreasing across the lanes) and each key's last lane writes its slot.
+template <int KIND, int METHOD>
+__global__ __launch_bounds__(256) void k_adj_pieces(AdjGenArgs a) {
+    __shared__ float Js[(RC_ADAPT_MAXDEPTH + 1) * 256];
+    if (a.counts[3]) return;
+    constexpr int NPAR = KIND == RC_FIELD_TRILINEAR ? 16 : 2;
+    int64_t nvis = a.counts[0];
+    int64_t ncand = a.counts[1] < a.cap_cand ? a.counts[1] : a.cap_cand;
+    int lane = threadIdx.x & (WAVE - 1);
+    int64_t wave = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    int64_t nw = (int64_t)gridDim.x * (blockDim.x / WAVE);
+    for (int64_t w = wave; w * WAVE < ncand; w += nw) {
+        int64_t g = w * WAVE + lane;
+        int64_t key = INT64_MAX;
+        float grad[GRAD_MAX];
+#pragma unroll
+        for (int c = 0; c < GRAD_MAX; c++) grad[c] = 0.0f;
+        if (g < ncand) {
+            int64_t v = 0;
+            Pairing p = pair_candidate(a, g, w, nvis, ncand, &v);
+            key = w + v;
+            if (p.hit) {
+                Piecewise P;
+                for (int k = 0; k < 3; k++) {
+                    P.rho[k] = p.rho[k];
+                    P.r[k] = p.rr[k];
+                    P.lo[k] = p.lo[k];
+                }
+                P.scale = ldexp(1.0, p.lv);
+                P.s_in = p.s_in;
+                P.s_out = p.s_out;
+                P.rnorm = ray_norm64(p.rr);
+                int nc = KIND == RC_FIELD_TRILINEAR ? 8 : 1;
+                for (int c = 0; c < 8; c++) {
+                    int cc = c < nc ? c : 0;
+                    P.kc[c] = a.kappa[(int64_t)p.leaf * nc + cc];
+                    P.ec[c] = a.eps[(int64_t)p.leaf * nc + cc];
+                    P.kd[c] = (double)P.kc[c];
+                }
+                float2 ad = a.adj_leaf[g];
+                pieces_grad<KIND, METHOD>(P, a.d0, a.c_rk, ad.x, ad.y, Js + threadIdx.x, grad);
+            }
+        }
+#pragma unroll
+        for (int dd = 1; dd < WAVE; dd <<= 1) {
+            int64_t kd = __shfl_up(key, dd);
+            bool same = lane >= dd && kd == key;
+#pragma unroll
+            for (int c = 0; c < NPAR; c++) {
+                float y = __shfl_up(grad[c], dd);
+                if (same) grad[c] += y;
+            }
+        }
+        int64_t knext = __shfl_down(key, 1);
+        bool last = key != INT64_MAX && (lane == WAVE - 1 || knext != key);
+        if (last) {
+            float* dst = a.partial + key * GRAD_MAX;
+#pragma unroll
+            for (int c = 0; c < NPAR; c++) dst[c] = grad[c];
+        }
+    }
+}
+
 }  // namespace
 }  // namespace rc
 
@@ -249,6 +446,58 @@ rc_status rc::rc_segments_general(const rc_forest* f, const rc_fields* fl, const
                 hipLaunchKernelGGL((k_segments_general<RC_FIELD_TRILINEAR, RC_INT_SIMPSON>), G, B, 0, st, a);
             else
                 hipLaunchKernelGGL((k_segments_general<RC_FIELD_CONST, RC_INT_SIMPSON>), G, B, 0, st, a);
+            break;
+        default:
+            return RC_EUNSUPPORTED;
+    }
+    RC_HIP(hipGetLastError());
+    return RC_OK;
+}
+
+rc_status rc::rc_adjoint_pieces(const rc_forest* f, const rc_fields* fl, const void* dcams, const rc_vforest* vf,
+                                const rc_integrator* in, const float* adj_leaf, float* partial, const rc_tuning* tune,
+                                hipStream_t st) {
+    AdjGenArgs a;
+    a.cams = (const Cam*)dcams;
+    a.level = f->level;
+    a.x = f->x;
+    a.y = f->y;
+    a.z = f->z;
+    a.N = f->nleaves;
+    a.kappa = fl->kappa;
+    a.eps = fl->eps;
+    a.vis_leaf = vf->vis_leaf;
+    a.vis_cam = vf->vis_cam;
+    a.vis_rect = vf->vis_rect;
+    a.cand_offset = vf->cand_offset;
+    a.counts = vf->counts;
+    a.cand_chunk = vf->cand_chunk;
+    a.cap_cand = vf->cap_cand;
+    a.adj_leaf = (const float2*)adj_leaf;
+    a.partial = partial;
+    a.d0 = 0;
+    while ((1 << a.d0) < in->substeps) a.d0++;
+    a.c_rk = in->c_rk;
+    dim3 G(stride_grid(vf->cap_cand, 256, tuned(tune, 3, 256 * 8))), B(256);
+    bool tri = fl->kind == RC_FIELD_TRILINEAR;
+    switch (in->method) {
+        case RC_INT_RK4:
+            if (tri)
+                hipLaunchKernelGGL((k_adj_pieces<RC_FIELD_TRILINEAR, RC_INT_RK4>), G, B, 0, st, a);
+            else
+                hipLaunchKernelGGL((k_adj_pieces<RC_FIELD_CONST, RC_INT_RK4>), G, B, 0, st, a);
+            break;
+        case RC_INT_GAUSS2:
+            if (tri)
+                hipLaunchKernelGGL((k_adj_pieces<RC_FIELD_TRILINEAR, RC_INT_GAUSS2>), G, B, 0, st, a);
+            else
+                hipLaunchKernelGGL((k_adj_pieces<RC_FIELD_CONST, RC_INT_GAUSS2>), G, B, 0, st, a);
+            break;
+        case RC_INT_SIMPSON:
+            if (tri)
+                hipLaunchKernelGGL((k_adj_pieces<RC_FIELD_TRILINEAR, RC_INT_SIMPSON>), G, B, 0, st, a);
+            else
+                hipLaunchKernelGGL((k_adj_pieces<RC_FIELD_CONST, RC_INT_SIMPSON>), G, B, 0, st, a);
             break;
         default:
             return RC_EUNSUPPORTED;

@@ -60,14 +60,20 @@ def test_equilibrium_intensity_fields(oracle_mod):
     _run(scene, "analytic", 1, 0.0, oracle_mod)
 
 
-@pytest.mark.parametrize("method,substeps,kind,background", [("gauss2", 4, "trilinear", 0.5),
-                                                              ("gauss2", 1, "trilinear", 0.0),
-                                                              ("simpson", 2, "trilinear", 0.5),
-                                                              ("simpson", 8, "const", 0.3),
-                                                              ("gauss2", 8, "const", 0.0)])
-def test_adjoint_of_gauss_and_simpson(oracle_mod, method, substeps, kind, background):
-    """The hand-written adjoint through eq. gaussAB and eq. simpson over equal pieces: coefficient gradients of
-    L = sum (I - I*)^2 against the oracle's (dual numbers, pinned by finite differences) within 1e-4."""
+@pytest.mark.parametrize("method,substeps,kind,background,c_rk", [("gauss2", 4, "trilinear", 0.5, 0.0),
+                                                                   ("gauss2", 1, "trilinear", 0.0, 0.0),
+                                                                   ("simpson", 2, "trilinear", 0.5, 0.0),
+                                                                   ("simpson", 8, "const", 0.3, 0.0),
+                                                                   ("gauss2", 8, "const", 0.0, 0.0),
+                                                                   ("rk4", 1, "trilinear", 0.5, 0.05),
+                                                                   ("gauss2", 2, "trilinear", 0.0, 0.05),
+                                                                   ("simpson", 1, "trilinear", 0.4, 0.03),
+                                                                   ("rk4", 4, "const", 0.2, 0.02),
+                                                                   ("simpson", 16, "const", 0.0, 0.05)])
+def test_adjoint_of_the_integrators(oracle_mod, method, substeps, kind, background, c_rk):
+    """The hand-written adjoint through eq. gaussAB and eq. simpson over equal pieces, and through the pieces of
+    Alg. adaptiverk (c_rk > 0) for RK4, Gauss and Simpson: coefficient gradients of L = sum (I - I*)^2 against
+    the oracle's (dual numbers, pinned by finite differences) within 1e-4."""
     torch = _torch()
     import paper_1809_01334_amd as P
     from test_gpu_parity import GRAD_TOL, rel_err
@@ -77,31 +83,27 @@ def test_adjoint_of_gauss_and_simpson(oracle_mod, method, substeps, kind, backgr
         rng = np.random.default_rng(substeps)
         N = scene.forest.nleaves
         scene.fields = synth.constant_fields(rng.uniform(0.1, 3.0, N), rng.uniform(0.0, 1.0, N))
-    print(f"[case] adjoint {method} x{substeps} {kind} background {background}", flush=True)
-    r = P.Renderer(scene.forest, scene.fields, scene.cameras, method, substeps)
+    print(f"[case] adjoint {method} x{substeps} {kind} background {background} c_rk {c_rk}", flush=True)
+    r = P.Renderer(scene.forest, scene.fields, scene.cameras, method, substeps, c_rk=c_rk)
     _, _, I = r.forward()
     target = np.random.default_rng(26).uniform(0.0, 0.3, I.shape[0])
     g = (2.0 * (I.double() - torch.from_numpy(target).to(I.device))).float().contiguous()
     dk, de = r.backward(g)
     torch.cuda.synchronize()
     cam = scene.cameras[0]
-    ref = oracle_mod.render(scene.forest, scene.fields, cam, method, substeps)
-    gk, ge = oracle_mod.grad(scene.forest, scene.fields, cam, 2.0 * (ref["I"] - target), method, substeps)
+    ref = oracle_mod.render(scene.forest, scene.fields, cam, method, substeps, c_rk=c_rk)
+    gk, ge = oracle_mod.grad(scene.forest, scene.fields, cam, 2.0 * (ref["I"] - target), method, substeps,
+                             c_rk=c_rk)
     ek = rel_err(dk.cpu().numpy().T, gk)
     ee = rel_err(de.cpu().numpy().T, ge)
     assert ek <= GRAD_TOL and ee <= GRAD_TOL, (ek, ee)
 
 
-def test_adjoint_rejects_the_recursion_and_shell_rejects_the_new_integrators():
+def test_adjoint_rejects_16_equal_pieces_and_shell_rejects_the_new_integrators():
     torch = _torch()
     import paper_1809_01334_amd as P
 
     scene = synth.small_scene(24, w=32, h=24)
-    r = P.Renderer(scene.forest, scene.fields, scene.cameras, "gauss2", 1, c_rk=0.05)
-    r.forward()
-    with pytest.raises(P.RcError) as e:
-        r.backward(torch.ones_like(r.I))
-    assert e.value.status == P._lib.RC_EUNSUPPORTED
     r = P.Renderer(scene.forest, scene.fields, scene.cameras, "simpson", 16)
     r.forward()
     with pytest.raises(P.RcError) as e:

@@ -145,22 +145,24 @@ def test_equilibrium_intensity_fields_match_emission_fields(oracle_mod):
 
 
 def test_integrator_gradients_match_finite_differences(oracle_mod):
-    """The oracle's coefficient gradients (dual numbers through eq. gaussAB and eq. simpson over equal pieces)
-    against central finite differences of its own loss L = sum (I - I*)^2, trilinear fields, background 0.4."""
+    """The oracle's coefficient gradients (dual numbers through eq. gaussAB and eq. simpson over equal pieces,
+    and through Alg. adaptiverk's pieces, whose split decisions a step of 1e-6 leaves unchanged) against central
+    finite differences of its own loss L = sum (I - I*)^2, trilinear fields, background 0.4."""
     O = oracle_mod
     s = synth.small_scene(12, lmin=1, lmax=3, ngauss=3, w=24, h=18, background=0.4)
     cam = s.cameras[0]
     f = s.fields
     kap0, eps0 = f.kappa.astype(np.float64), f.eps.astype(np.float64)
     rng = np.random.default_rng(13)
-    for method, sub in (("gauss2", 4), ("simpson", 2), ("gauss2", 1)):
-        r = O.render(s.forest, f, cam, method, sub)
+    for method, sub, c_rk in (("gauss2", 4, 0.0), ("simpson", 2, 0.0), ("gauss2", 1, 0.0), ("rk4", 1, 0.05),
+                              ("gauss2", 2, 0.05), ("simpson", 1, 0.05)):
+        r = O.render(s.forest, f, cam, method, sub, c_rk=c_rk)
         target = r["I"] + rng.normal(0, 0.05, r["I"].shape)
 
         def loss(kap, eps):
-            return ((O.render(s.forest, f, cam, method, sub, kappa=kap, eps=eps)["I"] - target) ** 2).sum()
+            return ((O.render(s.forest, f, cam, method, sub, kappa=kap, eps=eps, c_rk=c_rk)["I"] - target) ** 2).sum()
 
-        gk, ge = O.grad(s.forest, f, cam, 2 * (r["I"] - target), method, sub)
+        gk, ge = O.grad(s.forest, f, cam, 2 * (r["I"] - target), method, sub, c_rk=c_rk)
         leaves = np.flatnonzero(np.abs(gk).sum(0) > 0)
         assert len(leaves) >= 5
         for l in rng.choice(leaves, 5, replace=False):
@@ -177,4 +179,4 @@ def test_integrator_gradients_match_finite_differences(oracle_mod):
                     em[c, l] -= h
                 fd = (loss(kp, ep) - loss(km, em)) / (2 * h)
                 an = gk[c, l] if which == "k" else ge[c, l]
-                assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (method, sub, which, l, c, fd, an)
+                assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (method, sub, c_rk, which, l, c, fd, an)
