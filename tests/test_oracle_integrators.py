@@ -180,3 +180,37 @@ def test_integrator_gradients_match_finite_differences(oracle_mod):
                 fd = (loss(kp, ep) - loss(km, em)) / (2 * h)
                 an = gk[c, l] if which == "k" else ge[c, l]
                 assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (method, sub, c_rk, which, l, c, fd, an)
+
+
+def test_equilibrium_field_gradient_matches_finite_differences(oracle_mod):
+    """eq. BIrelation fields (constant kappa, equilibrium intensity I in place of eps), closed form: the oracle's
+    gradients with respect to kappa and I against central finite differences of L = sum (I_pix - I*)^2."""
+    O = oracle_mod
+    s = synth.small_scene(14, lmin=1, lmax=3, ngauss=3, w=24, h=18, background=0.3)
+    rng = np.random.default_rng(14)
+    N = s.forest.nleaves
+    f = synth.equilibrium_fields(rng.uniform(0.1, 3.0, N), rng.uniform(0.0, 1.5, N))
+    cam = s.cameras[0]
+    r = O.render(s.forest, f, cam, "analytic", 1)
+    target = r["I"] + rng.normal(0, 0.05, r["I"].shape)
+    kap0, int0 = f.kappa.astype(np.float64), f.eps.astype(np.float64)
+
+    def loss(kap, inten):
+        return ((O.render(s.forest, f, cam, "analytic", 1, kappa=kap, eps=inten)["I"] - target) ** 2).sum()
+
+    gk, gi = O.grad(s.forest, f, cam, 2 * (r["I"] - target), "analytic", 1)
+    leaves = np.flatnonzero(np.abs(gk).sum(0) > 0)
+    for l in rng.choice(leaves, 8, replace=False):
+        for which in ("k", "i"):
+            kp, km, ip, im = kap0.copy(), kap0.copy(), int0.copy(), int0.copy()
+            base = kap0 if which == "k" else int0
+            h = 1e-6 * max(1.0, abs(base[0, l]))
+            if which == "k":
+                kp[0, l] += h
+                km[0, l] -= h
+            else:
+                ip[0, l] += h
+                im[0, l] -= h
+            fd = (loss(kp, ip) - loss(km, im)) / (2 * h)
+            an = gk[0, l] if which == "k" else gi[0, l]
+            assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (which, l, fd, an)
