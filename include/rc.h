@@ -401,11 +401,11 @@ rc_status rc_merge_lists(const void *dcams, int32_t ncams, int64_t total_pixels,
  * gradients hold channel-major blocks as in rc_segments and rc_composite.
  * dL_dkappa, dL_deps [device, layout of rc_fields] are overwritten, or added
  * to when accumulate != 0.  adj_leaf [device, cap_cand * 2] and adj_node
- * [device, cap_rec * 2] are scratch.  Differentiated: the closed form; RK4,
- * Gauss and Simpson over 1, 2, 4 or 8 equal pieces; and the recursion
- * (c_rk > 0) of the three, its split decisions held fixed.  RC_EUNSUPPORTED
- * for other piece counts without the recursion, RC_GEOM_SHELL6 and surface
- * forests, and RC_FIELD_CONST_EQ fields.
+ * [device, cap_rec * 2] are scratch.  Differentiated: the closed form (for
+ * RC_FIELD_CONST_EQ with respect to kappa and I); RK4, Gauss and Simpson over
+ * 1, 2, 4 or 8 equal pieces; and the recursion (c_rk > 0) of the three, its
+ * split decisions held fixed.  RC_EUNSUPPORTED for other piece counts without
+ * the recursion, and for RC_GEOM_SHELL6 and surface forests.
  */
 rc_status rc_segments_backward(const rc_forest *forest, const rc_index *index, const rc_fields *fields,
                                const void *dcams, int32_t ncams, const rc_vforest *vf,

@@ -161,6 +161,14 @@ __device__ inline float stage_t(int p) {
 template <int KIND, int NSUB, int METHOD>
 __device__ inline void segment_grad(const float kc[8], const float ec[8], const SegGeom& sg, float gT, float J,
                                     float grad[GRAD_MAX]) {
+    if (KIND == 3) {
+        // eq. BIrelation: A = exp(-k dx), B = I (1 - A) with I in place of eps
+        float k = kc[0], I = ec[0], dx = sg.dx;
+        float A = expf(-k * dx);
+        grad[0] = gT * dx * A * (I - J);
+        grad[1] = gT * -expm1f(-k * dx);
+        return;
+    }
     if (KIND == 0) {
         float k = kc[0], e = ec[0], dx = sg.dx;
         float x = k * dx;
@@ -570,7 +578,9 @@ static rc_status backward_one(const rc_forest* f, const rc_index* ix, const rc_f
     int nc = fl->kind == RC_FIELD_TRILINEAR ? 8 : 1;
     dim3 G(lg), B(256);
     rc_status s = RC_OK;
-    if (in->method == RC_INT_ANALYTIC) {
+    if (in->method == RC_INT_ANALYTIC && fl->kind == RC_FIELD_CONST_EQ) {
+        hipLaunchKernelGGL((k_adj_leaf<3, 1, RC_INT_ANALYTIC>), G, B, 0, st, la);
+    } else if (in->method == RC_INT_ANALYTIC) {
         hipLaunchKernelGGL((k_adj_leaf<0, 1, RC_INT_ANALYTIC>), G, B, 0, st, la);
     } else if (in->c_rk > 0.0) {
         if ((s = rc_adjoint_pieces(f, fl, dcams, vf, in, adj_leaf, partial, tune, st)) != RC_OK) return s;

@@ -117,10 +117,11 @@ inline rc_status check_fields(const rc_fields* fl, const rc_integrator* in) {
 
 // The hand-written adjoint covers (kappa, eps) fields with the closed form,
 // with RK4, Gauss or Simpson over equal pieces (1, 2, 4 or 8, checked by the
-// entry point), and with the recursion of any of the three.
+// entry point) and with the recursion of any of the three, and (kappa, I)
+// equilibrium fields with the closed form.
 inline bool adjoint_supported(const rc_fields* fl, const rc_integrator* in) {
     (void)in;
-    return fl->kind != RC_FIELD_CONST_EQ && fl->kind != RC_FIELD_SURFACE;
+    return fl->kind != RC_FIELD_SURFACE;
 }
 
 // Integrators beyond the closed form and fixed-step RK4: rc_integrators.hip.
