@@ -317,6 +317,7 @@ def bench_batched(torch, P, synth, r, steps):
     rb.replay()
     t_batch = time_region(torch, rb.replay, steps)
     S = rb.count_segments()
+    rb_counts = rb.counts
     singles = [P.Renderer(r.forest, r.fields, [c], "rk4", 4, device="cuda:0", index=r.index) for c in cams]
 
     def plain():
@@ -327,11 +328,32 @@ def bench_batched(torch, P, synth, r, steps):
     t_plain = time_region(torch, plain, steps)
     log(f"[bench] batched: one graph {t_batch:.2f} ms, 64 plain forwards {t_plain:.2f} ms, segments {S}")
     del singles
+    del rb
+    # small views, where per-view launches dominate: 64 cameras of 128^2
+    rng = np.random.default_rng([1809, 1334, 128])
+    small = [synth.random_perspective_camera(rng, 128, 128) for _ in range(64)]
+    rs = P.Renderer(r.forest, r.fields, small, "rk4", 4, device="cuda:0", index=r.index)
+    rs.capture()
+    rs.replay()
+    t_small = time_region(torch, rs.replay, steps)
+    singles = [P.Renderer(r.forest, r.fields, [c], "rk4", 4, device="cuda:0", index=r.index) for c in small]
+
+    def plain_small():
+        for x in singles:
+            x.forward()
+
+    plain_small()
+    t_small_plain = time_region(torch, plain_small, steps)
+    log(f"[bench] 64 views of 128^2: one graph {t_small:.3f} ms, 64 plain forwards {t_small_plain:.3f} ms")
+    del singles, rs
+    torch.cuda.empty_cache()
     return {"workload": "64 cameras, resolutions from {256,512,1024,2048}^2, same forest",
-            "views": len(cams), "pixels": int(sum(c.npix for c in cams)), "candidates": rb.counts["ncand"],
+            "views": len(cams), "pixels": int(sum(c.npix for c in cams)), "candidates": rb_counts["ncand"],
             "segments": S, "batched_ms": t_batch, "plain_sum_ms": t_plain, "plain_over_batched": t_plain / t_batch,
             "ray_segments_per_s": S / (t_batch * 1e-3), "images_per_s": len(cams) / (t_batch * 1e-3),
-            "tuning": tune["tuning"]}
+            "tuning": tune["tuning"],
+            "small_views": {"views": 64, "resolution": 128, "batched_ms": t_small, "plain_sum_ms": t_small_plain,
+                            "plain_over_batched": t_small_plain / t_small}}
 
 
 def bench_integrators(torch, P, r, steps):
