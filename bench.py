@@ -357,8 +357,9 @@ def bench_batched(torch, P, synth, r, steps):
 
 
 def bench_integrators(torch, P, r, steps):
-    """Segment phase of the adaptive workload with each integrator (Sec. 2.7):
-    RK4, implicit Gauss and Simpson over 4 pieces, and RK4 with the recursion."""
+    """Segment phase and adjoint of the adaptive workload with each integrator
+    (Sec. 2.7): RK4, implicit Gauss and Simpson over 4 pieces, and RK4 and Gauss
+    with the recursion."""
     out = {}
     for name, method, sub, c_rk in (("rk4_x4", "rk4", 4, 0.0), ("gauss2_x4", "gauss2", 4, 0.0),
                                     ("simpson_x4", "simpson", 4, 0.0), ("rk4_adaptive_c0.5", "rk4", 1, 0.5),
@@ -366,8 +367,13 @@ def bench_integrators(torch, P, r, steps):
         ri = P.Renderer(r.forest, r.fields, r.cams.raw, method, sub, device="cuda:0", index=r.index, c_rk=c_rk)
         ri.segments()
         t = time_region(torch, ri.segments, steps)
-        out[name] = {"segments_ms": t}
-        log(f"[bench] integrator {name}: segments phase {t:.3f} ms")
+        # the adjoint of the same integrator (its pieces recomputed), after a forward
+        ri.forward()
+        g = torch.ones(ri.cams.npix, device="cuda:0")
+        ri.backward(g)
+        t_bwd = time_region(torch, lambda: ri.backward(g), steps)
+        out[name] = {"segments_ms": t, "backward_ms": t_bwd}
+        log(f"[bench] integrator {name}: segments phase {t:.3f} ms, adjoint {t_bwd:.3f} ms")
         del ri
     return out
 
