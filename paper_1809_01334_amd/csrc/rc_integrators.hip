@@ -426,7 +426,7 @@ rc_status rc::rc_segments_general(const rc_forest* f, const rc_fields* fl, const
     a.d0 = 0;
     while ((1 << a.d0) < in->substeps) a.d0++;
     a.c_rk = in->c_rk;
-    dim3 G(stride_grid(vf->cap_cand, 256, tuned(tune, 0, 256 * 8))), B(256);
+    dim3 G(stride_grid(vf->cap_cand, 256, tuned(tune, 0, 16384))), B(256);
     bool tri = fl->kind == RC_FIELD_TRILINEAR;
     switch (in->method) {
         case RC_INT_RK4:

@@ -228,7 +228,7 @@ extern "C" rc_status rc_segments(const rc_forest* f, const rc_fields* fl, const 
               fl->kappa,        fl->eps,        in->substeps,   vf->vis_leaf, vf->vis_cam, vf->vis_rect,
               vf->cand_offset,  vf->counts,     vf->cand_chunk, vf->cap_cand, (float2*)rec_leaf, hit,
               (double2*)sio,    fl->kind == RC_FIELD_CONST_EQ ? 1 : 0, fstride, vf->cap_cand};
-    unsigned grid = stride_grid(vf->cap_cand, 256, tuned(tune, 0, 256 * 8));
+    unsigned grid = stride_grid(vf->cap_cand, 256, tuned(tune, 0, 8192));
     dim3 G(grid), B(256);
     int nch = fl->nch;
     if (in->method == RC_INT_ANALYTIC) {

@@ -435,7 +435,7 @@ rc_status rc::rc_shell_segments(const rc_forest* f, const rc_fields* fl, const v
     a.rec = (float4*)rec_leaf;
     a.hit = hit;
     a.sio = sio;
-    dim3 G(stride_grid(vf->cap_cand, 256, tuned(tune, 0, 256 * 8))), B(256);
+    dim3 G(stride_grid(vf->cap_cand, 256, tuned(tune, 0, 16384))), B(256);
     int ns = in->method == RC_INT_ANALYTIC ? 0 : in->substeps;
     switch (ns) {
         case 0: hipLaunchKernelGGL((k_segments_shell<0>), G, B, 0, st, a); break;

@@ -132,7 +132,7 @@ rc_status rc::rc_surface_segments(const rc_forest* f, const rc_fields* fl, const
     a.rec = (float4*)rec_leaf;
     a.hit = hit;
     a.sio = sio;
-    hipLaunchKernelGGL(k_segments_surface, dim3(stride_grid(vf->cap_cand, 256, tuned(tune, 0, 256 * 8))), dim3(256),
+    hipLaunchKernelGGL(k_segments_surface, dim3(stride_grid(vf->cap_cand, 256, tuned(tune, 0, 8192))), dim3(256),
                        0, st, a);
     RC_HIP(hipGetLastError());
     return RC_OK;

@@ -18,7 +18,7 @@ import torch
 
 from . import _lib as L
 
-SEG_BLOCKS = (1024, 2048, 4096, 8192)
+SEG_BLOCKS = (2048, 4096, 8192, 16384, 32768)
 FOLD_BLOCKS = (1024, 2048, 4096, 8192, 16384)
 ROOT_BLOCKS = (1024, 2048, 4096, 8192)
 
