@@ -379,7 +379,7 @@ rc_status rc::rc_surface_ho_segments(const rc_forest* f, const rc_fields* fl, co
     a.rec = (float4*)rec_leaf;
     a.hit = hit;
     a.sio = sio;
-    dim3 G(stride_grid(vf->cap_cand, 256, tuned(tune, 0, 8192))), B(256);
+    dim3 G(stride_grid(vf->cap_cand, 256, tuned(tune, 0, 1024))), B(256);
     if (R == 2)
         hipLaunchKernelGGL(k_segments_surface_ho<2>, G, B, 0, st, a);
     else
