@@ -47,6 +47,33 @@ def test_shell_small_parity(oracle_mod, seed, lmin, lmax, w, h):
     _check_images(r, scene, oracle_mod)
 
 
+@pytest.mark.parametrize("seed", range(6))
+def test_shell_random_cases(oracle_mod, seed):
+    """Seeded random cases: refinement depth, one or two cameras at random distances and sizes (rays through
+    the hollow core), background, RK4 with 1, 2 or 4 substeps or constant fields in closed form."""
+    rng = np.random.default_rng([7171, seed])
+    lmin = int(rng.integers(1, 3))
+    scene = synth.shell_scene(40 + seed, lmin=lmin, lmax=lmin + int(rng.integers(1, 3)),
+                              w=int(rng.integers(30, 90)), h=int(rng.integers(30, 90)),
+                              dist=float(rng.uniform(1.6, 3.5)), background=float(rng.uniform(0.0, 0.5)))
+    if rng.integers(2):
+        N = scene.forest.nleaves
+        scene.fields = synth.constant_fields(rng.uniform(0.1, 2.0, N), rng.uniform(0.0, 1.0, N))
+        scene.method, scene.substeps = "analytic", 1
+    else:
+        scene.substeps = int(rng.choice([1, 2, 4]))
+    if rng.integers(2):
+        w, h = int(rng.integers(20, 60)), int(rng.integers(20, 60))
+        scene.cameras.append(synth.random_perspective_camera(rng, w, h, dist=float(rng.uniform(1.6, 3.0)),
+                                                             center=(0.0, 0.0, 0.0)))
+    r = _renderer(scene)
+    r.forward()
+    cams, leaves, off = _check_prune(r, scene, oracle_mod)
+    _check_shell_pairing(r, scene, oracle_mod, cams, leaves, off)
+    r.forward()
+    _check_images(r, scene, oracle_mod)
+
+
 def test_shell_constant_analytic_background_and_two_cameras(oracle_mod):
     scene = synth.shell_scene(5, lmin=1, lmax=3, w=80, h=64, dist=2.8, background=0.4)
     rng = np.random.default_rng(55)

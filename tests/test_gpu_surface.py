@@ -164,6 +164,32 @@ def test_mandelbrot_small(oracle_mod, instance):
     _check(r, f, fl, cams, oracle_mod)
 
 
+@pytest.mark.parametrize("seed", range(8))
+def test_random_warped_trees(oracle_mod, seed):
+    """Seeded random cases: one to three bilinear trees with random warped corners (rays may cross a tree twice,
+    trees may overlap in depth), random refinement, fields with opaque leaves, and one or two random cameras
+    (perspective or orthographic, random background): the full pairing and the images against the oracle."""
+    rng = np.random.default_rng([6161, seed])
+    ntrees = int(rng.integers(1, 4))
+    base = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [1, 1, 0]], np.float64)
+    corners = np.stack([base + rng.normal(0.0, 0.25, (4, 3)) + [0.0, 0.0, 0.35 * t] for t in range(ntrees)])
+    f = synth.random_quadtree_forest(rng, corners, 1, int(rng.integers(3, 6)), 0.5)
+    fl = synth.random_surface_fields(rng, f.nleaves, opaque_frac=float(rng.uniform(0.0, 0.4)))
+    cams = []
+    for _ in range(int(rng.integers(1, 3))):
+        w, h = int(rng.integers(30, 90)), int(rng.integers(30, 90))
+        if rng.integers(2):
+            d = rng.normal(size=3)
+            cams.append(_ortho(d, [0, 0, 1] if abs(d[2]) < 0.9 * np.linalg.norm(d) else [1, 0, 0],
+                               [0.5, 0.5, 0.35], w, h, 2.2 / w, background=float(rng.uniform(0, 0.5))))
+        else:
+            cams.append(synth.random_perspective_camera(rng, w, h, dist=3.0, center=(0.5, 0.5, 0.35),
+                                                        zfar=8.0, background=float(rng.uniform(0, 0.5))))
+    r = _renderer(f, fl, cams)
+    nh, _ = _check(r, f, fl, cams, oracle_mod)
+    assert nh > 100
+
+
 def test_surface_rejections_and_graph_replay(oracle_mod):
     torch = _torch()
     import paper_1809_01334_amd as P
