@@ -180,7 +180,8 @@ typedef struct rc_index {
 /* The visible forest ("vforest", Sec. 3.1) of a set of cameras, written by
  * rc_prune_visible and read by the other calls.  Capacities are inputs. */
 typedef struct rc_vforest {
-    int64_t cap_vis;       /* capacity of the visible (camera, leaf) list */
+    int64_t cap_vis;       /* capacity of the visible (camera, leaf) list; at most 2^31 - 2, else every
+                              call that takes the vforest returns RC_EUNSUPPORTED */
     int64_t cap_cand;      /* capacity of leaf candidate records (camera, leaf, pixel) */
     int64_t cap_rec;       /* capacity of internal-node records (camera, node, pixel) */
     int32_t *vis_leaf;     /* [device] cap_vis: leaf of visible pair v (camera-major, SFC order) */

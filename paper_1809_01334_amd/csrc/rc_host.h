@@ -91,6 +91,8 @@ inline rc_status check_vforest(const rc_vforest* vf, bool need_nodes) {
         return RC_EINVAL;
     if (need_nodes && (!vf->node_rect || !vf->node_offset)) return RC_EINVAL;
     if (vf->cap_vis < 0 || vf->cap_cand < 0 || vf->cap_rec < 0) return RC_EINVAL;
+    // the chunk table holds pair indices as int32
+    if (vf->cap_vis > (int64_t)0x7ffffffe) return RC_EUNSUPPORTED;
     return RC_OK;
 }
 

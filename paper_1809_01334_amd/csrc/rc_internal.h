@@ -177,13 +177,18 @@ __device__ inline Rect box_rect(const Cam& c, const double lo[3], const double h
 // pixel ray (eq. ray) and the slab test against a box
 // ---------------------------------------------------------------------------
 
+// MODE 0: perspective, 1: orthographic, -1: read from the camera.  A wave
+// whose lanes share one camera branches once on its mode, so the lanes do not
+// compute both rays and select.
+template <int MODE = -1>
 __device__ inline void pixel_ray(const Cam& c, int i, int j, double rho[3], double r[3]) {
 #pragma clang fp contract(off)
     double a = c.ell * ((double)i - c.cx);
     double b = c.ell * ((double)j - c.cy);
+    const bool ortho = MODE < 0 ? c.ortho != 0 : MODE == 1;
     for (int k = 0; k < 3; k++) {
         double off = a * c.t[k] + b * c.u[k];
-        if (c.ortho) {
+        if (ortho) {
             rho[k] = c.o[k] + off;
             r[k] = c.vh[k];
         } else {
@@ -311,8 +316,9 @@ __device__ inline SegGeom seg_geom(const double rho[3], const double r[3], doubl
         g.xf[k] = (float)((pf - lo[k]) * scale);
         g.dxi[k] = (float)((s_in - s_out) * r[k] * scale);
     }
-    // the ray's length scale is needed to FP32 accuracy only
-    float rn = sqrtf((float)(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]));
+    // the ray's length scale is needed to FP32 accuracy only: the hardware
+    // square root (within 1 ulp; |r|^2 is far from the denormal range)
+    float rn = __builtin_amdgcn_sqrtf((float)(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]));
     g.dx = (float)(s_out - s_in) * rn;
     return g;
 }
@@ -493,7 +499,7 @@ struct Pairing {
     double lo[3], rho[3], rr[3], s_in, s_out;
 };
 
-template <typename Args>
+template <int MODE, typename Args>
 __device__ inline Pairing pair_with(const Args& a, int64_t g, int64_t v, const Cam& c) {
     Pairing p;
     p.leaf = a.vis_leaf[v];
@@ -504,7 +510,7 @@ __device__ inline Pairing pair_with(const Args& a, int64_t g, int64_t v, const C
     p.lv = a.level[p.leaf];
     double hi[3];
     node_box(p.lv, a.x[p.leaf], a.y[p.leaf], a.z[p.leaf], p.lo, hi);
-    pixel_ray(c, i, j, p.rho, p.rr);
+    pixel_ray<MODE>(c, i, j, p.rho, p.rr);
     p.hit = slab_hit(c, p.rho, p.rr, p.lo, hi, p.s_in, p.s_out);
     return p;
 }
@@ -520,9 +526,10 @@ __device__ inline Pairing pair_candidate(const Args& a, int64_t g, int64_t w, in
     int c0 = __builtin_amdgcn_readfirstlane(cam);
     if (__all(cam == c0)) {
         Cam cs = load_cam_scalar(a.cams, c0);
-        return pair_with(a, g, v, cs);
+        if (cs.ortho) return pair_with<1>(a, g, v, cs);
+        return pair_with<0>(a, g, v, cs);
     }
-    return pair_with(a, g, v, a.cams[cam]);
+    return pair_with<-1>(a, g, v, a.cams[cam]);
 }
 
 // Camera of a pixel in the concatenated images.

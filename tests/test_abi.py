@@ -206,6 +206,29 @@ def test_integrator_validation():
         assert seg(kind, method, sub, c_rk) == L.RC_EINVAL  # null vforest arrays
 
 
+def test_visible_pair_capacity_is_limited_to_31_bits():
+    """The chunk table stores pair indices as int32, so a capacity of 2^31 or
+    more is refused before any device work."""
+    L = _lib()
+    lib = L.lib()
+    p = ctypes.c_void_p(16)
+    f = L.RcForest(1, 0, 8, None, p, p, p, p)
+    fl = L.RcFields(L.RC_FIELD_TRILINEAR, 1, p, p)
+    integ = L.RcIntegrator(L.RC_INT_RK4, 4, 0.0)
+
+    def seg(cap_vis):
+        vf = L.RcVforest()
+        vf.cap_vis, vf.cap_cand, vf.cap_rec = cap_vis, 64, 0
+        for nm in ("vis_leaf", "vis_cam", "vis_rect", "cand_offset", "leaf_vis", "counts"):
+            setattr(vf, nm, p)
+        return lib.rc_segments(ctypes.byref(f), ctypes.byref(fl), p, 1, ctypes.byref(vf), ctypes.byref(integ), p,
+                               None, None, None, None)
+
+    assert seg(2 ** 31) == L.RC_EUNSUPPORTED
+    assert seg(2 ** 31 - 1) == L.RC_EUNSUPPORTED
+    assert seg(-1) == L.RC_EINVAL
+
+
 def test_surface_validation():
     """Surface forests take 1 to 6 trees with a corner table, surface data only, and the
     closed-form surface model; the adjoint rejects them."""
