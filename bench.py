@@ -56,13 +56,13 @@ ANALYTIC_LEAF_BYTES = 37
 # 256 MiB device copy: x2.0 and x1.0), valid for the kernel sources whose
 # SHA-256 is given.
 MEASURED_TRAFFIC = {
-    "k_segments_rk4<2, 4, 1>": {"bytes": 240080791, "sources": ("rc_segments.hip", "rc_internal.h"),
-                             "sha256": "b52ccdc97a71d4a323190fa229eab9bf46b4339f2537e02d58c2e1334f94ebda"},
-    "k_segments_analytic<1>": {"bytes": 181899866, "sources": ("rc_segments.hip", "rc_internal.h"),
-                               "sha256": "b52ccdc97a71d4a323190fa229eab9bf46b4339f2537e02d58c2e1334f94ebda"},
+    "k_segments_rk4<2, 4, 1>": {"bytes": 239861512, "sources": ("rc_segments.hip", "rc_internal.h"),
+                             "sha256": "40869d34fe93ba4e3ee438249da176c63ce982bd3eaab3cf59d5429d6ec8ef3c"},
+    "k_segments_analytic<1>": {"bytes": 181929435, "sources": ("rc_segments.hip", "rc_internal.h"),
+                               "sha256": "40869d34fe93ba4e3ee438249da176c63ce982bd3eaab3cf59d5429d6ec8ef3c"},
     # per forward of the headline view: every fold launch of one rc_composite call
-    "composite": {"bytes": 404510565, "sources": ("rc_composite.hip", "rc_composite.h", "rc_internal.h"),
-                  "sha256": "ada139bcaedd54ab7ccc6c13f3ed3cfdf6c1c4ac90caa32c02d7f10cdf55dda7"},
+    "composite": {"bytes": 404487983, "sources": ("rc_composite.hip", "rc_composite.h", "rc_internal.h"),
+                  "sha256": "16e38bf2c81980522dcaf3a54c595fb05cf2ea5c8276a3874dc54d967e4d3b22"},
 }
 COPY_CALIB_BYTES = 256 << 20
 
