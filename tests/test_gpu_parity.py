@@ -227,6 +227,34 @@ def test_many_small_views_mixed_in_every_wave(oracle_mod):
     _check_images(r, scene, oracle_mod)
 
 
+def test_small_views_alternating_perspective_and_orthographic(oracle_mod):
+    """400 views of 1..9 x 1..9 pixels, perspective and orthographic in turn (random directions, pixel sizes and
+    backgrounds): waves hold candidates of both camera modes, so pairing takes its per-lane camera path as well
+    as the perspective and orthographic branches of one-camera waves. Visibility, all pairing and every pixel
+    against the oracle."""
+    rng = np.random.default_rng(4040)
+    scene = synth.small_scene(41, lmin=2, lmax=4)
+    cams = []
+    for k in range(400):
+        w, h = int(rng.integers(1, 10)), int(rng.integers(1, 10))
+        bg = float(rng.uniform(0.0, 0.5))
+        if k % 2 == 0:
+            cams.append(synth.random_perspective_camera(rng, w, h, background=bg))
+        else:
+            view = rng.normal(size=3)
+            c = _ortho_camera(w, h, float(rng.uniform(0.08, 0.4)), view, rng.normal(size=3),
+                              0.5 + rng.uniform(-0.2, 0.2, 3))
+            c.background = bg
+            cams.append(c)
+    scene.cameras = cams
+    r = _renderer(scene)
+    r.forward()
+    cams_, leaves, off = _check_prune(r, scene, oracle_mod)
+    _check_pairing(r, scene, oracle_mod, cams_, leaves, off)
+    r.forward()
+    _check_images(r, scene, oracle_mod)
+
+
 def test_near_plane_clipping(oracle_mod):
     """Camera close to the cube: the near plane (projection plane) cuts leaves."""
     scene = synth.small_scene(8, w=64, h=64)
