@@ -153,7 +153,8 @@ typedef struct rc_integrator {
 typedef struct rc_tuning {
     int32_t seg_blocks;   /* rc_segments (default 8192; 16384 for the shell and the
                              integrator variants, 1024 for degree-R surfaces) */
-    int32_t fold_blocks;  /* rc_composite and adjoint level passes (default 4096) */
+    int32_t fold_blocks;  /* level passes: rc_composite's default 8192; the adjoint's, the fused channels'
+                             and the shell's 4096 */
     int32_t root_blocks;  /* root passes over the image pixels (default 4096) */
     int32_t adj_blocks;   /* rc_segments_backward leaf adjoint (default 2048) */
 } rc_tuning;

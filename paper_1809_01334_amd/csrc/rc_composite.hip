@@ -70,7 +70,7 @@ __global__ __launch_bounds__(256) void k_fold_root(FoldCtx C, int32_t root, int6
 // Node records of levels maxlevel-1 .. 1, deepest first.
 rc_status fold_levels(const FoldCtx& C, const rc_index* ix, const rc_vforest* vf, float* rec_node,
                       const rc_tuning* tune, hipStream_t st) {
-    unsigned grid = stride_grid(vf->cap_rec, 256, tuned(tune, 1, 256 * 16));
+    unsigned grid = stride_grid(vf->cap_rec, 256, tuned(tune, 1, 256 * 32));
     for (int l = ix->maxlevel - 1; l >= 1; l--) {
         if (ix->level_begin[l + 1] == ix->level_begin[l]) continue;
         hipLaunchKernelGGL(k_fold_level, dim3(grid), dim3(256), 0, st, C, l, (float2*)rec_node);
