@@ -394,7 +394,15 @@ rc_status rc_merge_lists(const void *dcams, int32_t ncams, int64_t total_pixels,
                          float *I, int64_t *overlaps, void *stream);
 
 /*
- * Adjoint of the images with respect to the coefficients.  Given
+ * Adjoint of the images with respect to the coefficients.  The operation
+ * differentiated is the forward path above: the image of a pixel is the group
+ * product of its segments (Sec. 2.4, eq. aggregate), so with I = A_front (A_k
+ * J + B_k) + B_front for every segment k the derivative of I with respect to
+ * segment k's pair is (T J, T), T the product of the A in front of it and J the
+ * intensity entering it from behind.  The group inverse (Sec. 2.4,
+ * eq. identityinverse) and the reversal of a segment (Sec. 2.6, eq. swapxy,
+ * eq. substbetagamma) would recover J from the whole pixel by dividing by
+ * T A_k; this call instead passes both factors top-down.  Given
  * dL_dI [device, total_pixels], pass (g T_front, J_behind) down the same
  * hierarchy (T_front: transmittance in front of a node, J_behind: intensity
  * entering it from behind; no division), so that a segment receives

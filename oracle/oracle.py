@@ -49,6 +49,8 @@ def lib():
         L.or_render.argtypes = [I64, P, P, P, P, I32, P, P, I32, I32, D, P, I64, P, P, P, P, P, P]
         L.or_grad.restype = I32
         L.or_grad.argtypes = [I64, P, P, P, P, I32, P, P, I32, I32, D, P, I64, P, P, P, P]
+        L.or_grad_abs.restype = I32
+        L.or_grad_abs.argtypes = [I64, P, P, P, P, I32, P, P, I32, I32, D, P, I64, P, P, P, P]
         L.or_segment.restype = I32
         L.or_segment.argtypes = [I32, P, P, ctypes.c_uint8, ctypes.c_uint32, ctypes.c_uint32,
                                  ctypes.c_uint32, P, P, D, D, I32, I32, D, P, P]
@@ -276,6 +278,27 @@ def grad(forest, fields, cam, g, method="rk4", substeps=4, pixels=None, kappa=No
     gk, ge = np.zeros_like(k), np.zeros_like(e)
     lib().or_grad(forest.nleaves, _p(lv), _p(x), _p(y), _p(z), kind, _p(k), _p(e), METHODS[method],
                   int(substeps), float(c_rk), _p(_c(raw, np.float64)), nsel, _p(pix), _p(gg), _p(gk), _p(ge))
+    return gk, ge
+
+
+def grad_abs(forest, fields, cam, w, method="rk4", substeps=4, pixels=None, kappa=None, eps=None, c_rk=0.0):
+    """sum_p w_p |dI_p/dkappa|, sum_p w_p |dI_p/deps| ([nc][N]) for weights w >= 0: the
+    bound on how far a per-pixel perturbation of dL/dI no larger than w moves the gradient."""
+    raw = cam.raw() if hasattr(cam, "raw") else np.asarray(cam, np.float64)
+    lv, x, y, z = _forest_args(forest)
+    kind, k, e = _field_args(fields, kappa, eps)
+    ww = _c(w, np.float64)
+    if pixels is None:
+        nsel, pix = -1, None
+    else:
+        pix = _c(pixels, np.int64)
+        nsel = pix.shape[0]
+    gk, ge = np.zeros_like(k), np.zeros_like(e)
+    st = lib().or_grad_abs(forest.nleaves, _p(lv), _p(x), _p(y), _p(z), kind, _p(k), _p(e), METHODS[method],
+                           int(substeps), float(c_rk), _p(_c(raw, np.float64)), nsel, _p(pix), _p(ww), _p(gk),
+                           _p(ge))
+    if st != 0:
+        raise ValueError("grad_abs needs non-negative weights")
     return gk, ge
 
 

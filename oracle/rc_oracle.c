@@ -846,9 +846,43 @@ int or_render(int64_t n, const uint8_t *level, const uint32_t *x, const uint32_t
  * so dI/dB_k = T_k and dI/dA_k = T_k J_k with J_k the intensity entering
  * segment k from behind; segment derivatives come from dual numbers.
  */
+static int grad_sum(int64_t n, const uint8_t *level, const uint32_t *x, const uint32_t *y, const uint32_t *z,
+                    int kind, const double *kap, const double *eps, int method, int substeps, double c_rk,
+                    const double *cam, int64_t npix_sel, const int64_t *pix_sel, const double *g, double *gk,
+                    double *ge, int absolute);
+
 int or_grad(int64_t n, const uint8_t *level, const uint32_t *x, const uint32_t *y, const uint32_t *z,
             int kind, const double *kap, const double *eps, int method, int substeps, double c_rk,
             const double *cam, int64_t npix_sel, const int64_t *pix_sel, const double *g, double *gk, double *ge)
+{
+    return grad_sum(n, level, x, y, z, kind, kap, eps, method, substeps, c_rk, cam, npix_sel, pix_sel, g, gk, ge, 0);
+}
+
+/*
+ * Weighted absolute sensitivities: for weights g[p] >= 0, gk and ge receive
+ * sum_p g[p] |dI_p / dtheta| for every coefficient theta, with the same
+ * segments, fold factors and dual numbers as or_grad.  A leaf meets a pixel's
+ * ray in at most one segment, so each term is one segment's contribution.
+ * This bounds |sum_p dg_p dI_p/dtheta| for any per-pixel perturbation with
+ * |dg_p| <= g[p] (the triangle inequality).  Returns -1 on a negative weight.
+ */
+int or_grad_abs(int64_t n, const uint8_t *level, const uint32_t *x, const uint32_t *y, const uint32_t *z,
+                int kind, const double *kap, const double *eps, int method, int substeps, double c_rk,
+                const double *cam, int64_t npix_sel, const int64_t *pix_sel, const double *g, double *gk,
+                double *ge)
+{
+    orcam c;
+    cam_parse(cam, &c);
+    int64_t m = npix_sel >= 0 ? npix_sel : (int64_t)c.w * c.h;
+    for (int64_t q = 0; q < m; q++)
+        if (!(g[q] >= 0.0)) return -1;
+    return grad_sum(n, level, x, y, z, kind, kap, eps, method, substeps, c_rk, cam, npix_sel, pix_sel, g, gk, ge, 1);
+}
+
+static int grad_sum(int64_t n, const uint8_t *level, const uint32_t *x, const uint32_t *y, const uint32_t *z,
+                    int kind, const double *kap, const double *eps, int method, int substeps, double c_rk,
+                    const double *cam, int64_t npix_sel, const int64_t *pix_sel, const double *g, double *gk,
+                    double *ge, int absolute)
 {
     orcam c;
     cam_parse(cam, &c);
@@ -908,8 +942,10 @@ int or_grad(int64_t n, const uint8_t *level, const uint32_t *x, const uint32_t *
         dn A, B;
         segment_dn(&F, &b, rho, r, ray_norm(r), s->s_in, s->s_out, method, substeps, c_rk, np, &A, &B);
         for (int p = 0; p < nc; p++) {
-            gk[(int64_t)p * n + s->leaf] += dIdA[m] * A.d[p] + dIdB[m] * B.d[p];
-            ge[(int64_t)p * n + s->leaf] += dIdA[m] * A.d[nc + p] + dIdB[m] * B.d[nc + p];
+            double tk = dIdA[m] * A.d[p] + dIdB[m] * B.d[p];
+            double te = dIdA[m] * A.d[nc + p] + dIdB[m] * B.d[nc + p];
+            gk[(int64_t)p * n + s->leaf] += absolute ? fabs(tk) : tk;
+            ge[(int64_t)p * n + s->leaf] += absolute ? fabs(te) : te;
         }
     }
     free(dIdA);

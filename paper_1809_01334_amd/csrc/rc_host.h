@@ -139,6 +139,8 @@ rc_status rc_adjoint_pieces(const rc_forest* f, const rc_fields* fl, const void*
 // The per-call tables written by rc_prune_visible and read by later calls.
 inline rc_status check_tables(const rc_vforest* vf, const rc_index* ix, int32_t ncams) {
     if (!vf->cand_chunk) return RC_EINVAL;
+    // the record chunk table stores (level, camera, node) slot indices as int32
+    if (rc_node_slots(ix, ncams) > (int64_t)0x7ffffffe) return RC_EUNSUPPORTED;
     if (ix->maxlevel >= 1 && ncams > 0 && (int64_t)ncams * (ix->level_begin[ix->maxlevel] - ix->level_begin[1]) > 0 &&
         !vf->rec_chunk)
         return RC_EINVAL;

@@ -338,6 +338,9 @@ class Renderer:
         self.vf = None
         self.counts = None
         self.bwd_ready = False
+        # bumped by every call that changes the fields or rewrites the records, so
+        # that an autograd backward can tell whether they still belong to its forward
+        self.generation = 0
         self.plan()
 
     # -- sizing -----------------------------------------------------------
@@ -382,10 +385,12 @@ class Renderer:
         rc_prune_visible(self.forest, self.index, self.cams, self.vf, self.ws)
 
     def segments(self, hit=None, sio=None):
+        self.generation += 1
         rc_segments(self.forest, self.fields, self.cams, self.vf, self.method, self.substeps, self.rec_leaf, hit, sio,
                     self.tuning, self.c_rk)
 
     def composite(self):
+        self.generation += 1
         if self.fields.nch > 1:
             # every channel in one call, on the channel-major blocks
             rc_composite_channels(self.forest, self.index, self.cams, self.vf, self.fields.nch, self.rec_leaf,
@@ -397,6 +402,7 @@ class Renderer:
     def composite_per_channel(self):
         """rc_composite once per channel, on that channel's blocks of the records and images."""
         nl, nn, P = self.rec_floats * self.vf.cap_cand, self.rec_floats * self.vf.cap_rec, self.cams.npix
+        self.generation += 1
         for ch in range(self.fields.nch):
             rc_composite(self.forest, self.index, self.cams, self.vf, self.rec_leaf[ch * nl:(ch + 1) * nl],
                          self.rec_node[ch * nn:(ch + 1) * nn], self.A[ch * P:(ch + 1) * P],
@@ -413,6 +419,7 @@ class Renderer:
             self.n_entries = _empty(1, torch.int64, self.device)
             self.entries = None
         for _ in range(2):
+            self.generation += 1
             rc_composite_lists(self.forest, self.index, self.cams, self.vf, self.rec_leaf, self.rec_node,
                                self.list_offset, self.entries, self.n_entries, self.lists_ws, self.tuning)
             n = int(self.n_entries.item())
@@ -423,6 +430,7 @@ class Renderer:
 
     def lists_step(self):
         """Enqueue rc_composite_lists into the buffers sized by composite_lists()."""
+        self.generation += 1
         rc_composite_lists(self.forest, self.index, self.cams, self.vf, self.rec_leaf, self.rec_node,
                            self.list_offset, self.entries, self.n_entries, self.lists_ws, self.tuning)
 
@@ -481,10 +489,12 @@ class Renderer:
             self.backward(self.g_dLdI, self.g_dk, self.g_de)
 
     def replay(self):
+        self.generation += 1
         self.graph.replay()
         return self.A, self.B, self.I
 
     def set_fields(self, kappa: torch.Tensor, eps: torch.Tensor):
+        self.generation += 1
         self.fields = DeviceFields(kappa, eps, self.fields.kind == L.RC_FIELD_CONST_EQ,
                                    self.fields.kind == L.RC_FIELD_SURFACE)
 
@@ -508,18 +518,32 @@ class Renderer:
 
 
 class RenderFn(torch.autograd.Function):
-    """I = render(kappa, eps) with the hand-written adjoint of librc."""
+    """I = render(kappa, eps) with the hand-written adjoint of librc.
+
+    The adjoint reads the renderer's records of the forward.  If the same
+    renderer has changed fields or rendered again between this forward and its
+    backward (two render() calls in one loss, a target rendered with other
+    fields), the backward first restores this call's fields and recomputes its
+    forward, so the gradient is always taken at this call's inputs."""
 
     @staticmethod
     def forward(ctx, kappa, eps, renderer: Renderer):
-        renderer.set_fields(kappa.detach(), eps.detach())
+        kd, ed = kappa.detach(), eps.detach()
+        renderer.set_fields(kd, ed)
         _, _, I = renderer.forward()
         ctx.renderer = renderer
+        ctx.generation = renderer.generation
+        ctx.save_for_backward(kd, ed)
         return I.clone()
 
     @staticmethod
     def backward(ctx, gI):
-        dk, de = ctx.renderer.backward(gI.contiguous().float())
+        r = ctx.renderer
+        kd, ed = ctx.saved_tensors
+        if r.generation != ctx.generation:
+            r.set_fields(kd, ed)
+            r.forward()
+        dk, de = r.backward(gI.contiguous().float())
         return dk, de, None
 
 

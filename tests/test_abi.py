@@ -271,3 +271,32 @@ def test_surface_validation():
     st = lib.rc_segments_backward(ctypes.byref(f), ctypes.byref(ix), ctypes.byref(fl), p, 1, ctypes.byref(vf),
                                   ctypes.byref(integ), p, p, 1, p, p, p, p, p, 0, p, 0, None, None)
     assert st == L.RC_EUNSUPPORTED
+
+
+def test_node_slot_count_is_limited_to_31_bits():
+    """The record chunk table stores (level, camera, node) slot indices as int32,
+    so a slot count of 2^31 - 1 or more is refused before any device work."""
+    L = _lib()
+    lib = L.lib()
+    p = ctypes.c_void_p(16)
+    f = L.RcForest(1, 0, 8, None, p, p, p, p)
+    vf = L.RcVforest()
+    for nm in ("vis_leaf", "vis_cam", "vis_rect", "cand_offset", "leaf_vis", "node_rect", "node_offset", "counts",
+               "cand_chunk", "rec_chunk", "child_desc"):
+        setattr(vf, nm, p)
+    vf.cap_vis, vf.cap_cand, vf.cap_rec = 64, 64, 64
+
+    def prune(internal_below_root, ncams):
+        ix = L.RcIndex()
+        ix.child, ix.level, ix.x, ix.y, ix.z, ix.tree = p, p, p, p, p, p
+        ix.maxlevel = 2
+        ix.level_begin[0], ix.level_begin[1] = 0, 1
+        for l in range(2, len(ix.level_begin)):
+            ix.level_begin[l] = 1 + internal_below_root
+        ix.ninternal = ix.cap_internal = 1 + internal_below_root
+        assert lib.rc_node_slots(ctypes.byref(ix), ncams) == ncams * internal_below_root
+        return lib.rc_prune_visible(ctypes.byref(f), ctypes.byref(ix), p, ncams, ctypes.byref(vf), None, 0, None)
+
+    assert prune(2 ** 27, 16) == L.RC_EUNSUPPORTED        # 2^31 slots
+    assert prune(2 ** 31 - 1, 1) == L.RC_EUNSUPPORTED     # 2^31 - 1 slots
+    assert prune(2 ** 31 - 2, 1) == L.RC_EWORKSPACE       # the largest count passes, then needs a workspace

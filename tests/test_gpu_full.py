@@ -76,3 +76,56 @@ def test_adjoint_workload_full_size_sampled_loss(oracle_mod):
     ek = rel_err(dk.cpu().numpy().T, gk)
     ee = rel_err(de.cpu().numpy().T, ge)
     assert ek <= GRAD_TOL and ee <= GRAD_TOL, (ek, ee)
+
+
+@pytest.mark.timeout(900)
+def test_adjoint_workload_end_to_end(oracle_mod):
+    """The 512^2 adjoint workload end to end, each side differentiating its own images:
+    L = sum over the whole view of (I - I_target)^2, I and I_target rendered in FP32 on the
+    GPU through the autograd wrapper (dL/dI = 2 (I - I_target) formed by torch in FP32) and
+    in FP64 by the oracle.
+
+    The GPU's dL/dI carries the FP32 error of both images.  With both images within the
+    pixel tolerance, |dI_p| <= PIX_TOL max(|I_p|, 1e-3 max|I|) (checked first), the error
+    of dL/dI at p is at most e_p = 2 PIX_TOL (max(|I_p|, f) + max(|I*_p|, f*)), and it moves
+    the gradient of coefficient theta by at most sum_p e_p |dI_p/dtheta| (the oracle's
+    weighted absolute sensitivities).  The tolerance per coefficient is that bound plus
+    the adjoint's own GRAD_TOL max(|g*|, 1e-3 max|g*|), the bar of the adjoint-only test."""
+    torch = _torch()
+    import paper_1809_01334_amd as P
+
+    scene = synth.config_scene(5)
+    cam = scene.cameras[0]
+    tf = scene.extra["target_fields"]
+    print(f"[case] adjoint workload end to end N={scene.forest.nleaves} {cam.w}x{cam.h}", flush=True)
+    r = P.Renderer(scene.forest, scene.fields, scene.cameras, scene.method, scene.substeps)
+    rt = P.Renderer(r.forest, P.DeviceFields.from_synth(tf, r.device), scene.cameras, scene.method,
+                    scene.substeps, index=r.index)
+    kap = r.fields.kappa.clone().requires_grad_(True)
+    eps = r.fields.eps.clone().requires_grad_(True)
+    I = P.render(kap, eps, r)
+    It = P.render(rt.fields.kappa, rt.fields.eps, rt)
+    loss = ((I - It) ** 2).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    ref = oracle_mod.render(scene.forest, scene.fields, cam, scene.method, scene.substeps)
+    reft = oracle_mod.render(scene.forest, tf, cam, scene.method, scene.substeps)
+    Ig, Itg = I.detach().cpu().numpy(), It.detach().cpu().numpy()
+    assert rel_err(Ig, ref["I"]) <= PIX_TOL and rel_err(Itg, reft["I"]) <= PIX_TOL
+    go = 2.0 * (ref["I"] - reft["I"])
+    gk, ge = oracle_mod.grad(scene.forest, scene.fields, cam, go, scene.method, scene.substeps)
+
+    def floored(x):
+        return np.maximum(np.abs(x), 1e-3 * np.abs(x).max())
+
+    e = 2.0 * PIX_TOL * (floored(ref["I"]) + floored(reft["I"]))
+    ak, ae = oracle_mod.grad_abs(scene.forest, scene.fields, cam, e, scene.method, scene.substeps)
+    dk = kap.grad.cpu().numpy().T
+    de = eps.grad.cpu().numpy().T
+    worst = []
+    for nm, got, want, bound in (("kappa", dk, gk, ak), ("eps", de, ge, ae)):
+        tol = GRAD_TOL * floored(want) + bound
+        err = np.abs(got - want)
+        worst.append((nm, float((err / tol).max()), rel_err(got, want)))
+        assert np.all(err <= tol), (nm, float((err / tol).max()))
+    print(f"[measured] end-to-end gradient error / tolerance, and the plain relative error: {worst}", flush=True)

@@ -384,6 +384,41 @@ def test_autograd_function_and_accumulate(oracle_mod):
     assert torch.allclose(dk2, 2 * dk, rtol=1e-6, atol=0) and torch.allclose(de2, 2 * de, rtol=1e-6, atol=0)
 
 
+def test_two_renders_on_one_renderer_in_one_loss():
+    """render() twice on one Renderer with different fields inside one loss: each
+    call's gradient is taken at its own fields (the second forward overwrote the
+    records the first one's backward reads), equal bit for bit to two renderers."""
+    torch = _torch()
+    import paper_1809_01334_amd as P
+
+    scene = synth.small_scene(4, w=56, h=44)
+    scene.cameras[0].background = 0.5
+    r = _renderer(scene)
+    k0 = torch.from_numpy(P.DeviceFields.leaf_major(scene.fields.kappa)).cuda()
+    e0 = torch.from_numpy(P.DeviceFields.leaf_major(scene.fields.eps)).cuda()
+    gen = torch.Generator(device="cpu").manual_seed(41)
+    k1 = k0 + 0.05 * torch.randn(k0.shape, generator=gen).cuda()
+    e1 = e0 + 0.05 * torch.randn(e0.shape, generator=gen).cuda()
+    w = torch.rand(r.cams.npix, generator=gen).cuda()
+
+    def loss_of(rend_a, rend_b):
+        ka, ea = k0.clone().requires_grad_(True), e0.clone().requires_grad_(True)
+        kb, eb = k1.clone().requires_grad_(True), e1.clone().requires_grad_(True)
+        Ia = P.render(ka, ea, rend_a)
+        Ib = P.render(kb, eb, rend_b)
+        loss = ((Ia - Ib) ** 2 * w).sum() + (Ia * w).sum()
+        loss.backward()
+        torch.cuda.synchronize()
+        return ka.grad, ea.grad, kb.grad, eb.grad
+
+    one = loss_of(r, r)
+    r2 = P.Renderer(r.forest, P.DeviceFields(k1, e1), scene.cameras, scene.method, scene.substeps, index=r.index)
+    two = loss_of(r, r2)
+    for a, b in zip(one, two):
+        assert torch.equal(a, b)
+    assert float(one[0].abs().max()) > 0 and float(one[2].abs().max()) > 0
+
+
 def test_graph_replay_matches_eager():
     """HIP-graph replays, interleaved with eager work and syncs, equal the eager forward bit for bit."""
     torch = _torch()
