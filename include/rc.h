@@ -251,6 +251,25 @@ rc_status rc_prune_visible(const rc_forest *forest, const rc_index *index, const
                            rc_vforest *vf, void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * rc_prune_visible without a workspace argument and without allocating, for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops, hosts that forbid hipMalloc).  The workspace is a file-scope
+ * device array of RC_STATIC_SCRATCH_BYTES per device, held from the library's
+ * load until the process ends; its address is looked up once per device, on
+ * the first call with that device current (make that first call outside
+ * stream capture).  Outputs are bitwise those of rc_prune_visible.  Returns
+ * RC_EWORKSPACE when the call would need more than RC_STATIC_SCRATCH_BYTES,
+ * i.e. when rc_workspace_bytes(forest, index, ncams, NULL) exceeds it (about
+ * 8 M (camera, leaf) and (camera, internal node) items), and the errors of
+ * rc_prune_visible otherwise.  Calls on one device share the array: calls
+ * that overlap in time on one device (two streams, two host threads) race and
+ * must be ordered by the caller.
+ */
+#define RC_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+rc_status rc_prune_visible_static(const rc_forest *forest, const rc_index *index, const void *dcams, int32_t ncams,
+                                  rc_vforest *vf, void *stream);
+
+/*
  * Ray segments of every candidate (Sec. 3.2): for each visible pair and each
  * pixel of its rectangle, intersect the pixel's ray with the leaf (a slab test
  * whose shared faces give bitwise equal crossing depths) and integrate

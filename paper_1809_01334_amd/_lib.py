@@ -30,6 +30,7 @@ RC_ABSENT = -1
 RC_FIELD_CONST, RC_FIELD_TRILINEAR, RC_FIELD_CONST_EQ, RC_FIELD_SURFACE = 0, 1, 2, 3
 RC_INT_ANALYTIC, RC_INT_RK4, RC_INT_GAUSS2, RC_INT_SIMPSON = 0, 1, 2, 3
 RC_ADAPT_MAXDEPTH = 16
+RC_STATIC_SCRATCH_BYTES = 64 << 20
 
 
 class RcForest(ctypes.Structure):
@@ -72,6 +73,7 @@ _SIGS = {
     "rc_camera_prepare": (c_i32, [c_vp, c_i32, c_vp, P(c_i64), c_vp]),
     "rc_forest_index": (c_i32, [P(RcForest), P(RcIndex), c_vp, c_sz, c_vp]),
     "rc_prune_visible": (c_i32, [P(RcForest), P(RcIndex), c_vp, c_i32, P(RcVforest), c_vp, c_sz, c_vp]),
+    "rc_prune_visible_static": (c_i32, [P(RcForest), P(RcIndex), c_vp, c_i32, P(RcVforest), c_vp]),
     "rc_segments": (c_i32, [P(RcForest), P(RcFields), c_vp, c_i32, P(RcVforest), P(RcIntegrator), c_vp, c_vp, c_vp,
                             P(RcTuning), c_vp]),
     "rc_composite": (c_i32, [P(RcForest), P(RcIndex), c_vp, c_i32, P(RcVforest), c_vp, c_vp, c_i64, c_vp, c_vp, c_vp,

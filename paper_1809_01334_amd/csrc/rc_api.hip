@@ -104,8 +104,7 @@ extern "C" size_t rc_workspace_bytes(const rc_forest* f, const rc_index* ix, int
     b = bi > b ? bi : b;
     // rc_prune_visible: partials of the joint scan over leaves and node slots,
     // then the rectangles of the reduce pass (8 bytes per item)
-    int64_t items = N * nc + (ix ? rc_node_slots(ix, ncams) : 0);
-    size_t bp = rc::align_up(rc::scan_partial_bytes(items, sizeof(rc::I64x3))) + rc::align_up((size_t)items * 8);
+    size_t bp = rc::prune_ws_bytes(f, ix, ncams);
     b = bp > b ? bp : b;
     // rc_segments_backward: gradient partials per (wave chunk, visible pair)
     if (vf) {

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "rc.h"
+#include "rc_internal.h"
 
 namespace rc {
 
@@ -20,6 +21,14 @@ inline size_t backward_ws_bytes(int64_t cap_cand, int64_t cap_vis, int64_t ncams
     (void)N;
     int64_t nchunks = (cap_cand + WAVE - 1) / WAVE;
     return align_up((size_t)(nchunks + cap_vis + 1) * GRAD_MAX * sizeof(float));
+}
+
+// Workspace of rc_prune_visible: partials of the joint scan over (camera,
+// leaf) items and node slots, then every item's rectangle (8 bytes).
+inline size_t prune_ws_bytes(const rc_forest* f, const rc_index* ix, int32_t ncams) {
+    int64_t nc = ncams > 0 ? ncams : 1;
+    int64_t items = f->nleaves * nc + (ix ? rc_node_slots(ix, ncams) : 0);
+    return align_up(scan_partial_bytes(items, sizeof(I64x3))) + align_up((size_t)items * 8);
 }
 
 #define RC_HIP(call)                                 \

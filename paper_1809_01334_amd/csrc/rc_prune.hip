@@ -4,6 +4,8 @@
 // offsets, i.e. the paper's visible-pixel weights); one scan over
 // (level >= 1, camera, internal node) prefixes the record space of the
 // coarsening hierarchy used by compositing.
+#include <mutex>
+
 #include "rc_host.h"
 #include "rc_internal.h"
 #include "rc_shell.h"
@@ -297,16 +299,23 @@ __global__ __launch_bounds__(256) void k_tables(DescArgs a, int64_t nslots, int6
 
 using namespace rc;
 
-extern "C" rc_status rc_prune_visible(const rc_forest* f, const rc_index* ix, const void* dcams, int32_t ncams,
-                                      rc_vforest* vf, void* ws, size_t ws_bytes, void* stream) {
+namespace rc {
+namespace {
+
+rc_status check_prune_args(const rc_forest* f, const rc_index* ix, const void* dcams, int32_t ncams,
+                           const rc_vforest* vf) {
     rc_status s = check_forest(f);
     if (s != RC_OK) return s;
     if ((s = check_index(ix)) != RC_OK) return s;
     if ((s = check_vforest(vf, ix->maxlevel >= 1)) != RC_OK) return s;
     if (!dcams || ncams <= 0 || ncams > 32767) return RC_EINVAL;
-    if ((s = check_tables(vf, ix, ncams)) != RC_OK) return s;
-    if (!ws || ws_bytes < rc_workspace_bytes(f, ix, ncams, nullptr)) return RC_EWORKSPACE;
-    hipStream_t st = (hipStream_t)stream;
+    return check_tables(vf, ix, ncams);
+}
+
+// The prune itself, arguments validated; ws holds prune_ws_bytes() bytes
+// (scan partials and the stashed rectangles, all written before they are read).
+rc_status prune(const rc_forest* f, const rc_index* ix, const void* dcams, int32_t ncams, rc_vforest* vf, void* ws,
+                hipStream_t st) {
     const Cam* cams = (const Cam*)dcams;
     int64_t N = f->nleaves;
 
@@ -383,4 +392,49 @@ extern "C" rc_status rc_prune_visible(const rc_forest* f, const rc_index* ix, co
                        nc1, nc2, vf->cand_chunk, vf->rec_chunk);
     RC_HIP(hipGetLastError());
     return RC_OK;
+}
+
+// Workspace of the allocation-free prune: one array per device, holding the
+// last call's partials and rectangles until the process ends.
+__device__ __align__(256) unsigned char scratch[RC_STATIC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+void* scratch_dev[MAX_DEVICES];
+
+// Device address of the current device's scratch array, looked up once per
+// device (the array's name is only a host-side stand-in for it).
+rc_status scratch_ptr(void** out) {
+    int dev = -1;
+    RC_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) return RC_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_dev[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return RC_EHIP;
+        scratch_dev[dev] = p;
+    }
+    *out = scratch_dev[dev];
+    return RC_OK;
+}
+
+}  // namespace
+}  // namespace rc
+
+extern "C" rc_status rc_prune_visible(const rc_forest* f, const rc_index* ix, const void* dcams, int32_t ncams,
+                                      rc_vforest* vf, void* ws, size_t ws_bytes, void* stream) {
+    rc_status s = check_prune_args(f, ix, dcams, ncams, vf);
+    if (s != RC_OK) return s;
+    if (!ws || ws_bytes < rc_workspace_bytes(f, ix, ncams, nullptr)) return RC_EWORKSPACE;
+    return prune(f, ix, dcams, ncams, vf, ws, (hipStream_t)stream);
+}
+
+extern "C" rc_status rc_prune_visible_static(const rc_forest* f, const rc_index* ix, const void* dcams,
+                                             int32_t ncams, rc_vforest* vf, void* stream) {
+    rc_status s = check_prune_args(f, ix, dcams, ncams, vf);
+    if (s != RC_OK) return s;
+    if (prune_ws_bytes(f, ix, ncams) > RC_STATIC_SCRATCH_BYTES) return RC_EWORKSPACE;
+    void* ws = nullptr;
+    if ((s = scratch_ptr(&ws)) != RC_OK) return s;
+    return prune(f, ix, dcams, ncams, vf, ws, (hipStream_t)stream);
 }

@@ -300,3 +300,39 @@ def test_node_slot_count_is_limited_to_31_bits():
     assert prune(2 ** 27, 16) == L.RC_EUNSUPPORTED        # 2^31 slots
     assert prune(2 ** 31 - 1, 1) == L.RC_EUNSUPPORTED     # 2^31 - 1 slots
     assert prune(2 ** 31 - 2, 1) == L.RC_EWORKSPACE       # the largest count passes, then needs a workspace
+
+
+def test_static_prune_limits_its_scratch():
+    """The allocation-free prune refuses, before any device work, a call whose
+    workspace would exceed RC_STATIC_SCRATCH_BYTES (about 8 M items), and checks
+    its arguments like rc_prune_visible."""
+    L = _lib()
+    lib = L.lib()
+    p = ctypes.c_void_p(16)
+    vf = L.RcVforest()
+    for nm in ("vis_leaf", "vis_cam", "vis_rect", "cand_offset", "leaf_vis", "node_rect", "node_offset", "counts",
+               "cand_chunk", "rec_chunk", "child_desc"):
+        setattr(vf, nm, p)
+    vf.cap_vis, vf.cap_cand, vf.cap_rec = 64, 64, 64
+    ix = L.RcIndex()
+    ix.child, ix.level, ix.x, ix.y, ix.z, ix.tree = p, p, p, p, p, p
+    ix.maxlevel = 1
+    ix.level_begin[0] = 0
+    for l in range(1, len(ix.level_begin)):
+        ix.level_begin[l] = 1
+    ix.ninternal = ix.cap_internal = 1
+
+    def prune(nleaves, ncams):
+        f = L.RcForest(1, 0, nleaves, None, p, p, p, p)
+        want = lib.rc_workspace_bytes(ctypes.byref(f), ctypes.byref(ix), ncams, None)
+        st = lib.rc_prune_visible_static(ctypes.byref(f), ctypes.byref(ix), p, ncams, ctypes.byref(vf), None)
+        return st, want
+
+    st, want = prune(9_000_000, 1)
+    assert want > L.RC_STATIC_SCRATCH_BYTES and st == L.RC_EWORKSPACE
+    st, want = prune(1_000_000, 9)
+    assert want > L.RC_STATIC_SCRATCH_BYTES and st == L.RC_EWORKSPACE
+    assert lib.rc_prune_visible_static(None, ctypes.byref(ix), p, 1, ctypes.byref(vf), None) == L.RC_EINVAL
+    f = L.RcForest(1, 0, 8, None, p, p, p, p)
+    assert lib.rc_prune_visible_static(ctypes.byref(f), ctypes.byref(ix), None, 1, ctypes.byref(vf), None) == \
+        L.RC_EINVAL
