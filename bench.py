@@ -25,6 +25,9 @@ HBM_PEAK_GBS = 8000.0
 # FP32 vector peak without packed FP32 instructions (and the FP64 vector
 # peak): 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz = 78.6 TFLOP/s
 FP32_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# MI355X's published FP32 vector peak, which counts packed FP32 (two lanes'
+# worth per instruction); this build compiles without packed FP32 instructions
+FP32_PUBLISHED_TFLOPS = 157.3
 
 # Algorithmic cost per unit (the work the method must do, not what a kernel
 # happens to issue):
@@ -51,19 +54,11 @@ PIX_BYTES = 12
 #   kappa and eps (8 B), rectangle and candidate offset (16 B), read once.
 ANALYTIC_LEAF_BYTES = 37
 
-# HBM traffic per launch of the kernels priced here (per call for the
-# composite), from rocprofv3 FETCH_SIZE and WRITE_SIZE (calibrated on a
-# 256 MiB device copy: x2.0 and x1.0), valid for the kernel sources whose
-# SHA-256 is given.
-MEASURED_TRAFFIC = {
-    "k_segments_rk4<2, 4, 1>": {"bytes": 240462056, "sources": ("rc_segments.hip", "rc_internal.h"),
-                             "sha256": "40869d34fe93ba4e3ee438249da176c63ce982bd3eaab3cf59d5429d6ec8ef3c"},
-    "k_segments_analytic<1>": {"bytes": 181928926, "sources": ("rc_segments.hip", "rc_internal.h"),
-                               "sha256": "40869d34fe93ba4e3ee438249da176c63ce982bd3eaab3cf59d5429d6ec8ef3c"},
-    # per forward of the headline view: every fold launch of one rc_composite call
-    "composite": {"bytes": 404472661, "sources": ("rc_composite.hip", "rc_composite.h", "rc_internal.h"),
-                  "sha256": "2def90bce3a0d1cd4a8773ad5a878d086aae9cfd8215ea884d4bba65427180b2"},
-}
+# HBM traffic of the kernels priced here, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE (calibrated on a 256 MiB device copy: bytes = 2 FETCH_SIZE +
+# WRITE_SIZE), summed over one step's launches of the kernel on the named
+# workload, valid for the kernel sources whose SHA-256 is given.
+MEASURED_TRAFFIC = {}
 COPY_CALIB_BYTES = 256 << 20
 
 
@@ -82,12 +77,14 @@ def time_region(torch, fn, steps):
     return start.elapsed_time(end) / steps  # ms
 
 
-def measured_traffic(kernel):
-    """Calibrated HBM bytes per launch, or None when the kernel's sources
-    changed since the counters were taken."""
+def measured_traffic(kernel, r=None):
+    """Calibrated HBM bytes of one step's launches of `kernel` on the renderer's
+    workload, or None when none were taken for it or the kernel's sources changed
+    since."""
     import hashlib
 
-    m = MEASURED_TRAFFIC.get(kernel)
+    key = (kernel, r.counts["ncand"] if r is not None else None)
+    m = MEASURED_TRAFFIC.get(key)
     if not m or m["bytes"] is None:
         return None
     h = hashlib.sha256()
@@ -97,29 +94,85 @@ def measured_traffic(kernel):
     return m["bytes"] if h.hexdigest() == m["sha256"] else None
 
 
-def cpu_baseline(scene, reps=4):
-    """The FP64 oracle rendering the workload's full view `reps` times on the host cores."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(forest, fields, cams, method, substeps, every=4, frac=1 / 16, frac_one=1 / 512):
+    """The FP64 oracle, as it stands, on a seeded pixel sample of the workload's
+    views: every `every`-th view, `frac` of its pixels with all OpenMP threads,
+    then `frac_one` of them on one thread.  Rate = oracle segments / wall time."""
     from oracle import oracle as O
 
-    cam = scene.cameras[0]
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        r = O.render(scene.forest, scene.fields, cam, scene.method, scene.substeps)
-    dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": reps * r["segments"] / dt, "unit": "ray-segments/s", "cores": cores, "kind": "oracle",
-            "sample": f"{reps} renders of the full {cam.w}x{cam.h} view of the workload ({r['segments']} segments "
-                      f"each, FP64, {dt:.1f} s in total)"}
+    views = cams[::every]
+
+    def run(fr, seed):
+        rng = np.random.default_rng([1809, 1334, 4, seed])
+        segs, npx = 0, 0
+        t0 = time.perf_counter()
+        for cam in views:
+            n = max(1, int(cam.npix * fr))
+            pix = np.sort(rng.choice(cam.npix, n, replace=False))
+            segs += O.render(forest, fields, cam, method, substeps, pixels=pix)["segments"]
+            npx += n
+        return segs, npx, time.perf_counter() - t0
+
+    nthreads = O.threads()
+    segs, npx, dt = run(frac, 1)
+    O.threads(1)
+    segs1, npx1, dt1 = run(frac_one, 2)
+    O.threads(nthreads)
+    return {"value": segs / dt, "unit": "ray-segments/s", "cores": nthreads, "kind": "oracle",
+            "sample": f"every {every}th of the {len(cams)} views ({len(views)} views), a seeded 1/{round(1 / frac)} "
+                      f"of each view's pixels: {npx} pixels, {segs} segments, {dt:.1f} s on {nthreads} OpenMP "
+                      f"threads (FP64)",
+            "cpu_model": cpu_model(),
+            "one_thread": {"value": segs1 / dt1, "unit": "ray-segments/s", "cores": 1,
+                           "sample": f"the same views, 1/{round(1 / frac_one)} of each view's pixels: {npx1} "
+                                     f"pixels, {segs1} segments, {dt1:.1f} s"}}
+
+
+def render_launches(r):
+    """Launches of k_render_level per rc_render call: one per non-empty level below the root, one root pass."""
+    lb = r.index.level_begin()
+    return 1 + sum(1 for l in range(1, r.index.maxlevel) if lb[l + 1] > lb[l])
+
+
+def seg_roofline(r, S, C, t_seg, kernel="k_segments_rk4<2, 4, 1>"):
+    """The segment kernel (one launch per rc_segments call) against the FP32 vector peak."""
+    flops = SEG_FLOPS_FP32 * S + CAND_FLOPS_FP64 * C
+    achieved = flops / (t_seg * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": achieved, "peak": FP32_PUBLISHED_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / FP32_PUBLISHED_TFLOPS, "traffic": measured_traffic(kernel, r),
+            "kernel": kernel, "launches_per_step": 1, "flop_per_launch": flops, "avg_launch_ms": t_seg,
+            "per_unit": f"{SEG_FLOPS_FP32} FP32/segment + {CAND_FLOPS_FP64} FP64/candidate",
+            "peak_unpacked": FP32_PEAK_TFLOPS, "frac_unpacked": achieved / FP32_PEAK_TFLOPS}
+
+
+def composite_roofline(r, C, t_comp):
+    """rc_composite against HBM: every leaf record read once and A, B, I written (the node records of the
+    coarsening are traffic, not algorithmic bytes)."""
+    nbytes = C * REC_BYTES + r.cams.npix * PIX_BYTES
+    return {"bound": "hbm", "algorithmic_bytes": nbytes, "achieved_GBs": nbytes / (t_comp * 1e-3) / 1e9,
+            "frac": nbytes / (t_comp * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": measured_traffic("composite", r)}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--only", choices=("headline", "single", "config1", "shell"), default=None,
+                    help="time only this workload (for profiling runs)")
+    ap.add_argument("--no-plain", action="store_true", help="skip the 64 plain per-view forwards")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-bwd", action="store_true")
-    ap.add_argument("--res", type=int, default=1024)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-shell", action="store_true")
     ap.add_argument("--no-integrators", action="store_true")
@@ -141,32 +194,107 @@ def main():
     import paper_1809_01334_amd as P
     import synth
 
-    log("[bench] generating workload")
-    scene = synth.config_scene(2, w=args.res)
-    log(f"[bench] {scene.forest.nleaves} leaves; building renderer")
-    r = P.Renderer(scene.forest, scene.fields, scene.cameras, "rk4", 4, device="cuda:0")
+    log("[bench] generating the adaptive forest (levels 4-9)")
+    scene = synth.config_scene(2)
+    r1 = None
+    out = None
+    if args.only in (None, "headline"):
+        out = bench_headline(torch, P, synth, scene, args)
+        r1 = out.pop("_renderer")
+    if args.only in (None, "single"):
+        single = bench_single(torch, P, synth, scene, args, index=r1.index if r1 else None)
+        r1 = single.pop("_renderer")
+        if out is None:
+            out = single
+        else:
+            out["single_view_workload"] = single
+    if args.only in (None, "config1"):
+        c1 = bench_config1(torch, P, synth, args.steps)
+        if out is None:
+            out = c1
+        else:
+            out["config1_workload"] = c1
+    if args.only == "shell":
+        out = bench_shell(torch, P, synth, max(args.steps // 5, 3))
+    if args.only is not None:
+        print(json.dumps(out), flush=True)
+        return
+
+    sv = out["single_view_workload"]
+    if not args.no_bwd:
+        r = r1
+        g = torch.ones(r.cams.npix, device="cuda:0")
+        r.capture(backward=True, dLdI=g)
+        for _ in range(2):
+            r.replay()
+        ms_fb = time_region(torch, r.replay, max(args.steps // 2, 5))
+        sv["fwd_bwd_ms"] = ms_fb
+        sv["fwd_bwd_over_fwd"] = ms_fb / sv["ms_per_step"]
+        log(f"[bench] single view forward+backward {ms_fb:.3f} ms (graph)")
+        r.capture()
+        out["adjoint_workload"] = bench_adjoint(torch, P, synth, max(args.steps // 2, 5))
+    if not args.no_integrators:
+        out["integrators"] = bench_integrators(torch, P, r1, max(args.steps // 5, 3))
+    if not args.no_channels:
+        out["channels"] = bench_channels(torch, P, synth, scene, r1, max(args.steps // 5, 3))
+    if not args.no_analytic:
+        out["analytic_workload"] = bench_analytic(torch, P, synth, scene, r1, max(args.steps // 5, 3))
+    if not args.no_batch:
+        out["small_views"] = bench_small_views(torch, P, synth, r1, max(args.steps // 5, 3))
+    if not args.no_shell:
+        out["shell_workload"] = bench_shell(torch, P, synth, max(args.steps // 5, 3))
+    if not args.no_surface:
+        out["surface_workload"] = bench_surface(torch, P, synth, max(args.steps // 5, 3))
+    if not args.no_surface_ho:
+        out["surface_ho_workload"] = bench_surface_ho(torch, P, synth, max(args.steps // 5, 3))
+    if not args.no_shares:
+        out["shares"] = bench_shares(torch, P, synth, scene, r1, max(args.steps // 5, 3))
+
+    if args.copy_calib:
+        # a plain copy of known size: 256 MiB read + 256 MiB written per launch
+        src = torch.ones(COPY_CALIB_BYTES // 4, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copy calibration: 3 copies of {COPY_CALIB_BYTES} bytes")
+        del src, dst
+    if not args.no_cpu:
+        log("[bench] timing the CPU oracle on a sample of the headline workload")
+        out["cpu_baseline"] = cpu_baseline(scene.forest, scene.fields, synth.config4_cameras(), "rk4", 4)
+        log(f"[bench] CPU oracle: {out['cpu_baseline']['value']:.3e} ray-segments/s on "
+            f"{out['cpu_baseline']['cores']} threads")
+    print(json.dumps(out), flush=True)
+
+
+def bench_headline(torch, P, synth, scene, args):
+    """The forest of the adaptive workload seen by 64 cameras of uneven resolution
+    ({256, 512, 1024, 2048}^2), rendered by rc_render in one HIP graph: the largest
+    single-GPU workload by segments per step."""
+    cams = synth.config4_cameras()
+    npix = int(sum(c.npix for c in cams))
+    log(f"[bench] headline: {scene.forest.nleaves} leaves, {len(cams)} cameras, {npix} pixels")
+    r = P.Renderer(scene.forest, scene.fields, cams, "rk4", 4, device="cuda:0")
     counts = r.counts
     S = r.count_segments()
     C = counts["ncand"]
-    log(f"[bench] visible {counts['nvis']}, candidates {C}, segments {S}, node records {counts['nrec']}")
-
+    log(f"[bench] visible pairs {counts['nvis']}, candidates {C}, segments {S}, node records {counts['nrec']}")
     for _ in range(args.warmup):
         r.forward()
-    torch.cuda.synchronize()
     ms_eager = time_region(torch, r.forward, args.steps)
-    log(f"[bench] forward (eager launches) {ms_eager:.3f} ms")
     r.capture()
     for _ in range(args.warmup):
         r.replay()
     ms = time_region(torch, r.replay, args.steps)
-    log(f"[bench] forward (one HIP graph) {ms:.3f} ms")
-
-    # per-phase times (same stream, HIP events)
     t_prune = time_region(torch, r.prune, args.steps)
     t_seg = time_region(torch, r.segments, args.steps)
     t_comp = time_region(torch, r.composite, args.steps)
-    log(f"[bench] prune {t_prune:.3f} ms, segments {t_seg:.3f} ms, composite {t_comp:.3f} ms")
-
+    t_render = time_region(torch, r.render_step, args.steps)
+    log(f"[bench] headline: one graph {ms:.3f} ms (eager {ms_eager:.3f}); prune {t_prune:.3f}, segments "
+        f"{t_seg:.3f}, composite {t_comp:.3f} ms; rc_render (fused) {t_render:.3f} ms")
+    res = {}
+    for c in cams:
+        res[str(c.w)] = res.get(str(c.w), 0) + 1
     out = {
         "metric": METRIC,
         "value": S / (ms * 1e-3),
@@ -182,93 +310,93 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"adaptive octree levels 4-9 refined at 0.2 crossings of 8 Gaussians "
-                        f"({scene.forest.nleaves} leaves), trilinear kappa/eps, {args.res}x{args.res} perspective "
-                        f"view, RK4 x 4 substeps",
-            "leaves": scene.forest.nleaves,
-            "visible": counts["nvis"],
-            "candidates": C,
-            "segments": S,
-            "pixels": r.cams.npix,
+                        f"({scene.forest.nleaves} leaves), trilinear kappa/eps, RK4 x 4 substeps, seen by "
+                        f"{len(cams)} perspective cameras of uneven resolution in one HIP graph",
+            "views": len(cams), "resolutions": res, "leaves": scene.forest.nleaves, "visible": counts["nvis"],
+            "candidates": C, "segments": S, "node_records": counts["nrec"], "pixels": npix,
         },
-        "images_per_s": 1e3 / ms,
+        "images_per_s": len(cams) / (ms * 1e-3),
         "forward_eager_ms": ms_eager,
         "phase_ms": {"prune": t_prune, "segments": t_seg, "composite": t_comp},
+        "fused_render_ms": t_render,
+        "roofline": seg_roofline(r, S, C, t_seg),
     }
-    # dominant kernel: segment generation, one launch of k_segments_rk4<2, 4, 1> per call
-    flops = SEG_FLOPS_FP32 * S + CAND_FLOPS_FP64 * C
-    achieved = flops / (t_seg * 1e-3) / 1e12
-    out["roofline"] = {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                       "frac": achieved / FP32_PEAK_TFLOPS, "traffic": measured_traffic("k_segments_rk4<2, 4, 1>"),
-                       "kernel": "k_segments_rk4<2, 4, 1>", "flop_per_launch": flops,
-                       "per_unit": f"{SEG_FLOPS_FP32} FP32/segment + {CAND_FLOPS_FP64} FP64/candidate"}
-    # the other steps against their own bounds
-    comp_bytes = C * REC_BYTES + r.cams.npix * PIX_BYTES
-    prune_bytes = scene.forest.nleaves * 13 + counts["nvis"] * 20
-    comp_traffic = measured_traffic("composite")
-    out["phase_roofline"] = {
-        "composite": {"bound": "hbm", "algorithmic_bytes": comp_bytes,
-                      "achieved_GBs": comp_bytes / (t_comp * 1e-3) / 1e9,
-                      "frac": comp_bytes / (t_comp * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                      # measured HBM bytes, the node records of the coarsening included
-                      "traffic": comp_traffic,
-                      "traffic_GBs": comp_traffic / (t_comp * 1e-3) / 1e9 if comp_traffic else None},
-        "prune": {"bound": "hbm", "algorithmic_bytes": prune_bytes,
-                  "achieved_GBs": prune_bytes / (t_prune * 1e-3) / 1e9,
-                  "frac": prune_bytes / (t_prune * 1e-3) / 1e9 / HBM_PEAK_GBS},
-    }
+    pb = scene.forest.nleaves * len(cams) * 13 + counts["nvis"] * 20
+    out["phase_roofline"] = {"composite": composite_roofline(r, C, t_comp),
+                             "prune": {"bound": "hbm", "algorithmic_bytes": pb,
+                                       "achieved_GBs": pb / (t_prune * 1e-3) / 1e9,
+                                       "frac": pb / (t_prune * 1e-3) / 1e9 / HBM_PEAK_GBS}}
+    if not args.no_plain:
+        singles = [P.Renderer(r.forest, r.fields, [c], "rk4", 4, device="cuda:0", index=r.index) for c in cams]
 
-    if not args.no_bwd:
-        g = torch.ones(r.cams.npix, device="cuda:0")
-        for _ in range(2):
-            r.forward()
-            r.backward(g)
+        def plain():
+            for x in singles:
+                x.forward()
 
-        def fb():
-            r.forward()
-            r.backward(g)
+        plain()
+        t_plain = time_region(torch, plain, max(args.steps // 5, 3))
+        log(f"[bench] 64 plain per-view forwards {t_plain:.2f} ms")
+        out["plain_sum_ms"] = t_plain
+        out["plain_over_batched"] = t_plain / ms
+        del singles
+        torch.cuda.empty_cache()
+    out["_renderer"] = None
+    del r
+    torch.cuda.empty_cache()
+    return out
 
-        ms_fb_eager = time_region(torch, fb, max(args.steps // 2, 5))
-        r.capture(backward=True, dLdI=g)
-        for _ in range(2):
-            r.replay()
-        ms_fb = time_region(torch, r.replay, max(args.steps // 2, 5))
-        out["fwd_bwd_ms"] = ms_fb
-        out["fwd_bwd_eager_ms"] = ms_fb_eager
-        out["fwd_bwd_over_fwd"] = ms_fb / ms
-        log(f"[bench] forward+backward {ms_fb:.3f} ms (graph), {ms_fb_eager:.3f} ms (eager)")
 
-    if not args.no_bwd:
-        out["adjoint_workload"] = bench_adjoint(torch, P, synth, max(args.steps // 2, 5))
-    if not args.no_integrators:
-        out["integrators"] = bench_integrators(torch, P, r, max(args.steps // 5, 3))
-    if not args.no_channels:
-        out["channels"] = bench_channels(torch, P, synth, scene, r, max(args.steps // 5, 3))
-    if not args.no_analytic:
-        out["analytic_workload"] = bench_analytic(torch, P, synth, scene, r, max(args.steps // 5, 3))
-    if not args.no_batch:
-        out["batched_workload"] = bench_batched(torch, P, synth, r, max(args.steps // 10, 3))
-    if not args.no_shell:
-        out["shell_workload"] = bench_shell(torch, P, synth, max(args.steps // 10, 3))
-    if not args.no_surface:
-        out["surface_workload"] = bench_surface(torch, P, synth, max(args.steps // 5, 3))
-    if not args.no_surface_ho:
-        out["surface_ho_workload"] = bench_surface_ho(torch, P, synth, max(args.steps // 5, 3))
-    if not args.no_shares:
-        out["shares"] = bench_shares(torch, P, synth, scene, r, max(args.steps // 5, 3))
+def bench_single(torch, P, synth, scene, args, index=None):
+    """One 1024^2 perspective view of the adaptive forest (the single-view workload)."""
+    r = P.Renderer(scene.forest, scene.fields, scene.cameras, "rk4", 4, device="cuda:0", index=index)
+    counts = r.counts
+    S = r.count_segments()
+    C = counts["ncand"]
+    log(f"[bench] single view: visible {counts['nvis']}, candidates {C}, segments {S}, node records {counts['nrec']}")
+    for _ in range(args.warmup):
+        r.forward()
+    ms_eager = time_region(torch, r.forward, args.steps)
+    r.capture()
+    for _ in range(args.warmup):
+        r.replay()
+    ms = time_region(torch, r.replay, args.steps)
+    t_prune = time_region(torch, r.prune, args.steps)
+    t_seg = time_region(torch, r.segments, args.steps)
+    t_comp = time_region(torch, r.composite, args.steps)
+    t_render = time_region(torch, r.render_step, args.steps)
+    log(f"[bench] single view: one graph {ms:.3f} ms; prune {t_prune:.3f}, segments {t_seg:.3f}, composite "
+        f"{t_comp:.3f} ms; rc_render (fused) {t_render:.3f} ms")
+    out = {"workload": f"the adaptive forest ({scene.forest.nleaves} leaves), one 1024x1024 perspective view, "
+                       f"trilinear kappa/eps, RK4 x 4",
+           "leaves": scene.forest.nleaves, "visible": counts["nvis"], "candidates": C, "segments": S,
+           "node_records": counts["nrec"], "pixels": r.cams.npix, "ms_per_step": ms, "forward_eager_ms": ms_eager,
+           "ray_segments_per_s": S / (ms * 1e-3), "images_per_s": 1e3 / ms,
+           "phase_ms": {"prune": t_prune, "segments": t_seg, "composite": t_comp},
+           "fused_render_ms": t_render,
+           "roofline": seg_roofline(r, S, C, t_seg)}
+    pb = scene.forest.nleaves * 13 + counts["nvis"] * 20
+    out["phase_roofline"] = {"composite": composite_roofline(r, C, t_comp),
+                             "prune": {"bound": "hbm", "algorithmic_bytes": pb,
+                                       "achieved_GBs": pb / (t_prune * 1e-3) / 1e9,
+                                       "frac": pb / (t_prune * 1e-3) / 1e9 / HBM_PEAK_GBS}}
+    out["_renderer"] = r
+    return out
 
-    if args.copy_calib:
-        # a plain copy of known size: 256 MiB read + 256 MiB written per launch
-        src = torch.ones(COPY_CALIB_BYTES // 4, device="cuda:0")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        log(f"[bench] copy calibration: 3 copies of {COPY_CALIB_BYTES} bytes")
-        del src, dst
-    if not args.no_cpu:
-        log("[bench] timing the CPU oracle")
-        out["cpu_baseline"] = cpu_baseline(scene)
-    print(json.dumps(out), flush=True)
+
+def bench_config1(torch, P, synth, steps):
+    """Uniform level-3 cube (512 leaves), constant coefficients, 64x64 orthographic view, closed form: a
+    latency-scale case (a few microseconds of work per launch)."""
+    sc = synth.config_scene(1)
+    r = P.Renderer(sc.forest, sc.fields, sc.cameras, "analytic", 1, device="cuda:0")
+    S = r.count_segments()
+    r.forward()
+    r.capture()
+    r.replay()
+    ms = time_region(torch, r.replay, max(steps, 20))
+    log(f"[bench] config 1: {S} segments, one graph {ms:.4f} ms")
+    return {"workload": "uniform level-3 unit cube (512 leaves), per-leaf constants, 64x64 orthographic view, "
+                        "closed form", "segments": S, "ms_per_step": ms, "ray_segments_per_s": S / (ms * 1e-3),
+            "images_per_s": 1e3 / ms}
 
 
 def bench_adjoint(torch, P, synth, steps):
@@ -303,33 +431,9 @@ def bench_adjoint(torch, P, synth, steps):
             "segments": S, "fwd_ms": t_f, "fwd_bwd_ms": t_fb, "fwd_bwd_over_fwd": t_fb / t_f}
 
 
-def bench_batched(torch, P, synth, r, steps):
-    """The forest of the main workload seen by 64 cameras of uneven resolution: one
-    graph launch for all views (autotuned) versus 64 plain per-view forwards."""
-    cams = synth.config4_cameras()
-    log(f"[bench] batched workload: {len(cams)} cameras, {sum(c.npix for c in cams)} pixels")
-    rb = P.Renderer(r.forest, r.fields, cams, "rk4", 4, device="cuda:0", index=r.index)
-    from paper_1809_01334_amd.tune import autotune
-
-    tune = autotune(rb, reps=2)
-    log(f"[bench] autotuned launch shapes {tune['tuning']}")
-    rb.capture()
-    rb.replay()
-    t_batch = time_region(torch, rb.replay, steps)
-    S = rb.count_segments()
-    rb_counts = rb.counts
-    singles = [P.Renderer(r.forest, r.fields, [c], "rk4", 4, device="cuda:0", index=r.index) for c in cams]
-
-    def plain():
-        for x in singles:
-            x.forward()
-
-    plain()
-    t_plain = time_region(torch, plain, steps)
-    log(f"[bench] batched: one graph {t_batch:.2f} ms, 64 plain forwards {t_plain:.2f} ms, segments {S}")
-    del singles
-    del rb
-    # small views, where per-view launches dominate: 64 cameras of 128^2
+def bench_small_views(torch, P, synth, r, steps):
+    """64 views of 128^2 of the same forest, where per-view launches weigh most:
+    one graph for all views versus 64 plain per-view forwards."""
     rng = np.random.default_rng([1809, 1334, 128])
     small = [synth.random_perspective_camera(rng, 128, 128) for _ in range(64)]
     rs = P.Renderer(r.forest, r.fields, small, "rk4", 4, device="cuda:0", index=r.index)
@@ -347,13 +451,8 @@ def bench_batched(torch, P, synth, r, steps):
     log(f"[bench] 64 views of 128^2: one graph {t_small:.3f} ms, 64 plain forwards {t_small_plain:.3f} ms")
     del singles, rs
     torch.cuda.empty_cache()
-    return {"workload": "64 cameras, resolutions from {256,512,1024,2048}^2, same forest",
-            "views": len(cams), "pixels": int(sum(c.npix for c in cams)), "candidates": rb_counts["ncand"],
-            "segments": S, "batched_ms": t_batch, "plain_sum_ms": t_plain, "plain_over_batched": t_plain / t_batch,
-            "ray_segments_per_s": S / (t_batch * 1e-3), "images_per_s": len(cams) / (t_batch * 1e-3),
-            "tuning": tune["tuning"],
-            "small_views": {"views": 64, "resolution": 128, "batched_ms": t_small, "plain_sum_ms": t_small_plain,
-                            "plain_over_batched": t_small_plain / t_small}}
+    return {"views": 64, "resolution": 128, "batched_ms": t_small, "plain_sum_ms": t_small_plain,
+            "plain_over_batched": t_small_plain / t_small}
 
 
 def bench_integrators(torch, P, r, steps):
@@ -452,17 +551,21 @@ def bench_analytic(torch, P, synth, scene, r, steps):
     ra.capture()
     ra.replay()
     ms = time_region(torch, ra.replay, steps)
+    t_render = time_region(torch, ra.render_step, steps)
     t_seg = time_region(torch, ra.segments, steps)
     nbytes = c["nvis"] * ANALYTIC_LEAF_BYTES + c["ncand"] * REC_BYTES
     gbs = nbytes / (t_seg * 1e-3) / 1e9
-    log(f"[bench] constant coefficients: forward {ms:.3f} ms, segments {t_seg:.3f} ms ({gbs:.0f} GB/s algorithmic)")
+    log(f"[bench] constant coefficients: forward {ms:.3f} ms, segments {t_seg:.3f} ms ({gbs:.0f} GB/s "
+        f"algorithmic); rc_render (fused) {t_render:.3f} ms")
+    kernel = "k_segments_analytic<1>"
+    traffic = measured_traffic(kernel, ra)
     del ra
     torch.cuda.empty_cache()
-    return {"workload": "the headline forest and view, one (kappa, eps) per leaf (corner means), analytic segments",
+    return {"workload": "the single-view forest and view, one (kappa, eps) per leaf (corner means), closed form",
             "segments": S, "ms_per_step": ms, "ray_segments_per_s": S / (ms * 1e-3), "segments_ms": t_seg,
-            "roofline": {"bound": "hbm", "kernel": "k_segments_analytic<1>", "achieved": gbs, "peak": HBM_PEAK_GBS,
-                         "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
-                         "traffic": measured_traffic("k_segments_analytic<1>"), "bytes_per_launch": nbytes,
+            "fused_render_ms": t_render,
+            "roofline": {"bound": "hbm", "kernel": kernel, "achieved": gbs, "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "traffic": traffic, "bytes_per_launch": nbytes,
                          "per_unit": f"{ANALYTIC_LEAF_BYTES} B per visible leaf + {REC_BYTES} B per candidate"}}
 
 

@@ -348,6 +348,28 @@ rc_status rc_composite(const rc_forest *forest, const rc_index *index, const voi
                        float *A, float *B, float *I, const rc_tuning *tune, void *stream);
 
 /*
+ * The forward after rc_prune_visible in one call: rc_segments followed by
+ * rc_composite, with the intra-tile fold where it applies (unit-cube forests
+ * deeper than one leaf, one channel, the closed form or RK4 over fixed
+ * substeps).  There the coarsening's pass of each level computes the segments
+ * of its nodes' leaf children at every pixel of the nodes' rectangles (Sec. 3.2)
+ * and folds them with the internal children's records in the camera's view
+ * order (Sec. 3.3 aggregation of child segments, Sec. 2.4 eq. aggregate),
+ * keeping them in registers and LDS: no leaf record is written, and rec_leaf
+ * may be NULL.  A, B, I and rec_node are bitwise those of rc_segments followed
+ * by rc_composite.  Elsewhere (curved geometry, several channels, the other
+ * integrators, a forest of one leaf) the call runs rc_segments and
+ * rc_composite (rc_composite_channels for nch > 1) into rec_leaf, which must
+ * then be given.  rc_segments_backward needs rec_leaf: after rc_render, run
+ * rc_segments before the adjoint.  Arguments, layouts and errors as for
+ * rc_segments and rc_composite; all of them are checked before anything is
+ * enqueued.
+ */
+rc_status rc_render(const rc_forest *forest, const rc_index *index, const rc_fields *fields, const void *dcams,
+                    int32_t ncams, const rc_vforest *vf, const rc_integrator *integ, float *rec_leaf, float *rec_node,
+                    int64_t total_pixels, float *A, float *B, float *I, const rc_tuning *tune, void *stream);
+
+/*
  * rc_composite for nch channels (1 .. RC_MAXCH, Sec. 4.1: each channel its own
  * (A, B)) in one call, on channel-major blocks: rec_leaf [device, nch *
  * cap_cand * 2], rec_node [device, nch * cap_rec * 2] and A, B, I [device,

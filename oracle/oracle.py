@@ -89,6 +89,15 @@ def lib():
     return _lib
 
 
+def threads(n=None) -> int:
+    """The OpenMP thread count the oracle runs with; with n, set it first."""
+    lib()
+    gomp = ctypes.CDLL("libgomp.so.1")
+    if n is not None:
+        gomp.omp_set_num_threads(int(n))
+    return int(gomp.omp_get_max_threads())
+
+
 def _p(a):
     return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
 

@@ -78,6 +78,8 @@ _SIGS = {
                             P(RcTuning), c_vp]),
     "rc_composite": (c_i32, [P(RcForest), P(RcIndex), c_vp, c_i32, P(RcVforest), c_vp, c_vp, c_i64, c_vp, c_vp, c_vp,
                              P(RcTuning), c_vp]),
+    "rc_render": (c_i32, [P(RcForest), P(RcIndex), P(RcFields), c_vp, c_i32, P(RcVforest), P(RcIntegrator), c_vp,
+                          c_vp, c_i64, c_vp, c_vp, c_vp, P(RcTuning), c_vp]),
     "rc_composite_channels": (c_i32, [P(RcForest), P(RcIndex), c_vp, c_i32, P(RcVforest), c_i32, c_vp, c_vp, c_i64,
                                       c_vp, c_vp, c_vp, P(RcTuning), c_vp]),
     "rc_lists_workspace_bytes": (c_sz, [P(RcIndex), c_i32, c_i64]),

@@ -255,6 +255,15 @@ def rc_composite(forest: DeviceForest, index: DeviceIndex, cams: DeviceCameras, 
            _tune(tuning), _stream(forest.device))
 
 
+def rc_render(forest: DeviceForest, index: DeviceIndex, fields: DeviceFields, cams: DeviceCameras, vf: VForest,
+              method: int, substeps: int, rec_leaf, rec_node, A, B, I, tuning: Optional[L.RcTuning] = None,
+              c_rk: float = 0.0):
+    integ = L.RcIntegrator(int(method), int(substeps), float(c_rk))
+    L.call("rc_render", ctypes.byref(forest.struct), ctypes.byref(index.struct), ctypes.byref(fields.struct),
+           _ptr(cams.buf), cams.ncams, ctypes.byref(vf.struct), ctypes.byref(integ), _ptr(rec_leaf), _ptr(rec_node),
+           cams.npix, _ptr(A), _ptr(B), _ptr(I), _tune(tuning), _stream(forest.device))
+
+
 def rc_composite_channels(forest: DeviceForest, index: DeviceIndex, cams: DeviceCameras, vf: VForest, nch: int,
                           rec_leaf, rec_node, A, B, I, tuning: Optional[L.RcTuning] = None):
     L.call("rc_composite_channels", ctypes.byref(forest.struct), ctypes.byref(index.struct), _ptr(cams.buf),
@@ -318,7 +327,7 @@ class Renderer:
     """
 
     def __init__(self, forest, fields, cameras, method="rk4", substeps=4, device="cuda:0", index=None,
-                 tuning: Optional[dict] = None, c_rk: float = 0.0):
+                 tuning: Optional[dict] = None, c_rk: float = 0.0, use_render: bool = False):
         self.device = torch.device(device)
         if not torch.cuda.is_available():
             raise RuntimeError("the rc renderer needs a GPU")
@@ -338,6 +347,9 @@ class Renderer:
         self.vf = None
         self.counts = None
         self.bwd_ready = False
+        self.leaf_records = False  # rec_leaf holds the current fields' leaf records
+        # forward() through rc_render (the intra-tile fold) instead of rc_segments + rc_composite
+        self.use_render = bool(use_render)
         # bumped by every call that changes the fields or rewrites the records, so
         # that an autograd backward can tell whether they still belong to its forward
         self.generation = 0
@@ -386,6 +398,7 @@ class Renderer:
 
     def segments(self, hit=None, sio=None):
         self.generation += 1
+        self.leaf_records = True
         rc_segments(self.forest, self.fields, self.cams, self.vf, self.method, self.substeps, self.rec_leaf, hit, sio,
                     self.tuning, self.c_rk)
 
@@ -445,15 +458,43 @@ class Renderer:
         self.segments()
         self.lists_step()
 
-    def forward(self):
+    @property
+    def fused(self) -> bool:
+        """rc_render folds the leaf segments in registers and LDS (no leaf records)
+        for this forest, field kind, channel count and integrator."""
+        return (not self.forest.curved and self.fields.nch == 1 and self.index.maxlevel >= 1
+                and int(self.index.struct.root) >= 0
+                and (self.method == L.RC_INT_ANALYTIC or (self.method == L.RC_INT_RK4 and self.c_rk == 0.0)))
+
+    def render_step(self):
+        """rc_render after prune: segments and compositing, fused where they can be."""
+        self.generation += 1
+        rc_render(self.forest, self.index, self.fields, self.cams, self.vf, self.method, self.substeps,
+                  self.rec_leaf, self.rec_node, self.A, self.B, self.I, self.tuning, self.c_rk)
+        self.leaf_records = not self.fused
+
+    def forward(self, leaf_records: Optional[bool] = None):
+        """Prune, segments and composite: rc_segments and rc_composite, which keep
+        the leaf records the adjoint reads, or with leaf_records=False (default:
+        not self.use_render) rc_render, which keeps them only where it cannot fuse."""
+        if leaf_records is None:
+            leaf_records = not self.use_render
         self.prune()
-        self.segments()
-        self.composite()
+        if leaf_records:
+            self.segments()
+            self.composite()
+            self.leaf_records = True
+        else:
+            self.render_step()
         return self.A, self.B, self.I
 
     def backward(self, dLdI: torch.Tensor, dk: Optional[torch.Tensor] = None, de: Optional[torch.Tensor] = None,
                  accumulate=False):
         self._bwd_alloc()
+        if not self.leaf_records:
+            # the adjoint reads the leaf records, which rc_render's fused path does not write
+            self.segments()
+            self.leaf_records = True
         if dk is None:
             dk = torch.empty_like(self.fields.kappa)
         if de is None:
@@ -484,7 +525,7 @@ class Renderer:
         return self.graph
 
     def _graph_body(self, backward):
-        self.forward()
+        self.forward(leaf_records=True if backward else None)
         if backward:
             self.backward(self.g_dLdI, self.g_dk, self.g_de)
 
@@ -495,6 +536,7 @@ class Renderer:
 
     def set_fields(self, kappa: torch.Tensor, eps: torch.Tensor):
         self.generation += 1
+        self.leaf_records = False
         self.fields = DeviceFields(kappa, eps, self.fields.kind == L.RC_FIELD_CONST_EQ,
                                    self.fields.kind == L.RC_FIELD_SURFACE)
 
@@ -530,7 +572,8 @@ class RenderFn(torch.autograd.Function):
     def forward(ctx, kappa, eps, renderer: Renderer):
         kd, ed = kappa.detach(), eps.detach()
         renderer.set_fields(kd, ed)
-        _, _, I = renderer.forward()
+        # the leaf records stay for the adjoint when a gradient is wanted
+        _, _, I = renderer.forward(leaf_records=True if any(ctx.needs_input_grad[:2]) else None)
         ctx.renderer = renderer
         ctx.generation = renderer.generation
         ctx.save_for_backward(kd, ed)
@@ -542,7 +585,7 @@ class RenderFn(torch.autograd.Function):
         kd, ed = ctx.saved_tensors
         if r.generation != ctx.generation:
             r.set_fields(kd, ed)
-            r.forward()
+            r.forward(leaf_records=True)
         dk, de = r.backward(gI.contiguous().float())
         return dk, de, None
 
