@@ -594,14 +594,17 @@ __device__ inline T block_exclusive_scan(T v, T* sh, T& total) {
     return wpre + ex;
 }
 
-// Src: __device__ Item operator()(int64_t i) with member `T val`.
+// Src: __device__ Item operator()(int64_t i) with member `T val`.  Block b
+// covers items [b * SCAN_NT * ITEMS, (b + 1) * SCAN_NT * ITEMS); in step k its
+// threads take SCAN_NT consecutive items, so every load and store of a step is
+// coalesced across the wave.
 template <typename T, int ITEMS, typename Src>
 __global__ __launch_bounds__(SCAN_NT) void k_scan_reduce(int64_t n, Src src, T* partial) {
     __shared__ T sh[SCAN_NT / 64];
-    int64_t base = ((int64_t)blockIdx.x * SCAN_NT + threadIdx.x) * ITEMS;
+    int64_t base = (int64_t)blockIdx.x * SCAN_NT * ITEMS + threadIdx.x;
     T acc = T();
     for (int k = 0; k < ITEMS; k++) {
-        int64_t i = base + k;
+        int64_t i = base + (int64_t)k * SCAN_NT;
         if (i < n) acc = acc + src(i).val;
     }
     T total;
@@ -636,24 +639,28 @@ __global__ __launch_bounds__(SCAN_NT) void k_scan_partials(int64_t nb, T* partia
 
 // Dst: __device__ void operator()(int64_t i, T prefix, const Item& item) and
 //      __device__ void total(T tot)  (called once, by the last block).
+// Items as in k_scan_reduce; each step scans its SCAN_NT items across the
+// block and carries the step's total into the next.
 template <typename T, int ITEMS, typename Src, typename Dst>
 __global__ __launch_bounds__(SCAN_NT) void k_scan_apply(int64_t n, int64_t nb, Src src, Dst dst, const T* partial) {
+    typedef decltype(src(int64_t(0))) ItemT;
     __shared__ T sh[SCAN_NT / 64];
-    int64_t base = ((int64_t)blockIdx.x * SCAN_NT + threadIdx.x) * ITEMS;
-    T acc = T();
+    int64_t base = (int64_t)blockIdx.x * SCAN_NT * ITEMS + threadIdx.x;
+    T carry = partial[blockIdx.x];
     for (int k = 0; k < ITEMS; k++) {
-        int64_t i = base + k;
-        if (i < n) acc = acc + src(i).val;
-    }
-    T total;
-    T run = partial[blockIdx.x] + block_exclusive_scan<T, SCAN_NT>(acc, sh, total);
-    for (int k = 0; k < ITEMS; k++) {
-        int64_t i = base + k;
-        if (i < n) {
-            auto item = src(i);
-            dst(i, run, item);
-            run = run + item.val;
+        int64_t i = base + (int64_t)k * SCAN_NT;
+        if (i - threadIdx.x >= n) break;  // the block's remaining steps are empty (uniform)
+        bool in = i < n;
+        ItemT item{};
+        T v = T();
+        if (in) {
+            item = src(i);
+            v = item.val;
         }
+        T tot;
+        T ex = block_exclusive_scan<T, SCAN_NT>(v, sh, tot);
+        if (in) dst(i, carry + ex, item);
+        carry = carry + tot;
     }
     if (blockIdx.x == nb - 1 && threadIdx.x == 0) dst.total(partial[nb]);
 }
