@@ -165,7 +165,7 @@ typedef struct rc_tuning {
  * l encoded as -2 - l. */
 typedef struct rc_index {
     int32_t maxlevel;                       /* [out] deepest leaf level */
-    int32_t pad;
+    int32_t leaf_levels;                    /* [out] bit l set when some leaf has level l */
     int64_t ninternal;                      /* [out] internal nodes (required capacity on RC_ECAPACITY) */
     int64_t cap_internal;                   /* [in] capacity of the arrays below */
     int64_t level_begin[RC_QMAXLEVEL + 2];  /* [out] internal nodes of level l: [level_begin[l], level_begin[l+1]) */

@@ -19,6 +19,7 @@ from .render import (  # noqa: F401
     rc_forest_index,
     rc_merge_lists,
     rc_prune_visible,
+    rc_render,
     rc_segments,
     rc_segments_backward,
     render,

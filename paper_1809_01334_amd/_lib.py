@@ -51,7 +51,7 @@ class RcTuning(ctypes.Structure):
 
 
 class RcIndex(ctypes.Structure):
-    _fields_ = [("maxlevel", c_i32), ("pad", c_i32), ("ninternal", c_i64), ("cap_internal", c_i64),
+    _fields_ = [("maxlevel", c_i32), ("leaf_levels", c_i32), ("ninternal", c_i64), ("cap_internal", c_i64),
                 ("level_begin", c_i64 * (RC_QMAXLEVEL + 2)), ("root", c_i32), ("ntrees", c_i32),
                 ("roots", c_i32 * RC_MAXTREES), ("child", c_vp), ("level", c_vp), ("x", c_vp), ("y", c_vp),
                 ("z", c_vp), ("tree", c_vp)]

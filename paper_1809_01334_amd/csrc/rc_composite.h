@@ -105,6 +105,12 @@ __device__ inline int64_t record_slot(const FoldCtx& C, int64_t g, int64_t w, in
     return upper_index(C.node_offset, lo, hi, g);
 }
 
+// One level pass of the coarsening (records of level l from their children's)
+// and the root pass into the images, as rc_composite launches them.
+rc_status launch_fold_level(const FoldCtx& C, int l, float* rec_node, unsigned grid, hipStream_t st);
+rc_status launch_fold_root(const FoldCtx& C, int32_t root, int64_t npix, float* A, float* B, float* I,
+                           const rc_vforest* vf, unsigned grid, hipStream_t st);
+
 // Node records of levels maxlevel-1 .. 1 (rc_composite.hip).
 rc_status fold_levels(const FoldCtx& C, const rc_index* ix, const rc_vforest* vf, float* rec_node,
                       const rc_tuning* tune, hipStream_t st);

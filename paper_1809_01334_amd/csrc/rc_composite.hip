@@ -67,6 +67,18 @@ __global__ __launch_bounds__(256) void k_fold_root(FoldCtx C, int32_t root, int6
 
 }  // namespace
 
+rc_status launch_fold_level(const FoldCtx& C, int l, float* rec_node, unsigned grid, hipStream_t st) {
+    hipLaunchKernelGGL(k_fold_level, dim3(grid), dim3(256), 0, st, C, l, (float2*)rec_node);
+    return hipGetLastError() == hipSuccess ? RC_OK : RC_EHIP;
+}
+
+rc_status launch_fold_root(const FoldCtx& C, int32_t root, int64_t npix, float* A, float* B, float* I,
+                           const rc_vforest* vf, unsigned grid, hipStream_t st) {
+    hipLaunchKernelGGL(k_fold_root, dim3(grid), dim3(256), 0, st, C, root, npix, A, B, I, vf->leaf_vis,
+                       vf->vis_rect, vf->cand_offset);
+    return hipGetLastError() == hipSuccess ? RC_OK : RC_EHIP;
+}
+
 // Node records of levels maxlevel-1 .. 1, deepest first.
 rc_status fold_levels(const FoldCtx& C, const rc_index* ix, const rc_vforest* vf, float* rec_node,
                       const rc_tuning* tune, hipStream_t st) {

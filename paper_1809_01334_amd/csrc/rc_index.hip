@@ -21,7 +21,7 @@ __device__ inline bool tree_start(const int64_t* tb, int ntrees, int64_t i) {
     return false;
 }
 
-// status[0]: error flags, status[1]: maximum level
+// status[0]: error flags, status[1]: maximum level, status[2]: leaf levels (bit mask)
 __global__ void k_validate(int64_t n, const uint8_t* level, const uint32_t* x, const uint32_t* y, const uint32_t* z,
                            const int64_t* tb, int ntrees, int maxallowed, int flat, int* status) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -39,6 +39,7 @@ __global__ void k_validate(int64_t n, const uint8_t* level, const uint32_t* x, c
         return;
     }
     atomicMax(&status[1], l);
+    atomicOr(&status[2], 1 << l);
     if (i > 0 && !tree_start(tb, ntrees, i)) {
         int lp = level[i - 1];
         if (lp > QMAX) return;
@@ -163,7 +164,7 @@ extern "C" rc_status rc_forest_index(const rc_forest* f, rc_index* ix, void* ws,
     hipLaunchKernelGGL(k_validate, dim3(nb), dim3(256), 0, st, N, f->level, f->x, f->y, f->z, (const int64_t*)dtb, nt,
                        maxallowed, is_surface(f) ? 1 : 0, status);
     RC_HIP(hipGetLastError());
-    int hs[2];
+    int hs[3];
     RC_HIP(hipMemcpyAsync(hs, status, sizeof(hs), hipMemcpyDeviceToHost, st));
     RC_HIP(hipStreamSynchronize(st));
     if (hs[0] != 0) return RC_EFOREST;
@@ -171,6 +172,7 @@ extern "C" rc_status rc_forest_index(const rc_forest* f, rc_index* ix, void* ws,
     for (int k = 0; k < nt; k++)
         if (maxlevel == 0 && htb[k + 1] - htb[k] > 1) return RC_EFOREST;
     ix->maxlevel = maxlevel;
+    ix->leaf_levels = hs[2];
     ix->ntrees = nt;
 
     // all capacity-guarded: a first pass with too little room still counts

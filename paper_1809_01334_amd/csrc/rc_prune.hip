@@ -241,12 +241,19 @@ struct DescArgs {
     int natural;  // 1: children in Morton order (curved geometry), 0: view order
 };
 
+// Descriptor q of (camera, internal node) t / 8.  A node of level >= 1 whose
+// own rectangle is empty holds no record, so nothing reads its descriptors
+// and they are not written; the roots' always are.
 __device__ inline void child_desc_entry(const DescArgs& a, int64_t t) {
     int q = (int)(t & 7);
     int64_t dslot = t >> 3;
     int64_t cam = divu(dslot, a.ninternal);
     int64_t m = dslot - cam * a.ninternal;
     int l = a.nlevel[m];
+    if (l >= 1) {
+        int64_t M = a.L.level_begin[l + 1] - a.L.level_begin[l];
+        if (load_rect(a.node_rect + 4 * (a.L.slot_begin[l] + cam * M + (m - a.L.level_begin[l]))).empty()) return;
+    }
     int sb = a.natural ? 0 : view_bits(a.cams[cam], l, a.nx[m], a.ny[m], a.nz[m]);
     int32_t ref = a.child[m * 8 + (q ^ sb)];
     Rect r{1, 0, 1, 0};

@@ -300,16 +300,26 @@ __global__ __launch_bounds__(256) void k_render_level(RenderArgs a, int l, float
 template <int KIND, int NSUB>
 rc_status launch_render(const RenderArgs& a, const rc_index* ix, const rc_vforest* vf, float* rec_node,
                         const rc_tuning* tune, hipStream_t st) {
+    // passes whose children include no leaf are plain folds
     unsigned grid = stride_grid(vf->cap_rec, 256, tuned(tune, 1, 2048));
+    unsigned fgrid = stride_grid(vf->cap_rec, 256, tuned(tune, 1, 256 * 32));
+    unsigned rgrid = stride_grid(a.npix, 256, tuned(tune, 2, 4096));
     for (int l = ix->maxlevel - 1; l >= 1; l--) {
         if (ix->level_begin[l + 1] == ix->level_begin[l]) continue;
-        hipLaunchKernelGGL((k_render_level<KIND, NSUB>), dim3(grid), dim3(256), 0, st, a, l, (float2*)rec_node);
-        RC_HIP(hipGetLastError());
+        if (ix->leaf_levels & (1 << (l + 1))) {
+            hipLaunchKernelGGL((k_render_level<KIND, NSUB>), dim3(grid), dim3(256), 0, st, a, l, (float2*)rec_node);
+            RC_HIP(hipGetLastError());
+        } else {
+            rc_status s = launch_fold_level(a.C, l, rec_node, fgrid, st);
+            if (s != RC_OK) return s;
+        }
     }
-    hipLaunchKernelGGL((k_render_level<KIND, NSUB>), dim3(stride_grid(a.npix, 256, tuned(tune, 2, 4096))),
-                       dim3(256), 0, st, a, 0, (float2*)nullptr);
-    RC_HIP(hipGetLastError());
-    return RC_OK;
+    if (ix->leaf_levels & 2) {
+        hipLaunchKernelGGL((k_render_level<KIND, NSUB>), dim3(rgrid), dim3(256), 0, st, a, 0, (float2*)nullptr);
+        RC_HIP(hipGetLastError());
+        return RC_OK;
+    }
+    return launch_fold_root(a.C, a.root, a.npix, a.A, a.B, a.I, vf, rgrid, st);
 }
 
 }  // namespace
@@ -345,6 +355,9 @@ extern "C" rc_status rc_render(const rc_forest* f, const rc_index* ix, const rc_
     }
     RenderArgs a;
     a.C = make_fold_ctx(f, ix, dcams, ncams, vf, rec_leaf, rec_node);
+    // the plain fold passes read a dummy record where a child misses the pixel:
+    // give them a readable address when there are no leaf records
+    if (!rec_leaf) a.C.rec_leaf = (const float2*)vf->child_desc;
     a.child = ix->child;
     a.nx = ix->x;
     a.ny = ix->y;

@@ -214,3 +214,27 @@ def test_fused_forward_against_the_oracle(oracle_mod):
             for x, y in ((A[sl], ref["A"]), (B[sl], ref["B"]), (I[sl], ref["I"])):
                 den = np.maximum(np.abs(y), 1e-3 * max(np.abs(y).max(), 1e-30))
                 assert float((np.abs(x - y) / den).max()) <= 1e-5
+
+
+def test_fused_forward_without_leaf_records():
+    """rc_render with rec_leaf = NULL where it fuses (the leaf records are not needed): the same images and
+    node records as with them, on a forest with leaves at several levels (fused and plain passes) and on a
+    one-level forest (the root pass integrates the leaves)."""
+    torch = _torch()
+    import paper_1809_01334_amd as P
+
+    for scene in (synth.small_scene(78, lmin=3, lmax=5, w=64, h=48, ncams=2),
+                  synth.Scene("uniform8", synth.uniform_forest(1), synth.constant_fields(np.linspace(0.2, 1.5, 8),
+                                                                                          np.linspace(0.1, 0.9, 8)),
+                              [synth.random_perspective_camera(np.random.default_rng(78), 30, 20)], "analytic", 1)):
+        r = P.Renderer(scene.forest, scene.fields, scene.cameras, scene.method, scene.substeps)
+        assert r.fused
+        want = _two_call(r)
+        for t in (r.A, r.B, r.I, r.rec_node):
+            t.fill_(float("nan"))
+        r.prune()
+        P.rc_render(r.forest, r.index, r.fields, r.cams, r.vf, r.method, r.substeps, None, r.rec_node, r.A, r.B, r.I)
+        torch.cuda.synchronize()
+        got = [r.A, r.B, r.I, r.rec_node[:2 * r.counts["nrec"]]]
+        for a, b in zip(got, want):
+            assert torch.equal(a, b)

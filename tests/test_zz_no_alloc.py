@@ -38,19 +38,38 @@ def _outputs(vf, r):
     return {k: (v if isinstance(v, np.ndarray) else v.cpu().numpy()) for k, v in out.items()}
 
 
-def _static_prune(r):
+def _poisoned_vforest(r):
+    """A vforest of r's capacities with every array filled with -7, so that the
+    entries a call leaves unwritten (the descriptors of invisible nodes) compare
+    equal and anything else shows."""
     import paper_1809_01334_amd as P
+
+    vf = P.VForest(r.device, r.forest.nleaves, r.cams.ncams, r.nslots, r.vf.cap_vis, r.vf.cap_cand, r.vf.cap_rec,
+                   r.index.ninternal)
+    for t in (vf.vis_leaf, vf.vis_cam, vf.vis_rect, vf.cand_offset, vf.leaf_vis, vf.node_rect, vf.node_offset,
+              vf.cand_chunk, vf.rec_chunk, vf.child_desc):
+        t.fill_(-7)
+    return vf
+
+
+def _static_prune(r):
     from paper_1809_01334_amd import _lib as L
 
     torch = _torch()
-    vf = P.VForest(r.device, r.forest.nleaves, r.cams.ncams, r.nslots, r.vf.cap_vis, r.vf.cap_cand, r.vf.cap_rec,
-                   r.index.ninternal)
-    # poison the outputs, so that anything the call leaves unwritten shows
-    for t in (vf.vis_leaf, vf.cand_offset, vf.leaf_vis, vf.node_offset, vf.cand_chunk, vf.rec_chunk, vf.child_desc):
-        t.fill_(-7)
+    vf = _poisoned_vforest(r)
     st = ctypes.c_void_p(torch.cuda.current_stream(r.device).cuda_stream)
     L.call("rc_prune_visible_static", ctypes.byref(r.forest.struct), ctypes.byref(r.index.struct),
            ctypes.c_void_p(r.cams.buf.data_ptr()), r.cams.ncams, ctypes.byref(vf.struct), st)
+    torch.cuda.synchronize()
+    return vf
+
+
+def _plain_prune(r):
+    import paper_1809_01334_amd as P
+
+    torch = _torch()
+    vf = _poisoned_vforest(r)
+    P.rc_prune_visible(r.forest, r.index, r.cams, vf, r.ws)
     torch.cuda.synchronize()
     return vf
 
@@ -66,9 +85,7 @@ def test_static_prune_matches_prune_on_two_calls():
     for scene in (big, small):
         print(f"[case] static prune: N={scene.forest.nleaves} cams={len(scene.cameras)}", flush=True)
         r = P.Renderer(scene.forest, scene.fields, scene.cameras, scene.method, scene.substeps)
-        r.prune()
-        torch.cuda.synchronize()
-        want = _outputs(r.vf, r)
+        want = _outputs(_plain_prune(r), r)
         vf = _static_prune(r)
         got = _outputs(vf, r)
         assert want["counts"][3] == 0 and want["counts"][0] > 0
