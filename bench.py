@@ -58,7 +58,17 @@ ANALYTIC_LEAF_BYTES = 37
 # WRITE_SIZE (calibrated on a 256 MiB device copy: bytes = 2 FETCH_SIZE +
 # WRITE_SIZE), summed over one step's launches of the kernel on the named
 # workload, valid for the kernel sources whose SHA-256 is given.
-MEASURED_TRAFFIC = {}
+_SEG_SRC = ("rc_segments.hip", "rc_internal.h")
+_SEG_SHA = "b29f3a5dbf96bd08a70b123da9e7df65ea4b86019272877d61e2817cd50d1633"
+_COMP_SRC = ("rc_composite.hip", "rc_composite.h", "rc_internal.h")
+_COMP_SHA = "c31cfa8cd17c442049152d58a92efadc281bb24408909e0e27476801a0844a03"
+MEASURED_TRAFFIC = {
+    # keyed by (kernel, candidates of the workload): the 64 views, then the single 1024^2 view
+    ("k_segments_rk4<2, 4, 1>", 1331258581): {"bytes": 18933002965, "sources": _SEG_SRC, "sha256": _SEG_SHA},
+    ("composite", 1331258581): {"bytes": 36692339764, "sources": _COMP_SRC, "sha256": _COMP_SHA},
+    ("k_segments_rk4<2, 4, 1>", 14164540): {"bytes": 240382234, "sources": _SEG_SRC, "sha256": _SEG_SHA},
+    ("composite", 14164540): {"bytes": 404483284, "sources": _COMP_SRC, "sha256": _COMP_SHA},
+}
 COPY_CALIB_BYTES = 256 << 20
 
 
@@ -92,6 +102,17 @@ def measured_traffic(kernel, r=None):
         with open(os.path.join(ROOT, "paper_1809_01334_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return m["bytes"] if h.hexdigest() == m["sha256"] else None
+
+
+def copy_calibration(torch):
+    """Three plain device copies of 256 MiB (read and written): the reference
+    against which FETCH_SIZE and WRITE_SIZE are scaled to bytes."""
+    src = torch.ones(COPY_CALIB_BYTES // 4, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"[bench] copy calibration: 3 copies of {COPY_CALIB_BYTES} bytes")
 
 
 def cpu_model():
@@ -159,8 +180,10 @@ def composite_roofline(r, C, t_comp):
     """rc_composite against HBM: every leaf record read once and A, B, I written (the node records of the
     coarsening are traffic, not algorithmic bytes)."""
     nbytes = C * REC_BYTES + r.cams.npix * PIX_BYTES
+    traffic = measured_traffic("composite", r)
     return {"bound": "hbm", "algorithmic_bytes": nbytes, "achieved_GBs": nbytes / (t_comp * 1e-3) / 1e9,
-            "frac": nbytes / (t_comp * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": measured_traffic("composite", r)}
+            "frac": nbytes / (t_comp * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": traffic,
+            "traffic_GBs": traffic / (t_comp * 1e-3) / 1e9 if traffic else None}
 
 
 def main():
@@ -217,6 +240,8 @@ def main():
     if args.only == "shell":
         out = bench_shell(torch, P, synth, max(args.steps // 5, 3))
     if args.only is not None:
+        if args.copy_calib:
+            copy_calibration(torch)
         print(json.dumps(out), flush=True)
         return
 
@@ -251,14 +276,7 @@ def main():
         out["shares"] = bench_shares(torch, P, synth, scene, r1, max(args.steps // 5, 3))
 
     if args.copy_calib:
-        # a plain copy of known size: 256 MiB read + 256 MiB written per launch
-        src = torch.ones(COPY_CALIB_BYTES // 4, device="cuda:0")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        log(f"[bench] copy calibration: 3 copies of {COPY_CALIB_BYTES} bytes")
-        del src, dst
+        copy_calibration(torch)
     if not args.no_cpu:
         log("[bench] timing the CPU oracle on a sample of the headline workload")
         out["cpu_baseline"] = cpu_baseline(scene.forest, scene.fields, synth.config4_cameras(), "rk4", 4)
