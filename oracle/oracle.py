@@ -76,6 +76,13 @@ def lib():
         L.or_ho_surface_render.restype = I32
         L.or_ho_surface_render.argtypes = [I64, I32, P, P, P, P, P, P, P, P, I64, P, P, P, P, P, P, I32]
         L.or_ho_map.argtypes = [P, I32, I64, P, P]
+        L.or_vol_cands.restype = I32
+        L.or_vol_cands.argtypes = [I64, P, P, P, I32, P, P, P, P, P, P, P, P, P]
+        L.or_vol_render.restype = I32
+        L.or_vol_render.argtypes = [I64, I32, P, P, P, P, P, P, I32, P, P, I32, I32, P, I64, P, P, P, P, P, P]
+        L.or_vol_map.argtypes = [P, I32, I64, P, P]
+        L.or_vol_inverse.restype = I32
+        L.or_vol_inverse.argtypes = [P, I32, I64, P, P]
         L.or_surface_render.argtypes = [I64, I32, P, P, P, P, P, P, P, P, I64, P, P, P, P, P, P]
         L.or_shell_map.argtypes = [P, I32, P, P]
         L.or_shell_inverse.argtypes = [P, I32, P, P]
@@ -457,3 +464,60 @@ def shell_inverse(geom, k, x):
     t = np.zeros(3)
     lib().or_shell_inverse(_p(_c(geom, np.float64)), int(k), _p(_c(x, np.float64)), _p(t))
     return t
+
+
+# ---------------------------------------------------------------- degree-R volume trees
+
+
+def _vol_args(forest):
+    return (forest.ntrees, _c(forest.tree_begin, np.int64), _c(forest.geom_params, np.float64))
+
+
+def vol_render(forest, fields, cam, method="rk4", substeps=4, pixels=None):
+    """FP64 image of one camera of a volume forest: dict A, B, I, nseg, segments, overlaps."""
+    raw = cam.raw() if hasattr(cam, "raw") else np.asarray(cam, np.float64)
+    lv, x, y, z = _forest_args(forest)
+    kind, k, e = _field_args(fields)
+    W, H = int(raw[14]), int(raw[15])
+    if pixels is None:
+        npo, pix, nsel = W * H, None, -1
+    else:
+        pix = _c(pixels, np.int64)
+        npo = nsel = pix.shape[0]
+    A, B, I = np.zeros(npo), np.zeros(npo), np.zeros(npo)
+    nseg = np.zeros(npo, np.int32)
+    stats = np.zeros(4, np.int64)
+    nt, tb, gp = _vol_args(forest)
+    st = lib().or_vol_render(forest.nleaves, nt, _p(tb), _p(gp), _p(lv), _p(x), _p(y), _p(z), kind, _p(k), _p(e),
+                             METHODS[method], int(substeps), _p(_c(raw, np.float64)), nsel, _p(pix), _p(A), _p(B),
+                             _p(I), _p(nseg), _p(stats))
+    assert st == 0
+    return {"A": A, "B": B, "I": I, "nseg": nseg, "segments": int(stats[0]), "overlaps": int(stats[1])}
+
+
+def vol_cands(forest, cam_raw, leaf, pi, pj):
+    """Intervals of explicit candidates (leaf, pixel (i, j)): counts and the first two (s_in, s_out)."""
+    lv, x, y, z = _forest_args(forest)
+    nt, tb, gp = _vol_args(forest)
+    leaf = _c(leaf, np.int64)
+    m = leaf.shape[0]
+    nseg = np.zeros(max(m, 1), np.int32)
+    iv = np.zeros((max(m, 1), 4), np.float64)
+    st = lib().or_vol_cands(m, _p(leaf), _p(_c(pi, np.int32)), _p(_c(pj, np.int32)), nt, _p(tb), _p(gp), _p(lv),
+                            _p(x), _p(y), _p(z), _p(_c(cam_raw, np.float64)), _p(nseg), _p(iv))
+    assert st == 0
+    return nseg[:m], iv[:m]
+
+
+def vol_map(geom, tree, xi):
+    xi = _c(np.atleast_2d(xi), np.float64)
+    out = np.zeros_like(xi)
+    lib().or_vol_map(_p(_c(geom, np.float64)), int(tree), xi.shape[0], _p(xi), _p(out))
+    return out
+
+
+def vol_inverse(geom, tree, x):
+    x = _c(np.atleast_2d(x), np.float64)
+    out = np.zeros_like(x)
+    ok = lib().or_vol_inverse(_p(_c(geom, np.float64)), int(tree), x.shape[0], _p(x), _p(out))
+    return out, bool(ok)

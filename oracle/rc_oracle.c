@@ -2110,9 +2110,10 @@ static int ho_newton(const orho *H, const double *rho, const double *d1, const d
  * method runs from the centre of each square left; a root counts in the
  * square whose half-open extent holds it (far tree edges closed).  A square
  * whose Newton iteration does not end inside it is split again, down to
- * OR_HO_MAXDEPTH, so that close roots near a tangency are separated. */
+ * OR_HO_MAXDEPTH, so that close roots near a tangency are separated.  Newton has
+ * converged when its step falls below tol. */
 static int ho_hits(const orcam *cm, const orho *H, const double *rho, const double *r, double *hs, double *ht1,
-                   double *ht2, int cap)
+                   double *ht2, int cap, double tol)
 {
     int k = 0;
     if (fabs(r[1]) < fabs(r[k])) k = 1;
@@ -2147,7 +2148,7 @@ static int ho_hits(const orcam *cm, const orho *H, const double *rho, const doub
         for (int it = 0; it < 40; it++) {
             double s1, s2;
             if (!ho_newton(H, rho, d1, d2, &t1, &t2, &s1, &s2)) break;
-            if (fabs(s1) + fabs(s2) < 1e-15) {
+            if (fabs(s1) + fabs(s2) < tol) {
                 ok = 1;
                 break;
             }
@@ -2219,7 +2220,7 @@ int or_ho_surface_render(int64_t n, int ntrees, const int64_t *tree_begin, const
             orho H;
             ho_init(&H, R, geom + 1 + 3 * npt * k);
             double s[2 * OR_HO_MAXR * OR_HO_MAXR], t1[2 * OR_HO_MAXR * OR_HO_MAXR], t2[2 * OR_HO_MAXR * OR_HO_MAXR];
-            int m = ho_hits(&c, &H, rho, r, s, t1, t2, 2 * R * R);
+            int m = ho_hits(&c, &H, rho, r, s, t1, t2, 2 * R * R, 1e-15);
             for (int a = 0; a < m && nh < 64; a++) {
                 int64_t leaf = surface_leaf(level, x, y, tree_begin[k], tree_begin[k + 1], t1[a], t2[a]);
                 if (leaf < 0) continue;
@@ -2278,4 +2279,449 @@ void or_ho_map(const double *geom, int tree, int64_t m, const double *t, double 
     orho H;
     ho_init(&H, R, geom + 1 + 3 * (R + 1) * (R + 1) * tree);
     for (int64_t i = 0; i < m; i++) ho_eval(&H, t[2 * i], t[2 * i + 1], out + 3 * i, NULL, NULL);
+}
+
+/* ------------------------------------------------------------------------ */
+/* degree-R volume trees: each tree maps its reference cube by a tensor     */
+/* product of degree-R Lagrange polynomials on the Gauss-Lobatto nodes       */
+/* (eq. nodal, eq. tensorgeom).  A ray meets a leaf (a sub-cube of the       */
+/* reference cube) where it crosses the leaf's six curved faces (App. A.1:   */
+/* each face is a degree-R patch, searched as the surfaces above); the       */
+/* crossings cut the clip range into pieces, and the pieces whose midpoint   */
+/* maps back into the leaf's cube are the ray's path through the leaf        */
+/* (Sec. 2.1), adjacent ones joined.                                         */
+/* ------------------------------------------------------------------------ */
+
+#define OR_VOL_MAXCROSS 64 /* face crossings kept per (leaf, ray) */
+
+typedef struct {
+    orho B;        /* degree, nodes and the node basis (its z unused) */
+    const double *z; /* (R+1)^3 control points of 3 doubles, m1 fastest, then m2, then m3 */
+} orvol;
+
+static void vol_init(orvol *V, int R, const double *z)
+{
+    ho_init(&V->B, R, NULL);
+    V->z = z;
+}
+
+/* X(xi) and its Jacobian J[k][a] = dX_k / dxi_a. */
+static void vol_eval(const orvol *V, const double *xi, double *X, double J[3][3])
+{
+    int n = V->B.R + 1;
+    double p[3][OR_HO_MAXR + 1], d[3][OR_HO_MAXR + 1];
+    for (int a = 0; a < 3; a++) ho_basis(&V->B, xi[a], p[a], d[a]);
+    for (int k = 0; k < 3; k++) {
+        double v = 0.0, v0 = 0.0, v1 = 0.0, v2 = 0.0;
+        for (int m3 = 0; m3 < n; m3++)
+            for (int m2 = 0; m2 < n; m2++)
+                for (int m1 = 0; m1 < n; m1++) {
+                    double zc = V->z[3 * (m1 + n * (m2 + n * m3)) + k];
+                    v += zc * p[0][m1] * p[1][m2] * p[2][m3];
+                    v0 += zc * d[0][m1] * p[1][m2] * p[2][m3];
+                    v1 += zc * p[0][m1] * d[1][m2] * p[2][m3];
+                    v2 += zc * p[0][m1] * p[1][m2] * d[2][m3];
+                }
+        X[k] = v;
+        if (J) {
+            J[k][0] = v0;
+            J[k][1] = v1;
+            J[k][2] = v2;
+        }
+    }
+}
+
+/* Reference coordinates of the point x: Newton's method on X(xi) = x from the
+ * start xi (replaced by the result).  Returns 1 when the step falls below
+ * 1e-14 within 60 iterations, 0 otherwise. */
+static int vol_inverse(const orvol *V, const double *x, double *xi)
+{
+    for (int it = 0; it < 60; it++) {
+        double X[3], J[3][3], e[3];
+        vol_eval(V, xi, X, J);
+        for (int k = 0; k < 3; k++) e[k] = X[k] - x[k];
+        /* solve J s = e by Cramer's rule */
+        double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                     J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                     J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+        if (!(det != 0.0) || !isfinite(det)) return 0;
+        double s[3];
+        for (int c = 0; c < 3; c++) {
+            double M[3][3];
+            for (int k = 0; k < 3; k++)
+                for (int a = 0; a < 3; a++) M[k][a] = a == c ? e[k] : J[k][a];
+            s[c] = (M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1]) - M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0]) +
+                    M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0])) /
+                   det;
+        }
+        double step = 0.0;
+        for (int a = 0; a < 3; a++) {
+            xi[a] -= s[a];
+            step += fabs(s[a]);
+        }
+        if (!(fabs(xi[0]) < 4.0 && fabs(xi[1]) < 4.0 && fabs(xi[2]) < 4.0)) return 0;
+        if (step < 1e-14) return 1;
+    }
+    return 0;
+}
+
+typedef struct {
+    const orvol *V;
+    double lo[3], len; /* the leaf's cube in the tree's reference coordinates */
+} orvleaf;
+
+static orvleaf vol_leaf(const orvol *V, uint8_t level, uint32_t x, uint32_t y, uint32_t z)
+{
+    orvleaf L;
+    L.V = V;
+    double q = ldexp(1.0, -OR_QMAX);
+    L.lo[0] = (double)x * q;
+    L.lo[1] = (double)y * q;
+    L.lo[2] = (double)z * q;
+    L.len = ldexp(1.0, -(int)level);
+    return L;
+}
+
+/* Leaf reference coordinates of a real-space point (the field's argument). */
+static void vol_ref(const void *ctx, const double *x, double *xil)
+{
+    const orvleaf *L = (const orvleaf *)ctx;
+    double xi[3];
+    for (int a = 0; a < 3; a++) xi[a] = L->lo[a] + 0.5 * L->len;
+    vol_inverse(L->V, x, xi);
+    for (int a = 0; a < 3; a++) xil[a] = (xi[a] - L->lo[a]) / L->len;
+}
+
+static int vol_inside(const orvleaf *L, const double *x)
+{
+    double xi[3];
+    for (int a = 0; a < 3; a++) xi[a] = L->lo[a] + 0.5 * L->len;
+    if (!vol_inverse(L->V, x, xi)) return 0;
+    for (int a = 0; a < 3; a++)
+        if (!(xi[a] >= L->lo[a] && xi[a] <= L->lo[a] + L->len)) return 0;
+    return 1;
+}
+
+/* Face f of the leaf (axis f / 2 at its low (f even) or high end) as a
+ * degree-R surface patch over [0, 1]^2: its control points are the map's
+ * values on the face's node grid, which the patch interpolates exactly. */
+static void vol_face(const orvleaf *L, int f, double *zf)
+{
+    int R = L->V->B.R, n = R + 1;
+    int k = f / 2, a = (k + 1) % 3, b = (k + 2) % 3;
+    for (int m2 = 0; m2 < n; m2++)
+        for (int m1 = 0; m1 < n; m1++) {
+            double xi[3];
+            xi[k] = L->lo[k] + ((f & 1) ? L->len : 0.0);
+            xi[a] = L->lo[a] + L->len * L->V->B.eta[m1];
+            xi[b] = L->lo[b] + L->len * L->V->B.eta[m2];
+            vol_eval(L->V, xi, zf + 3 * (m1 + n * m2), NULL);
+        }
+}
+
+static int cmp_dbl(const void *pa, const void *pb)
+{
+    double a = *(const double *)pa, b = *(const double *)pb;
+    return a < b ? -1 : (a > b ? 1 : 0);
+}
+
+/* The ray's intervals inside the leaf, clipped to the camera's range: up to
+ * cap intervals (s_in, s_out) into iv, nearest first; returns their number. */
+static int vol_pair(const orcam *cm, const orvleaf *L, const double *rho, const double *r, double *iv, int cap)
+{
+    int R = L->V->B.R, n = R + 1;
+    double ev[OR_VOL_MAXCROSS + 2];
+    int ne = 0;
+    ev[ne++] = cm->smin;
+    ev[ne++] = cm->smax;
+    for (int f = 0; f < 6; f++) {
+        double zf[3 * (OR_HO_MAXR + 1) * (OR_HO_MAXR + 1)];
+        vol_face(L, f, zf);
+        orho H;
+        ho_init(&H, R, zf);
+        double hs[2 * OR_HO_MAXR * OR_HO_MAXR], t1[2 * OR_HO_MAXR * OR_HO_MAXR], t2[2 * OR_HO_MAXR * OR_HO_MAXR];
+        /* a leaf's face is small: Newton's step stalls near 1e-15 there, so the
+         * convergence test is looser; the canonical polish follows anyway */
+        int m = ho_hits(cm, &H, rho, r, hs, t1, t2, 2 * R * R, 1e-12);
+        for (int q = 0; q < m && ne < OR_VOL_MAXCROSS + 2; q++) ev[ne++] = hs[q];
+        (void)n;
+    }
+    qsort(ev, (size_t)ne, sizeof(double), cmp_dbl);
+    int ni = 0;
+    double cur_in = 0.0, cur_out = -1.0;
+    int open = 0;
+    for (int q = 0; q + 1 < ne; q++) {
+        double a = ev[q], b = ev[q + 1];
+        if (!(b > a)) continue;
+        double sm = 0.5 * (a + b), x[3];
+        for (int k = 0; k < 3; k++) x[k] = rho[k] + sm * r[k];
+        int in = vol_inside(L, x);
+        if (in && open && a == cur_out) {
+            cur_out = b; /* adjacent pieces inside: one interval */
+        } else if (in) {
+            if (open) {
+                if (ni < cap) {
+                    iv[2 * ni] = cur_in;
+                    iv[2 * ni + 1] = cur_out;
+                }
+                ni++;
+            }
+            open = 1;
+            cur_in = a;
+            cur_out = b;
+        }
+    }
+    if (open) {
+        if (ni < cap) {
+            iv[2 * ni] = cur_in;
+            iv[2 * ni + 1] = cur_out;
+        }
+        ni++;
+    }
+    return ni;
+}
+
+/* Conservative pixel rectangle of a leaf: the camera-space box of the
+ * Bernstein coefficients of the map over the leaf's cube (convex hull
+ * property), from the map's values on an equispaced grid of the cube, widened
+ * by a relative 1e-9. */
+static int vol_rect(const orcam *c, const orvleaf *L, int *rect)
+{
+    int R = L->V->B.R, n = R + 1;
+    double vals[3][(OR_HO_MAXR + 1) * (OR_HO_MAXR + 1) * (OR_HO_MAXR + 1)];
+    for (int j3 = 0; j3 < n; j3++)
+        for (int j2 = 0; j2 < n; j2++)
+            for (int j1 = 0; j1 < n; j1++) {
+                double xi[3] = {L->lo[0] + L->len * j1 / R, L->lo[1] + L->len * j2 / R, L->lo[2] + L->len * j3 / R};
+                double X[3];
+                vol_eval(L->V, xi, X, NULL);
+                const double *ax[3] = {c->t, c->u, c->vh};
+                for (int k = 0; k < 3; k++) {
+                    double e[3] = {X[0] - c->o[0], X[1] - c->o[1], X[2] - c->o[2]};
+                    vals[k][j1 + n * (j2 + n * j3)] = dot3(ax[k], e);
+                }
+            }
+    double lo[3], hi[3], mag = 0.0;
+    for (int k = 0; k < 3; k++) {
+        /* equispaced values -> Bernstein coefficients along each axis in turn */
+        double *v = vals[k], t[(OR_HO_MAXR + 1) * (OR_HO_MAXR + 1) * (OR_HO_MAXR + 1)];
+        for (int ax = 0; ax < 3; ax++) {
+            int st = ax == 0 ? 1 : (ax == 1 ? n : n * n);
+            for (int q = 0; q < n * n * n; q++) {
+                int jj = (q / st) % n;
+                double s = 0.0;
+                for (int j = 0; j < n; j++) s += L->V->B.einv[jj * n + j] * v[q + (j - jj) * st];
+                t[q] = s;
+            }
+            for (int q = 0; q < n * n * n; q++) v[q] = t[q];
+        }
+        lo[k] = INFINITY;
+        hi[k] = -INFINITY;
+        for (int q = 0; q < n * n * n; q++) {
+            lo[k] = fmin(lo[k], v[q]);
+            hi[k] = fmax(hi[k], v[q]);
+        }
+        mag = fmax(mag, fmax(fabs(lo[k]), fabs(hi[k])));
+    }
+    double m = 1e-9 * (1.0 + mag);
+    for (int k = 0; k < 3; k++) {
+        lo[k] -= m;
+        hi[k] += m;
+    }
+    rect[0] = rect[2] = 1;
+    rect[1] = rect[3] = 0;
+    if (hi[2] < c->n || lo[2] > c->zfar) return 0;
+    double Z0 = lo[2] < c->n ? c->n : lo[2], Z1 = hi[2] > c->zfar ? c->zfar : hi[2];
+    pixel_range(c, lo[0], hi[0], Z0, Z1, c->cx, c->w, &rect[0], &rect[1]);
+    pixel_range(c, lo[1], hi[1], Z0, Z1, c->cy, c->h, &rect[2], &rect[3]);
+    return rect[0] <= rect[1] && rect[2] <= rect[3];
+}
+
+/* Intervals of explicit candidates: leaf[q] at pixel (pi[q], pj[q]) of camera
+ * cam; nseg[q] = the number of intervals, iv[4 q .. 4 q + 3] the first two
+ * (s_in, s_out) pairs, zeros where absent.  geom: [R, then (R+1)^3 control
+ * points of 3 doubles per tree]. */
+int or_vol_cands(int64_t m, const int64_t *leaf, const int32_t *pi, const int32_t *pj, int ntrees,
+                 const int64_t *tree_begin, const double *geom, const uint8_t *level, const uint32_t *x,
+                 const uint32_t *y, const uint32_t *z, const double *cam, int32_t *nseg, double *iv)
+{
+    orcam c;
+    cam_parse(cam, &c);
+    int R = (int)geom[0];
+    if (R < 2 || R > OR_HO_MAXR) return -1;
+    int npt = (R + 1) * (R + 1) * (R + 1);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t q = 0; q < m; q++) {
+        int64_t l = leaf[q];
+        orvol V;
+        vol_init(&V, R, geom + 1 + 3 * npt * tree_of(l, ntrees, tree_begin));
+        orvleaf L = vol_leaf(&V, level[l], x[l], y[l], z[l]);
+        double rho[3], r[3], w[2 * OR_VOL_MAXCROSS];
+        pixel_ray(&c, pi[q], pj[q], rho, r);
+        int k = vol_pair(&c, &L, rho, r, w, OR_VOL_MAXCROSS);
+        nseg[q] = k;
+        for (int h = 0; h < 4; h++) iv[4 * q + h] = 0.0;
+        for (int h = 0; h < k && h < 2; h++) {
+            iv[4 * q + 2 * h] = w[2 * h];
+            iv[4 * q + 2 * h + 1] = w[2 * h + 1];
+        }
+    }
+    return 0;
+}
+
+/* Render one camera of a volume forest: every leaf whose conservative
+ * rectangle holds the pixel contributes its intervals, integrated with the
+ * field at reference coordinates from the inverse map (Newton), then all of a
+ * pixel's segments are folded nearest first.  Arguments and outputs as
+ * or_shell_render; stats[0] = segments, stats[1] = overlaps. */
+int or_vol_render(int64_t n, int ntrees, const int64_t *tree_begin, const double *geom, const uint8_t *level,
+                  const uint32_t *x, const uint32_t *y, const uint32_t *z, int kind, const double *kap,
+                  const double *eps, int method, int substeps, const double *cam, int64_t npix_sel,
+                  const int64_t *pix_sel, double *Aout, double *Bout, double *Iout, int32_t *nseg_pix, int64_t *stats)
+{
+    orcam c;
+    cam_parse(cam, &c);
+    int R = (int)geom[0];
+    if (R < 2 || R > OR_HO_MAXR) return -1;
+    int npt = (R + 1) * (R + 1) * (R + 1);
+    int64_t W = c.w, H = c.h, P = W * H;
+    int64_t npo = (npix_sel >= 0) ? npix_sel : P;
+    int64_t *selmap = NULL;
+    if (npix_sel >= 0) {
+        selmap = (int64_t *)malloc(sizeof(int64_t) * (size_t)P);
+        for (int64_t p = 0; p < P; p++) selmap[p] = -1;
+        for (int64_t q = 0; q < npix_sel; q++) selmap[pix_sel[q]] = q;
+    }
+    /* candidates (leaf, pixel) of every leaf's rectangle */
+    int64_t cap = 1 << 16, nc = 0;
+    int64_t *cl = (int64_t *)malloc(sizeof(int64_t) * (size_t)cap), *cp = (int64_t *)malloc(sizeof(int64_t) * (size_t)cap);
+    for (int64_t l = 0; l < n; l++) {
+        orvol V;
+        vol_init(&V, R, geom + 1 + 3 * npt * tree_of(l, ntrees, tree_begin));
+        orvleaf L = vol_leaf(&V, level[l], x[l], y[l], z[l]);
+        int rr[4];
+        if (!vol_rect(&c, &L, rr)) continue;
+        for (int j = rr[2]; j <= rr[3]; j++)
+            for (int i = rr[0]; i <= rr[1]; i++) {
+                int64_t p = (int64_t)j * W + i;
+                if (selmap && selmap[p] < 0) continue;
+                if (nc == cap) {
+                    cap *= 2;
+                    cl = (int64_t *)realloc(cl, sizeof(int64_t) * (size_t)cap);
+                    cp = (int64_t *)realloc(cp, sizeof(int64_t) * (size_t)cap);
+                }
+                cl[nc] = l;
+                cp[nc] = p;
+                nc++;
+            }
+    }
+    /* intervals per candidate (up to 4), then the segments */
+    double *civ = (double *)malloc(sizeof(double) * 8 * (size_t)(nc > 0 ? nc : 1));
+    int *cn = (int *)malloc(sizeof(int) * (size_t)(nc > 0 ? nc : 1));
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t q = 0; q < nc; q++) {
+        int64_t l = cl[q];
+        orvol V;
+        vol_init(&V, R, geom + 1 + 3 * npt * tree_of(l, ntrees, tree_begin));
+        orvleaf L = vol_leaf(&V, level[l], x[l], y[l], z[l]);
+        double rho[3], r[3], w[2 * OR_VOL_MAXCROSS];
+        pixel_ray(&c, (int)(cp[q] % W), (int)(cp[q] / W), rho, r);
+        int k = vol_pair(&c, &L, rho, r, w, OR_VOL_MAXCROSS);
+        cn[q] = k < 4 ? k : 4;
+        for (int h = 0; h < cn[q]; h++) {
+            civ[8 * q + 2 * h] = w[2 * h];
+            civ[8 * q + 2 * h + 1] = w[2 * h + 1];
+        }
+    }
+    int64_t ns = 0;
+    for (int64_t q = 0; q < nc; q++) ns += cn[q];
+    orseg *segs = (orseg *)malloc(sizeof(orseg) * (size_t)(ns > 0 ? ns : 1));
+    ns = 0;
+    for (int64_t q = 0; q < nc; q++)
+        for (int h = 0; h < cn[q]; h++) {
+            segs[ns].pix = selmap ? selmap[cp[q]] : cp[q];
+            segs[ns].s_in = civ[8 * q + 2 * h];
+            segs[ns].s_out = civ[8 * q + 2 * h + 1];
+            segs[ns].leaf = cl[q];
+            ns++;
+        }
+    free(cl);
+    free(cp);
+    free(civ);
+    free(cn);
+    free(selmap);
+    qsort(segs, (size_t)ns, sizeof(orseg), seg_cmp);
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t k = 0; k < ns; k++) {
+        orseg *s = &segs[k];
+        int64_t p = (npix_sel >= 0) ? pix_sel[s->pix] : s->pix;
+        double rho[3], r[3];
+        pixel_ray(&c, (int)(p % W), (int)(p / W), rho, r);
+        int64_t l = s->leaf;
+        orvol V;
+        vol_init(&V, R, geom + 1 + 3 * npt * tree_of(l, ntrees, tree_begin));
+        orvleaf L = vol_leaf(&V, level[l], x[l], y[l], z[l]);
+        leaffield F;
+        leaf_field(kind, n, l, kap, eps, &F);
+        dn A, B;
+        segment_dn_ref(&F, vol_ref, &L, rho, r, ray_norm(r), s->s_in, s->s_out, method, substeps, 0.0, 0, &A, &B);
+        s->A = A.v;
+        s->B = B.v;
+    }
+    int64_t overlaps = 0;
+    for (int64_t q = 0; q < npo; q++) {
+        Aout[q] = 1.0;
+        Bout[q] = 0.0;
+        if (nseg_pix) nseg_pix[q] = 0;
+    }
+    int64_t k = 0;
+    while (k < ns) {
+        int64_t q = segs[k].pix;
+        double acc[2] = {1.0, 0.0};
+        double prev_out = -INFINITY;
+        int cnt = 0;
+        for (; k < ns && segs[k].pix == q; k++) {
+            if (segs[k].s_in < prev_out - 1e-12 * fabs(prev_out)) overlaps++;
+            prev_out = segs[k].s_out;
+            double sg[2] = {segs[k].A, segs[k].B}, t[2];
+            or_combine(acc, sg, t);
+            acc[0] = t[0];
+            acc[1] = t[1];
+            cnt++;
+        }
+        Aout[q] = acc[0];
+        Bout[q] = acc[1];
+        if (nseg_pix) nseg_pix[q] = cnt;
+    }
+    for (int64_t q = 0; q < npo; q++) Iout[q] = Aout[q] * c.bg + Bout[q];
+    if (stats) {
+        stats[0] = ns;
+        stats[1] = overlaps;
+    }
+    free(segs);
+    return 0;
+}
+
+/* X of tree `tree` at m reference points, and its inverse by Newton's method
+ * from the cube's centre (for tests). */
+void or_vol_map(const double *geom, int tree, int64_t m, const double *xi, double *out)
+{
+    int R = (int)geom[0];
+    orvol V;
+    vol_init(&V, R, geom + 1 + 3 * (R + 1) * (R + 1) * (R + 1) * tree);
+    for (int64_t i = 0; i < m; i++) vol_eval(&V, xi + 3 * i, out + 3 * i, NULL);
+}
+
+int or_vol_inverse(const double *geom, int tree, int64_t m, const double *x, double *xi)
+{
+    int R = (int)geom[0];
+    orvol V;
+    vol_init(&V, R, geom + 1 + 3 * (R + 1) * (R + 1) * (R + 1) * tree);
+    int ok = 1;
+    for (int64_t i = 0; i < m; i++) {
+        double t[3] = {0.5, 0.5, 0.5};
+        ok &= vol_inverse(&V, x + 3 * i, t);
+        for (int a = 0; a < 3; a++) xi[3 * i + a] = t[a];
+    }
+    return ok;
 }

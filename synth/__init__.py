@@ -54,3 +54,11 @@ from .surface import (  # noqa: F401
     random_surface_fields,
     surface_forest,
 )
+from .volume import (  # noqa: F401
+    bent_map,
+    random_quadratic_map,
+    vol_geom,
+    vol_tree,
+    volume_forest,
+    volume_scene,
+)
