@@ -69,7 +69,15 @@ typedef int32_t rc_status;
 #define RC_MAXCH 3          /* channels per call (RGB) */
 #define RC_MAXLISTS 16     /* shares rc_merge_lists takes at once */
 
-enum { RC_GEOM_UNIT_CUBE = 0, RC_GEOM_SHELL6 = 1, RC_GEOM_SURFACE = 2, RC_GEOM_SURFACE2 = 3, RC_GEOM_SURFACE3 = 4 };
+enum {
+    RC_GEOM_UNIT_CUBE = 0,
+    RC_GEOM_SHELL6 = 1,
+    RC_GEOM_SURFACE = 2,
+    RC_GEOM_SURFACE2 = 3,
+    RC_GEOM_SURFACE3 = 4,
+    RC_GEOM_VOLUME2 = 5,
+    RC_GEOM_VOLUME3 = 6
+};
 enum { RC_FIELD_CONST = 0, RC_FIELD_TRILINEAR = 1, RC_FIELD_CONST_EQ = 2, RC_FIELD_SURFACE = 3 };
 enum { RC_INT_ANALYTIC = 0, RC_INT_RK4 = 1, RC_INT_GAUSS2 = 2, RC_INT_SIMPSON = 3 };
 #define RC_ADAPT_MAXDEPTH 16  /* deepest halving of the adaptive recursion */
@@ -94,9 +102,16 @@ enum { RC_INT_ANALYTIC = 0, RC_INT_RK4 = 1, RC_INT_GAUSS2 = 2, RC_INT_SIMPSON = 
  *   the tensor product of degree-R Lagrange polynomials (R = 2, 3) on the
  *   Gauss-Lobatto nodes of [0, 1] (eq. nodal, eq. tensorgeom): geom_table
  *   holds (R+1)^2 control points z_{m1, m2} of 3 doubles per tree, m1 fastest
- *   (the map's values at the node pairs). */
+ *   (the map's values at the node pairs).
+ * RC_GEOM_VOLUME2, RC_GEOM_VOLUME3: 1 .. 6 octrees, each mapping its reference
+ *   cube by the tensor product of degree-R Lagrange polynomials (R = 2, 3) on
+ *   the Gauss-Lobatto nodes (eq. nodal, eq. tensorgeom; curved elements,
+ *   Sec. 2.1): geom_table holds (R+1)^3 control points z_{m1, m2, m3} of 3
+ *   doubles per tree, m1 fastest, then m2 (the map's values at the node
+ *   triples).  Fields are per leaf in its reference coordinates, as on the
+ *   unit cube. */
 typedef struct rc_forest {
-    int32_t ntrees;             /* trees in the share: 1 (unit cube), 6 (shell), 1 .. 6 (surfaces) */
+    int32_t ntrees;             /* trees in the share: 1 (unit cube), 6 (shell), 1 .. 6 (surfaces, volumes) */
     int32_t geom;               /* RC_GEOM_* */
     int64_t nleaves;            /* N >= 1 */
     const int64_t *tree_begin;  /* [host] ntrees + 1 leaf offsets per tree */
@@ -316,6 +331,19 @@ rc_status rc_prune_visible_static(const rc_forest *forest, const rc_index *index
  * two nearest hits; hit[] counts all.  Leaf
  * rectangles come from the camera-aligned box of the leaf's Bernstein
  * coefficients (App. A.2).
+ *
+ * RC_GEOM_VOLUME2 / 3 forests (curved elements, Sec. 2.1; App. A.1): the ray
+ * crosses the leaf's six faces, each a degree-R patch searched as the
+ * degree-R surfaces above (crossings polished canonically on the tree's face
+ * polynomial, so that leaves sharing a face find the same depth); the
+ * crossings cut the clip range into pieces, a piece whose midpoint maps back
+ * into the leaf's cube (Newton's method on the tree map, FP64) is inside, and
+ * adjacent inside pieces join.  Each interval is integrated with RK4 over 1,
+ * 2, 4 or 8 equal substeps with field points mapped back the same way, or in
+ * closed form for constant fields (analytic).  Records, hit[] and sio[] as
+ * for the shell: the two nearest intervals, hit[] counting all.  Other
+ * integrators: RC_EUNSUPPORTED.  Leaf rectangles come from the camera-aligned
+ * box of the Bernstein coefficients of the map over the leaf's cube.
  */
 rc_status rc_segments(const rc_forest *forest, const rc_fields *fields, const void *dcams, int32_t ncams,
                       const rc_vforest *vf, const rc_integrator *integ, float *rec_leaf, uint8_t *hit,

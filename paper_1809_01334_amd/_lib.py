@@ -23,6 +23,7 @@ RC_EHIP = -6
 RC_QMAXLEVEL = 19
 RC_CAMERA_DOUBLES = 20
 RC_GEOM_UNIT_CUBE, RC_GEOM_SHELL6, RC_GEOM_SURFACE, RC_GEOM_SURFACE2, RC_GEOM_SURFACE3 = 0, 1, 2, 3, 4
+RC_GEOM_VOLUME2, RC_GEOM_VOLUME3 = 5, 6
 RC_MAXTREES = 64
 RC_MAXLISTS = 16
 RC_MAXCH = 3

@@ -42,7 +42,8 @@ inline rc_status check_forest(const rc_forest* f) {
         if (f->ntrees != 1) return RC_EUNSUPPORTED;
     } else if (f->geom == RC_GEOM_SHELL6) {
         if (f->ntrees != 6 || !f->geom_table || !f->tree_begin) return RC_EINVAL;
-    } else if (f->geom == RC_GEOM_SURFACE || f->geom == RC_GEOM_SURFACE2 || f->geom == RC_GEOM_SURFACE3) {
+    } else if (f->geom == RC_GEOM_SURFACE || f->geom == RC_GEOM_SURFACE2 || f->geom == RC_GEOM_SURFACE3 ||
+               f->geom == RC_GEOM_VOLUME2 || f->geom == RC_GEOM_VOLUME3) {
         if (f->ntrees < 1 || f->ntrees > 6 || !f->geom_table || !f->tree_begin) return RC_EINVAL;
     } else {
         return RC_EUNSUPPORTED;
@@ -64,9 +65,12 @@ inline bool is_surface(const rc_forest* f) {
 inline int surface_degree(const rc_forest* f) {
     return f->geom == RC_GEOM_SURFACE2 ? 2 : f->geom == RC_GEOM_SURFACE3 ? 3 : 1;
 }
+inline bool is_volume(const rc_forest* f) { return f->geom == RC_GEOM_VOLUME2 || f->geom == RC_GEOM_VOLUME3; }
+// Degree of a volume forest's tree maps.
+inline int volume_degree(const rc_forest* f) { return f->geom == RC_GEOM_VOLUME3 ? 3 : 2; }
 // Geometries whose records hold two depth-tagged intervals and whose node
 // rectangles are unions of the children's.
-inline bool is_curved(const rc_forest* f) { return is_shell(f) || is_surface(f); }
+inline bool is_curved(const rc_forest* f) { return is_shell(f) || is_surface(f) || is_volume(f); }
 
 // Curved six-tree shell variants of rc_segments and rc_composite (arguments
 // already validated by the entry points).
@@ -81,6 +85,9 @@ rc_status rc_shell_composite(const rc_forest* f, const rc_index* ix, const void*
 rc_status rc_surface_ho_segments(const rc_forest* f, const rc_fields* fl, const void* dcams, const rc_vforest* vf,
                                  const rc_integrator* in, float* rec_leaf, uint8_t* hit, double* sio,
                                  const rc_tuning* tune, hipStream_t st);
+rc_status rc_volume_segments(const rc_forest* f, const rc_fields* fl, const void* dcams, const rc_vforest* vf,
+                             const rc_integrator* in, float* rec_leaf, uint8_t* hit, double* sio,
+                             const rc_tuning* tune, hipStream_t st);
 rc_status rc_surface_segments(const rc_forest* f, const rc_fields* fl, const void* dcams, const rc_vforest* vf,
                               const rc_integrator* in, float* rec_leaf, uint8_t* hit, double* sio,
                               const rc_tuning* tune, hipStream_t st);

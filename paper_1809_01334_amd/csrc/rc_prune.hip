@@ -11,6 +11,7 @@
 #include "rc_shell.h"
 #include "rc_surface.h"
 #include "rc_surface_ho.h"
+#include "rc_volume.h"
 
 namespace rc {
 namespace {
@@ -99,6 +100,30 @@ struct PruneSrcHo {
         int k = 0;
         while (k + 1 < ntrees && l >= tb[k + 1]) k++;
         it.r = ho_rect<R>(cams[cam], G, k, level[l], x[l], y[l]);
+        it.val = it.r.empty() ? I64x3{0, 0, 0} : I64x3{1, it.r.area(), 0};
+        store_rect(stash + 4 * i, it.r);
+        return it;
+    }
+};
+
+// Leaves of a degree-R volume forest: rectangles from the camera-space
+// Bernstein coefficients of the map over the leaf's cube (App. A.2).
+template <int R>
+struct PruneSrcVol {
+    const Cam* cams;
+    const uint8_t* level;
+    const uint32_t *x, *y, *z;
+    int64_t N;
+    VolGeom V;
+    int64_t tb[7];
+    int ntrees;
+    int16_t* stash;
+    __device__ Item operator()(int64_t i) const {
+        Item it;
+        int64_t cam = divu(i, N), l = i - cam * N;
+        int k = 0;
+        while (k + 1 < ntrees && l >= tb[k + 1]) k++;
+        it.r = vol_rect<R>(cams[cam], V, k, level[l], x[l], y[l], z[l]);
         it.val = it.r.empty() ? I64x3{0, 0, 0} : I64x3{1, it.r.area(), 0};
         store_rect(stash + 4 * i, it.r);
         return it;
@@ -358,7 +383,19 @@ rc_status prune(const rc_forest* f, const rc_index* ix, const void* dcams, int32
     } else {
         // leaves first; node rectangles are unions of their children's
         int R = surface_degree(f);
-        if (is_surface(f) && R > 1) {
+        if (is_volume(f)) {
+            VolGeom V;
+            vol_geom_init(volume_degree(f), f->geom_table, V);
+            if (volume_degree(f) == 2) {
+                PruneSrcVol<2> vs{cams, f->level, f->x, f->y, f->z, N, V, {}, f->ntrees, src.stash};
+                for (int k = 0; k < 7; k++) vs.tb[k] = k <= f->ntrees ? f->tree_begin[k] : N;
+                RC_HIP(launch_scan2<I64x3>(items, vs, stash, dst, (I64x3*)ws, st));
+            } else {
+                PruneSrcVol<3> vs{cams, f->level, f->x, f->y, f->z, N, V, {}, f->ntrees, src.stash};
+                for (int k = 0; k < 7; k++) vs.tb[k] = k <= f->ntrees ? f->tree_begin[k] : N;
+                RC_HIP(launch_scan2<I64x3>(items, vs, stash, dst, (I64x3*)ws, st));
+            }
+        } else if (is_surface(f) && R > 1) {
             HoGeom G;
             ho_geom_init(R, f->geom_table, G);
             int64_t tb7[7];

@@ -212,7 +212,9 @@ extern "C" rc_status rc_segments(const rc_forest* f, const rc_fields* fl, const 
             float* rec = rec_leaf + ch * rstride;
             uint8_t* h = ch == 0 ? hit : nullptr;
             double* io = ch == 0 ? sio : nullptr;
-            if (is_surface(f) && surface_degree(f) > 1)
+            if (is_volume(f))
+                s = rc_volume_segments(f, &one, dcams, vf, in, rec, h, io, tune, st);
+            else if (is_surface(f) && surface_degree(f) > 1)
                 s = rc_surface_ho_segments(f, &one, dcams, vf, in, rec, h, io, tune, st);
             else if (is_surface(f))
                 s = rc_surface_segments(f, &one, dcams, vf, in, rec, h, io, tune, st);

@@ -199,4 +199,88 @@ __device__ inline Rect ho_rect(const Cam& c, const HoGeom& G, int tree, int leve
     return cam_rect(c, lo[0] - m, hi[0] + m, lo[1] - m, hi[1] + m, lo[2] - m, hi[2] + m);
 }
 
+// Krawczyk's test on the square [u0, u0 + h] x [v0, v0 + h] of the leaf,
+// widened by a relative 1e-9: with F = (f1, f2) and M the inverse Jacobian at
+// the centre c, K = c - M F(c) + (I - M [J]) (Q - c), [J] the Jacobian's range
+// over the square from the sub-square nets S1, S2 (differences of Bernstein
+// coefficients).  K disjoint from Q: no root in Q (returns 0); K inside Q:
+// exactly one (returns 1); otherwise undecided (returns 2).
+template <int R>
+__device__ inline int ho_krawczyk(const double (&f1)[(R + 1) * (R + 1)], const double (&f2)[(R + 1) * (R + 1)],
+                                  const double (&S1)[(R + 1) * (R + 1)], const double (&S2)[(R + 1) * (R + 1)],
+                                  double u0, double v0, double h) {
+    constexpr int N = R + 1;
+    double cu = u0 + 0.5 * h, cv = v0 + 0.5 * h;
+    double a, au, av, b, bu, bv;
+    ho_eval<R>(f1, cu, cv, a, au, av);
+    ho_eval<R>(f2, cu, cv, b, bu, bv);
+    double det = au * bv - av * bu;
+    if (!(det != 0.0) || !isfinite(det)) return 2;
+    double m00 = bv / det, m01 = -av / det, m10 = -bu / det, m11 = au / det;
+    // ranges of the four partial derivatives over the square (leaf coordinates)
+    double lo[4], hi[4];
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        lo[q] = INFINITY;
+        hi[q] = -INFINITY;
+    }
+#pragma unroll
+    for (int k2 = 0; k2 < N; k2++)
+#pragma unroll
+        for (int k1 = 0; k1 < N; k1++) {
+            if (k1 < R) {
+                double d1 = S1[k1 + 1 + N * k2] - S1[k1 + N * k2], d2 = S2[k1 + 1 + N * k2] - S2[k1 + N * k2];
+                lo[0] = fmin(lo[0], d1);
+                hi[0] = fmax(hi[0], d1);
+                lo[2] = fmin(lo[2], d2);
+                hi[2] = fmax(hi[2], d2);
+            }
+            if (k2 < R) {
+                double d1 = S1[k1 + N * (k2 + 1)] - S1[k1 + N * k2], d2 = S2[k1 + N * (k2 + 1)] - S2[k1 + N * k2];
+                lo[1] = fmin(lo[1], d1);
+                hi[1] = fmax(hi[1], d1);
+                lo[3] = fmin(lo[3], d2);
+                hi[3] = fmax(hi[3], d2);
+            }
+        }
+    double sc = (double)R / h;  // d/du of the sub-square polynomial is R/h times the differences
+    double mid[4], rad[4];
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        mid[q] = 0.5 * (lo[q] + hi[q]) * sc;
+        rad[q] = (0.5 * (hi[q] - lo[q]) * sc) * (1.0 + 1e-9) + 1e-300;
+    }
+    // rows of I - M [J]: [J] = [[J00, J01], [J10, J11]] = [[d f1/du, d f1/dv], [d f2/du, d f2/dv]]
+    double e00 = fabs(1.0 - (m00 * mid[0] + m01 * mid[2])) + (fabs(m00) * rad[0] + fabs(m01) * rad[2]);
+    double e01 = fabs(0.0 - (m00 * mid[1] + m01 * mid[3])) + (fabs(m00) * rad[1] + fabs(m01) * rad[3]);
+    double e10 = fabs(0.0 - (m10 * mid[0] + m11 * mid[2])) + (fabs(m10) * rad[0] + fabs(m11) * rad[2]);
+    double e11 = fabs(1.0 - (m10 * mid[1] + m11 * mid[3])) + (fabs(m10) * rad[1] + fabs(m11) * rad[3]);
+    double r = 0.5 * h * (1.0 + 1e-9);
+    double k0 = cu - (m00 * a + m01 * b), k1 = cv - (m10 * a + m11 * b);
+    double r0 = r * (e00 + e01), r1 = r * (e10 + e11);
+    if (!(isfinite(k0) && isfinite(k1) && isfinite(r0) && isfinite(r1))) return 2;
+    if (k0 + r0 < cu - r || k0 - r0 > cu + r || k1 + r1 < cv - r || k1 - r1 > cv + r) return 0;
+    if (k0 - r0 > cu - r && k0 + r0 < cu + r && k1 - r1 > cv - r && k1 + r1 < cv + r) return 1;
+    return 2;
+}
+
+// Newton's method on (f1, f2) = 0 with the nets over the leaf square, from (u, v).
+template <int R>
+__device__ inline bool ho_newton_local(const double (&f1)[(R + 1) * (R + 1)], const double (&f2)[(R + 1) * (R + 1)],
+                                       double& u, double& v) {
+    for (int it = 0; it < 30; it++) {
+        double a, au, av, b, bu, bv;
+        ho_eval<R>(f1, u, v, a, au, av);
+        ho_eval<R>(f2, u, v, b, bu, bv);
+        double det = au * bv - av * bu;
+        if (det == 0.0) return false;
+        double du = (bv * a - av * b) / det, dv = (au * b - bu * a) / det;
+        u -= du;
+        v -= dv;
+        if (!(fabs(u) < 4.0 && fabs(v) < 4.0)) return false;
+        if (fabs(du) + fabs(dv) < 1e-14) return true;
+    }
+    return false;
+}
+
 }  // namespace rc

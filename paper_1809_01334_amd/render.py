@@ -60,14 +60,17 @@ class DeviceForest:
     @property
     def curved(self) -> bool:
         """Records hold two depth-tagged intervals (shell intervals, surface hits)."""
-        return self.geom in (L.RC_GEOM_SHELL6, L.RC_GEOM_SURFACE, L.RC_GEOM_SURFACE2, L.RC_GEOM_SURFACE3)
+        return self.geom in (L.RC_GEOM_SHELL6, L.RC_GEOM_SURFACE, L.RC_GEOM_SURFACE2, L.RC_GEOM_SURFACE3,
+                             L.RC_GEOM_VOLUME2, L.RC_GEOM_VOLUME3)
 
     @classmethod
     def from_synth(cls, forest, device):
         table = forest.geom_params
-        if forest.geom == "surface_ho":
+        if forest.geom in ("surface_ho", "volume"):
             # [R, control points]: the degree picks the geometry code
-            geom = {2: L.RC_GEOM_SURFACE2, 3: L.RC_GEOM_SURFACE3}[int(table[0])]
+            codes = ({2: L.RC_GEOM_SURFACE2, 3: L.RC_GEOM_SURFACE3} if forest.geom == "surface_ho"
+                     else {2: L.RC_GEOM_VOLUME2, 3: L.RC_GEOM_VOLUME3})
+            geom = codes[int(table[0])]
             table = table[1:]
         else:
             geom = {"unit_cube": L.RC_GEOM_UNIT_CUBE, "shell6": L.RC_GEOM_SHELL6,

@@ -1,0 +1,148 @@
+"""GPU parity of degree-R volume forests (Sec. 2.1 curved elements, eq. nodal,
+eq. tensorgeom; App. A.1 ray against the leaf's face patches; App. A.2 boxes).
+
+The GPU searches each candidate's six leaf faces in camera space and polishes
+the crossings on the tree's face polynomial; the oracle evaluates the leaf's
+faces in world space and searches them with its own subdivision.  Per
+candidate, the number of intervals must match the oracle's for that (leaf,
+pixel), the interval ends agree to 1e-9 relative, every oracle interval lies
+in a GPU candidate (the interval totals match), and A, B and I agree to 1e-5
+relative (floor 1e-3 of the image maximum).
+"""
+
+import numpy as np
+import pytest
+
+import synth
+from synth.scene import _sorted_forest, straddle_refiner
+from test_gpu_parity import PIX_TOL, _torch, rel_err
+from test_gpu_surface import _candidates
+
+pytestmark = pytest.mark.gpu
+
+
+def _check_vol(forest, fields, cams, O, method="rk4", substeps=4, cand_sample=None):
+    torch = _torch()
+    import paper_1809_01334_amd as P
+
+    print(f"[case] degree-{int(forest.geom_params[0])} volume N={forest.nleaves} trees={forest.ntrees} "
+          f"cams={[(c.w, c.h) for c in cams]} {method} x{substeps}", flush=True)
+    r = P.Renderer(forest, fields, cams, method, substeps)
+    r.forward()
+    hit, sio = r.debug_segments()
+    torch.cuda.synchronize()
+    ccam, cleaf, cpix = _candidates(r)
+    n = len(ccam)
+    hit = hit[:n].cpu().numpy().astype(np.int64)
+    sio = sio[:4 * n].cpu().numpy().reshape(-1, 4)
+    r.forward()
+    A, B, I = (t.cpu().numpy() for t in (r.A, r.B, r.I))
+    total = 0
+    rng = np.random.default_rng(3)
+    for k, cam in enumerate(cams):
+        ref = O.vol_render(forest, fields, cam, method, substeps)
+        sel = np.nonzero(ccam == k)[0]
+        # every oracle interval is in some GPU candidate: the totals agree
+        assert int(hit[sel].sum()) == ref["segments"], (k, int(hit[sel].sum()), ref["segments"])
+        total += ref["segments"]
+        if cand_sample is not None and len(sel) > cand_sample:
+            sel = np.sort(rng.choice(sel, cand_sample, replace=False))
+        pi, pj = cpix[sel] % cam.w, cpix[sel] // cam.w
+        ns, iv = O.vol_cands(forest, cam.raw(), cleaf[sel], pi, pj)
+        if not np.array_equal(hit[sel], ns):
+            bad = np.nonzero(hit[sel] != ns)[0]
+            for b in bad[:8]:
+                print(f"[mismatch] cam {k} pixel ({pi[b]}, {pj[b]}) leaf {cleaf[sel][b]} gpu {hit[sel][b]} "
+                      f"{sio[sel][b]} oracle {ns[b]} {iv[b]}", flush=True)
+            raise AssertionError((k, len(bad)))
+        s = sio[sel]
+        one, two = ns >= 1, ns >= 2
+        np.testing.assert_allclose(s[one][:, :2], iv[one][:, :2], rtol=1e-9, atol=1e-12)
+        np.testing.assert_allclose(s[two][:, 2:], iv[two][:, 2:], rtol=1e-9, atol=1e-12)
+        sl = slice(r.cams.img_off[k], r.cams.img_off[k + 1])
+        for nm, x in (("A", A[sl]), ("B", B[sl]), ("I", I[sl])):
+            e = rel_err(x, ref[nm])
+            assert e <= PIX_TOL, (k, nm, e)
+    return total
+
+
+def _cubic_map(t1, t2, t3):
+    """A tree map of degree 3 in every reference coordinate (a degree-3 tree reproduces it exactly)."""
+    return np.stack([t1 + 0.05 * t2 ** 3 - 0.03 * t1 * t3, t2 + 0.04 * t3 * t1 * t1,
+                     t3 + 0.06 * t1 ** 3 - 0.03 * t2 * t2 * t3], -1)
+
+
+@pytest.mark.parametrize("R", [2, 3])
+def test_curved_adaptive_forest_rk4(oracle_mod, R):
+    sc = synth.volume_scene(0, R=R, lmin=1, lmax=4, w=64, h=48, ncams=2)
+    assert _check_vol(sc.forest, sc.fields, sc.cameras, oracle_mod) > 10000
+
+
+def test_cubic_tree_map(oracle_mod):
+    rng = np.random.default_rng([1809, 1334, 77])
+    centers, sigmas = rng.uniform(0, 1, (3, 3)), rng.uniform(0.08, 0.2, 3)
+    base = synth.adaptive_forest(straddle_refiner(centers, sigmas), 1, 4)
+    forest = synth.volume_forest([synth.vol_tree(_cubic_map, 3)], 3, base)
+    fields = synth.trilinear_fields_from_gaussians(base, centers, sigmas)
+    cams = [synth.random_perspective_camera(rng, 56, 40) for _ in range(2)]
+    for ns in (1, 8):
+        assert _check_vol(forest, fields, cams, oracle_mod, "rk4", ns) > 5000
+
+
+@pytest.mark.parametrize("c", [0.25, -0.4])
+def test_bent_cube_constant_medium_analytic(oracle_mod, c):
+    """Constant coefficients in closed form over the bent cube, one leaf and a refined forest; the oracle's
+    image here equals the closed-form chord (pinned on the CPU)."""
+    cam = synth.perspective_camera([2.2, -1.4, 2.0], [0.5, 0.5, 0.6 + 0.3 * c], [0, 0, 1], 1.0, 40.0, 48, 40, 6.0)
+    for base in (synth.uniform_forest(0), synth.uniform_forest(3)):
+        N = base.nleaves
+        forest = synth.volume_forest([synth.vol_tree(synth.bent_map(c), 2)], 2, base)
+        fields = synth.constant_fields(np.full(N, 1.25), np.full(N, 0.75))
+        assert _check_vol(forest, fields, [cam], oracle_mod, "analytic", 1) > 500
+
+
+def test_two_trees(oracle_mod):
+    """Two trees side by side (the second shifted by one along x and bent the other way): leaves find their
+    tree through tree_begin, and the shared face is crossed once from each side."""
+    rng = np.random.default_rng([1809, 1334, 78])
+    centers, sigmas = rng.uniform(0, 1, (3, 3)), rng.uniform(0.1, 0.25, 3)
+    b0 = synth.adaptive_forest(straddle_refiner(centers, sigmas), 1, 3)
+    b1 = synth.uniform_forest(2)
+    t0 = synth.vol_tree(lambda a, b, cc: np.stack([a, b, cc + 0.2 * a * (1 - a)], -1), 2)
+    t1 = synth.vol_tree(lambda a, b, cc: np.stack([a + 1.0, b, cc - 0.15 * a * (1 - a)], -1), 2)
+    lv = np.concatenate([b0.level, b1.level])
+    xs, ys, zs = (np.concatenate([getattr(b0, n), getattr(b1, n)]) for n in ("x", "y", "z"))
+    tree = np.repeat(np.arange(2), [b0.nleaves, b1.nleaves]).astype(np.int64)
+    forest = _sorted_forest(lv, xs, ys, zs, tree, "volume", synth.vol_geom([t0, t1], 2), 2)
+    N = forest.nleaves
+    kap = rng.uniform(0.5, 2.0, (8, N)).astype(np.float32)
+    eps = rng.uniform(0.1, 1.0, (8, N)).astype(np.float32)
+    fields = synth.Fields("trilinear", kap, eps)
+    cams = [synth.perspective_camera([1.0, -2.5, 1.8], [1.0, 0.5, 0.5], [0, 0, 1], 1.0, 50.0, 64, 40, 8.0),
+            synth.perspective_camera([3.2, 1.9, -0.8], [0.9, 0.4, 0.6], [0, 0, 1], 1.0, 45.0, 48, 48, 8.0)]
+    assert _check_vol(forest, fields, cams, oracle_mod, "rk4", 2) > 5000
+
+
+def test_larger_view_sampled_candidates(oracle_mod):
+    """A 256 x 192 view of a deeper forest: totals and images everywhere, pairing on 4000 sampled candidates."""
+    sc = synth.volume_scene(1, R=2, lmin=2, lmax=5, w=256, h=192, ncams=1, amp=0.08)
+    assert _check_vol(sc.forest, sc.fields, sc.cameras, oracle_mod, cand_sample=4000) > 100000
+
+
+def test_volume_unsupported_paths(oracle_mod):
+    """The adjoint, per-pixel lists, integrators other than RK4 with equal substeps (and closed form for
+    constant fields) and closed form on trilinear fields are rejected with RC_EUNSUPPORTED."""
+    torch = _torch()
+    import paper_1809_01334_amd as P
+
+    sc = synth.volume_scene(2, R=2, lmin=1, lmax=2, w=32, h=24)
+    r = P.Renderer(sc.forest, sc.fields, sc.cameras, "rk4", 4)
+    r.forward()
+    with pytest.raises(P.RcError) as e:
+        r.backward(torch.ones_like(r.I))
+    assert e.value.status == P._lib.RC_EUNSUPPORTED
+    for method, ns in (("analytic", 1), ("gauss2", 4), ("simpson", 4), ("rk4", 3)):
+        r = P.Renderer(sc.forest, sc.fields, sc.cameras, method, ns)
+        with pytest.raises(P.RcError) as e:
+            r.forward()
+        assert e.value.status == P._lib.RC_EUNSUPPORTED, (method, ns)
