@@ -87,6 +87,16 @@ def time_region(torch, fn, steps):
     return start.elapsed_time(end) / steps  # ms
 
 
+def tune_fold_skip(r):
+    """The autotuner's choice of the levels whose node records compositing leaves
+    out (the forward's images do not depend on it)."""
+    from paper_1809_01334_amd.tune import autotune
+
+    res = autotune(r, reps=3, keys=("fold_skip",))
+    log(f"[bench] fold_skip {res['tuning']['fold_skip']:#b}: composite ms {res['ms']['fold_skip']}")
+    return res["tuning"]["fold_skip"]
+
+
 def measured_traffic(kernel, r=None):
     """Calibrated HBM bytes of one step's launches of `kernel` on the renderer's
     workload, or None when none were taken for it or the kernel's sources changed
@@ -297,6 +307,7 @@ def bench_headline(torch, P, synth, scene, args):
     S = r.count_segments()
     C = counts["ncand"]
     log(f"[bench] visible pairs {counts['nvis']}, candidates {C}, segments {S}, node records {counts['nrec']}")
+    skip = tune_fold_skip(r)
     for _ in range(args.warmup):
         r.forward()
     ms_eager = time_region(torch, r.forward, args.steps)
@@ -332,6 +343,7 @@ def bench_headline(torch, P, synth, scene, args):
                         f"{len(cams)} perspective cameras of uneven resolution in one HIP graph",
             "views": len(cams), "resolutions": res, "leaves": scene.forest.nleaves, "visible": counts["nvis"],
             "candidates": C, "segments": S, "node_records": counts["nrec"], "pixels": npix,
+            "fold_skip": skip,
         },
         "images_per_s": len(cams) / (ms * 1e-3),
         "forward_eager_ms": ms_eager,
@@ -371,6 +383,7 @@ def bench_single(torch, P, synth, scene, args, index=None):
     S = r.count_segments()
     C = counts["ncand"]
     log(f"[bench] single view: visible {counts['nvis']}, candidates {C}, segments {S}, node records {counts['nrec']}")
+    skip = tune_fold_skip(r)
     for _ in range(args.warmup):
         r.forward()
     ms_eager = time_region(torch, r.forward, args.steps)
@@ -387,7 +400,8 @@ def bench_single(torch, P, synth, scene, args, index=None):
     out = {"workload": f"the adaptive forest ({scene.forest.nleaves} leaves), one 1024x1024 perspective view, "
                        f"trilinear kappa/eps, RK4 x 4",
            "leaves": scene.forest.nleaves, "visible": counts["nvis"], "candidates": C, "segments": S,
-           "node_records": counts["nrec"], "pixels": r.cams.npix, "ms_per_step": ms, "forward_eager_ms": ms_eager,
+           "node_records": counts["nrec"], "fold_skip": skip, "pixels": r.cams.npix, "ms_per_step": ms,
+           "forward_eager_ms": ms_eager,
            "ray_segments_per_s": S / (ms * 1e-3), "images_per_s": 1e3 / ms,
            "phase_ms": {"prune": t_prune, "segments": t_seg, "composite": t_comp},
            "fused_render_ms": t_render,

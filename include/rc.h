@@ -165,6 +165,7 @@ typedef struct rc_integrator {
 /* Launch shapes of the grid-stride kernels, in 256-thread workgroups; 0 (or a
  * NULL rc_tuning pointer) selects the default.  Forward results do not depend
  * on these values; adjoint sums are deterministic for a given value. */
+#define RC_MAX_FOLD_RUN 2
 typedef struct rc_tuning {
     int32_t seg_blocks;   /* rc_segments (default 8192; 16384 for the shell and the
                              integrator variants, 1024 for degree-R surfaces) */
@@ -172,6 +173,14 @@ typedef struct rc_tuning {
                              and the shell's 4096 */
     int32_t root_blocks;  /* root passes over the image pixels (default 4096) */
     int32_t adj_blocks;   /* rc_segments_backward leaf adjoint (default 2048) */
+    uint32_t fold_skip;   /* rc_composite and rc_render on the unit cube, one channel: bit l set (1 <= l <
+                             maxlevel) leaves level l's node records unwritten; the pass of the nearest
+                             written level above (or the root pass) folds the skipped levels itself, in the
+                             same association, so images are bit for bit the same.  At most
+                             RC_MAX_FOLD_RUN consecutive levels may be skipped (RC_EINVAL otherwise); bits
+                             outside 1 .. maxlevel - 1 are ignored, and rc_render keeps the levels whose
+                             walk would reach a leaf.  Default 0.  The node records of a call with
+                             fold_skip != 0 are NOT valid input to rc_segments_backward. */
 } rc_tuning;
 
 /* Static node table of a forest share: the internal nodes above the leaves,

@@ -27,6 +27,7 @@ RC_GEOM_VOLUME2, RC_GEOM_VOLUME3 = 5, 6
 RC_MAXTREES = 64
 RC_MAXLISTS = 16
 RC_MAXCH = 3
+RC_MAX_FOLD_RUN = 2
 RC_ABSENT = -1
 RC_FIELD_CONST, RC_FIELD_TRILINEAR, RC_FIELD_CONST_EQ, RC_FIELD_SURFACE = 0, 1, 2, 3
 RC_INT_ANALYTIC, RC_INT_RK4, RC_INT_GAUSS2, RC_INT_SIMPSON = 0, 1, 2, 3
@@ -48,7 +49,8 @@ class RcIntegrator(ctypes.Structure):
 
 
 class RcTuning(ctypes.Structure):
-    _fields_ = [("seg_blocks", c_i32), ("fold_blocks", c_i32), ("root_blocks", c_i32), ("adj_blocks", c_i32)]
+    _fields_ = [("seg_blocks", c_i32), ("fold_blocks", c_i32), ("root_blocks", c_i32), ("adj_blocks", c_i32),
+                ("fold_skip", ctypes.c_uint32)]
 
 
 class RcIndex(ctypes.Structure):

@@ -21,6 +21,8 @@ struct FoldCtx {
     const int64_t* counts;
     int64_t nslots;
     SlotLayout L;
+    const int32_t* child;        // static node table: children and anchors of internal nodes
+    const uint32_t *nx, *ny, *nz;
 };
 
 inline FoldCtx make_fold_ctx(const rc_forest* f, const rc_index* ix, const void* dcams, int32_t ncams,
@@ -39,6 +41,10 @@ inline FoldCtx make_fold_ctx(const rc_forest* f, const rc_index* ix, const void*
     C.counts = vf->counts;
     C.L = make_layout(ix, ncams);
     C.nslots = C.L.slot_begin[ix->maxlevel > 0 ? ix->maxlevel : 0];
+    C.child = ix->child;
+    C.nx = ix->x;
+    C.ny = ix->y;
+    C.nz = ix->z;
     return C;
 }
 
@@ -105,14 +111,35 @@ __device__ inline int64_t record_slot(const FoldCtx& C, int64_t g, int64_t w, in
     return upper_index(C.node_offset, lo, hi, g);
 }
 
-// One level pass of the coarsening (records of level l from their children's)
-// and the root pass into the images, as rc_composite launches them.
-rc_status launch_fold_level(const FoldCtx& C, int l, float* rec_node, unsigned grid, hipStream_t st);
-rc_status launch_fold_root(const FoldCtx& C, int32_t root, int64_t npix, float* A, float* B, float* I,
+// One level pass of the coarsening (records of level l from their
+// children's, folding the `run` skipped levels below l on the way) and the
+// root pass into the images (walking `run` skipped levels below the root),
+// as rc_composite launches them.
+rc_status launch_fold_level(const FoldCtx& C, int l, int run, float* rec_node, unsigned grid, hipStream_t st);
+rc_status launch_fold_root(const FoldCtx& C, int32_t root, int run, int64_t npix, float* A, float* B, float* I,
                            const rc_vforest* vf, unsigned grid, hipStream_t st);
 
 // Node records of levels maxlevel-1 .. 1 (rc_composite.hip).
 rc_status fold_levels(const FoldCtx& C, const rc_index* ix, const rc_vforest* vf, float* rec_node,
                       const rc_tuning* tune, hipStream_t st);
+
+// The levels whose node records a unit-cube forward leaves unwritten (bits 1
+// .. maxlevel - 1 of the tuning's fold_skip; none when the root is not an
+// internal node), and whether no run of them exceeds RC_MAX_FOLD_RUN.
+inline uint32_t fold_skip_mask(const rc_index* ix, const rc_tuning* t) {
+    if (!t || ix->root < 0 || ix->maxlevel < 2) return 0;
+    uint32_t levels = ((1u << ix->maxlevel) - 1u) & ~1u;
+    return t->fold_skip & levels;
+}
+inline int skip_run(uint32_t mask, int l) {
+    int d = 0;
+    while (l + 1 + d < 32 && (mask & (1u << (l + 1 + d)))) d++;
+    return d;
+}
+inline bool fold_skip_ok(uint32_t mask) {
+    for (int l = 0; l < 31; l++)
+        if (skip_run(mask, l) > RC_MAX_FOLD_RUN) return false;
+    return true;
+}
 
 }  // namespace rc

@@ -65,17 +65,215 @@ __global__ __launch_bounds__(256) void k_fold_root(FoldCtx C, int32_t root, int6
     }
 }
 
+// Per-wave LDS of the walk: the descriptors and children of the node being
+// walked at each depth, fetched by lanes 0..7 with one load each.
+struct WalkLDS {
+    uint4 desc[RC_MAX_FOLD_RUN][8];
+    int32_t child[RC_MAX_FOLD_RUN][8];
+};
+
+// The camera's view-order inputs, read once per walk.
+struct WalkCam {
+    double o[3], vh[3];
+    int ortho;
+};
+
+__device__ inline WalkCam walk_cam(const FoldCtx& C, int cam) {
+    WalkCam wc;
+    const Cam& cc = C.cams[cam];
+    wc.ortho = cc.ortho;
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        wc.o[k] = cc.o[k];
+        wc.vh[k] = cc.vh[k];
+    }
+    return wc;
+}
+
+__device__ inline int walk_view_bits(const WalkCam& c, int level, uint32_t x, uint32_t y, uint32_t z) {
+    if (c.ortho) return (c.vh[0] < 0.0 ? 1 : 0) | (c.vh[1] < 0.0 ? 2 : 0) | (c.vh[2] < 0.0 ? 4 : 0);
+    uint32_t half = 1u << (QMAX - level - 1);
+    double m0 = (double)(x + half) * QSCALE;
+    double m1 = (double)(y + half) * QSCALE;
+    double m2 = (double)(z + half) * QSCALE;
+    return (c.o[0] >= m0 ? 1 : 0) | (c.o[1] >= m1 ? 2 : 0) | (c.o[2] >= m2 ? 4 : 0);
+}
+
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Value at pixel (i, j) of internal node m (level l) for camera cam: the fold
+// of its children's values, nearest first, from the identity -- the record a
+// level pass would write there.  Children that are internal nodes within D
+// more levels are folded here in turn; the others' records are read.  cam and
+// m are the same in every lane; lanes with act = false load no records and
+// take part in the votes only.
+template <int D>
+__device__ float2 walk_node(const FoldCtx& C, const WalkCam& wc, WalkLDS& S, int cam, int64_t m, int l, bool act,
+                            int i, int j) {
+    const int64_t dslot = (int64_t)cam * C.ninternal + m;
+    float2 acc = make_float2(1.0f, 0.0f);
+    if constexpr (D == 0) {
+        ChildDesc d[8];
+        bool has[8];
+        float2 rv[8];
+#pragma unroll
+        for (int q = 0; q < 8; q++) {
+            d[q] = load_desc_scalar(C.desc, dslot * 8 + q);
+            has[q] = act && desc_has(d[q], i, j);
+            rv[q] = has[q] ? *desc_ptr(C, d[q], true, i, j) : make_float2(1.0f, 0.0f);
+        }
+#pragma unroll
+        for (int q = 0; q < 8; q++)
+            if (has[q]) acc = seg_combine(acc, rv[q]);
+    } else {
+        const int lane = threadIdx.x & (WAVE - 1);
+        wave_sync();  // the slot's previous node is done with
+        if (lane < 8) {
+            S.desc[D - 1][lane] = reinterpret_cast<const uint4*>(C.desc)[dslot * 8 + lane];
+            S.child[D - 1][lane] = C.child[m * 8 + lane];
+        }
+        int sb = walk_view_bits(wc, l, C.nx[m], C.ny[m], C.nz[m]);
+        wave_sync();
+#pragma unroll 1
+        for (int q = 0; q < 8; q++) {
+            uint4 u = S.desc[D - 1][q];
+            ChildDesc d;
+            d.i0 = (int16_t)(u.x & 0xffff);
+            d.i1 = (int16_t)(u.x >> 16);
+            d.j0 = (int16_t)(u.y & 0xffff);
+            d.j1 = (int16_t)(u.y >> 16);
+            d.off = (int64_t)(((uint64_t)u.w << 32) | (uint64_t)u.z);
+            bool has = act && desc_has(d, i, j);
+            if (!__any(has)) continue;
+            if (d.off >= 0) {
+                int64_t cm = __builtin_amdgcn_readfirstlane(S.child[D - 1][q ^ sb]);
+                float2 v = walk_node<D - 1>(C, wc, S, cam, cm, l + 1, has, i, j);
+                if (has) acc = seg_combine(acc, v);
+            } else if (has) {
+                acc = seg_combine(acc, C.rec_leaf[-1 - d.off + desc_index(d, i, j)]);
+            }
+        }
+    }
+    return acc;
+}
+
+// Root pass that walks W levels below the root: node records are read from
+// level W + 1 down.  A wave takes 64 consecutive pixels and walks once per
+// camera among them.
+template <int W>
+__global__ __launch_bounds__(256) void k_fold_walk(FoldCtx C, int32_t root, int64_t npix, float* A, float* B,
+                                                   float* I) {
+    __shared__ WalkLDS SL[256 / WAVE];
+    if (C.counts[3]) return;
+    WalkLDS& S = SL[threadIdx.x / WAVE];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int lane = threadIdx.x & (WAVE - 1);
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x - lane); base < npix; base += stride) {
+        int64_t p = base + lane;
+        bool valid = p < npix;
+        int cam = 0, i = 0, j = 0;
+        if (valid) {
+            cam = camera_of_pixel(C.cams, C.ncams, p);
+            int64_t loc = p - C.cams[cam].img_off;
+            int w = C.cams[cam].w;
+            j = (int)(loc / w);
+            i = (int)(loc - (int64_t)j * w);
+        }
+        bool pending = valid;
+        float2 acc = make_float2(1.0f, 0.0f);
+        for (;;) {
+            uint64_t pm = __ballot(pending);
+            if (pm == 0) break;
+            int c0 = __builtin_amdgcn_readfirstlane(__shfl(cam, __ffsll((unsigned long long)pm) - 1));
+            bool mine = pending && cam == c0;
+            WalkCam wc = walk_cam(C, c0);
+            float2 v = walk_node<W>(C, wc, S, c0, root, 0, mine, i, j);
+            if (mine) {
+                acc = v;
+                pending = false;
+            }
+        }
+        if (valid) {
+            A[p] = acc.x;
+            B[p] = acc.y;
+            I[p] = fmaf(acc.x, (float)C.cams[cam].bg, acc.y);
+        }
+    }
+}
+
+// Level pass whose children's level is skipped: each record folds the RUN
+// skipped levels below its node on the fly.  A wave walks once per node among
+// its records (one or two for the large rectangles of the upper levels).
+template <int RUN>
+__global__ __launch_bounds__(256) void k_fold_level_walk(FoldCtx C, int l, float2* out) {
+    __shared__ WalkLDS SL[256 / WAVE];
+    if (C.counts[3]) return;
+    WalkLDS& S = SL[threadIdx.x / WAVE];
+    int64_t s0 = C.L.slot_begin[l], s1 = C.L.slot_begin[l + 1];
+    int64_t R0 = C.node_offset[s0], R1 = C.node_offset[s1], Rtot = C.node_offset[C.nslots];
+    int64_t M = C.L.level_begin[l + 1] - C.L.level_begin[l];
+    int lane = threadIdx.x & (WAVE - 1);
+    int64_t wave = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    int64_t nw = (int64_t)gridDim.x * (blockDim.x / WAVE);
+    for (int64_t w = R0 / WAVE + wave; w * WAVE < R1; w += nw) {
+        int64_t g = w * WAVE + lane;
+        bool act = g >= R0 && g < R1;
+        int64_t gg = act ? g : (g < R0 ? R0 : R1 - 1);
+        int64_t slot = record_slot(C, gg, w, s0, s1, Rtot);
+        Rect r = load_rect(C.node_rect + 4 * slot);
+        int k = (int)(gg - C.node_offset[slot]);
+        int i, j;
+        rect_pixel(r, k, i, j);
+        bool pending = act;
+        float2 res = make_float2(1.0f, 0.0f);
+        for (;;) {
+            uint64_t pm = __ballot(pending);
+            if (pm == 0) break;
+            int src = __ffsll((unsigned long long)pm) - 1;
+            int64_t sl = uniform64(__shfl(slot, src));
+            bool mine = pending && slot == sl;
+            int64_t loc = sl - s0;
+            int64_t cam = divu(loc, M);
+            int64_t m = C.L.level_begin[l] + (loc - cam * M);
+            WalkCam wc = walk_cam(C, (int)cam);
+            float2 v = walk_node<RUN>(C, wc, S, (int)cam, m, l, mine, i, j);
+            if (mine) {
+                res = v;
+                pending = false;
+            }
+        }
+        if (act) out[g] = res;
+    }
+}
+
 }  // namespace
 
-rc_status launch_fold_level(const FoldCtx& C, int l, float* rec_node, unsigned grid, hipStream_t st) {
-    hipLaunchKernelGGL(k_fold_level, dim3(grid), dim3(256), 0, st, C, l, (float2*)rec_node);
+rc_status launch_fold_level(const FoldCtx& C, int l, int run, float* rec_node, unsigned grid, hipStream_t st) {
+    float2* out = (float2*)rec_node;
+    switch (run) {
+        case 0: hipLaunchKernelGGL(k_fold_level, dim3(grid), dim3(256), 0, st, C, l, out); break;
+        case 1: hipLaunchKernelGGL(k_fold_level_walk<1>, dim3(grid), dim3(256), 0, st, C, l, out); break;
+        case 2: hipLaunchKernelGGL(k_fold_level_walk<2>, dim3(grid), dim3(256), 0, st, C, l, out); break;
+        default: return RC_EINVAL;
+    }
     return hipGetLastError() == hipSuccess ? RC_OK : RC_EHIP;
 }
 
-rc_status launch_fold_root(const FoldCtx& C, int32_t root, int64_t npix, float* A, float* B, float* I,
+rc_status launch_fold_root(const FoldCtx& C, int32_t root, int run, int64_t npix, float* A, float* B, float* I,
                            const rc_vforest* vf, unsigned grid, hipStream_t st) {
-    hipLaunchKernelGGL(k_fold_root, dim3(grid), dim3(256), 0, st, C, root, npix, A, B, I, vf->leaf_vis,
-                       vf->vis_rect, vf->cand_offset);
+    switch (run) {
+        case 0:
+            hipLaunchKernelGGL(k_fold_root, dim3(grid), dim3(256), 0, st, C, root, npix, A, B, I, vf->leaf_vis,
+                               vf->vis_rect, vf->cand_offset);
+            break;
+        case 1: hipLaunchKernelGGL(k_fold_walk<1>, dim3(grid), dim3(256), 0, st, C, root, npix, A, B, I); break;
+        case 2: hipLaunchKernelGGL(k_fold_walk<2>, dim3(grid), dim3(256), 0, st, C, root, npix, A, B, I); break;
+        default: return RC_EINVAL;
+    }
     return hipGetLastError() == hipSuccess ? RC_OK : RC_EHIP;
 }
 
@@ -105,11 +303,14 @@ extern "C" rc_status rc_composite(const rc_forest* f, const rc_index* ix, const 
     if ((s = check_tables(vf, ix, ncams)) != RC_OK) return s;
     hipStream_t st = (hipStream_t)stream;
     if (is_curved(f)) return rc_shell_composite(f, ix, dcams, ncams, vf, rec_leaf, rec_node, npix, A, B, I, tune, st);
+    uint32_t skip = fold_skip_mask(ix, tune);
+    if (!fold_skip_ok(skip)) return RC_EINVAL;
     FoldCtx C = make_fold_ctx(f, ix, dcams, ncams, vf, rec_leaf, rec_node);
-    if ((s = fold_levels(C, ix, vf, rec_node, tune, st)) != RC_OK) return s;
-    hipLaunchKernelGGL(k_fold_root, dim3(stride_grid(npix, 256, tuned(tune, 2, 256 * 16))), dim3(256), 0, st, C,
-                       ix->root, npix, A,
-                       B, I, vf->leaf_vis, vf->vis_rect, vf->cand_offset);
-    RC_HIP(hipGetLastError());
-    return RC_OK;
+    unsigned grid = stride_grid(vf->cap_rec, 256, tuned(tune, 1, 256 * 32));
+    for (int l = ix->maxlevel - 1; l >= 1; l--) {
+        if (ix->level_begin[l + 1] == ix->level_begin[l] || (skip & (1u << l))) continue;
+        if ((s = launch_fold_level(C, l, skip_run(skip, l), rec_node, grid, st)) != RC_OK) return s;
+    }
+    unsigned rg = stride_grid(npix, 256, tuned(tune, 2, 256 * 16));
+    return launch_fold_root(C, ix->root, skip_run(skip, 0), npix, A, B, I, vf, rg, st);
 }

@@ -242,9 +242,31 @@ struct NodeAreaDst {
     }
 };
 
-// table[w] = the item k whose range [off[k], off[k+1]) holds index 64 w.
-__device__ inline void chunk_entry(const int64_t* off, int64_t n, int64_t w, int32_t* table) {
-    table[w] = (int32_t)upper_index_wide(off, 0, n, w * WAVE);
+// table[w] = the item k whose range [off[k], off[k+1]) holds index 64 w,
+// written by the items: item k (valid in this lane) fills the chunks whose
+// first index lies in its range.  Ranges of more than four chunks are filled
+// by the whole wave, one item at a time.  Items with empty ranges write
+// nothing, so a chunk gets the one item that holds its first index.
+// Wave-uniform control: every lane of the wave calls it.
+__device__ inline void chunk_scatter(const int64_t* off, int64_t k, bool valid, int64_t nchunks, int32_t* table) {
+    int64_t c0 = 0, c1 = 0;
+    if (valid) {
+        c0 = (off[k] + WAVE - 1) / WAVE;
+        c1 = (off[k + 1] + WAVE - 1) / WAVE;
+        if (c1 > nchunks) c1 = nchunks;
+    }
+    bool big = c1 - c0 > 4;
+    if (!big)
+        for (int64_t c = c0; c < c1; c++) table[c] = (int32_t)k;
+    uint64_t bm = __ballot(big);
+    const int lane = threadIdx.x & (WAVE - 1);
+    while (bm) {
+        int src = __ffsll((unsigned long long)bm) - 1;
+        bm &= bm - 1;
+        int64_t b0 = __shfl(c0, src), b1 = __shfl(c1, src);
+        int32_t bk = (int32_t)__shfl(k, src);
+        for (int64_t c = b0 + lane; c < b1; c += WAVE) table[c] = bk;
+    }
 }
 
 // Children of every (camera, internal node) in view order with their
@@ -306,22 +328,26 @@ __device__ inline void child_desc_entry(const DescArgs& a, int64_t t) {
 }
 
 // Chunk tables of candidates and node records, then the child descriptors,
-// in one grid: index ranges [0, nc1), [nc1, nc1 + nc2), [nc1 + nc2, end).
-__global__ __launch_bounds__(256) void k_tables(DescArgs a, int64_t nslots, int64_t nc1, int64_t nc2,
+// in one grid: index ranges [0, np) over visible pairs, [np, np + ns) over
+// node slots, [np + ns, end) over descriptors; np and ns are multiples of the
+// wave size, so a wave stays within one range.
+__global__ __launch_bounds__(256) void k_tables(DescArgs a, int64_t nslots, int64_t np, int64_t ns,
                                                 int32_t* cand_chunk, int32_t* rec_chunk) {
     if (a.counts[3]) return;
     int64_t nvis = a.counts[0];
     int64_t w1 = (a.counts[1] + WAVE - 1) / WAVE, w2 = (a.counts[2] + WAVE - 1) / WAVE;
-    int64_t end = nc1 + nc2 + a.total;
+    int64_t end = np + ns + a.total;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < end; t += stride) {
-        if (t < nc1) {
-            if (t < w1) chunk_entry(a.cand_offset, nvis, t, cand_chunk);
-        } else if (t < nc1 + nc2) {
-            int64_t w = t - nc1;
-            if (w < w2) chunk_entry(a.node_offset, nslots, w, rec_chunk);
-        } else {
-            child_desc_entry(a, t - nc1 - nc2);
+    const int lane = threadIdx.x & (WAVE - 1);
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x - lane); base < end; base += stride) {
+        int64_t t = base + lane;
+        if (base < np) {
+            chunk_scatter(a.cand_offset, t, t < nvis, w1, cand_chunk);
+        } else if (base < np + ns) {
+            int64_t k = t - np;
+            chunk_scatter(a.node_offset, k, k < nslots, w2, rec_chunk);
+        } else if (t < end) {
+            child_desc_entry(a, t - np - ns);
         }
     }
 }
@@ -431,9 +457,9 @@ rc_status prune(const rc_forest* f, const rc_index* ix, const void* dcams, int32
                 ix->z,         vf->leaf_vis, vf->vis_rect,    vf->cand_offset,
                 vf->node_rect, vf->node_offset, vf->counts,   (ChildDesc*)vf->child_desc,
                 L,             shell ? 1 : 0};
-    int64_t nc1 = vf->cap_cand / WAVE + 1, nc2 = nslots > 0 ? vf->cap_rec / WAVE + 1 : 0;
-    hipLaunchKernelGGL(k_tables, dim3(stride_grid(nc1 + nc2 + da.total, 256, 256 * 32)), dim3(256), 0, st, da, nslots,
-                       nc1, nc2, vf->cand_chunk, vf->rec_chunk);
+    int64_t np = (vf->cap_vis + WAVE - 1) / WAVE * WAVE, ns = (nslots + WAVE - 1) / WAVE * WAVE;
+    hipLaunchKernelGGL(k_tables, dim3(stride_grid(np + ns + da.total, 256, 256 * 32)), dim3(256), 0, st, da, nslots,
+                       np, ns, vf->cand_chunk, vf->rec_chunk);
     RC_HIP(hipGetLastError());
     return RC_OK;
 }

@@ -304,13 +304,23 @@ rc_status launch_render(const RenderArgs& a, const rc_index* ix, const rc_vfores
     unsigned grid = stride_grid(vf->cap_rec, 256, tuned(tune, 1, 2048));
     unsigned fgrid = stride_grid(vf->cap_rec, 256, tuned(tune, 1, 256 * 32));
     unsigned rgrid = stride_grid(a.npix, 256, tuned(tune, 2, 4096));
+    // skipped levels stay skipped only where the walk over them reaches no
+    // leaf: the leaves' records are not written here
+    uint32_t skip = fold_skip_mask(ix, tune);
+    if (!fold_skip_ok(skip)) return RC_EINVAL;
+    for (int l = 0; l < ix->maxlevel; l++) {
+        int d = skip_run(skip, l);
+        if (d == 0 || (l > 0 && (skip & (1u << l)))) continue;  // l heads a run of skipped levels below it
+        uint32_t reach = ((2u << (l + d + 1)) - 1u) & ~((2u << l) - 1u);  // levels l+1 .. l+d+1
+        if (ix->leaf_levels & reach) skip &= ~(((2u << (l + d)) - 1u) & ~((2u << l) - 1u));
+    }
     for (int l = ix->maxlevel - 1; l >= 1; l--) {
-        if (ix->level_begin[l + 1] == ix->level_begin[l]) continue;
+        if (ix->level_begin[l + 1] == ix->level_begin[l] || (skip & (1u << l))) continue;
         if (ix->leaf_levels & (1 << (l + 1))) {
             hipLaunchKernelGGL((k_render_level<KIND, NSUB>), dim3(grid), dim3(256), 0, st, a, l, (float2*)rec_node);
             RC_HIP(hipGetLastError());
         } else {
-            rc_status s = launch_fold_level(a.C, l, rec_node, fgrid, st);
+            rc_status s = launch_fold_level(a.C, l, skip_run(skip, l), rec_node, fgrid, st);
             if (s != RC_OK) return s;
         }
     }
@@ -319,7 +329,7 @@ rc_status launch_render(const RenderArgs& a, const rc_index* ix, const rc_vfores
         RC_HIP(hipGetLastError());
         return RC_OK;
     }
-    return launch_fold_root(a.C, a.root, a.npix, a.A, a.B, a.I, vf, rgrid, st);
+    return launch_fold_root(a.C, a.root, skip_run(skip, 0), a.npix, a.A, a.B, a.I, vf, rgrid, st);
 }
 
 }  // namespace

@@ -351,6 +351,7 @@ class Renderer:
         self.counts = None
         self.bwd_ready = False
         self.leaf_records = False  # rec_leaf holds the current fields' leaf records
+        self.node_records = False  # rec_node holds every level's node records (no fold_skip)
         # forward() through rc_render (the intra-tile fold) instead of rc_segments + rc_composite
         self.use_render = bool(use_render)
         # bumped by every call that changes the fields or rewrites the records, so
@@ -405,15 +406,28 @@ class Renderer:
         rc_segments(self.forest, self.fields, self.cams, self.vf, self.method, self.substeps, self.rec_leaf, hit, sio,
                     self.tuning, self.c_rk)
 
-    def composite(self):
+    def _tuning(self, full_records: bool):
+        """The tuning for a call; full_records: with every node record (fold_skip 0)."""
+        if not full_records or self.tuning.fold_skip == 0:
+            return self.tuning
+        t = L.RcTuning()
+        ctypes.pointer(t)[0] = self.tuning
+        t.fold_skip = 0
+        return t
+
+    def composite(self, full_records: bool = False):
+        """rc_composite (every channel in one call); full_records: write every
+        level's node records, as the adjoint needs, whatever the tuning skips."""
         self.generation += 1
+        tuning = self._tuning(full_records)
         if self.fields.nch > 1:
             # every channel in one call, on the channel-major blocks
             rc_composite_channels(self.forest, self.index, self.cams, self.vf, self.fields.nch, self.rec_leaf,
-                                  self.rec_node, self.A, self.B, self.I, self.tuning)
+                                  self.rec_node, self.A, self.B, self.I, tuning)
         else:
             rc_composite(self.forest, self.index, self.cams, self.vf, self.rec_leaf, self.rec_node, self.A, self.B,
-                         self.I, self.tuning)
+                         self.I, tuning)
+        self.node_records = tuning.fold_skip == 0 or self.fields.nch > 1
 
     def composite_per_channel(self):
         """rc_composite once per channel, on that channel's blocks of the records and images."""
@@ -475,17 +489,20 @@ class Renderer:
         rc_render(self.forest, self.index, self.fields, self.cams, self.vf, self.method, self.substeps,
                   self.rec_leaf, self.rec_node, self.A, self.B, self.I, self.tuning, self.c_rk)
         self.leaf_records = not self.fused
+        self.node_records = self.tuning.fold_skip == 0
 
-    def forward(self, leaf_records: Optional[bool] = None):
+    def forward(self, leaf_records: Optional[bool] = None, for_adjoint: bool = False):
         """Prune, segments and composite: rc_segments and rc_composite, which keep
         the leaf records the adjoint reads, or with leaf_records=False (default:
-        not self.use_render) rc_render, which keeps them only where it cannot fuse."""
+        not self.use_render) rc_render, which keeps them only where it cannot fuse.
+        for_adjoint: keep every record the adjoint reads (leaf records, and node
+        records of the levels the tuning's fold_skip would leave out)."""
         if leaf_records is None:
             leaf_records = not self.use_render
         self.prune()
-        if leaf_records:
+        if leaf_records or for_adjoint:
             self.segments()
-            self.composite()
+            self.composite(full_records=for_adjoint)
             self.leaf_records = True
         else:
             self.render_step()
@@ -498,6 +515,10 @@ class Renderer:
             # the adjoint reads the leaf records, which rc_render's fused path does not write
             self.segments()
             self.leaf_records = True
+            self.node_records = False
+        if not self.node_records:
+            # and every level's node records, which a fold_skip forward leaves out
+            self.composite(full_records=True)
         if dk is None:
             dk = torch.empty_like(self.fields.kappa)
         if de is None:
@@ -528,7 +549,7 @@ class Renderer:
         return self.graph
 
     def _graph_body(self, backward):
-        self.forward(leaf_records=True if backward else None)
+        self.forward(leaf_records=True if backward else None, for_adjoint=backward)
         if backward:
             self.backward(self.g_dLdI, self.g_dk, self.g_de)
 
@@ -576,7 +597,8 @@ class RenderFn(torch.autograd.Function):
         kd, ed = kappa.detach(), eps.detach()
         renderer.set_fields(kd, ed)
         # the leaf records stay for the adjoint when a gradient is wanted
-        _, _, I = renderer.forward(leaf_records=True if any(ctx.needs_input_grad[:2]) else None)
+        grad = any(ctx.needs_input_grad[:2])
+        _, _, I = renderer.forward(leaf_records=True if grad else None, for_adjoint=grad)
         ctx.renderer = renderer
         ctx.generation = renderer.generation
         ctx.save_for_backward(kd, ed)
@@ -588,7 +610,7 @@ class RenderFn(torch.autograd.Function):
         kd, ed = ctx.saved_tensors
         if r.generation != ctx.generation:
             r.set_fields(kd, ed)
-            r.forward(leaf_records=True)
+            r.forward(leaf_records=True, for_adjoint=True)
         dk, de = r.backward(gI.contiguous().float())
         return dk, de, None
 

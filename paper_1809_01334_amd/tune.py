@@ -1,8 +1,9 @@
 """Autotuner for the launch shapes of a Renderer (rc_tuning).
 
 For a fixed forest and camera set it times the forward with candidate
-workgroup counts for the segment kernel, the level folds and the root fold
-(coordinate descent, HIP events on the renderer's stream) and keeps the
+workgroup counts for the segment kernel, the level folds and the root fold,
+and the levels of the coarsening whose node records compositing leaves out
+(coordinate descent, HIP events on the renderer's stream), and keeps the
 fastest.  Forward results are identical for every shape, so tuning changes
 time only.  Chosen shapes can be cached in a JSON file keyed by the
 workload's signature.
@@ -21,6 +22,8 @@ from . import _lib as L
 SEG_BLOCKS = (2048, 4096, 8192, 16384, 32768)
 FOLD_BLOCKS = (1024, 2048, 4096, 8192, 16384)
 ROOT_BLOCKS = (1024, 2048, 4096, 8192)
+# levels whose node records the forward leaves out, folded by the pass above
+FOLD_SKIP = (0, 0b10, 0b100, 0b1000, 0b1010, 0b1100)
 
 
 def _time(renderer, fn, reps: int) -> float:
@@ -41,8 +44,9 @@ def signature(renderer) -> str:
     return f"N{renderer.forest.nleaves}-vis{c['nvis']}-cand{c['ncand']}-rec{c['nrec']}-m{renderer.method}-s{renderer.substeps}-{wh}"
 
 
-def autotune(renderer, reps: int = 5, cache: Optional[str] = None) -> Dict:
-    """Pick rc_tuning for `renderer` in place; returns the choice and the timings."""
+def autotune(renderer, reps: int = 5, cache: Optional[str] = None, keys: Optional[tuple] = None) -> Dict:
+    """Pick rc_tuning for `renderer` in place; returns the choice and the timings.
+    keys: tune only these fields (the others keep the renderer's values)."""
     sig = signature(renderer)
     if cache and os.path.exists(cache):
         try:
@@ -54,11 +58,17 @@ def autotune(renderer, reps: int = 5, cache: Optional[str] = None) -> Dict:
             return known[sig]
     renderer.prune()
     renderer.segments()
-    best = {"seg_blocks": 0, "fold_blocks": 0, "root_blocks": 0, "adj_blocks": 0}
+    t0 = renderer.tuning
+    best = {k: int(getattr(t0, k)) for k in ("seg_blocks", "fold_blocks", "root_blocks", "adj_blocks", "fold_skip")}
+    if keys is None:
+        best = {k: 0 for k in best}
     log = {}
     for key, opts, fn in (("seg_blocks", SEG_BLOCKS, renderer.segments),
                           ("fold_blocks", FOLD_BLOCKS, renderer.composite),
-                          ("root_blocks", ROOT_BLOCKS, renderer.composite)):
+                          ("root_blocks", ROOT_BLOCKS, renderer.composite),
+                          ("fold_skip", FOLD_SKIP, renderer.composite)):
+        if keys is not None and key not in keys:
+            continue
         times = {}
         for v in opts:
             renderer.tuning = L.RcTuning(**{**best, key: v})

@@ -60,8 +60,23 @@ def _check_prune(r, scene, O):
     expect = np.full(lv.shape, -1, np.int64)
     expect[cams * scene.forest.nleaves + leaves] = np.arange(nvis)
     assert np.array_equal(lv, expect)
+    _check_chunk_tables(r, off, c)
     torch.cuda.synchronize()
     return cams, leaves, off
+
+
+def _check_chunk_tables(r, off, c):
+    """Chunk tables: the visible pair holding candidate 64 w, and the node slot holding node record 64 w (the
+    last item whose offset is at most 64 w)."""
+    w1 = (int(off[-1]) + 63) // 64
+    want = np.searchsorted(off, 64 * np.arange(w1), side="right") - 1
+    assert np.array_equal(r.vf.cand_chunk[:w1].cpu().numpy(), want)
+    if r.nslots > 0:
+        noff = r.vf.node_offset[:r.nslots + 1].cpu().numpy()
+        assert int(noff[-1]) == c["nrec"]
+        w2 = (c["nrec"] + 63) // 64
+        want = np.searchsorted(noff, 64 * np.arange(w2), side="right") - 1
+        assert np.array_equal(r.vf.rec_chunk[:w2].cpu().numpy(), want)
 
 
 def _check_pairing(r, scene, O, cams, leaves, off):
