@@ -243,7 +243,12 @@ struct NodeAreaDst {
 };
 
 // table[w] = the item k whose range [off[k], off[k+1]) holds index 64 w,
-// written by the items: item k (valid in this lane) fills the chunks whose
+// searched for one chunk.
+__device__ inline void chunk_entry(const int64_t* off, int64_t n, int64_t w, int32_t* table) {
+    table[w] = (int32_t)upper_index_wide(off, 0, n, w * WAVE);
+}
+
+// The same table written by the items: item k (valid in this lane) fills the chunks whose
 // first index lies in its range.  Ranges of more than four chunks are filled
 // by the whole wave, one item at a time.  Items with empty ranges write
 // nothing, so a chunk gets the one item that holds its first index.
@@ -328,11 +333,14 @@ __device__ inline void child_desc_entry(const DescArgs& a, int64_t t) {
 }
 
 // Chunk tables of candidates and node records, then the child descriptors,
-// in one grid: index ranges [0, np) over visible pairs, [np, np + ns) over
-// node slots, [np + ns, end) over descriptors; np and ns are multiples of the
-// wave size, so a wave stays within one range.
+// in one grid: index ranges [0, np) for the candidate table, [np, np + ns)
+// for the record table, [np + ns, end) over descriptors.  A table's items are
+// its chunks (each searches the offsets) or, with `scatter`, the offsets'
+// items (visible pairs or slots; each fills its chunks).  np and ns are
+// multiples of the wave size, so a wave stays within one range.
 __global__ __launch_bounds__(256) void k_tables(DescArgs a, int64_t nslots, int64_t np, int64_t ns,
-                                                int32_t* cand_chunk, int32_t* rec_chunk) {
+                                                int scatter_cand, int scatter_rec, int32_t* cand_chunk,
+                                                int32_t* rec_chunk) {
     if (a.counts[3]) return;
     int64_t nvis = a.counts[0];
     int64_t w1 = (a.counts[1] + WAVE - 1) / WAVE, w2 = (a.counts[2] + WAVE - 1) / WAVE;
@@ -342,15 +350,26 @@ __global__ __launch_bounds__(256) void k_tables(DescArgs a, int64_t nslots, int6
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x - lane); base < end; base += stride) {
         int64_t t = base + lane;
         if (base < np) {
-            chunk_scatter(a.cand_offset, t, t < nvis, w1, cand_chunk);
+            if (scatter_cand)
+                chunk_scatter(a.cand_offset, t, t < nvis, w1, cand_chunk);
+            else if (t < w1)
+                chunk_entry(a.cand_offset, nvis, t, cand_chunk);
         } else if (base < np + ns) {
             int64_t k = t - np;
-            chunk_scatter(a.node_offset, k, k < nslots, w2, rec_chunk);
+            if (scatter_rec)
+                chunk_scatter(a.node_offset, k, k < nslots, w2, rec_chunk);
+            else if (k < w2)
+                chunk_entry(a.node_offset, nslots, k, rec_chunk);
         } else if (t < end) {
             child_desc_entry(a, t - np - ns);
         }
     }
 }
+
+// A chunk table is searched per chunk while the offsets it searches stay in
+// cache (probes cost little), and written from the offsets' items beyond that
+// (each probe would be a memory round trip); both give the same table.
+constexpr int64_t CHUNK_SEARCH_MAX_ITEMS = (int64_t)1 << 22;
 
 }  // namespace
 }  // namespace rc
@@ -457,9 +476,13 @@ rc_status prune(const rc_forest* f, const rc_index* ix, const void* dcams, int32
                 ix->z,         vf->leaf_vis, vf->vis_rect,    vf->cand_offset,
                 vf->node_rect, vf->node_offset, vf->counts,   (ChildDesc*)vf->child_desc,
                 L,             shell ? 1 : 0};
-    int64_t np = (vf->cap_vis + WAVE - 1) / WAVE * WAVE, ns = (nslots + WAVE - 1) / WAVE * WAVE;
+    int sc = vf->cap_vis > CHUNK_SEARCH_MAX_ITEMS, sr = nslots > CHUNK_SEARCH_MAX_ITEMS;
+    int64_t np = sc ? vf->cap_vis : vf->cap_cand / WAVE + 1;
+    int64_t ns = nslots == 0 ? 0 : (sr ? nslots : vf->cap_rec / WAVE + 1);
+    np = (np + WAVE - 1) / WAVE * WAVE;
+    ns = (ns + WAVE - 1) / WAVE * WAVE;
     hipLaunchKernelGGL(k_tables, dim3(stride_grid(np + ns + da.total, 256, 256 * 32)), dim3(256), 0, st, da, nslots,
-                       np, ns, vf->cand_chunk, vf->rec_chunk);
+                       np, ns, sc, sr, vf->cand_chunk, vf->rec_chunk);
     RC_HIP(hipGetLastError());
     return RC_OK;
 }

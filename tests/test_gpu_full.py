@@ -1,8 +1,9 @@
 """GPU parity at the full sizes of the batched and the adjoint workloads.
 
 * 64 cameras of resolutions from {256, 512, 1024, 2048}^2 on the 839959-leaf adaptive
-  forest, rendered in one launch sequence: sampled pixels of four views against the oracle
-  (1e-5), and two views bit for bit against rendering them alone.
+  forest, rendered in one launch sequence: the chunk tables (written from the ranges at
+  this size) against a search of the offsets, sampled pixels of four views against the
+  oracle (1e-5), and two views bit for bit against rendering them alone.
 * The 512^2 adjoint workload (785604 leaves, background 0.5): the loss
   L = sum (I - I_target)^2 over 2000 sampled pixels, dL/dI taken from the oracle's images
   and handed to both adjoints; the gradients with respect to all per-corner coefficients
@@ -13,7 +14,7 @@ import numpy as np
 import pytest
 
 import synth
-from test_gpu_parity import GRAD_TOL, PIX_TOL, _torch, rel_err
+from test_gpu_parity import GRAD_TOL, PIX_TOL, _check_chunk_tables, _torch, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -29,6 +30,10 @@ def test_batched_64_views_full_size(oracle_mod):
     rb = P.Renderer(scene.forest, scene.fields, cams, "rk4", 4)
     A, B, I = (t.clone() for t in rb.forward())
     torch.cuda.synchronize()
+    # past 2^22 visible pairs and slots the chunk tables are written from the ranges: same tables as a search
+    c = rb.vf.read_counts()
+    assert c["nvis"] > 1 << 22 and rb.nslots > 1 << 22
+    _check_chunk_tables(rb, rb.vf.cand_offset[:c["nvis"] + 1].cpu().numpy(), c)
     rng = np.random.default_rng(44)
     sizes = [c.w for c in cams]
     views = sorted({sizes.index(s) for s in set(sizes)})[:4]
