@@ -2108,7 +2108,9 @@ static int ho_newton(const orho *H, const double *rho, const double *d1, const d
  * the clip range, nearest first (up to cap): the tree square is subdivided
  * OR_HO_DEPTH times, discarding squares that cannot hold a hit, and Newton's
  * method runs from the centre of each square left; a root counts in the
- * square whose half-open extent holds it (far tree edges closed).  A square
+ * square whose half-open extent holds it rounded to the 2^-40 grid of the
+ * canonical polish (far tree edges closed), and ht1, ht2 return it so rounded
+ * (the leaf holding it is found from them).  A square
  * whose Newton iteration does not end inside it is split again, down to
  * OR_HO_MAXDEPTH, so that close roots near a tangency are separated.  Newton has
  * converged when its step falls below tol. */
@@ -2155,15 +2157,22 @@ static int ho_hits(const orcam *cm, const orho *H, const double *rho, const doub
         }
         /* canonical polish: the same start for every square that converged to this
          * root, so that exactly one square holds the result */
+        const double g = 1099511627776.0; /* 2^40 */
+        double q1 = t1, q2 = t2;
         if (ok) {
-            const double g = 1099511627776.0; /* 2^40 */
             t1 = nearbyint(t1 * g) / g;
             t2 = nearbyint(t2 * g) / g;
             double s1, s2;
             for (int it = 0; it < 2; it++) ok = ok && ho_newton(H, rho, d1, d2, &t1, &t2, &s1, &s2);
+            /* the square and the leaf that hold the root are decided on the root
+             * rounded to the same grid, which holds every leaf edge: a root within
+             * rounding of an edge goes to the leaf starting there, whatever the
+             * last bits of the polish */
+            q1 = nearbyint(t1 * g) / g;
+            q2 = nearbyint(t2 * g) / g;
         }
-        int in1 = (t1 >= a1 && t1 < a1 + h) || (t1 == 1.0 && a1 + h == 1.0);
-        int in2 = (t2 >= a2 && t2 < a2 + h) || (t2 == 1.0 && a2 + h == 1.0);
+        int in1 = (q1 >= a1 && q1 < a1 + h) || (q1 == 1.0 && a1 + h == 1.0);
+        int in2 = (q2 >= a2 && q2 < a2 + h) || (q2 == 1.0 && a2 + h == 1.0);
         if (!(ok && in1 && in2)) {
             if (d < OR_HO_MAXDEPTH) {
                 for (int c = 3; c >= 0; c--) {
@@ -2187,8 +2196,8 @@ static int ho_hits(const orcam *cm, const orho *H, const double *rho, const doub
             ht2[b] = ht2[b - 1];
         }
         hs[b] = s;
-        ht1[b] = t1;
-        ht2[b] = t2;
+        ht1[b] = q1;
+        ht2[b] = q2;
     }
     return nh;
 }

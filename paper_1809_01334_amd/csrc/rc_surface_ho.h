@@ -268,6 +268,7 @@ __device__ inline int ho_krawczyk(const double (&f1)[(R + 1) * (R + 1)], const d
 template <int R>
 __device__ inline bool ho_newton_local(const double (&f1)[(R + 1) * (R + 1)], const double (&f2)[(R + 1) * (R + 1)],
                                        double& u, double& v) {
+    double prev = INFINITY;
     for (int it = 0; it < 30; it++) {
         double a, au, av, b, bu, bv;
         ho_eval<R>(f1, u, v, a, au, av);
@@ -278,7 +279,13 @@ __device__ inline bool ho_newton_local(const double (&f1)[(R + 1) * (R + 1)], co
         u -= du;
         v -= dv;
         if (!(fabs(u) < 4.0 && fabs(v) < 4.0)) return false;
-        if (fabs(du) + fabs(dv) < 1e-14) return true;
+        double step = fabs(du) + fabs(dv);
+        if (step < 1e-14) return true;
+        // near a tangency the Jacobian is close to singular and the steps stall
+        // at rounding level above 1e-14: a small step that no longer shrinks
+        // has converged as far as the arithmetic allows
+        if (step < 1e-8 && step > 0.25 * prev) return true;
+        prev = step;
     }
     return false;
 }

@@ -62,11 +62,17 @@ __device__ inline void ho_candidate(const HoArgs& a, int64_t g, int64_t vp, cons
     double len = (double)(1u << (QMAX - lv));
     double w1[3], w2[3], off1, off2, rcam[3];
     ho_pixel_planes(c, i, j, w1, off1, w2, off2, rcam);
+    // the search covers the leaf's square padded by half a step of the 2^-40
+    // grid that decides which leaf holds a root (tree units): a root that
+    // rounds onto this leaf's edge from outside is this leaf's to find
+    const double pad = 0x1p-41;
+    const double a0 = (double)lx * inv - pad, a1 = ((double)lx + len) * inv + pad;
+    const double b0 = (double)ly * inv - pad, b1 = ((double)ly + len) * inv + pad;
     double L1[N2], L2[N2];
     ho_net<R>(a.G, tree, c.o, w1, off1, L1);
     ho_net<R>(a.G, tree, c.o, w2, off2, L2);
-    ho_restrict<R>(L1, (double)lx * inv, ((double)lx + len) * inv, (double)ly * inv, ((double)ly + len) * inv);
-    ho_restrict<R>(L2, (double)lx * inv, ((double)lx + len) * inv, (double)ly * inv, ((double)ly + len) * inv);
+    ho_restrict<R>(L1, a0, a1, b0, b1);
+    ho_restrict<R>(L2, a0, a1, b0, b1);
     HoHit h0{0.0, make_float2(1.0f, 0.0f)}, h1 = h0;
     int cnt = 0;
     if (ho_may_vanish(L1) && ho_may_vanish(L2)) {
@@ -94,7 +100,7 @@ __device__ inline void ho_candidate(const HoArgs& a, int64_t g, int64_t vp, cons
                     // one root in the (widened) square, or the deepest square: Newton from the centre
                     double u = u0 + 0.5 * hs, v = v0 + 0.5 * hs;
                     if (ho_newton_local<R>(L1, L2, u, v)) {
-                        double t1 = ((double)lx + u * len) * inv, t2 = ((double)ly + v * len) * inv;
+                        double t1 = a0 + u * (a1 - a0), t2 = b0 + v * (b1 - b0);
                         // canonical polish on the tree's polynomials
                         double T1[N2], T2[N2];
                         ho_net<R>(a.G, tree, c.o, w1, off1, T1);
@@ -115,12 +121,16 @@ __device__ inline void ho_candidate(const HoArgs& a, int64_t g, int64_t vp, cons
                                 t2 -= (pu * q - qu * p) / det;
                             }
                         }
+                        // the leaf and the square holding the root are decided on the
+                        // root rounded to the same grid, which holds every leaf edge
+                        double q1 = rint(t1 * gq) / gq, q2 = rint(t2 * gq) / gq;
                         double lu, lv2;
-                        if (ok && t1 >= 0.0 && t1 <= 1.0 && t2 >= 0.0 && t2 <= 1.0 &&
-                            surf_leaf_has(lv, lx, ly, t1, t2, lu, lv2)) {
+                        if (ok && q1 >= 0.0 && q1 <= 1.0 && q2 >= 0.0 && q2 <= 1.0 &&
+                            surf_leaf_has(lv, lx, ly, q1, q2, lu, lv2)) {
                             // a root in a neighbouring square is that square's to count
                             int n = 1 << d;
-                            int c1 = (int)fmin(lu * n, (double)(n - 1)), c2 = (int)fmin(lv2 * n, (double)(n - 1));
+                            double w1c = (q1 - a0) / (a1 - a0), w2c = (q2 - b0) / (b1 - b0);
+                            int c1 = (int)fmin(w1c * n, (double)(n - 1)), c2 = (int)fmin(w2c * n, (double)(n - 1));
                             if (c1 == (int)i1 && c2 == (int)i2) {
                                 // depth along the ray and the patch normal, in camera space
                                 double jt1[3], jt2[3], pz = 0.0;

@@ -5,8 +5,10 @@ surface; Sec. 2.8 surface model).
 Checked against: the nodal and partition-of-unity properties and polynomial
 reproduction; the bilinear oracle on a degree-elevated flat hexagon; the
 paraboloid z = c (t1^2 + t2^2) as a quadratic in the ray parameter (two hits);
-a cubic graph seen from above (depth and angle law in closed form); and
-watertightness of a curved hexagon by a point-in-polygon test.
+a cubic graph seen from above (depth and angle law in closed form);
+watertightness of a curved hexagon by a point-in-polygon test; and the rule for
+a root on a leaf edge (the leaf whose half-open extent holds the root rounded to
+the 2^-40 grid).
 """
 
 import math
@@ -143,3 +145,35 @@ def test_curved_hexagon_is_watertight(oracle_mod):
     nh = (out["hit_leaf"] >= 0).sum(1)
     assert np.all(nh[inside] == 1) and np.all(nh[~inside] == 0)
     assert inside.sum() > 2000
+
+
+@pytest.mark.parametrize("R", [2, 3])
+def test_edge_rays_go_to_the_leaf_starting_there(oracle_mod, R):
+    """A graph x = (t1, t2, f) seen from above: the hit of a vertical ray through (x, y) has parameters (x, y), so
+    a ray through a leaf edge or corner must hit exactly one leaf, the one whose half-open extent holds (x, y)
+    rounded to the 2^-40 grid: the leaf starting at the edge for offsets within half a grid step (1e-14), the
+    geometric one beyond it (1e-12)."""
+    f = _forest_one_tree(lambda a, b: np.stack([a, b, 0.2 * a * a - 0.15 * a * b + 0.1 * b], -1), R, level=3)
+    fl = synth.random_surface_fields(np.random.default_rng(90 + R), f.nleaves)
+    x0 = f.x.astype(np.float64) / (1 << synth.QMAX)
+    y0 = f.y.astype(np.float64) / (1 << synth.QMAX)
+    g = 2.0 ** 40
+
+    def leaf_at(u, v):
+        u, v = round(u * g) / g, round(v * g) / g
+        hit = np.nonzero((x0 <= u) & (u < x0 + 0.125) & (y0 <= v) & (v < y0 + 0.125))[0]
+        assert len(hit) == 1
+        return int(hit[0])
+
+    cases = 0
+    for e, t in ((0.5, 0.3), (0.25, 0.875), (0.625, 0.0625)):
+        for d in (0.0, 1e-14, -1e-14, 1e-12, -1e-12):
+            for u, v in ((e + d, t), (t, e + d), (e + d, e + d)):
+                cam = _ortho([0, 0, -1], [0, 1, 0], [u, v, 0.0], 1, 1, 1e-3, dist=3.0, zfar=6.0)
+                out = oracle_mod.ho_surface_render(f, fl, cam, hits=True)
+                got = out["hit_leaf"][0][out["hit_leaf"][0] >= 0]
+                assert len(got) == 1 and int(got[0]) == leaf_at(u, v), (u, v, got)
+                cases += 1
+    # the rounding decides: 1e-14 below an edge goes to the leaf starting there, 1e-12 below it does not
+    assert leaf_at(0.5 - 1e-14, 0.3) == leaf_at(0.5, 0.3) != leaf_at(0.5 - 1e-12, 0.3)
+    assert cases == 45
