@@ -59,15 +59,17 @@ ANALYTIC_LEAF_BYTES = 37
 # WRITE_SIZE), summed over one step's launches of the kernel on the named
 # workload, valid for the kernel sources whose SHA-256 is given.
 _SEG_SRC = ("rc_segments.hip", "rc_internal.h")
-_SEG_SHA = "b29f3a5dbf96bd08a70b123da9e7df65ea4b86019272877d61e2817cd50d1633"
+_SEG_SHA = "69126465805e6e77639aa399c4433d09922202638ae986e0a78f0ba145cba27d"
 _COMP_SRC = ("rc_composite.hip", "rc_composite.h", "rc_internal.h")
-_COMP_SHA = "c31cfa8cd17c442049152d58a92efadc281bb24408909e0e27476801a0844a03"
+_COMP_SHA = "a81881b6c8571343506658e1835138d0329656cd99cb611312693126475c9556"
 MEASURED_TRAFFIC = {
-    # keyed by (kernel, candidates of the workload): the 64 views, then the single 1024^2 view
-    ("k_segments_rk4<2, 4, 1>", 1331258581): {"bytes": 18933002965, "sources": _SEG_SRC, "sha256": _SEG_SHA},
-    ("composite", 1331258581): {"bytes": 36692339764, "sources": _COMP_SRC, "sha256": _COMP_SHA},
-    ("k_segments_rk4<2, 4, 1>", 14164540): {"bytes": 240382234, "sources": _SEG_SRC, "sha256": _SEG_SHA},
-    ("composite", 14164540): {"bytes": 404483284, "sources": _COMP_SRC, "sha256": _COMP_SHA},
+    # keyed by (kernel, candidates of the workload) -- the 64 views, then the single 1024^2 view -- and for
+    # compositing also by the fold_skip mask of the call (the levels whose records it does not write)
+    ("k_segments_rk4<2, 4, 1>", 1331258581): {"bytes": 18944933185, "sources": _SEG_SRC, "sha256": _SEG_SHA},
+    ("composite", 1331258581, 12): {"bytes": 26285487331, "sources": _COMP_SRC, "sha256": _COMP_SHA},
+    ("k_segments_rk4<2, 4, 1>", 14164540): {"bytes": 240249147, "sources": _SEG_SRC, "sha256": _SEG_SHA},
+    ("composite", 14164540, 2): {"bytes": 381707302, "sources": _COMP_SRC, "sha256": _COMP_SHA},
+    ("composite", 14164540, 4): {"bytes": 364071568, "sources": _COMP_SRC, "sha256": _COMP_SHA},
 }
 COPY_CALIB_BYTES = 256 << 20
 
@@ -87,11 +89,15 @@ def time_region(torch, fn, steps):
     return start.elapsed_time(end) / steps  # ms
 
 
-def tune_fold_skip(r):
-    """The autotuner's choice of the levels whose node records compositing leaves
-    out (the forward's images do not depend on it)."""
+def tune_fold_skip(r, fixed=None):
+    """The levels whose node records compositing leaves out (the forward's
+    images do not depend on them): `fixed`, or the autotuner's choice."""
     from paper_1809_01334_amd.tune import autotune
 
+    if fixed is not None:
+        r.tuning.fold_skip = fixed
+        log(f"[bench] fold_skip {fixed:#b} (given)")
+        return fixed
     res = autotune(r, reps=3, keys=("fold_skip",))
     log(f"[bench] fold_skip {res['tuning']['fold_skip']:#b}: composite ms {res['ms']['fold_skip']}")
     return res["tuning"]["fold_skip"]
@@ -104,6 +110,8 @@ def measured_traffic(kernel, r=None):
     import hashlib
 
     key = (kernel, r.counts["ncand"] if r is not None else None)
+    if kernel == "composite":
+        key = key + (int(r.tuning.fold_skip),)
     m = MEASURED_TRAFFIC.get(key)
     if not m or m["bytes"] is None:
         return None
@@ -216,6 +224,9 @@ def main():
     ap.add_argument("--no-analytic", action="store_true")
     ap.add_argument("--copy-calib", action="store_true",
                     help="end with plain 256 MiB device copies, the reference for HBM byte counters")
+    ap.add_argument("--fold-skip", type=int, default=None,
+                    help="levels whose node records compositing leaves out (rc_tuning.fold_skip) for the headline "
+                         "and single-view workloads; default: the autotuner's choice")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the forest share of one "
@@ -307,7 +318,7 @@ def bench_headline(torch, P, synth, scene, args):
     S = r.count_segments()
     C = counts["ncand"]
     log(f"[bench] visible pairs {counts['nvis']}, candidates {C}, segments {S}, node records {counts['nrec']}")
-    skip = tune_fold_skip(r)
+    skip = tune_fold_skip(r, args.fold_skip)
     for _ in range(args.warmup):
         r.forward()
     ms_eager = time_region(torch, r.forward, args.steps)
@@ -383,7 +394,7 @@ def bench_single(torch, P, synth, scene, args, index=None):
     S = r.count_segments()
     C = counts["ncand"]
     log(f"[bench] single view: visible {counts['nvis']}, candidates {C}, segments {S}, node records {counts['nrec']}")
-    skip = tune_fold_skip(r)
+    skip = tune_fold_skip(r, args.fold_skip)
     for _ in range(args.warmup):
         r.forward()
     ms_eager = time_region(torch, r.forward, args.steps)
