@@ -146,3 +146,40 @@ def test_volume_unsupported_paths(oracle_mod):
         with pytest.raises(P.RcError) as e:
             r.forward()
         assert e.value.status == P._lib.RC_EUNSUPPORTED, (method, ns)
+
+
+def test_two_channels_and_graph_replay(oracle_mod):
+    """Two trilinear channels through RK4 x 4: each channel's images bit for bit those of a one-channel render of
+    its fields (the channel loop pairs again per channel), and against the oracle; the
+    forward captured as a HIP graph replays to the eager images, with eager work between replays."""
+    torch = _torch()
+    import paper_1809_01334_amd as P
+
+    sc = synth.volume_scene(3, R=2, lmin=1, lmax=4, w=48, h=40, ncams=2, background=0.2)
+    rng = np.random.default_rng([1809, 1334, 5100])
+    second = synth.Fields("trilinear", (sc.fields.kappa * rng.uniform(0.5, 1.5, sc.fields.kappa.shape)).astype(np.float32),
+                          (sc.fields.eps * rng.uniform(0.5, 1.5, sc.fields.eps.shape)).astype(np.float32))
+    chans = [sc.fields, second]
+    print(f"[case] volume, 2 channels, N={sc.forest.nleaves}", flush=True)
+    r = P.Renderer(sc.forest, synth.stack_channels(chans), sc.cameras, "rk4", 4)
+    r.forward()
+    torch.cuda.synchronize()
+    Pn = r.cams.npix
+    for ch, fl in enumerate(chans):
+        r1 = P.Renderer(sc.forest, fl, sc.cameras, "rk4", 4)
+        r1.forward()
+        torch.cuda.synchronize()
+        for nm in ("A", "B", "I"):
+            assert torch.equal(getattr(r, nm)[ch * Pn:(ch + 1) * Pn], getattr(r1, nm)), (ch, nm)
+        for k, cam in enumerate(sc.cameras):
+            ref = oracle_mod.vol_render(sc.forest, fl, cam, "rk4", 4)
+            sl = slice(ch * Pn + r.cams.img_off[k], ch * Pn + r.cams.img_off[k + 1])
+            assert rel_err(r.I[sl].cpu().numpy(), ref["I"]) <= PIX_TOL, (ch, k)
+    ref = r.I.clone()
+    r.capture()
+    for _ in range(3):
+        r.I.zero_()
+        torch.cuda.synchronize()
+        r.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(r.I, ref)
