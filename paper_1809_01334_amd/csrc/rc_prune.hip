@@ -280,7 +280,6 @@ struct DescArgs {
     const Cam* cams;
     int64_t N, ninternal, total;
     const int32_t* child;
-    const uint8_t* nlevel;
     const uint32_t *nx, *ny, *nz;
     const int32_t* leaf_vis;
     const int16_t* vis_rect;
@@ -293,36 +292,73 @@ struct DescArgs {
     int natural;  // 1: children in Morton order (curved geometry), 0: view order
 };
 
-// Descriptor q of (camera, internal node) t / 8.  A node of level >= 1 whose
-// own rectangle is empty holds no record, so nothing reads its descriptors
-// and they are not written; the roots' always are.
-__device__ inline void child_desc_entry(const DescArgs& a, int64_t t) {
-    int q = (int)(t & 7);
-    int64_t dslot = t >> 3;
-    int64_t cam = divu(dslot, a.ninternal);
-    int64_t m = dslot - cam * a.ninternal;
-    int l = a.nlevel[m];
-    if (l >= 1) {
-        int64_t M = a.L.level_begin[l + 1] - a.L.level_begin[l];
-        if (load_rect(a.node_rect + 4 * (a.L.slot_begin[l] + cam * M + (m - a.L.level_begin[l]))).empty()) return;
+// Descriptors t0 .. t0 + 63 (t0 a multiple of 64, wave-uniform): lanes
+// 8k .. 8k + 7 write the eight children of (camera, internal node)
+// t0 / 8 + k, in view order.  A node of level >= 1 whose own rectangle is
+// empty holds no record, so nothing reads its descriptors and they are not
+// written; the roots' always are.  The loads that do not depend on one another
+// go out together: the node's own rectangle, anchor and children (in natural
+// order, then permuted to view order across the node's lanes) and the camera
+// through the scalar cache when the wave has one; then the children's tables.
+// lb, sb: the slot layout's level_begin and slot_begin in LDS.
+__device__ inline void child_desc_wave(const DescArgs& a, const int64_t* lb, const int64_t* sb, int64_t t0,
+                                       int lane) {
+    const int64_t t = t0 + lane;
+    const bool valid = t < a.total;
+    const int q = lane & 7;
+    const int64_t d0 = uniform64(t0 >> 3);
+    int64_t cam = divu(d0, a.ninternal);
+    int64_t m = d0 - cam * a.ninternal + (lane >> 3);
+    while (m >= a.ninternal) {
+        m -= a.ninternal;
+        cam++;
     }
-    int sb = a.natural ? 0 : view_bits(a.cams[cam], l, a.nx[m], a.ny[m], a.nz[m]);
-    int32_t ref = a.child[m * 8 + (q ^ sb)];
+    if (!valid) cam = m = 0;  // in-bounds loads, nothing stored
+    // the node's level: nodes are stored level by level, so it is the largest
+    // l with lb[l] <= m (lb[0] = 0 <= m < lb[maxlevel] = ninternal)
+    int l = 0;
+    for (int hi = a.L.maxlevel; hi - l > 1;) {
+        int mid = (l + hi) >> 1;
+        if (lb[mid] <= m)
+            l = mid;
+        else
+            hi = mid;
+    }
+    const uint32_t x = a.nx[m], y = a.ny[m], z = a.nz[m];
+    const int32_t nat = a.child[m * 8 + q];
+    // the own rectangle (of a node below the roots; the roots' slot 0 stands
+    // in, read and ignored, so that the load is not behind a branch)
+    bool own_empty = false;
+    Rect own{0, 0, 0, 0};
+    if (a.L.maxlevel >= 2)  // there are slots
+        own = load_rect(a.node_rect + 4 * (l >= 1 ? sb[l] + cam * (lb[l + 1] - lb[l]) + (m - lb[l]) : 0));
+    int bits = 0;
+    if (!a.natural) {
+        const int64_t c0 = uniform64(cam);
+        if (__all(cam == c0)) {
+            Cam cs = load_cam_scalar(a.cams, (int)c0);
+            bits = view_bits(cs, l, x, y, z);
+        } else {
+            bits = view_bits(a.cams[cam], l, x, y, z);
+        }
+    }
+    const int32_t ref = __shfl(nat, (lane & ~7) | (q ^ bits));
+    own_empty = l >= 1 && own.empty();
+    if (!valid || own_empty) return;
+    // a leaf child's pair and an internal child's slot are looked up together
     Rect r{1, 0, 1, 0};
     int64_t off = 0;
-    if (ref <= -2) {
-        int64_t leaf = -2 - (int64_t)ref;
-        int32_t v = a.leaf_vis[cam * a.N + leaf];
-        if (v >= 0) {
-            r = load_rect(a.vis_rect + 4 * (int64_t)v);
-            off = -1 - a.cand_offset[v];
-        }
-    } else if (ref >= 0) {
-        int lc = l + 1;
-        int64_t M = a.L.level_begin[lc + 1] - a.L.level_begin[lc];
-        int64_t slot = a.L.slot_begin[lc] + cam * M + (ref - a.L.level_begin[lc]);
+    int32_t v = -1;
+    if (ref <= -2) v = a.leaf_vis[cam * a.N + (-2 - (int64_t)ref)];
+    if (ref >= 0) {
+        const int lc = l + 1;
+        int64_t slot = sb[lc] + cam * (lb[lc + 1] - lb[lc]) + (ref - lb[lc]);
         r = load_rect(a.node_rect + 4 * slot);
         off = a.node_offset[slot];
+    }
+    if (v >= 0) {
+        r = load_rect(a.vis_rect + 4 * (int64_t)v);
+        off = -1 - a.cand_offset[v];
     }
     uint4 u;
     u.x = (uint32_t)(uint16_t)r.i0 | ((uint32_t)(uint16_t)r.i1 << 16);
@@ -342,6 +378,12 @@ __global__ __launch_bounds__(256) void k_tables(DescArgs a, int64_t nslots, int6
                                                 int scatter_cand, int scatter_rec, int32_t* cand_chunk,
                                                 int32_t* rec_chunk) {
     if (a.counts[3]) return;
+    __shared__ int64_t lb[RC_QMAXLEVEL + 2], sb[RC_QMAXLEVEL + 2];
+    if (threadIdx.x < RC_QMAXLEVEL + 2) {
+        lb[threadIdx.x] = a.L.level_begin[threadIdx.x];
+        sb[threadIdx.x] = a.L.slot_begin[threadIdx.x];
+    }
+    __syncthreads();
     int64_t nvis = a.counts[0];
     int64_t w1 = (a.counts[1] + WAVE - 1) / WAVE, w2 = (a.counts[2] + WAVE - 1) / WAVE;
     int64_t end = np + ns + a.total;
@@ -360,8 +402,8 @@ __global__ __launch_bounds__(256) void k_tables(DescArgs a, int64_t nslots, int6
                 chunk_scatter(a.node_offset, k, k < nslots, w2, rec_chunk);
             else if (k < w2)
                 chunk_entry(a.node_offset, nslots, k, rec_chunk);
-        } else if (t < end) {
-            child_desc_entry(a, t - np - ns);
+        } else {
+            child_desc_wave(a, lb, sb, base - np - ns, lane);
         }
     }
 }
@@ -472,8 +514,8 @@ rc_status prune(const rc_forest* f, const rc_index* ix, const void* dcams, int32
     }
 
     DescArgs da{cams,          N,            ix->ninternal,   ix->ninternal * ncams * 8,
-                ix->child,     ix->level,    ix->x,           ix->y,
-                ix->z,         vf->leaf_vis, vf->vis_rect,    vf->cand_offset,
+                ix->child,     ix->x,        ix->y,           ix->z,
+                vf->leaf_vis,  vf->vis_rect, vf->cand_offset,
                 vf->node_rect, vf->node_offset, vf->counts,   (ChildDesc*)vf->child_desc,
                 L,             shell ? 1 : 0};
     int sc = vf->cap_vis > CHUNK_SEARCH_MAX_ITEMS, sr = nslots > CHUNK_SEARCH_MAX_ITEMS;

@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 
 import synth
-from test_gpu_parity import GRAD_TOL, PIX_TOL, _check_chunk_tables, _torch, rel_err
+from test_gpu_parity import GRAD_TOL, PIX_TOL, _check_child_desc, _check_chunk_tables, _torch, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -34,6 +34,7 @@ def test_batched_64_views_full_size(oracle_mod):
     c = rb.vf.read_counts()
     assert c["nvis"] > 1 << 22 and rb.nslots > 1 << 22
     _check_chunk_tables(rb, rb.vf.cand_offset[:c["nvis"] + 1].cpu().numpy(), c)
+    _check_child_desc(rb, sample=1 << 20)
     rng = np.random.default_rng(44)
     sizes = [c.w for c in cams]
     views = sorted({sizes.index(s) for s in set(sizes)})[:4]

@@ -61,8 +61,75 @@ def _check_prune(r, scene, O):
     expect[cams * scene.forest.nleaves + leaves] = np.arange(nvis)
     assert np.array_equal(lv, expect)
     _check_chunk_tables(r, off, c)
+    _check_child_desc(r)
     torch.cuda.synchronize()
     return cams, leaves, off
+
+
+def _check_child_desc(r, sample=None, seed=0):
+    """Child descriptors (16 bytes per child of each (camera, internal node), the children in view order for the
+    unit cube): the child's rectangle and record offset as the prune's own tables give them (a leaf's visible
+    pair, -1 - its candidate offset; a node's slot and its record offset); an absent or invisible child is the
+    empty rectangle (1, 0, 1, 0) with offset 0.  Nodes below the roots whose own rectangle is empty have no
+    records; their descriptors are not written and not compared.  `sample`: that many (camera, node) entries."""
+    ix, vf = r.index, r.vf
+    ni, ncams, N = ix.ninternal, r.cams.ncams, r.forest.nleaves
+    if ni == 0:
+        return
+    lb = ix.level_begin()
+    lev = ix.level[:ni].cpu().numpy().astype(np.int64)
+    child = ix.child[:8 * ni].cpu().numpy().reshape(ni, 8).astype(np.int64)
+    anchor = np.stack([getattr(ix, a)[:ni].cpu().numpy().view(np.uint32).astype(np.int64) for a in "xyz"], 1)
+    nrect = vf.node_rect[:4 * r.nslots].cpu().numpy().reshape(-1, 4)
+    noff = vf.node_offset[:r.nslots + 1].cpu().numpy()
+    nvis = vf.read_counts()["nvis"]
+    lvis = vf.leaf_vis[:ncams * N].cpu().numpy().astype(np.int64)
+    vrect = vf.vis_rect[:4 * nvis].cpu().numpy().reshape(-1, 4)
+    coff = vf.cand_offset[:nvis + 1].cpu().numpy()
+    raw = np.ascontiguousarray(vf.child_desc[:ncams * ni * 8 * 4].cpu().numpy())
+    drect = raw.view(np.int16).reshape(-1, 8)[:, :4]
+    doff = raw.view(np.int64).reshape(-1, 2)[:, 1]
+
+    e = np.arange(ncams * ni, dtype=np.int64)
+    if sample is not None and len(e) > sample:
+        e = np.sort(np.random.default_rng(seed).choice(len(e), sample, replace=False))
+    cam, m = e // ni, e % ni
+    l = lev[m]
+    M = lb[np.minimum(l + 1, ix.maxlevel)] - lb[l]
+    slot_begin = lambda lv: ncams * (lb[np.clip(lv, 1, ix.maxlevel)] - lb[1])  # noqa: E731
+    own = slot_begin(l) + cam * M + (m - lb[l])
+    keep = np.ones(len(m), bool)
+    k1 = l > 0
+    keep[k1] = (nrect[own[k1], 0] <= nrect[own[k1], 1]) & (nrect[own[k1], 2] <= nrect[own[k1], 3])
+    cam, m, l, e = cam[keep], m[keep], l[keep], e[keep]
+    if r.forest.curved:
+        sb = np.zeros(len(m), np.int64)
+    else:
+        C = r.cams.raw[cam]
+        half = (1 << (19 - l - 1)).astype(np.float64)
+        centre = (anchor[m] + half[:, None]) * 2.0 ** -19
+        persp = np.sum(np.where(C[:, 0:3] >= centre, 1, 0) * [1, 2, 4], 1)
+        ortho = np.sum(np.where(C[:, 3:6] < 0.0, 1, 0) * [1, 2, 4], 1)
+        sb = np.where(C[:, 16] != 0.0, ortho, persp)
+    for q in range(8):
+        ref = child[m, q ^ sb]
+        want_rect = np.tile(np.array([1, 0, 1, 0], np.int16), (len(m), 1))
+        want_off = np.zeros(len(m), np.int64)
+        leaf = ref <= -2
+        v = np.full(len(m), -1, np.int64)
+        v[leaf] = lvis[cam[leaf] * N + (-2 - ref[leaf])]
+        seen = v >= 0
+        want_rect[seen] = vrect[v[seen]]
+        want_off[seen] = -1 - coff[v[seen]]
+        node = ref >= 0
+        lc = l[node] + 1
+        Mc = lb[np.minimum(lc + 1, ix.maxlevel)] - lb[lc]
+        cs = slot_begin(lc) + cam[node] * Mc + (ref[node] - lb[lc])
+        want_rect[node] = nrect[cs]
+        want_off[node] = noff[cs]
+        t = e * 8 + q
+        assert np.array_equal(drect[t], want_rect), q
+        assert np.array_equal(doff[t], want_off), q
 
 
 def _check_chunk_tables(r, off, c):
