@@ -65,11 +65,19 @@ __global__ __launch_bounds__(256) void k_fold_root(FoldCtx C, int32_t root, int6
     }
 }
 
-// Per-wave LDS of the walk: the descriptors and children of the node being
-// walked at each depth, fetched by lanes 0..7 with one load each.
+// Per-wave LDS of the walk.  top: the walked node's descriptors (view order)
+// and children (natural order).  At depth d (a node with d more skipped levels
+// below it) the descriptors of all eight children come in one batch, one per
+// lane: bdesc[d - 1][q] holds child q's (natural order), and for d >= 2 also
+// bchild[d - 1][q] its children and bbits[d - 1][q] its view bits.  A child
+// is then walked from LDS, and a covered grandchild costs one round trip to
+// memory (its records), not two.
 struct WalkLDS {
-    uint4 desc[RC_MAX_FOLD_RUN][8];
-    int32_t child[RC_MAX_FOLD_RUN][8];
+    uint4 top[8];
+    int32_t topchild[8];
+    uint4 bdesc[RC_MAX_FOLD_RUN][8][8];
+    int32_t bchild[RC_MAX_FOLD_RUN][8][8];
+    int32_t bbits[RC_MAX_FOLD_RUN][8];
 };
 
 // The camera's view-order inputs, read once per walk.
@@ -105,16 +113,27 @@ __device__ inline void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Value at pixel (i, j) of internal node m (level l) for camera cam: the fold
-// of its children's values, nearest first, from the identity -- the record a
-// level pass would write there.  Children that are internal nodes within D
-// more levels are folded here in turn; the others' records are read.  cam and
-// m are the same in every lane; lanes with act = false load no records and
-// take part in the votes only.
+__device__ inline ChildDesc unpack_desc(const uint4& u) {
+    ChildDesc d;
+    d.i0 = (int16_t)(u.x & 0xffff);
+    d.i1 = (int16_t)(u.x >> 16);
+    d.j0 = (int16_t)(u.y & 0xffff);
+    d.j1 = (int16_t)(u.y >> 16);
+    d.off = (int64_t)(((uint64_t)u.w << 32) | (uint64_t)u.z);
+    return d;
+}
+
+// Value at pixel (i, j) of an internal node of level l for camera cam: the
+// fold of its children's values, nearest first, from the identity -- the
+// record a level pass would write there.  desc: the node's eight descriptors
+// (view order), child: its children (natural order), sb: its view bits, all in
+// LDS.  Children that are internal nodes within D more levels are folded here
+// in turn; the others' records are read.  Every lane of the wave calls it with
+// the same node; lanes with act = false load no records and take part in the
+// votes only.
 template <int D>
-__device__ float2 walk_node(const FoldCtx& C, const WalkCam& wc, WalkLDS& S, int cam, int64_t m, int l, bool act,
-                            int i, int j) {
-    const int64_t dslot = (int64_t)cam * C.ninternal + m;
+__device__ float2 walk_from(const FoldCtx& C, const WalkCam& wc, WalkLDS& S, int cam, int l, bool act, int i, int j,
+                            const uint4* desc, const int32_t* child, int sb) {
     float2 acc = make_float2(1.0f, 0.0f);
     if constexpr (D == 0) {
         ChildDesc d[8];
@@ -122,7 +141,7 @@ __device__ float2 walk_node(const FoldCtx& C, const WalkCam& wc, WalkLDS& S, int
         float2 rv[8];
 #pragma unroll
         for (int q = 0; q < 8; q++) {
-            d[q] = load_desc_scalar(C.desc, dslot * 8 + q);
+            d[q] = unpack_desc(desc[q]);
             has[q] = act && desc_has(d[q], i, j);
             rv[q] = has[q] ? *desc_ptr(C, d[q], true, i, j) : make_float2(1.0f, 0.0f);
         }
@@ -131,27 +150,34 @@ __device__ float2 walk_node(const FoldCtx& C, const WalkCam& wc, WalkLDS& S, int
             if (has[q]) acc = seg_combine(acc, rv[q]);
     } else {
         const int lane = threadIdx.x & (WAVE - 1);
-        wave_sync();  // the slot's previous node is done with
-        if (lane < 8) {
-            S.desc[D - 1][lane] = reinterpret_cast<const uint4*>(C.desc)[dslot * 8 + lane];
-            S.child[D - 1][lane] = C.child[m * 8 + lane];
+        wave_sync();  // the previous node of this depth is done with its batch
+        {
+            const int q = lane >> 3, qq = lane & 7;
+            const int32_t cq = child[q];
+            if (cq >= 0) {
+                S.bdesc[D - 1][q][qq] =
+                    reinterpret_cast<const uint4*>(C.desc)[((int64_t)cam * C.ninternal + cq) * 8 + qq];
+                if constexpr (D >= 2) S.bchild[D - 1][q][qq] = C.child[(int64_t)cq * 8 + qq];
+            }
+            if constexpr (D >= 2) {
+                const int32_t cl = child[lane & 7];
+                if (lane < 8 && cl >= 0) S.bbits[D - 1][lane] = walk_view_bits(wc, l + 1, C.nx[cl], C.ny[cl], C.nz[cl]);
+            }
         }
-        int sb = walk_view_bits(wc, l, C.nx[m], C.ny[m], C.nz[m]);
         wave_sync();
 #pragma unroll 1
-        for (int q = 0; q < 8; q++) {
-            uint4 u = S.desc[D - 1][q];
-            ChildDesc d;
-            d.i0 = (int16_t)(u.x & 0xffff);
-            d.i1 = (int16_t)(u.x >> 16);
-            d.j0 = (int16_t)(u.y & 0xffff);
-            d.j1 = (int16_t)(u.y >> 16);
-            d.off = (int64_t)(((uint64_t)u.w << 32) | (uint64_t)u.z);
+        for (int qv = 0; qv < 8; qv++) {
+            ChildDesc d = unpack_desc(desc[qv]);
             bool has = act && desc_has(d, i, j);
             if (!__any(has)) continue;
             if (d.off >= 0) {
-                int64_t cm = __builtin_amdgcn_readfirstlane(S.child[D - 1][q ^ sb]);
-                float2 v = walk_node<D - 1>(C, wc, S, cam, cm, l + 1, has, i, j);
+                const int q = qv ^ sb;
+                float2 v;
+                if constexpr (D >= 2)
+                    v = walk_from<D - 1>(C, wc, S, cam, l + 1, has, i, j, S.bdesc[D - 1][q], S.bchild[D - 1][q],
+                                         S.bbits[D - 1][q]);
+                else
+                    v = walk_from<0>(C, wc, S, cam, l + 1, has, i, j, S.bdesc[0][q], nullptr, 0);
                 if (has) acc = seg_combine(acc, v);
             } else if (has) {
                 acc = seg_combine(acc, C.rec_leaf[-1 - d.off + desc_index(d, i, j)]);
@@ -159,6 +185,22 @@ __device__ float2 walk_node(const FoldCtx& C, const WalkCam& wc, WalkLDS& S, int
         }
     }
     return acc;
+}
+
+// walk_from for internal node m, its descriptors, children and view bits
+// loaded first (cam and m the same in every lane).
+template <int D>
+__device__ float2 walk_node(const FoldCtx& C, const WalkCam& wc, WalkLDS& S, int cam, int64_t m, int l, bool act,
+                            int i, int j) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    wave_sync();  // the previous walk is done with the node's slots
+    if (lane < 8) {
+        S.top[lane] = reinterpret_cast<const uint4*>(C.desc)[((int64_t)cam * C.ninternal + m) * 8 + lane];
+        S.topchild[lane] = C.child[m * 8 + lane];
+    }
+    int sb = walk_view_bits(wc, l, C.nx[m], C.ny[m], C.nz[m]);
+    wave_sync();
+    return walk_from<D>(C, wc, S, cam, l, act, i, j, S.top, S.topchild, sb);
 }
 
 // Root pass that walks W levels below the root: node records are read from
