@@ -45,7 +45,14 @@ struct PruneSrc {
         Item it;
         double lo[3], hi[3];
         if (i < nleafitems) {
-            int64_t cam = divu(i, N), l = i - cam * N;
+            // the camera of the wave's first item, then of this one (a wave
+            // holds items of at most a few cameras)
+            const int64_t i0 = uniform64(i);
+            int64_t cam = divu(i0, N), l = i - cam * N;
+            while (l >= N) {
+                l -= N;
+                cam++;
+            }
             if (geom) {
                 int k = 0;
                 while (k + 1 < ntrees && l >= tb[k + 1]) k++;
@@ -67,15 +74,24 @@ struct PruneSrc {
             }
             it.val = it.r.empty() ? I64x3{0, 0, 0} : I64x3{1, it.r.area(), 0};
         } else {
-            int64_t s = i - nleafitems;
+            // the level of the wave's first slot (a uniform search), then of
+            // this one
+            const int64_t s = i - nleafitems, s0 = uniform64(s);
             int lv = 1;
+            while (lv < L.maxlevel && s0 >= L.slot_begin[lv + 1]) lv++;
             while (lv < L.maxlevel && s >= L.slot_begin[lv + 1]) lv++;
             int64_t M = L.level_begin[lv + 1] - L.level_begin[lv];
             int64_t loc = s - L.slot_begin[lv];
             int64_t cam = divu(loc, M);
             int64_t m = L.level_begin[lv] + (loc - cam * M);
             node_box(nlevel[m], nx[m], ny[m], nz[m], lo, hi);
-            it.r = box_rect(cams[cam], lo, hi);
+            int c0 = __builtin_amdgcn_readfirstlane((int)cam);
+            if (__all(cam == c0)) {
+                Cam cs = load_cam_scalar(cams, c0);
+                it.r = box_rect(cs, lo, hi);
+            } else {
+                it.r = box_rect(cams[cam], lo, hi);
+            }
             it.val = I64x3{0, 0, it.r.area()};
         }
         return it;
