@@ -3,6 +3,8 @@
 // descriptors written by rc_prune_visible.
 #pragma once
 
+#include <stddef.h>
+
 #include "rc_host.h"
 #include "rc_internal.h"
 
@@ -46,6 +48,32 @@ inline FoldCtx make_fold_ctx(const rc_forest* f, const rc_index* ix, const void*
     C.ny = ix->y;
     C.nz = ix->z;
     return C;
+}
+
+// First pixel of camera idx through the scalar cache: `idx` must be wave-uniform.
+static_assert(offsetof(Cam, img_off) % 8 == 0, "img_off is read as a 64-bit word");
+__device__ inline int64_t cam_img_off_scalar(const Cam* cams, int idx) {
+    return (int64_t)((const_u64_ptr)(cams + idx))[offsetof(Cam, img_off) / 8];
+}
+
+// camera_of_pixel for every active lane of a wave: one search for the first
+// active lane's pixel through the scalar cache; the lanes whose pixel lies in
+// another image (a wave that straddles images) search on their own.
+__device__ inline int camera_of_pixel_wave(const Cam* cams, int ncams, int64_t p) {
+    const int64_t p0 = uniform64(p);
+    int lo = 0, hi = ncams;
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (cam_img_off_scalar(cams, mid) <= p0)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    const int64_t b0 = cam_img_off_scalar(cams, lo);
+    const int64_t b1 = lo + 1 < ncams ? cam_img_off_scalar(cams, lo + 1) : INT64_MAX;
+    const bool in = p >= b0 && p < b1;
+    if (__all(in)) return lo;
+    return in ? lo : camera_of_pixel(cams, ncams, p);
 }
 
 __device__ inline bool desc_has(const ChildDesc& d, int i, int j) {

@@ -98,7 +98,7 @@ __global__ __launch_bounds__(256) void k_fold_root_ch(FoldCtx C, ChStrides S, in
     if (C.counts[3]) return;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < npix; p += stride) {
-        int cam = camera_of_pixel(C.cams, C.ncams, p);
+        int cam = camera_of_pixel_wave(C.cams, C.ncams, p);
         const Cam& c = C.cams[cam];
         int64_t loc = p - c.img_off;
         int j = (int)(loc / c.w);

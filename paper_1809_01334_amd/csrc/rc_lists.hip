@@ -381,7 +381,7 @@ __global__ __launch_bounds__(256) void k_merge_lists(MergeArgs M) {
                 ov++;
         }
         if (bad) acc = make_float2(NAN, NAN);
-        int cam = camera_of_pixel(M.cams, M.ncams, p);
+        int cam = camera_of_pixel_wave(M.cams, M.ncams, p);
         M.A[p] = acc.x;
         M.B[p] = acc.y;
         M.I[p] = fmaf(acc.x, (float)M.cams[cam].bg, acc.y);

@@ -263,7 +263,7 @@ __global__ __launch_bounds__(256) void k_render_level(RenderArgs a, int l, float
             int64_t p = w * WAVE + lane;
             bool act = p < a.npix;
             int64_t pp = act ? p : a.npix - 1;
-            int cam = camera_of_pixel(C.cams, C.ncams, pp);
+            int cam = camera_of_pixel_wave(C.cams, C.ncams, pp);
             const Cam& c = C.cams[cam];
             int64_t loc = pp - c.img_off;
             int j = (int)(loc / c.w);
