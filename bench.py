@@ -102,10 +102,11 @@ def torch_mod():
     return torch
 
 
-def tune(r, args):
-    """Launch shapes and skipped levels for the renderer: the autotuner's
-    choice, kept per workload in the tuning cache (searched again with
-    --retune); the forward's images do not depend on them."""
+def tune(r, args, adjoint=False):
+    """Launch shapes and skipped levels for the renderer (and with `adjoint`
+    the leaf adjoint's workgroups): the autotuner's choice, kept per workload
+    in the tuning cache (searched again with --retune); the images do not
+    depend on them, the gradients by rounding only."""
     from paper_1809_01334_amd.tune import autotune
 
     if args.retune:
@@ -113,6 +114,13 @@ def tune(r, args):
         r.forward()
         reps = int(min(50, max(3, math.ceil(5.0 / max(time_region(torch_mod(), r.forward, 3), 1e-3)))))
         res = autotune(r, reps=reps)
+        if adjoint:
+            from paper_1809_01334_amd.tune import autotune_adjoint
+
+            g = torch_mod().ones(r.cams.npix, device=r.device)
+            adj = autotune_adjoint(r, g, reps=reps)
+            res["tuning"]["adj_blocks"] = adj["adj_blocks"]
+            res["ms"]["adj_blocks"] = adj["ms"]
         cache = os.path.join(ROOT, "gpurun_out", "tuning.json") if args.retune_out else TUNING_CACHE
         known = json.load(open(cache)) if os.path.exists(cache) else {}
         known[res["signature"]] = res
@@ -417,7 +425,7 @@ def bench_single(torch, P, synth, scene, args, index=None):
     S = r.count_segments()
     C = counts["ncand"]
     log(f"[bench] single view: visible {counts['nvis']}, candidates {C}, segments {S}, node records {counts['nrec']}")
-    tuning = tune(r, args)
+    tuning = tune(r, args, adjoint=True)
     for _ in range(args.warmup):
         r.forward()
     ms_eager = time_region(torch, r.forward, args.steps)

@@ -24,6 +24,8 @@ FOLD_BLOCKS = (1024, 2048, 4096, 8192, 16384)
 ROOT_BLOCKS = (1024, 2048, 4096, 8192)
 # levels whose node records the forward leaves out, folded by the pass above
 FOLD_SKIP = (0, 0b10, 0b100, 0b1000, 0b1010, 0b1100)
+# workgroups of the leaf adjoint (rc_segments_backward)
+ADJ_BLOCKS = (1024, 2048, 4096, 8192, 16384)
 
 
 def _time(renderer, fn, reps: int) -> float:
@@ -88,3 +90,22 @@ def autotune(renderer, reps: int = 5, cache: Optional[str] = None, keys: Optiona
         with open(cache, "w") as fh:
             json.dump(known, fh, indent=1)
     return result
+
+
+def autotune_adjoint(renderer, dLdI: torch.Tensor, reps: int = 5) -> Dict:
+    """Workgroups of the leaf adjoint (rc_tuning.adj_blocks): the backward
+    after a forward meant for the adjoint, timed with each candidate.  For a
+    given grid the gradients are reproducible bit for bit; between grids they
+    differ by rounding only (a (chunk, pair) partial sums its hits in batches
+    whose split depends on the grid).  Sets the renderer's adj_blocks to the
+    fastest; returns it with the timings."""
+    renderer.forward(for_adjoint=True)
+    dk = torch.empty_like(renderer.fields.kappa)
+    de = torch.empty_like(renderer.fields.eps)
+    times = {}
+    for v in ADJ_BLOCKS:
+        renderer.tuning.adj_blocks = v
+        times[v] = _time(renderer, lambda: renderer.backward(dLdI, dk, de), reps)
+    best = min(times, key=times.get)
+    renderer.tuning.adj_blocks = best
+    return {"adj_blocks": best, "ms": {str(k): round(t, 4) for k, t in times.items()}}

@@ -548,6 +548,31 @@ def test_batched_views_equal_single_views_and_tuning_invariance():
     _check_images(rb, scene, _oracle())
 
 
+def test_adjoint_grid_determinism():
+    """For a given leaf-adjoint grid (adj_blocks) the gradients are the same bit for bit on every run.  Between
+    grids they differ by rounding only: a (chunk, pair) partial sums its hits in batches of 64 whose split
+    depends on the grid.  autotune_adjoint leaves the fastest grid in the renderer."""
+    torch = _torch()
+    import paper_1809_01334_amd as P
+    from paper_1809_01334_amd.tune import ADJ_BLOCKS, autotune_adjoint
+
+    scene = synth.small_scene(11, ncams=3, w=80, h=60, background=0.2)
+    r = _renderer(scene)
+    g = torch.linspace(-1.0, 1.0, r.cams.npix, device=r.device)
+    r.forward(for_adjoint=True)
+    ref = [t.clone() for t in r.backward(g)]
+    for ab in (1, 7, 2048, 16384):
+        r.tuning.adj_blocks = ab
+        first = [t.clone() for t in r.backward(g)]
+        again = r.backward(g)
+        assert all(torch.equal(a, b) for a, b in zip(first, again)), ab
+        for a, b in zip(first, ref):
+            a, b = a.cpu().numpy(), b.cpu().numpy()
+            np.testing.assert_allclose(a, b, rtol=1e-5, atol=1e-6 * np.abs(b).max(), err_msg=str(ab))
+    res = autotune_adjoint(r, g, reps=1)
+    assert res["adj_blocks"] in ADJ_BLOCKS and r.tuning.adj_blocks == res["adj_blocks"]
+
+
 def _oracle():
     from oracle import oracle as O
 
