@@ -344,7 +344,6 @@ __device__ inline void child_desc_wave(const DescArgs& a, const int64_t* lb, con
     const int32_t nat = a.child[m * 8 + q];
     // the own rectangle (of a node below the roots; the roots' slot 0 stands
     // in, read and ignored, so that the load is not behind a branch)
-    bool own_empty = false;
     Rect own{0, 0, 0, 0};
     if (a.L.maxlevel >= 2)  // there are slots
         own = load_rect(a.node_rect + 4 * (l >= 1 ? sb[l] + cam * (lb[l + 1] - lb[l]) + (m - lb[l]) : 0));
@@ -359,8 +358,7 @@ __device__ inline void child_desc_wave(const DescArgs& a, const int64_t* lb, con
         }
     }
     const int32_t ref = __shfl(nat, (lane & ~7) | (q ^ bits));
-    own_empty = l >= 1 && own.empty();
-    if (!valid || own_empty) return;
+    if (!valid || (l >= 1 && own.empty())) return;
     // a leaf child's pair and an internal child's slot are looked up together
     Rect r{1, 0, 1, 0};
     int64_t off = 0;
