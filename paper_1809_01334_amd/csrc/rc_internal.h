@@ -677,12 +677,59 @@ inline int64_t scan_blocks(int64_t n) {
     return nb < 1 ? 1 : nb;
 }
 
+// Up to this many blocks each block of the apply pass sums the totals of the
+// blocks before it itself (integer sums, exact in any order), and the
+// partials pass is left out: one launch fewer for at most 48 KB of cached
+// reads per block.
+constexpr int64_t SCAN_FUSED_MAX_BLOCKS = 2048;
+
+// k_scan_apply whose blocks take their carry from the reduce pass's block
+// totals (partial[0 .. nb)) instead of an exclusive prefix of them; the last
+// block hands the grand total to dst.total.
 template <typename T, int ITEMS, typename Src, typename Dst>
-inline hipError_t launch_scan_n(int64_t n, int64_t nb, Src src, Dst dst, T* partial, hipStream_t st) {
-    hipLaunchKernelGGL((k_scan_reduce<T, ITEMS, Src>), dim3((unsigned)nb), dim3(SCAN_NT), 0, st, n, src, partial);
+__global__ __launch_bounds__(SCAN_NT) void k_scan_apply_fused(int64_t n, int64_t nb, Src src, Dst dst,
+                                                              const T* partial) {
+    typedef decltype(src(int64_t(0))) ItemT;
+    __shared__ T sh[SCAN_NT / 64];
+    T acc = T();
+    for (int64_t k = threadIdx.x; k < (int64_t)blockIdx.x; k += SCAN_NT) acc = acc + partial[k];
+    T carry;
+    block_exclusive_scan<T, SCAN_NT>(acc, sh, carry);
+    int64_t base = (int64_t)blockIdx.x * SCAN_NT * ITEMS + threadIdx.x;
+    for (int k = 0; k < ITEMS; k++) {
+        int64_t i = base + (int64_t)k * SCAN_NT;
+        if (i - threadIdx.x >= n) break;  // the block's remaining steps are empty (uniform)
+        bool in = i < n;
+        ItemT item{};
+        T v = T();
+        if (in) {
+            item = src(i);
+            v = item.val;
+        }
+        T tot;
+        T ex = block_exclusive_scan<T, SCAN_NT>(v, sh, tot);
+        if (in) dst(i, carry + ex, item);
+        carry = carry + tot;
+    }
+    if (blockIdx.x == nb - 1 && threadIdx.x == 0) dst.total(carry);
+}
+
+template <typename T, int ITEMS, typename Src, typename Dst>
+inline void launch_scan_tail(int64_t n, int64_t nb, Src src, Dst dst, T* partial, hipStream_t st) {
+    if (nb <= SCAN_FUSED_MAX_BLOCKS) {
+        hipLaunchKernelGGL((k_scan_apply_fused<T, ITEMS, Src, Dst>), dim3((unsigned)nb), dim3(SCAN_NT), 0, st, n,
+                           nb, src, dst, (const T*)partial);
+        return;
+    }
     hipLaunchKernelGGL((k_scan_partials<T>), dim3(1), dim3(SCAN_NT), 0, st, nb, partial);
     hipLaunchKernelGGL((k_scan_apply<T, ITEMS, Src, Dst>), dim3((unsigned)nb), dim3(SCAN_NT), 0, st, n, nb, src,
                        dst, (const T*)partial);
+}
+
+template <typename T, int ITEMS, typename Src, typename Dst>
+inline hipError_t launch_scan_n(int64_t n, int64_t nb, Src src, Dst dst, T* partial, hipStream_t st) {
+    hipLaunchKernelGGL((k_scan_reduce<T, ITEMS, Src>), dim3((unsigned)nb), dim3(SCAN_NT), 0, st, n, src, partial);
+    launch_scan_tail<T, ITEMS>(n, nb, src, dst, partial, st);
     return hipGetLastError();
 }
 
@@ -691,9 +738,7 @@ inline hipError_t launch_scan_n(int64_t n, int64_t nb, Src src, Dst dst, T* part
 template <typename T, int ITEMS, typename SrcR, typename SrcA, typename Dst>
 inline hipError_t launch_scan2_n(int64_t n, int64_t nb, SrcR sr, SrcA sa, Dst dst, T* partial, hipStream_t st) {
     hipLaunchKernelGGL((k_scan_reduce<T, ITEMS, SrcR>), dim3((unsigned)nb), dim3(SCAN_NT), 0, st, n, sr, partial);
-    hipLaunchKernelGGL((k_scan_partials<T>), dim3(1), dim3(SCAN_NT), 0, st, nb, partial);
-    hipLaunchKernelGGL((k_scan_apply<T, ITEMS, SrcA, Dst>), dim3((unsigned)nb), dim3(SCAN_NT), 0, st, n, nb, sa,
-                       dst, (const T*)partial);
+    launch_scan_tail<T, ITEMS>(n, nb, sa, dst, partial, st);
     return hipGetLastError();
 }
 
