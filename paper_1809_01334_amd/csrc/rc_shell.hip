@@ -137,7 +137,7 @@ __device__ inline void wave_sync_lds() {
 }
 
 template <int NSUB>
-__global__ __launch_bounds__(256) void k_segments_shell(ShellSegArgs a) {
+__global__ __launch_bounds__(256, 4) void k_segments_shell(ShellSegArgs a) {
     __shared__ ShellQueue Q[256 / WAVE];
     if (a.counts[3]) return;
     int64_t nvis = a.counts[0];
