@@ -250,6 +250,7 @@ def main():
     ap.add_argument("--no-shares", action="store_true")
     ap.add_argument("--no-surface", action="store_true")
     ap.add_argument("--no-surface-ho", action="store_true")
+    ap.add_argument("--no-volume", action="store_true")
     ap.add_argument("--no-channels", action="store_true")
     ap.add_argument("--no-analytic", action="store_true")
     ap.add_argument("--copy-calib", action="store_true",
@@ -324,6 +325,8 @@ def main():
         out["surface_workload"] = bench_surface(torch, P, synth, max(args.steps // 5, 3))
     if not args.no_surface_ho:
         out["surface_ho_workload"] = bench_surface_ho(torch, P, synth, max(args.steps // 5, 3))
+    if not args.no_volume:
+        out["volume_workload"] = bench_volume(torch, P, synth, max(args.steps // 5, 3))
     if not args.no_shares:
         out["shares"] = bench_shares(torch, P, synth, scene, r1, max(args.steps // 5, 3))
 
@@ -712,6 +715,34 @@ def bench_surface_ho(torch, P, synth, steps):
     return {"workload": f"degree-2 lifted hexagon, Mandelbrot refinement levels 4-11 ({f.nleaves} leaves), "
                         f"1024x1024, transparent transfer", "leaves": f.nleaves, "visible": c["nvis"],
             "candidates": c["ncand"], "hits": H, "ms_per_step": ms, "hits_per_s": H / (ms * 1e-3),
+            "phase_ms": {"prune": t_prune, "segments": t_seg, "composite": t_comp}}
+
+
+def bench_volume(torch, P, synth, steps):
+    """Degree-2 volume trees (curved elements): an adaptive forest of levels
+    2-6 refined around Gaussians on one curved tree, trilinear fields, RK4 x 4,
+    one 512x512 perspective view."""
+    log("[bench] degree-2 volume workload: generating")
+    sc = synth.volume_scene(7, R=2, lmin=2, lmax=6, w=512, h=512, amp=0.08)
+    r = P.Renderer(sc.forest, sc.fields, sc.cameras, "rk4", 4, device="cuda:0")
+    c = r.counts
+    r.forward()
+    hit, _ = r.debug_segments()
+    S = int(hit[:c["ncand"]].to(torch.int64).sum().item())
+    r.forward()
+    r.capture()
+    r.replay()
+    ms = time_region(torch, r.replay, steps)
+    t_prune = time_region(torch, r.prune, steps)
+    t_seg = time_region(torch, r.segments, steps)
+    t_comp = time_region(torch, r.composite, steps)
+    log(f"[bench] degree-2 volume: {sc.forest.nleaves} leaves, visible {c['nvis']}, candidates {c['ncand']}, "
+        f"intervals {S}; forward {ms:.3f} ms; prune {t_prune:.3f}, segments {t_seg:.3f}, composite {t_comp:.3f} ms")
+    del r
+    torch.cuda.empty_cache()
+    return {"workload": f"degree-2 volume tree (curved elements), adaptive levels 2-6 ({sc.forest.nleaves} leaves), "
+                        f"trilinear kappa/eps, RK4 x 4, 512x512", "leaves": sc.forest.nleaves, "visible": c["nvis"],
+            "candidates": c["ncand"], "intervals": S, "ms_per_step": ms, "ray_segments_per_s": S / (ms * 1e-3),
             "phase_ms": {"prune": t_prune, "segments": t_seg, "composite": t_comp}}
 
 
