@@ -121,10 +121,11 @@ def tune(r, args, adjoint=False):
             adj = autotune_adjoint(r, g, reps=reps)
             res["tuning"]["adj_blocks"] = adj["adj_blocks"]
             res["ms"]["adj_blocks"] = adj["ms"]
-        cache = os.path.join(ROOT, "gpurun_out", "tuning.json") if args.retune_out else TUNING_CACHE
+        cache = args.retune_out or TUNING_CACHE
         known = json.load(open(cache)) if os.path.exists(cache) else {}
         known[res["signature"]] = res
-        os.makedirs(os.path.dirname(cache), exist_ok=True)
+        if os.path.dirname(cache):
+            os.makedirs(os.path.dirname(cache), exist_ok=True)
         with open(cache, "w") as fh:
             json.dump(known, fh, indent=1)
     else:
@@ -258,7 +259,8 @@ def main():
     ap.add_argument("--retune", action="store_true",
                     help="search the launch shapes and skipped levels of the headline and single-view workloads again "
                          "and store them in the tuning cache (default: take them from the cache)")
-    ap.add_argument("--retune-out", action="store_true", help="with --retune, write gpurun_out/tuning.json instead")
+    ap.add_argument("--retune-out", default=None, metavar="PATH",
+                    help="with --retune, write the choices to this JSON file instead of the package's tuning cache")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the forest share of one "
