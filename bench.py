@@ -344,8 +344,8 @@ def main():
 
 def bench_headline(torch, P, synth, scene, args):
     """The forest of the adaptive workload seen by 64 cameras of uneven resolution
-    ({256, 512, 1024, 2048}^2), rendered by rc_render in one HIP graph: the largest
-    single-GPU workload by segments per step."""
+    ({256, 512, 1024, 2048}^2), its forward (prune, segments, composite) captured in
+    one HIP graph: the largest single-GPU workload by segments per step."""
     cams = synth.config4_cameras()
     npix = int(sum(c.npix for c in cams))
     log(f"[bench] headline: {scene.forest.nleaves} leaves, {len(cams)} cameras, {npix} pixels")

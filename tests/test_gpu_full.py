@@ -4,6 +4,8 @@
   forest, rendered in one launch sequence: the chunk tables (written from the ranges at
   this size) against a search of the offsets, sampled pixels of four views against the
   oracle (1e-5), and two views bit for bit against rendering them alone.
+* The same 64 views in the benchmark's launch configuration (tuning cache, one HIP graph
+  replayed): bit for bit the default configuration's images.
 * The 512^2 adjoint workload (785604 leaves, background 0.5): the loss
   L = sum (I - I_target)^2 over 2000 sampled pixels, dL/dI taken from the oracle's images
   and handed to both adjoints; the gradients with respect to all per-corner coefficients
@@ -52,6 +54,49 @@ def test_batched_64_views_full_size(oracle_mod):
         _, _, Is = rs.forward()
         sl = slice(rb.cams.img_off[k], rb.cams.img_off[k + 1])
         assert torch.equal(Is, I[sl]), k
+
+
+@pytest.mark.timeout(600)
+def test_batched_64_views_bench_configuration(oracle_mod):
+    """The 64 views as the benchmark times them: launch shapes and skipped levels from the
+    workload's entry in the package's tuning cache, the forward captured in one HIP graph and
+    replayed.  A, B and I of every replay equal, bit for bit, those of an eager forward with
+    the default launch shapes and every level written, and sampled pixels of the largest view
+    match the oracle."""
+    torch = _torch()
+    import json
+    import os
+
+    import paper_1809_01334_amd as P
+    from paper_1809_01334_amd import _lib as L
+    from paper_1809_01334_amd.tune import signature
+
+    scene = synth.config_scene(2)
+    cams = synth.config4_cameras()
+    r = P.Renderer(scene.forest, scene.fields, cams, "rk4", 4)
+    A0, B0, I0 = (t.clone() for t in r.forward())
+    cache = os.path.join(os.path.dirname(P.__file__), "tuning.json")
+    sig = signature(r)
+    known = json.load(open(cache))
+    assert sig in known, f"no tuning cache entry for {sig}"
+    tuned = known[sig]["tuning"]
+    print(f"[case] 64 views in the tuned configuration {tuned}, one HIP graph", flush=True)
+    assert tuned["fold_skip"] != 0  # the walk of skipped levels runs at full size
+    r.tuning = L.RcTuning(**tuned)
+    r.capture()
+    for rep in range(3):
+        A, B, I = r.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(A, A0) and torch.equal(B, B0) and torch.equal(I, I0), rep
+        r.prune()  # eager work between the replays
+        torch.cuda.synchronize()
+    k = max(range(len(cams)), key=lambda i: cams[i].npix)
+    cam = cams[k]
+    pix = np.sort(np.random.default_rng(45).choice(cam.npix, 1000, replace=False))
+    ref = oracle_mod.render(scene.forest, scene.fields, cam, "rk4", 4, pixels=pix)
+    lo = r.cams.img_off[k]
+    got = I[lo:lo + cam.npix].cpu().numpy()[pix]
+    assert rel_err(got, ref["I"]) <= PIX_TOL
 
 
 @pytest.mark.timeout(600)
