@@ -5,7 +5,8 @@
   this size) against a search of the offsets, sampled pixels of four views against the
   oracle (1e-5), and two views bit for bit against rendering them alone.
 * The same 64 views in the benchmark's launch configuration (tuning cache, one HIP graph
-  replayed): bit for bit the default configuration's images.
+  replayed): bit for bit the default configuration's images.  The 1024^2 view likewise, with
+  its forward + adjoint graph against an eager backward (bit for bit) and the oracle (1e-4).
 * The 512^2 adjoint workload (785604 leaves, background 0.5): the loss
   L = sum (I - I_target)^2 over 2000 sampled pixels, dL/dI taken from the oracle's images
   and handed to both adjoints; the gradients with respect to all per-corner coefficients
@@ -97,6 +98,55 @@ def test_batched_64_views_bench_configuration(oracle_mod):
     lo = r.cams.img_off[k]
     got = I[lo:lo + cam.npix].cpu().numpy()[pix]
     assert rel_err(got, ref["I"]) <= PIX_TOL
+
+
+@pytest.mark.timeout(600)
+def test_single_view_bench_configuration(oracle_mod):
+    """The 1024^2 view as the benchmark times it: the tuning cache's launch shapes, skipped
+    levels and leaf-adjoint grid; the forward, and the forward + adjoint, each captured in one
+    HIP graph and replayed.  The forward's replays equal an eager forward with the default
+    launch shapes bit for bit; the captured gradients equal an eager backward on the same grid
+    bit for bit and match the oracle's gradient of a loss on 2000 sampled pixels."""
+    torch = _torch()
+    import json
+    import os
+
+    import paper_1809_01334_amd as P
+    from paper_1809_01334_amd import _lib as L
+    from paper_1809_01334_amd.tune import signature
+
+    scene = synth.config_scene(2)
+    cam = scene.cameras[0]
+    r = P.Renderer(scene.forest, scene.fields, scene.cameras, "rk4", 4)
+    A0, B0, I0 = (t.clone() for t in r.forward())
+    known = json.load(open(os.path.join(os.path.dirname(P.__file__), "tuning.json")))
+    sig = signature(r)
+    assert sig in known, f"no tuning cache entry for {sig}"
+    tuned = known[sig]["tuning"]
+    print(f"[case] one 1024^2 view in the tuned configuration {tuned}", flush=True)
+    r.tuning = L.RcTuning(**tuned)
+    r.capture()
+    for rep in range(2):
+        A, B, I = r.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(A, A0) and torch.equal(B, B0) and torch.equal(I, I0), rep
+    pix = np.sort(np.random.default_rng(46).choice(cam.npix, 2000, replace=False))
+    go = np.random.default_rng(47).standard_normal(2000).astype(np.float32)
+    g = torch.zeros(r.cams.npix, dtype=torch.float32, device=r.device)
+    g[torch.from_numpy(pix).to(r.device)] = torch.from_numpy(go).to(r.device)
+    r.forward()
+    dk, de = (t.clone() for t in r.backward(g))
+    torch.cuda.synchronize()
+    r.capture(backward=True, dLdI=g)
+    for rep in range(2):
+        r.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(r.g_dk, dk) and torch.equal(r.g_de, de), rep
+    gk, ge = oracle_mod.grad(scene.forest, scene.fields, cam, go.astype(np.float64), "rk4", 4, pixels=pix)
+    assert np.abs(gk).max() > 0 and np.abs(ge).max() > 0
+    ek = rel_err(dk.cpu().numpy().T, gk)
+    ee = rel_err(de.cpu().numpy().T, ge)
+    assert ek <= GRAD_TOL and ee <= GRAD_TOL, (ek, ee)
 
 
 @pytest.mark.timeout(600)
