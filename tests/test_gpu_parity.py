@@ -501,6 +501,58 @@ def test_two_renders_on_one_renderer_in_one_loss():
     assert float(one[0].abs().max()) > 0 and float(one[2].abs().max()) > 0
 
 
+def test_over_capacity_prune_makes_later_calls_no_ops_and_retry_renders():
+    """A prune whose visible-pair, candidate or node-record capacity is one short sets the status word and still
+    counts every total; rc_segments, rc_composite, rc_render and rc_segments_backward then leave their outputs
+    untouched, and a retry with the counted sizes renders bit for bit what a planned renderer renders."""
+    torch = _torch()
+    import importlib
+
+    R = importlib.import_module("paper_1809_01334_amd.render")  # the module, not the package's render()
+
+    scene = synth.small_scene(12, w=64, h=48, background=0.3)
+    r = _renderer(scene)
+    A0, B0, I0 = (t.clone() for t in r.forward())
+    g = torch.linspace(-1.0, 1.0, r.cams.npix, device=r.device)
+    dk0, de0 = (t.clone() for t in r.backward(g))
+    c = r.vf.read_counts()
+    full = (c["nvis"], c["ncand"], c["nrec"])
+    N, nc, dev = r.forest.nleaves, r.cams.ncams, r.device
+    nan = float("nan")
+
+    def buffers(vf):
+        ws = torch.empty(R.workspace_bytes(r.forest, r.index, nc, vf), dtype=torch.uint8, device=dev)
+        rec_leaf, rec_node = torch.full_like(r.rec_leaf, nan), torch.full_like(r.rec_node, nan)
+        A, B, I = (torch.full((r.cams.npix,), nan, device=dev) for _ in range(3))
+        return ws, rec_leaf, rec_node, A, B, I
+
+    for k in range(3):
+        caps = tuple(v - 1 if j == k else v for j, v in enumerate(full))
+        vf = R.VForest(dev, N, nc, r.nslots, *caps, r.index.ninternal)
+        ws, rec_leaf, rec_node, A, B, I = buffers(vf)
+        R.rc_prune_visible(r.forest, r.index, r.cams, vf, ws)
+        got = vf.read_counts()
+        assert got["status"] == (2 if k == 2 else 1) and (got["nvis"], got["ncand"], got["nrec"]) == full, (k, got)
+        R.rc_segments(r.forest, r.fields, r.cams, vf, r.method, r.substeps, rec_leaf)
+        R.rc_composite(r.forest, r.index, r.cams, vf, rec_leaf, rec_node, A, B, I)
+        R.rc_render(r.forest, r.index, r.fields, r.cams, vf, r.method, r.substeps, rec_leaf, rec_node, A, B, I)
+        dk, de = torch.full_like(dk0, nan), torch.full_like(de0, nan)
+        R.rc_segments_backward(r.forest, r.index, r.fields, r.cams, vf, r.method, r.substeps, rec_leaf, rec_node,
+                               g, r.adj_leaf, r.adj_node, dk, de, False, ws)
+        torch.cuda.synchronize()
+        for nm, t in (("rec_leaf", rec_leaf), ("rec_node", rec_node), ("A", A), ("B", B), ("I", I), ("dk", dk),
+                      ("de", de)):
+            assert bool(torch.isnan(t).all()), (k, nm)
+    vf = R.VForest(dev, N, nc, r.nslots, *full, r.index.ninternal)
+    ws, rec_leaf, rec_node, A, B, I = buffers(vf)
+    R.rc_prune_visible(r.forest, r.index, r.cams, vf, ws)
+    assert vf.read_counts()["status"] == 0
+    R.rc_segments(r.forest, r.fields, r.cams, vf, r.method, r.substeps, rec_leaf)
+    R.rc_composite(r.forest, r.index, r.cams, vf, rec_leaf, rec_node, A, B, I)
+    torch.cuda.synchronize()
+    assert torch.equal(A, A0) and torch.equal(B, B0) and torch.equal(I, I0)
+
+
 def test_graph_replay_matches_eager():
     """HIP-graph replays, interleaved with eager work and syncs, equal the eager forward bit for bit."""
     torch = _torch()
